@@ -1,0 +1,373 @@
+"""FP64 CPU oracle of the ALCC/MAPG iteration for least-squares convex regression.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the package smoke check and
+by the benchmark's CPU-baseline leg, never by the product path.  It shares no
+code with the HIP library; the two meet only in the seeded inputs of ``synth``.
+
+The O(N^2) constraint operators A1, A2, A1^T, A2^T are plain C loops
+(``cr_oracle.c``); everything else is numpy float64, written in the order and
+notation of the paper (Aybat & Wang, "A Parallel Method for Large Scale Convex
+Regression Problems"):
+
+* problem: eq. "regularize" (Sec. II-C), min 1/2||y-ybar||^2 + gamma/2||xi||^2
+  s.t. A1 y + A2 xi >= 0;
+* ALCC: the augmented-Lagrangian outer loop of Fig. 3 (Sec. II-E);
+* MAPG: the block-wise accelerated projected gradient inner loop of Fig. 4;
+* P_k, h_k and their gradients: eq. "subproblem" and the gradient formulas
+  that follow it (Sec. II-E);
+* bounding balls Q_y, Q_xi from a feasible point: first paragraph of Sec. II-E.
+
+Readings of passages the paper leaves open are listed in the design notes and
+repeated next to the code that takes them.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cr_oracle.c")
+_LIB = os.path.join(_HERE, "libcr_oracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the C operators with gcc (-O2 -fopenmp).  Returns the .so path."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.cro_forward.argtypes = [ctypes.c_int64, ctypes.c_int, dp, dp, dp, dp]
+        lib.cro_forward.restype = None
+        lib.cro_adjoint.argtypes = [ctypes.c_int64, ctypes.c_int, dp, dp, dp, dp]
+        lib.cro_adjoint.restype = None
+        lib.cro_pair_residual.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int64, ctypes.c_int64]
+        lib.cro_pair_residual.restype = ctypes.c_double
+        lib.cro_adjoint_one.argtypes = [ctypes.c_int64, ctypes.c_int, dp, ctypes.c_int64,
+                                        dp, dp, dp, dp]
+        lib.cro_adjoint_one.restype = None
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Constraint operators (eq. "original_compact"; matrix-free, Sec. II-E)
+# ---------------------------------------------------------------------------
+
+def forward(X, y, xi) -> np.ndarray:
+    """R = A1 y + A2 xi as an N x N array, R[i, j] = y_i - y_j - xi_j^T (x_i - x_j); R[i, i] = 0."""
+    X, y, xi = _f64(X), _f64(y), _f64(xi)
+    N, n = X.shape
+    R = np.empty((N, N), dtype=np.float64)
+    _load().cro_forward(N, n, _p(X), _p(y), _p(xi.reshape(N, n)), _p(R))
+    return R
+
+
+def adjoint(X, Z):
+    """(A1^T z, A2^T z) for a pair array Z[i, j] (diagonal ignored); A2^T z is N x n."""
+    X, Z = _f64(X), _f64(Z)
+    N, n = X.shape
+    u = np.empty(N)
+    v = np.empty((N, n))
+    _load().cro_adjoint(N, n, _p(X), _p(Z), _p(u), _p(v))
+    return u, v
+
+
+def pair_residual(X, y, xi, i: int, j: int) -> float:
+    X, y, xi = _f64(X), _f64(y), _f64(xi)
+    return float(_load().cro_pair_residual(X.shape[1], _p(X), _p(y), _p(xi), i, j))
+
+
+def adjoint_one(X, m: int, zrow, zcol):
+    """Entry m of A1^T z and block m of A2^T z from row m (z_mj) and column m (z_im) of z."""
+    X, zrow, zcol = _f64(X), _f64(zrow), _f64(zcol)
+    N, n = X.shape
+    u = np.empty(1)
+    v = np.empty(n)
+    _load().cro_adjoint_one(N, n, _p(X), m, _p(zrow), _p(zcol), _p(u), _p(v))
+    return float(u[0]), v
+
+
+def neg_part(v):
+    """(v)_- := max(-v, 0), taken elementwise (the paper's notation, Sec. II-D)."""
+    return np.maximum(-v, 0.0)
+
+
+# ---------------------------------------------------------------------------
+# Problem constants
+# ---------------------------------------------------------------------------
+
+def sigma2_A1(N: int) -> float:
+    """sigma_max(A1)^2.  A1^T A1 = 2(N I - 1 1^T) (every pair contributes e_i - e_j
+    twice, once per order), whose largest eigenvalue is 2N."""
+    return 2.0 * N
+
+
+def sigma2_A2(X) -> float:
+    """sigma_max(A2)^2.  Row (i,j) of A2 touches only block j, so A2^T A2 is block
+    diagonal with blocks S_j = sum_{i != j} (x_i - x_j)(x_i - x_j)^T; the answer is
+    max_j lambda_max(S_j) (numpy eigvalsh per block)."""
+    X = _f64(X)
+    N, n = X.shape
+    best = 0.0
+    step = max(1, 4_000_000 // max(1, N * n))
+    for j0 in range(0, N, step):
+        D = X[None, :, :] - X[j0:j0 + step, None, :]          # (b, N, n): x_i - x_j
+        S = np.einsum("bik,bil->bkl", D, D)
+        best = max(best, float(np.linalg.eigvalsh(S)[:, -1].max()))
+    return best
+
+
+def affine_fit(X, ybar, gamma: float):
+    """Feasible starting point and bounding radii (Sec. II-E, first paragraph).
+
+    The least-squares affine fit yhat = X a + b (numpy lstsq) with xi_l = a for
+    every l has A1 yhat + A2 xihat = 0, so it is feasible.  Then
+    Bbar = sqrt(||yhat - ybar||^2 + gamma ||xihat||^2), Bbar_y = Bbar and
+    Bbar_xi = Bbar / sqrt(gamma).
+    """
+    X, ybar = _f64(X), _f64(ybar)
+    N, n = X.shape
+    M = np.hstack([X, np.ones((N, 1))])
+    coef, *_ = np.linalg.lstsq(M, ybar, rcond=None)
+    a, b = coef[:n], coef[n]
+    yhat = X @ a + b
+    xihat = np.tile(a, (N, 1))
+    Bbar = math.sqrt(float(np.sum((yhat - ybar) ** 2)) + gamma * float(np.sum(xihat ** 2)))
+    return yhat, xihat, Bbar, Bbar, Bbar / math.sqrt(gamma)
+
+
+# ---------------------------------------------------------------------------
+# ALCC subproblem P_k (eq. "subproblem") and its gradient
+# ---------------------------------------------------------------------------
+
+def penalty_weights(X, y, xi, theta):
+    """w = (A1 y + A2 xi - theta)_- for every pair, diagonal 0."""
+    R = forward(X, y, xi)
+    W = neg_part(R - theta)
+    np.fill_diagonal(W, 0.0)
+    return W
+
+
+def grad_P(X, ybar, gamma, mu, theta, y, xi):
+    """(grad_y P_k, grad_xi P_k) at (y, xi):
+    grad_y  = (y - ybar)/mu      - A1^T (A1 y + A2 xi - theta)_-
+    grad_xi = (gamma/mu) xi      - A2^T (A1 y + A2 xi - theta)_-"""
+    W = penalty_weights(X, y, xi, theta)
+    u, v = adjoint(X, W)
+    return (y - ybar) / mu - u, (gamma / mu) * xi - v
+
+
+def P_value(X, ybar, gamma, mu, theta, y, xi) -> float:
+    W = penalty_weights(X, y, xi, theta)
+    return (0.5 / mu) * float(np.sum((y - ybar) ** 2)) + (0.5 * gamma / mu) * float(np.sum(xi ** 2)) \
+        + 0.5 * float(np.sum(W * W))
+
+
+def project_ball(v, center, radius):
+    """Euclidean projection onto {z : ||z - center||_2 <= radius}."""
+    d = v - center
+    nrm = float(np.sqrt(np.sum(d * d)))
+    if nrm <= radius:
+        return v.copy()
+    return center + d * (radius / nrm)
+
+
+# ---------------------------------------------------------------------------
+# Parameters
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Params:
+    """ALCC/MAPG parameters.  The paper gives no values for any of them; the
+    defaults are this implementation's readings (see the design notes)."""
+    gamma: float = 1e-3          # Tikhonov weight (eq. "regularize")
+    mu1: float = 0.0             # <= 0: 1/sigma_max(A1)^2 = 1/(2N)
+    c: float = 4.0               # mu_{k+1} = c mu_k, c > 1
+    kappa: float = 0.1           # kappa > 0 in the tau/alpha decay
+    tau1: float = 1.0            # first subproblem tolerance
+    alpha_y1: float = 0.0        # <= 0: 1e-2 * Bbar_y
+    alpha_xi1: float = 0.0       # <= 0: 1e-2 * Bbar
+    step_scale: float = 0.5      # MAPG step = step_scale / L (reading of Lemma 3)
+    kkt_tol: float = 1e-4
+    max_outer: int = 30
+    inner_iters: int = 0         # > 0: fixed schedule, exactly this many MAPG steps per outer
+    max_inner: int = 20000       # cap on l_max when the schedule is adaptive
+    Ly_override: float = 0.0
+    Lxi_override: float = 0.0
+    By_override: float = 0.0
+    Bxi_override: float = 0.0
+
+
+def resolve(params: Params, N: int, Bbar: float, gamma: float):
+    mu1 = params.mu1 if params.mu1 > 0 else 1.0 / (2.0 * N)
+    ay = params.alpha_y1 if params.alpha_y1 > 0 else 1e-2 * Bbar
+    axi = params.alpha_xi1 if params.alpha_xi1 > 0 else 1e-2 * Bbar
+    return mu1, ay, axi
+
+
+# ---------------------------------------------------------------------------
+# MAPG (Fig. 4) and ALCC (Fig. 3)
+# ---------------------------------------------------------------------------
+
+def mapg(X, ybar, gamma, mu, theta, Ly, Lxi, y0, xi0, By, Bxi, alpha_y, alpha_xi,
+         lmax, step_scale=0.5, adaptive=True, trace=None):
+    """Modified accelerated projected gradient on P_k over Q_y x Q_xi.
+
+    Iteration 0: y1_0 = y2_1 = y0, same for xi, t_1 = 1.  Iteration l:
+    block projected-gradient steps from the extrapolated point (y2_l, xi2_l)
+    with step step_scale/L per block, the momentum sequence
+    t_{l+1} = (1 + sqrt(1 + 4 t_l^2))/2, extrapolation with weight
+    (t_l - 1)/t_{l+1}, and return of (y1_l, xi1_l) when both block moves
+    ||y1_l - y2_l||, ||xi1_l - xi2_l|| are within alpha (adaptive) or l = lmax.
+    Returns (y, xi, iterations)."""
+    y1_prev, xi1_prev = y0.copy(), xi0.copy()
+    y2, xi2 = y0.copy(), xi0.copy()
+    t = 1.0
+    zero = np.zeros_like(xi0)
+    for l in range(1, lmax + 1):
+        gy, gxi = grad_P(X, ybar, gamma, mu, theta, y2, xi2)
+        y1 = project_ball(y2 - (step_scale / Ly) * gy, ybar, By)
+        xi1 = project_ball(xi2 - (step_scale / Lxi) * gxi, zero, Bxi)
+        t_next = (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0
+        beta = (t - 1.0) / t_next
+        dy = float(np.sqrt(np.sum((y1 - y2) ** 2)))
+        dxi = float(np.sqrt(np.sum((xi1 - xi2) ** 2)))
+        if trace is not None:
+            trace.append((l, dy, dxi))
+        y2 = y1 + beta * (y1 - y1_prev)
+        xi2 = xi1 + beta * (xi1 - xi1_prev)
+        y1_prev, xi1_prev = y1, xi1
+        t = t_next
+        if adaptive and dy <= alpha_y and dxi <= alpha_xi:
+            return y1, xi1, l
+    return y1_prev, xi1_prev, lmax
+
+
+def kkt_measures(X, ybar, gamma, y, xi, lam):
+    """First-order optimality residuals of eq. "regularize" at (y, xi) with a
+    multiplier estimate lam >= 0 (one entry per pair):
+      stationarity  y - ybar - A1^T lam,  gamma xi - A2^T lam   (inf-norms)
+      infeasibility max_ij (r_ij)_-  with r = A1 y + A2 xi
+      complementarity max_ij lam_ij |r_ij|
+    and the combined KKT = max of the four / (1 + ||ybar||_inf).
+    Also the paper's normalized infeasibility ||(r)_-||_2 / sqrt(N^2-N) and
+    normalized gap lam^T r / (N^2-N) (Sec. III)."""
+    N = X.shape[0]
+    R = forward(X, y, xi)
+    u, v = adjoint(X, lam)
+    st_y = float(np.max(np.abs(y - ybar - u)))
+    st_xi = float(np.max(np.abs(gamma * xi - v)))
+    rneg = neg_part(R)
+    np.fill_diagonal(rneg, 0.0)
+    infeas = float(rneg.max())
+    LR = lam * R
+    np.fill_diagonal(LR, 0.0)
+    compl = float(np.max(np.abs(LR)))
+    scale = 1.0 + float(np.max(np.abs(ybar)))
+    return dict(stat_y=st_y, stat_xi=st_xi, infeas=infeas, compl=compl,
+                kkt=max(st_y, st_xi, infeas, compl) / scale,
+                infeas_norm=float(np.sqrt(np.sum(rneg * rneg))) / math.sqrt(N * N - N),
+                gap_norm=float(np.sum(LR)) / (N * N - N),
+                objective=0.5 * float(np.sum((y - ybar) ** 2)))
+
+
+@dataclasses.dataclass
+class Result:
+    y: np.ndarray
+    xi: np.ndarray
+    theta: np.ndarray
+    outer: int
+    inner_total: int
+    inner_per_outer: list
+    history: list
+    converged: bool
+
+
+def alcc(X, ybar, params: Optional[Params] = None, y0=None, xi0=None,
+         record_kkt: bool = True) -> Result:
+    """ALCC (Fig. 3) on eq. "regularize", MAPG (Fig. 4) as the inner solver.
+
+    Outer iteration k:
+      1. L^y_k = 1/mu_k + sigma_max(A1)^2,  L^xi_k = gamma/mu_k + sigma_max(A2)^2
+      2. l^max_k = ceil(4 sqrt((L^y Bbar_y^2 + L^xi Bbar_xi^2)/tau_k))   (fixed count
+         instead when params.inner_iters > 0; capped by params.max_inner)
+      3. (y_k, xi_k) = MAPG(P_k, ..., (y_{k-1}, xi_{k-1}), alpha_k, l^max_k)
+      4. theta_{k+1} = (mu_k/mu_{k+1}) (A1 y_k + A2 xi_k - theta_k)_-
+      5. mu_{k+1} = c mu_k,  tau_{k+1} = tau_k/(c k^{1+kappa})^2
+      6. alpha_{k+1} = alpha_k/(c k^{1+kappa})^2 (both blocks)
+    theta_1 = 0.  The multiplier estimate after step 4 is mu_{k+1} theta_{k+1};
+    the run stops after the first outer iteration whose KKT measure is within
+    params.kkt_tol (adaptive schedule only) or after params.max_outer."""
+    p = params or Params()
+    X, ybar = _f64(X), _f64(ybar)
+    N, n = X.shape
+    gamma = p.gamma
+    yhat, xihat, Bbar, By, Bxi = affine_fit(X, ybar, gamma)
+    if p.By_override > 0:
+        By = p.By_override
+    if p.Bxi_override > 0:
+        Bxi = p.Bxi_override
+    s2A1 = sigma2_A1(N)
+    s2A2 = sigma2_A2(X)
+    mu, ay, axi = resolve(p, N, Bbar, gamma)
+    tau = p.tau1
+    y = yhat if y0 is None else _f64(y0).copy()
+    xi = xihat if xi0 is None else _f64(xi0).reshape(N, n).copy()
+    theta = np.zeros((N, N))
+    fixed = p.inner_iters > 0
+    inner_list, hist = [], []
+    converged = False
+    k = 0
+    for k in range(1, p.max_outer + 1):
+        Ly = p.Ly_override if p.Ly_override > 0 else 1.0 / mu + s2A1
+        Lxi = p.Lxi_override if p.Lxi_override > 0 else gamma / mu + s2A2
+        if fixed:
+            lmax = p.inner_iters
+        else:
+            lmax = int(math.ceil(4.0 * math.sqrt((Ly * By ** 2 + Lxi * Bxi ** 2) / tau)))
+            lmax = max(1, min(lmax, p.max_inner))
+        y, xi, used = mapg(X, ybar, gamma, mu, theta, Ly, Lxi, y, xi, By, Bxi, ay, axi,
+                           lmax, p.step_scale, adaptive=not fixed)
+        inner_list.append(used)
+        mu_next = p.c * mu
+        R = forward(X, y, xi)
+        Wk = neg_part(R - theta)
+        np.fill_diagonal(Wk, 0.0)
+        theta = (mu / mu_next) * Wk
+        if record_kkt:
+            m = kkt_measures(X, ybar, gamma, y, xi, mu_next * theta)
+            m.update(k=k, inner=used, mu=mu)
+            hist.append(m)
+            if not fixed and m["kkt"] <= p.kkt_tol:
+                converged = True
+        decay = (p.c * k ** (1.0 + p.kappa)) ** 2
+        mu, tau, ay, axi = mu_next, tau / decay, ay / decay, axi / decay
+        if converged:
+            break
+    return Result(y, xi, theta, k, int(sum(inner_list)), inner_list, hist, converged)
