@@ -1,0 +1,217 @@
+/*
+ * cr.h - C ABI of the MI355X (gfx950) convex-regression pair engine.
+ *
+ * The library solves the Tikhonov-regularized least-squares convex-regression
+ * QP (Aybat & Wang, "A Parallel Method for Large Scale Convex Regression
+ * Problems", Sec. II-C, eq. "regularize"):
+ *
+ *     min_{y in R^N, xi in R^{N x n}}  1/2 ||y - ybar||^2 + gamma/2 ||xi||^2
+ *     s.t.  y_i >= y_j + xi_j^T (x_i - x_j)   for every ordered pair i != j
+ *
+ * with the ALCC augmented-Lagrangian method (Sec. II-E, Fig. 3) and MAPG, its
+ * block-wise accelerated projected-gradient inner solver (Sec. II-E, Fig. 4).
+ * The cost of every MAPG iteration is one pass over all N(N-1) constraint
+ * pairs (the products with A1, A2, A1^T, A2^T that the paper names as the
+ * bottleneck of each MAPG iteration), done on the GPU without ever forming
+ * A1 or A2.
+ *
+ * Conventions for every entry point:
+ *  - All pointers named *_dev are device pointers on the device that is
+ *    current for the calling thread; arrays are dense and row-major:
+ *    X is N x n (row l = x_l), ybar and y are N, xi is N x n (row l = xi_l),
+ *    theta (inspection calls only) is N x N with theta[i*N + j] the
+ *    multiplier of the pair (i, j).  X, ybar, y and xi are IEEE double in
+ *    every precision mode; the precision mode only selects the arithmetic of
+ *    the O(N^2) pair pass.
+ *  - "stream" is a hipStream_t passed as void* (0 = the null stream).  Work is
+ *    enqueued on that stream; the calls marked "host-synchronous" also wait
+ *    for it.
+ *  - Every call returns a cr_status.  Arguments are validated on the host
+ *    before any HIP call, so argument errors are reported without touching a
+ *    GPU.  No exception or abort crosses the ABI.
+ *  - The library never allocates device memory for problem data: the caller
+ *    provides one workspace of cr_workspace_bytes() bytes (256-byte aligned)
+ *    and keeps it, X and ybar alive until cr_destroy().
+ */
+#ifndef CR_H
+#define CR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cr_status;
+enum {
+    CR_OK = 0,
+    CR_ERR_ARG = 1,          /* invalid argument (message in cr_last_error) */
+    CR_ERR_NOMEM = 2,        /* workspace smaller than cr_workspace_bytes() */
+    CR_ERR_HIP = 3,          /* a HIP runtime call failed */
+    CR_ERR_NONFINITE = 4,    /* NaN/Inf in X or ybar, or in an iterate */
+    CR_NOT_CONVERGED = 5,    /* max_outer reached before kkt_tol; outputs valid */
+    CR_ERR_STATE = 6,        /* call not valid in the context's current state */
+    CR_ERR_UNSUPPORTED = 7   /* e.g. n above CR_MAX_DIM */
+};
+
+/* Arithmetic of the pair pass. */
+enum {
+    CR_F64 = 0,        /* FP64 MFMA, theta stored in FP64 */
+    CR_F32 = 1,        /* FP32 MFMA, theta stored in FP32 */
+    CR_MIXED_BF16 = 2  /* BF16 MFMA on hi/lo splits, FP32 accumulation, theta FP32 */
+};
+
+/* Modes of cr_pairwise_step. */
+enum {
+    CR_GRAD = 0,          /* gradient of P_k at (y, xi) */
+    CR_THETA_UPDATE = 1   /* ALCC multiplier step at (y, xi) plus KKT residuals */
+};
+
+#define CR_MAX_DIM 31     /* largest supported point dimension n */
+
+/*
+ * Parameters of ALCC (Fig. 3) and MAPG (Fig. 4).  The paper gives no values;
+ * cr_params_default() fills this implementation's defaults.
+ *   gamma       Tikhonov weight (> 0)                               [1e-3]
+ *   mu1         first penalty parameter mu_1; <= 0 selects 1/(2N)   [0]
+ *   c           mu_{k+1} = c mu_k, c > 1                            [4]
+ *   kappa       decay exponent of tau_k and alpha_k, > 0            [0.1]
+ *   tau1        first subproblem tolerance tau_1 (> 0)              [1]
+ *   alpha_y1    MAPG stopping radius for y; <= 0 selects 1e-2 Bbar  [0]
+ *   alpha_xi1   MAPG stopping radius for xi; <= 0 selects 1e-2 Bbar [0]
+ *   step_scale  MAPG block step is step_scale / L (0 < s <= 1)      [0.5]
+ *   kkt_tol     outer stop when the KKT measure is <= kkt_tol       [1e-4]
+ *   max_outer   ALCC iteration cap                                  [30]
+ *   inner_iters > 0: fixed schedule, exactly this many MAPG
+ *               iterations per ALCC iteration and no early stops    [0]
+ *   max_inner   cap on l_max_k in the adaptive schedule             [20000]
+ *   precision   CR_F64, CR_F32 or CR_MIXED_BF16                     [CR_F64]
+ *   *_override  > 0 replaces the computed L^y, L^xi, Bbar_y, Bbar_xi [0]
+ */
+typedef struct {
+    double gamma, mu1, c, kappa, tau1, alpha_y1, alpha_xi1, step_scale, kkt_tol;
+    int32_t max_outer, inner_iters, max_inner, precision;
+    double Ly_override, Lxi_override, By_override, Bxi_override;
+} cr_params;
+
+/*
+ * Result summary.  kkt is max(stat_y, stat_xi, infeas, compl) / (1 + |ybar|_inf)
+ * at the last ALCC iterate (y_k, xi_k) with multiplier lam = mu_k (theta_k - r)_+:
+ *   stat_y  = |y - ybar - A1^T lam|_inf     stat_xi = |gamma xi - A2^T lam|_inf
+ *   infeas  = max_ij (r_ij)_-               compl   = max_ij lam_ij |r_ij|
+ * infeas_norm and gap_norm are the paper's normalized infeasibility
+ * ||(r)_-||_2 / sqrt(N^2-N) and gap lam^T r / (N^2-N) (Sec. III).
+ * pair_updates = N(N-1) * inner_iters; seconds is the wall time of the
+ * iteration loop (after initialisation).
+ */
+typedef struct {
+    int32_t outer_iters, status;
+    int64_t inner_iters;
+    double objective, kkt, stat_y, stat_xi, infeas, compl_, infeas_norm, gap_norm;
+    double seconds, pair_updates;
+    double sigma2_A1, sigma2_A2, Bbar_y, Bbar_xi;
+} cr_info;
+
+typedef struct cr_ctx cr_ctx;
+
+/* Fill *p with the defaults listed above.  CR_ERR_ARG if p is NULL. */
+cr_status cr_params_default(cr_params* p);
+
+/* Static text for a status code (never NULL). */
+const char* cr_status_string(cr_status s);
+
+/* Last error message of a context, or of the last failed call that had no
+ * context (ctx == NULL).  Never NULL; valid until the next call. */
+const char* cr_last_error(const cr_ctx* ctx);
+
+/*
+ * Bytes of device workspace needed for N points of dimension n under params
+ * (dominated by the N x N multiplier array theta of Fig. 3, stored once, in
+ * FP64 for CR_F64 and FP32 otherwise).  Pure host arithmetic.
+ * Errors: CR_ERR_ARG for N < 2, n < 1, bad params or bytes == NULL;
+ * CR_ERR_UNSUPPORTED for n > CR_MAX_DIM.
+ */
+cr_status cr_workspace_bytes(int64_t N, int32_t n, const cr_params* params, size_t* bytes);
+
+/*
+ * Create a solver context bound to (X, ybar) and to stream.  Borrows X_dev,
+ * ybar_dev and the workspace (the caller keeps them alive and unmodified
+ * until cr_destroy).  Computes on the device: the pass-precision copies of X,
+ * sigma_max(A1)^2 = 2N, sigma_max(A2)^2 = max_j lambda_max(S_j) with
+ * S_j = sum_i (x_i - x_j)(x_i - x_j)^T, the least-squares affine fit that
+ * supplies the feasible point and the radii Bbar_y = Bbar,
+ * Bbar_xi = Bbar / sqrt(gamma) of Sec. II-E, and the ALCC starting point
+ * (y_0, xi_0) = that fit, theta_1 = 0.  Host-synchronous.
+ * Errors: CR_ERR_ARG (null pointers, N < 2, n < 1, gamma <= 0, c <= 1,
+ * kappa <= 0, tau1 <= 0, step_scale not in (0, 1], max_outer < 1,
+ * unknown precision), CR_ERR_UNSUPPORTED (n > CR_MAX_DIM), CR_ERR_NOMEM
+ * (ws_bytes too small), CR_ERR_NONFINITE (NaN/Inf in X or ybar),
+ * CR_ERR_HIP.  On error *out is NULL.
+ */
+cr_status cr_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params,
+                  const void* X_dev, const void* ybar_dev, void* workspace_dev,
+                  size_t ws_bytes, void* stream);
+
+/* Release the host-side context (the workspace stays the caller's). */
+cr_status cr_destroy(cr_ctx* ctx);
+
+/*
+ * One pass over all N(N-1) pairs at the point (y_dev, xi_dev) with the
+ * context's current theta (Sec. II-E):
+ *  CR_GRAD:   r = A1 y + A2 xi, w = (r - theta)_-, and
+ *             gy_dev  = (y - ybar)/mu - A1^T w        (= grad_y P_k)
+ *             gxi_dev = (gamma/mu) xi - A2^T w        (= grad_xi P_k)
+ *             mu_next is ignored; theta is unchanged.
+ *  CR_THETA_UPDATE: Fig. 3 step 4, theta <- (mu/mu_next) (r - theta)_-,
+ *             with lam = mu (theta_old - r)_+ written as the stationarity
+ *             residuals gy_dev = y - ybar - A1^T lam and
+ *             gxi_dev = gamma xi - A2^T lam; the KKT scalars of the pass are
+ *             returned by the next cr_get_info().
+ * Asynchronous on the context stream.  gy_dev (N) and gxi_dev (N x n) are
+ * FP64 outputs owned by the caller.
+ * Errors: CR_ERR_ARG (null pointers, unknown mode, mu <= 0, or
+ * mu_next <= 0 in CR_THETA_UPDATE), CR_ERR_HIP.
+ */
+cr_status cr_pairwise_step(cr_ctx* ctx, int32_t mode, const void* y_dev, const void* xi_dev,
+                           void* gy_dev, void* gxi_dev, double mu, double mu_next);
+
+/*
+ * Run ALCC/MAPG from the context's starting point to kkt_tol (adaptive
+ * schedule) or for max_outer x inner_iters MAPG iterations (fixed schedule).
+ * Writes the final ALCC iterate (y_k, xi_k) to y_dev (N) and xi_dev (N x n),
+ * both FP64 buffers owned by the caller, and fills *info if not NULL.
+ * Host-synchronous.  The context's theta and starting point are reset
+ * first, so repeated calls repeat the same computation.
+ * Returns CR_OK, CR_NOT_CONVERGED (adaptive schedule, kkt_tol not reached
+ * within max_outer; outputs and info still valid), CR_ERR_NONFINITE,
+ * CR_ERR_ARG or CR_ERR_HIP.
+ */
+cr_status cr_run(cr_ctx* ctx, void* y_dev, void* xi_dev, cr_info* info);
+
+/*
+ * cr_init + cr_run + cr_destroy in one call (the workspace is borrowed only
+ * for the duration of the call).  Host-synchronous.  Same errors as those.
+ */
+cr_status cr_solve(const void* X_dev, const void* ybar_dev, int64_t N, int32_t n,
+                   const cr_params* params, void* y_dev, void* xi_dev,
+                   void* workspace_dev, size_t ws_bytes, cr_info* info, void* stream);
+
+/* Inspection and test hooks --------------------------------------------- */
+
+/* Copy the context's theta to / from an N x N FP64 device array (diagonal
+ * entries are ignored on input and written as 0 on output).  Asynchronous. */
+cr_status cr_get_theta(cr_ctx* ctx, void* theta_dev);
+cr_status cr_set_theta(cr_ctx* ctx, const void* theta_dev);
+
+/* Copy the ALCC starting point (the affine fit) to FP64 device arrays. */
+cr_status cr_get_start(cr_ctx* ctx, void* y_dev, void* xi_dev);
+
+/* Host-synchronous: constants of the context and, after a CR_THETA_UPDATE
+ * pass or a run, the KKT scalars of the last multiplier step. */
+cr_status cr_get_info(cr_ctx* ctx, cr_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CR_H */

@@ -62,6 +62,8 @@ def _load():
         lib.cro_adjoint_one.argtypes = [ctypes.c_int64, ctypes.c_int, dp, ctypes.c_int64,
                                         dp, dp, dp, dp]
         lib.cro_adjoint_one.restype = None
+        lib.cro_residual_row_col.argtypes = [ctypes.c_int64, ctypes.c_int, dp, dp, dp, ctypes.c_int64, dp, dp]
+        lib.cro_residual_row_col.restype = None
         _lib = lib
     return _lib
 
@@ -111,6 +113,15 @@ def adjoint_one(X, m: int, zrow, zcol):
     v = np.empty(n)
     _load().cro_adjoint_one(N, n, _p(X), m, _p(zrow), _p(zcol), _p(u), _p(v))
     return float(u[0]), v
+
+
+def residual_row_col(X, y, xi, m: int):
+    """(row m, column m) of R = A1 y + A2 xi (pairs (m, j) and (i, m)); entry m is 0."""
+    X, y, xi = _f64(X), _f64(y), _f64(xi)
+    N, n = X.shape
+    row, col = np.empty(N), np.empty(N)
+    _load().cro_residual_row_col(N, n, _p(X), _p(y), _p(xi.reshape(N, n)), m, _p(row), _p(col))
+    return row, col
 
 
 def neg_part(v):

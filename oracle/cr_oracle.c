@@ -107,3 +107,14 @@ void cro_adjoint_one(int64_t N, int n, const double* X, int64_t m,
         v_m[k] = -acc;
     }
 }
+
+/* Row m (pairs (m, j)) and column m (pairs (i, m)) of A1 y + A2 xi, with the
+ * diagonal entry set to 0; for sampled checks at full problem sizes. */
+void cro_residual_row_col(int64_t N, int n, const double* X, const double* y,
+                          const double* xi, int64_t m, double* row, double* col)
+{
+    for (int64_t j = 0; j < N; ++j)
+        row[j] = (j == m) ? 0.0 : pair_residual(n, X, y, xi, m, j);
+    for (int64_t i = 0; i < N; ++i)
+        col[i] = (i == m) ? 0.0 : pair_residual(n, X, y, xi, i, m);
+}

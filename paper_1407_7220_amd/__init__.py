@@ -1,0 +1,272 @@
+"""MI355X (gfx950) engine for least-squares convex regression.
+
+A thin ctypes binding of the C ABI in ``include/cr.h`` (``libcr.so``, built
+from ``csrc/``).  It only marshals arguments: every step of the solver runs in
+the HIP kernels of the library.  PyTorch supplies device memory and the
+stream; importing this package fails loudly when the library is missing.
+
+Problem (Aybat & Wang, Sec. II-C, eq. "regularize"):
+    min 1/2||y - ybar||^2 + gamma/2||xi||^2
+    s.t. y_i >= y_j + xi_j^T (x_i - x_j) for all i != j,
+solved by ALCC (Fig. 3) with MAPG (Fig. 4) as the inner solver.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+__all__ = [
+    "Params", "Info", "CRError", "Context", "solve", "workspace_bytes", "lib_path",
+    "F64", "F32", "MIXED_BF16", "GRAD", "THETA_UPDATE", "MAX_DIM",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libcr.so")
+
+F64, F32, MIXED_BF16 = 0, 1, 2
+GRAD, THETA_UPDATE = 0, 1
+MAX_DIM = 31
+
+OK, ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_NONFINITE, NOT_CONVERGED, ERR_STATE, ERR_UNSUPPORTED = range(8)
+
+
+class _CParams(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in
+                ("gamma", "mu1", "c", "kappa", "tau1", "alpha_y1", "alpha_xi1", "step_scale", "kkt_tol")] + \
+               [(k, ctypes.c_int32) for k in ("max_outer", "inner_iters", "max_inner", "precision")] + \
+               [(k, ctypes.c_double) for k in ("Ly_override", "Lxi_override", "By_override", "Bxi_override")]
+
+
+class _CInfo(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int32), ("status", ctypes.c_int32), ("inner_iters", ctypes.c_int64)] + \
+               [(k, ctypes.c_double) for k in
+                ("objective", "kkt", "stat_y", "stat_xi", "infeas", "compl_", "infeas_norm", "gap_norm",
+                 "seconds", "pair_updates", "sigma2_A1", "sigma2_A2", "Bbar_y", "Bbar_xi")]
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(
+            "libcr.so is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
+            "or `python paper_1407_7220_amd/build.py` first")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    pp, pi = ctypes.POINTER(_CParams), ctypes.POINTER(_CInfo)
+    sig = {
+        "cr_params_default": (i32, [pp]),
+        "cr_status_string": (ctypes.c_char_p, [i32]),
+        "cr_last_error": (ctypes.c_char_p, [vp]),
+        "cr_workspace_bytes": (i32, [i64, i32, pp, ctypes.POINTER(ctypes.c_size_t)]),
+        "cr_init": (i32, [ctypes.POINTER(vp), i64, i32, pp, vp, vp, vp, ctypes.c_size_t, vp]),
+        "cr_destroy": (i32, [vp]),
+        "cr_pairwise_step": (i32, [vp, i32, vp, vp, vp, vp, dbl, dbl]),
+        "cr_run": (i32, [vp, vp, vp, pi]),
+        "cr_solve": (i32, [vp, vp, i64, i32, pp, vp, vp, vp, ctypes.c_size_t, pi, vp]),
+        "cr_get_theta": (i32, [vp, vp]),
+        "cr_set_theta": (i32, [vp, vp]),
+        "cr_get_start": (i32, [vp, vp, vp]),
+        "cr_get_info": (i32, [vp, pi]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+EXPORTED = ("cr_params_default", "cr_status_string", "cr_last_error", "cr_workspace_bytes", "cr_init",
+            "cr_destroy", "cr_pairwise_step", "cr_run", "cr_solve", "cr_get_theta", "cr_set_theta",
+            "cr_get_start", "cr_get_info")
+
+
+class CRError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_lib.cr_status_string(status).decode(), msg))
+        self.status = status
+
+
+def _check(status: int, ctx=None, allow=(OK,)):
+    if status not in allow:
+        raise CRError(status, (_lib.cr_last_error(ctx) or b"").decode())
+    return status
+
+
+@dataclasses.dataclass
+class Params:
+    """ALCC/MAPG parameters (see ``include/cr.h``); None keeps the library default."""
+    gamma: Optional[float] = None
+    mu1: Optional[float] = None
+    c: Optional[float] = None
+    kappa: Optional[float] = None
+    tau1: Optional[float] = None
+    alpha_y1: Optional[float] = None
+    alpha_xi1: Optional[float] = None
+    step_scale: Optional[float] = None
+    kkt_tol: Optional[float] = None
+    max_outer: Optional[int] = None
+    inner_iters: Optional[int] = None
+    max_inner: Optional[int] = None
+    precision: Optional[int] = None
+    Ly_override: Optional[float] = None
+    Lxi_override: Optional[float] = None
+    By_override: Optional[float] = None
+    Bxi_override: Optional[float] = None
+
+    def to_c(self) -> _CParams:
+        p = _CParams()
+        _check(_lib.cr_params_default(ctypes.byref(p)))
+        for f in dataclasses.fields(self):
+            v = getattr(self, f.name)
+            if v is not None:
+                setattr(p, f.name, v)
+        return p
+
+
+@dataclasses.dataclass
+class Info:
+    outer_iters: int
+    status: int
+    inner_iters: int
+    objective: float
+    kkt: float
+    stat_y: float
+    stat_xi: float
+    infeas: float
+    compl: float
+    infeas_norm: float
+    gap_norm: float
+    seconds: float
+    pair_updates: float
+    sigma2_A1: float
+    sigma2_A2: float
+    Bbar_y: float
+    Bbar_xi: float
+
+    @classmethod
+    def from_c(cls, ci: _CInfo) -> "Info":
+        d = {f: getattr(ci, f) for f, _ in _CInfo._fields_}
+        d["compl"] = d.pop("compl_")
+        return cls(**d)
+
+
+def workspace_bytes(N: int, n: int, params: Optional[Params] = None) -> int:
+    out = ctypes.c_size_t(0)
+    cp = (params or Params()).to_c()
+    _check(_lib.cr_workspace_bytes(int(N), int(n), ctypes.byref(cp), ctypes.byref(out)))
+    return int(out.value)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_f64(t, shape, name):
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("%s must be a contiguous float64 CUDA tensor" % name)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """A solver context bound to (X, ybar) on the current CUDA/HIP device and stream.
+
+    Keeps references to X, ybar and the workspace tensor for its lifetime."""
+
+    def __init__(self, X, ybar, params: Optional[Params] = None):
+        torch = _torch()
+        self.N, self.n = int(X.shape[0]), int(X.shape[1])
+        self.params = params or Params()
+        self._X = X
+        self._ybar = ybar
+        px = _dev_f64(X, (self.N, self.n), "X")
+        py = _dev_f64(ybar, (self.N,), "ybar")
+        nbytes = workspace_bytes(self.N, self.n, self.params)
+        self._ws = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
+        self._cp = self.params.to_c()
+        h = ctypes.c_void_p()
+        _check(_lib.cr_init(ctypes.byref(h), self.N, self.n, ctypes.byref(self._cp), px, py,
+                            ctypes.c_void_p(self._ws.data_ptr()), nbytes, _stream()))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.cr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _new(self, *shape):
+        torch = _torch()
+        return torch.empty(*shape, dtype=torch.float64, device=self._X.device)
+
+    def pairwise_step(self, mode: int, y, xi, mu: float, mu_next: float = 0.0):
+        """One pass over all pairs (CR_GRAD or CR_THETA_UPDATE); returns (gy, gxi)."""
+        gy, gxi = self._new(self.N), self._new(self.N, self.n)
+        _check(_lib.cr_pairwise_step(self._h, int(mode), _dev_f64(y, (self.N,), "y"),
+                                     _dev_f64(xi, (self.N, self.n), "xi"), ctypes.c_void_p(gy.data_ptr()),
+                                     ctypes.c_void_p(gxi.data_ptr()), float(mu), float(mu_next)), self._h)
+        return gy, gxi
+
+    def run(self):
+        """ALCC/MAPG to kkt_tol (or the fixed schedule); returns (y, xi, Info)."""
+        y, xi = self._new(self.N), self._new(self.N, self.n)
+        ci = _CInfo()
+        _check(_lib.cr_run(self._h, ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(xi.data_ptr()),
+                           ctypes.byref(ci)), self._h, allow=(OK, NOT_CONVERGED))
+        return y, xi, Info.from_c(ci)
+
+    def get_theta(self):
+        th = self._new(self.N, self.N)
+        _check(_lib.cr_get_theta(self._h, ctypes.c_void_p(th.data_ptr())), self._h)
+        return th
+
+    def set_theta(self, theta):
+        _check(_lib.cr_set_theta(self._h, _dev_f64(theta, (self.N, self.N), "theta")), self._h)
+
+    def get_start(self):
+        y, xi = self._new(self.N), self._new(self.N, self.n)
+        _check(_lib.cr_get_start(self._h, ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(xi.data_ptr())), self._h)
+        return y, xi
+
+    def info(self) -> Info:
+        ci = _CInfo()
+        _check(_lib.cr_get_info(self._h, ctypes.byref(ci)), self._h)
+        return Info.from_c(ci)
+
+
+def solve(X, ybar, params: Optional[Params] = None):
+    """cr_solve: returns (y, xi, Info) for float64 CUDA tensors X (N x n) and ybar (N)."""
+    torch = _torch()
+    N, n = int(X.shape[0]), int(X.shape[1])
+    p = params or Params()
+    cp = p.to_c()
+    px = _dev_f64(X, (N, n), "X")
+    py = _dev_f64(ybar, (N,), "ybar")
+    nbytes = workspace_bytes(N, n, p)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
+    y = torch.empty(N, dtype=torch.float64, device=X.device)
+    xi = torch.empty(N, n, dtype=torch.float64, device=X.device)
+    ci = _CInfo()
+    _check(_lib.cr_solve(px, py, N, n, ctypes.byref(cp), ctypes.c_void_p(y.data_ptr()),
+                         ctypes.c_void_p(xi.data_ptr()), ctypes.c_void_p(ws.data_ptr()), nbytes,
+                         ctypes.byref(ci), _stream()), None, allow=(OK, NOT_CONVERGED))
+    return y, xi, Info.from_c(ci)

@@ -1,0 +1,554 @@
+// Host driver of the convex-regression pair engine: argument checks, workspace
+// layout, set-up, and the ALCC (Fig. 3) / MAPG (Fig. 4) schedule.  The MAPG
+// iteration [pair pass -> reduction + step -> projection + momentum] is
+// captured once as a hipGraph of kGraphIters iterations and replayed; the
+// alpha test of Fig. 4 and the l_max cap are evaluated on the device, which
+// turns the remaining iterations of a replay into no-ops.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/cr.h"
+#include "cr_device.h"
+
+
+namespace {
+
+constexpr int kGraphIters = 32;
+thread_local std::string g_last_error;
+
+struct Layout {
+    int64_t N = 0, Nrow = 0, ld = 0;
+    int n = 0, nc = 0, ks = 0, kp = 0, qp = 0, esz = 8, tw = 2;
+    int strips = 0, chunks = 0, rpc = 0, nb = 0, nsu = 0;
+    size_t off_theta, off_xp, off_xiaug, off_ycol, off_rowpart, off_cpart, off_kkt;
+    size_t off_y1p, off_y2, off_vy, off_y0, off_xi1p, off_xi2, off_vxi, off_xi0;
+    size_t off_blockpart, off_supart, off_su, off_oa, off_st;
+    size_t total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout make_layout(int64_t N, int n, int precision) {
+    Layout L;
+    L.N = N;
+    L.n = n;
+    L.nc = n + 1;
+    L.esz = precision == CR_F64 ? 8 : 4;
+    L.tw = L.esz == 8 ? 2 : 4;
+    L.Nrow = ((N + 63) / 64) * 64;
+    L.ld = ((N + 63) / 64) * 64;
+    L.ks = cr::ks_of(n);
+    L.kp = 4 * L.ks;
+    L.qp = cr::qp_of_ks(L.ks, L.esz);
+    L.strips = (int)(L.ld / (16 * L.tw));
+    // Enough workgroups to fill 256 CUs several times over, but long enough
+    // row chunks that the per-chunk column partials stay small.
+    const int64_t target = 2048;
+    int64_t chunks = (target + L.strips - 1) / L.strips;
+    chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, L.Nrow / 64));
+    int64_t rpc = (L.Nrow + chunks - 1) / chunks;
+    rpc = ((rpc + 63) / 64) * 64;
+    L.rpc = (int)rpc;
+    L.chunks = (int)((L.Nrow + rpc - 1) / rpc);
+    L.nb = (int)((L.ld + cr::kBlock - 1) / cr::kBlock);
+    L.nsu = (int)((N + 1023) / 1024);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    L.off_theta = take((size_t)L.Nrow * L.ld * L.esz);
+    L.off_xp = take((size_t)(L.Nrow / 16) * 64 * L.qp * L.esz);
+    L.off_xiaug = take((size_t)L.ld * L.kp * L.esz);
+    L.off_ycol = take((size_t)L.Nrow * L.esz);
+    L.off_rowpart = take((size_t)L.strips * L.Nrow * L.esz);
+    L.off_cpart = take((size_t)L.chunks * L.ld * L.nc * L.esz);
+    L.off_kkt = take((size_t)L.strips * L.chunks * 4 * 8);
+    L.off_y1p = take((size_t)L.Nrow * 8);
+    L.off_y2 = take((size_t)L.Nrow * 8);
+    L.off_vy = take((size_t)L.Nrow * 8);
+    L.off_y0 = take((size_t)L.Nrow * 8);
+    L.off_xi1p = take((size_t)L.Nrow * n * 8);
+    L.off_xi2 = take((size_t)L.Nrow * n * 8);
+    L.off_vxi = take((size_t)L.Nrow * n * 8);
+    L.off_xi0 = take((size_t)L.Nrow * n * 8);
+    L.off_blockpart = take((size_t)std::max<int64_t>(L.nb, 1) * 4 * 8);
+    L.off_supart = take((size_t)(std::max<int64_t>((int64_t)L.nsu * (n * n + n + 3), L.nb) + 64) * 8);
+    L.off_su = take((size_t)(3 * n + 2 + n * n + 8) * 8);
+    L.off_oa = take(sizeof(cr::OuterArgs));
+    L.off_st = take(sizeof(cr::DevState));
+    L.total = o + 256;  // slack for re-aligning an unaligned base
+    return L;
+}
+
+bool check_params(const cr_params* p, std::string& msg) {
+    if (!p) { msg = "params is NULL"; return false; }
+    if (!(p->gamma > 0) || !std::isfinite(p->gamma)) { msg = "gamma must be finite and > 0"; return false; }
+    if (!(p->c > 1) || !std::isfinite(p->c)) { msg = "c must be > 1"; return false; }
+    if (!(p->kappa > 0)) { msg = "kappa must be > 0"; return false; }
+    if (!(p->tau1 > 0)) { msg = "tau1 must be > 0"; return false; }
+    if (!(p->step_scale > 0 && p->step_scale <= 1)) { msg = "step_scale must be in (0, 1]"; return false; }
+    if (p->max_outer < 1) { msg = "max_outer must be >= 1"; return false; }
+    if (p->inner_iters < 0) { msg = "inner_iters must be >= 0"; return false; }
+    if (p->inner_iters == 0 && p->max_inner < 1) { msg = "max_inner must be >= 1"; return false; }
+    if (!(p->kkt_tol >= 0)) { msg = "kkt_tol must be >= 0"; return false; }
+    if (p->precision != CR_F64 && p->precision != CR_F32 && p->precision != CR_MIXED_BF16) {
+        msg = "unknown precision";
+        return false;
+    }
+    if (p->precision == CR_MIXED_BF16) { msg = "CR_MIXED_BF16 is not available in this build"; return false; }
+    return true;
+}
+
+cr_status check_dims(int64_t N, int32_t n, std::string& msg) {
+    if (N < 2) { msg = "N must be >= 2"; return CR_ERR_ARG; }
+    if (n < 1) { msg = "n must be >= 1"; return CR_ERR_ARG; }
+    if (n > CR_MAX_DIM) { msg = "n above CR_MAX_DIM is not supported"; return CR_ERR_UNSUPPORTED; }
+    if (N > (int64_t)1 << 22) { msg = "N too large"; return CR_ERR_ARG; }
+    return CR_OK;
+}
+
+}  // namespace
+
+struct cr_ctx {
+    Layout L;
+    cr_params p;
+    int64_t N;
+    int n;
+    bool f64;
+    hipStream_t user_stream = nullptr;
+    hipStream_t cs = nullptr;            // internal stream (graph capture needs a non-null stream)
+    hipGraphExec_t graph = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int32_t* pinned_flag = nullptr;      // 2 slots
+    cr::DevState* pinned_state = nullptr;
+    const double* X = nullptr;
+    const double* ybar = nullptr;
+    char* ws = nullptr;
+    cr::DevState* st = nullptr;
+    cr::OuterArgs* oa = nullptr;
+    double sigma2_A1 = 0, sigma2_A2 = 0, Bbar = 0, By = 0, Bxi = 0, ybar_inf = 0;
+    std::string err;
+    cr::DevState last{};
+    bool have_kkt = false;
+    char* P(size_t off) const { return ws + off; }
+    double* D(size_t off) const { return reinterpret_cast<double*>(ws + off); }
+};
+
+static cr_status fail(cr_ctx* ctx, cr_status s, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    g_last_error = msg;
+    return s;
+}
+
+#define HIPCHK(ctx, call)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail(ctx, CR_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+static cr::PassArgs pass_args(cr_ctx* c, int mode, double theta_scale, const int32_t* active) {
+    const Layout& L = c->L;
+    cr::PassArgs a{};
+    a.N = L.N; a.Nrow = L.Nrow; a.ld = L.ld; a.nc = L.nc; a.rows_per_chunk = L.rpc; a.mode = mode;
+    a.theta = c->P(L.off_theta); a.xp = c->P(L.off_xp); a.xiaug = c->P(L.off_xiaug); a.ycol = c->P(L.off_ycol);
+    a.rowpart = c->P(L.off_rowpart); a.cpart = c->P(L.off_cpart); a.kktpart = c->D(L.off_kkt);
+    a.theta_scale = theta_scale; a.active = active;
+    return a;
+}
+
+static dim3 pass_grid(const Layout& L) { return dim3((unsigned)L.strips, (unsigned)L.chunks); }
+
+static cr::ReduceArgs reduce_args(cr_ctx* c, int mode, const double* y, const double* xi, double* oy, double* oxi,
+                                  double mu) {
+    const Layout& L = c->L;
+    cr::ReduceArgs a{};
+    a.N = L.N; a.Nrow = L.Nrow; a.ld = L.ld; a.n = L.n; a.nc = L.nc; a.strips = L.strips; a.chunks = L.chunks;
+    a.mode = mode; a.npass = L.strips * L.chunks;
+    a.rowpart = c->P(L.off_rowpart); a.cpart = c->P(L.off_cpart);
+    a.X = c->X; a.ybar = c->ybar; a.y = y; a.xi = xi; a.out_y = oy; a.out_xi = oxi;
+    a.blockpart = c->D(L.off_blockpart); a.kktpart = c->D(L.off_kkt);
+    a.oa = c->oa; a.st = c->st; a.mu = mu; a.gamma = c->p.gamma;
+    return a;
+}
+
+static cr::PointArgs point_args(cr_ctx* c, const double* y, const double* xi, int write_state) {
+    const Layout& L = c->L;
+    cr::PointArgs a{};
+    a.N = L.N; a.Nrow = L.Nrow; a.ld = L.ld; a.n = L.n; a.kp = L.kp; a.write_state = write_state;
+    a.X = c->X; a.y = y; a.xi = xi;
+    a.y1p = c->D(L.off_y1p); a.y2 = c->D(L.off_y2); a.xi1p = c->D(L.off_xi1p); a.xi2 = c->D(L.off_xi2);
+    a.xiaug = c->P(L.off_xiaug); a.ycol = c->P(L.off_ycol);
+    return a;
+}
+
+static cr::UpdateArgs update_args(cr_ctx* c) {
+    const Layout& L = c->L;
+    cr::UpdateArgs a{};
+    a.N = L.N; a.ld = L.ld; a.n = L.n; a.kp = L.kp;
+    a.X = c->X; a.ybar = c->ybar; a.vy = c->D(L.off_vy); a.vxi = c->D(L.off_vxi);
+    a.y1p = c->D(L.off_y1p); a.y2 = c->D(L.off_y2); a.xi1p = c->D(L.off_xi1p); a.xi2 = c->D(L.off_xi2);
+    a.xiaug = c->P(L.off_xiaug); a.ycol = c->P(L.off_ycol);
+    a.blockpart = c->D(L.off_blockpart); a.oa = c->oa; a.st = c->st;
+    return a;
+}
+
+// One MAPG iteration: pair pass at (y2, xi2), gradient step, projection and momentum.
+static hipError_t enqueue_mapg_iteration(cr_ctx* c, hipStream_t s) {
+    const Layout& L = c->L;
+    cr::PassArgs pa = pass_args(c, 0, 0.0, &c->st->active);
+    hipError_t e = cr::launch_pair_pass(c->f64, L.ks, pa, pass_grid(L), s);
+    if (e != hipSuccess) return e;
+    cr::ReduceArgs ra = reduce_args(c, 0, c->D(L.off_y2), c->D(L.off_xi2), c->D(L.off_vy), c->D(L.off_vxi), 0.0);
+    e = cr::launch_reduce(c->f64, ra, s);
+    if (e != hipSuccess) return e;
+    cr::UpdateArgs ua = update_args(c);
+    return cr::launch_update(c->f64, ua, s);
+}
+
+static cr_status build_graph(cr_ctx* c) {
+    if (c->graph) return CR_OK;
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->cs, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < kGraphIters && e == hipSuccess; ++q) e = enqueue_mapg_iteration(c, c->cs);
+    hipError_t e2 = hipStreamEndCapture(c->cs, &g);
+    if (e != hipSuccess) return fail(c, CR_ERR_HIP, std::string("capture: ") + hipGetErrorString(e));
+    if (e2 != hipSuccess) return fail(c, CR_ERR_HIP, std::string("end capture: ") + hipGetErrorString(e2));
+    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) { c->graph = nullptr; return fail(c, CR_ERR_HIP, std::string("instantiate: ") + hipGetErrorString(e)); }
+    return CR_OK;
+}
+
+extern "C" {
+
+cr_status cr_params_default(cr_params* p) {
+    if (!p) return fail(nullptr, CR_ERR_ARG, "params is NULL");
+    std::memset(p, 0, sizeof(*p));
+    p->gamma = 1e-3;
+    p->mu1 = 0.0;
+    p->c = 4.0;
+    p->kappa = 0.1;
+    p->tau1 = 1.0;
+    p->alpha_y1 = 0.0;
+    p->alpha_xi1 = 0.0;
+    p->step_scale = 0.5;
+    p->kkt_tol = 1e-4;
+    p->max_outer = 30;
+    p->inner_iters = 0;
+    p->max_inner = 20000;
+    p->precision = CR_F64;
+    return CR_OK;
+}
+
+const char* cr_status_string(cr_status s) {
+    switch (s) {
+        case CR_OK: return "CR_OK";
+        case CR_ERR_ARG: return "CR_ERR_ARG";
+        case CR_ERR_NOMEM: return "CR_ERR_NOMEM";
+        case CR_ERR_HIP: return "CR_ERR_HIP";
+        case CR_ERR_NONFINITE: return "CR_ERR_NONFINITE";
+        case CR_NOT_CONVERGED: return "CR_NOT_CONVERGED";
+        case CR_ERR_STATE: return "CR_ERR_STATE";
+        case CR_ERR_UNSUPPORTED: return "CR_ERR_UNSUPPORTED";
+        default: return "CR_UNKNOWN_STATUS";
+    }
+}
+
+const char* cr_last_error(const cr_ctx* ctx) { return ctx ? ctx->err.c_str() : g_last_error.c_str(); }
+
+cr_status cr_workspace_bytes(int64_t N, int32_t n, const cr_params* params, size_t* bytes) {
+    std::string msg;
+    if (!bytes) return fail(nullptr, CR_ERR_ARG, "bytes is NULL");
+    cr_status s = check_dims(N, n, msg);
+    if (s != CR_OK) return fail(nullptr, s, msg);
+    if (!check_params(params, msg)) return fail(nullptr, CR_ERR_ARG, msg);
+    *bytes = make_layout(N, n, params->precision).total;
+    return CR_OK;
+}
+
+cr_status cr_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params, const void* X_dev,
+                  const void* ybar_dev, void* workspace_dev, size_t ws_bytes, void* stream) {
+    std::string msg;
+    if (!out) return fail(nullptr, CR_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    cr_status s = check_dims(N, n, msg);
+    if (s != CR_OK) return fail(nullptr, s, msg);
+    if (!check_params(params, msg)) return fail(nullptr, CR_ERR_ARG, msg);
+    if (!X_dev || !ybar_dev || !workspace_dev) return fail(nullptr, CR_ERR_ARG, "X, ybar and workspace must be non-NULL");
+    Layout L = make_layout(N, n, params->precision);
+    if (ws_bytes < L.total) return fail(nullptr, CR_ERR_NOMEM, "workspace smaller than cr_workspace_bytes()");
+
+    cr_ctx* c = new (std::nothrow) cr_ctx();
+    if (!c) return fail(nullptr, CR_ERR_NOMEM, "host allocation failed");
+    c->L = L;
+    c->p = *params;
+    c->N = N;
+    c->n = n;
+    c->f64 = params->precision == CR_F64;
+    c->user_stream = (hipStream_t)stream;
+    c->X = (const double*)X_dev;
+    c->ybar = (const double*)ybar_dev;
+    c->ws = (char*)align256((size_t)workspace_dev);
+    c->st = reinterpret_cast<cr::DevState*>(c->P(L.off_st));
+    c->oa = reinterpret_cast<cr::OuterArgs*>(c->P(L.off_oa));
+    auto bad = [&](cr_status st) { cr_destroy(c); return st; };
+    hipError_t e = hipStreamCreateWithFlags(&c->cs, hipStreamNonBlocking);
+    if (e != hipSuccess) { fail(nullptr, CR_ERR_HIP, std::string("stream: ") + hipGetErrorString(e)); return bad(CR_ERR_HIP); }
+    for (int q = 0; q < 2; ++q) {
+        e = hipEventCreateWithFlags(&c->ev[q], hipEventDisableTiming);
+        if (e != hipSuccess) { fail(nullptr, CR_ERR_HIP, "event create"); return bad(CR_ERR_HIP); }
+    }
+    e = hipHostMalloc((void**)&c->pinned_flag, 64, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->pinned_state, sizeof(cr::DevState), hipHostMallocDefault);
+    if (e != hipSuccess) { fail(nullptr, CR_ERR_HIP, "pinned host allocation"); return bad(CR_ERR_HIP); }
+
+    // order after the caller's prior work on its stream
+    hipEvent_t ue = c->ev[0];
+    if ((e = hipEventRecord(ue, c->user_stream)) != hipSuccess || (e = hipStreamWaitEvent(c->cs, ue, 0)) != hipSuccess) {
+        fail(nullptr, CR_ERR_HIP, std::string("stream join: ") + hipGetErrorString(e));
+        return bad(CR_ERR_HIP);
+    }
+    hipStream_t cs = c->cs;
+    e = cr::launch_zero(c->P(L.off_st), (sizeof(cr::DevState) + 15) / 16 * 16, cs);
+    if (e == hipSuccess) e = cr::launch_zero(c->P(L.off_theta), (size_t)L.Nrow * L.ld * L.esz, cs);
+    if (e == hipSuccess) e = cr::launch_zero(c->P(L.off_y0), (size_t)L.Nrow * 8, cs);
+    if (e == hipSuccess) e = cr::launch_zero(c->P(L.off_xi0), (size_t)L.Nrow * n * 8, cs);
+    if (e == hipSuccess)
+        e = cr::launch_setup(c->X, c->ybar, N, n, params->gamma, c->D(L.off_su), c->D(L.off_supart), c->D(L.off_y0),
+                             c->D(L.off_xi0), c->st, cs);
+    if (e == hipSuccess) e = cr::launch_prep_xp(c->f64, c->X, N, n, L.Nrow, L.ks, L.qp, c->P(L.off_xp), cs);
+    if (e == hipSuccess) {
+        cr::PointArgs pa = point_args(c, c->D(L.off_y0), c->D(L.off_xi0), 1);
+        e = cr::launch_set_point(c->f64, pa, cs);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(c->pinned_state, c->st, sizeof(cr::DevState), hipMemcpyDeviceToHost, cs);
+    if (e == hipSuccess) e = hipStreamSynchronize(cs);
+    if (e != hipSuccess) { fail(nullptr, CR_ERR_HIP, std::string("set-up: ") + hipGetErrorString(e)); return bad(CR_ERR_HIP); }
+    const cr::DevState& h = *c->pinned_state;
+    if (h.nonfinite) { fail(nullptr, CR_ERR_NONFINITE, "X or ybar holds NaN or Inf"); return bad(CR_ERR_NONFINITE); }
+    c->sigma2_A1 = 2.0 * (double)N;
+    c->sigma2_A2 = h.sigma2_A2;
+    c->Bbar = h.Bbar;
+    c->By = params->By_override > 0 ? params->By_override : h.Bbar;
+    c->Bxi = params->Bxi_override > 0 ? params->Bxi_override : h.Bbar / std::sqrt(params->gamma);
+    c->ybar_inf = h.ybar_inf;
+    if (!std::isfinite(c->sigma2_A2) || !std::isfinite(c->Bbar)) {
+        fail(nullptr, CR_ERR_NONFINITE, "non-finite problem constants");
+        return bad(CR_ERR_NONFINITE);
+    }
+    *out = c;
+    return CR_OK;
+}
+
+cr_status cr_destroy(cr_ctx* c) {
+    if (!c) return CR_OK;
+    if (c->cs) hipStreamSynchronize(c->cs);
+    if (c->graph) hipGraphExecDestroy(c->graph);
+    for (int q = 0; q < 2; ++q)
+        if (c->ev[q]) hipEventDestroy(c->ev[q]);
+    if (c->pinned_flag) hipHostFree(c->pinned_flag);
+    if (c->pinned_state) hipHostFree(c->pinned_state);
+    if (c->cs) hipStreamDestroy(c->cs);
+    delete c;
+    return CR_OK;
+}
+
+cr_status cr_pairwise_step(cr_ctx* c, int32_t mode, const void* y_dev, const void* xi_dev, void* gy_dev,
+                           void* gxi_dev, double mu, double mu_next) {
+    if (!c) return fail(nullptr, CR_ERR_ARG, "ctx is NULL");
+    if (!y_dev || !xi_dev || !gy_dev || !gxi_dev) return fail(c, CR_ERR_ARG, "y, xi, gy and gxi must be non-NULL");
+    if (mode != CR_GRAD && mode != CR_THETA_UPDATE) return fail(c, CR_ERR_ARG, "unknown mode");
+    if (!(mu > 0) || !std::isfinite(mu)) return fail(c, CR_ERR_ARG, "mu must be > 0");
+    if (mode == CR_THETA_UPDATE && (!(mu_next > 0) || !std::isfinite(mu_next)))
+        return fail(c, CR_ERR_ARG, "mu_next must be > 0");
+    const Layout& L = c->L;
+    hipStream_t s = c->user_stream;
+    cr::PointArgs pt = point_args(c, (const double*)y_dev, (const double*)xi_dev, 0);
+    HIPCHK(c, cr::launch_set_point(c->f64, pt, s));
+    const double scale = mode == CR_THETA_UPDATE ? mu / mu_next : 0.0;
+    cr::PassArgs pa = pass_args(c, mode == CR_THETA_UPDATE ? 1 : 0, scale, &c->st->one);
+    HIPCHK(c, cr::launch_pair_pass(c->f64, L.ks, pa, pass_grid(L), s));
+    cr::ReduceArgs ra = reduce_args(c, mode == CR_THETA_UPDATE ? 2 : 1, (const double*)y_dev, (const double*)xi_dev,
+                                    (double*)gy_dev, (double*)gxi_dev, mu);
+    HIPCHK(c, cr::launch_reduce(c->f64, ra, s));
+    if (mode == CR_THETA_UPDATE) c->have_kkt = true;
+    return CR_OK;
+}
+
+static void fill_info(cr_ctx* c, const cr::DevState& h, cr_info* info) {
+    info->objective = h.obj;
+    const double scale = 1.0 + c->ybar_inf;
+    info->stat_y = h.stat_y;
+    info->stat_xi = h.stat_xi;
+    info->infeas = h.infeas;
+    info->compl_ = h.compl_;
+    info->kkt = std::max(std::max(h.stat_y, h.stat_xi), std::max(h.infeas, h.compl_)) / scale;
+    const double np = (double)c->N * (double)(c->N - 1);
+    info->infeas_norm = std::sqrt(h.infeas_sq) / std::sqrt(np);
+    info->gap_norm = h.gap / np;
+    info->sigma2_A1 = c->sigma2_A1;
+    info->sigma2_A2 = c->sigma2_A2;
+    info->Bbar_y = c->By;
+    info->Bbar_xi = c->Bxi;
+}
+
+cr_status cr_get_info(cr_ctx* c, cr_info* info) {
+    if (!c || !info) return fail(c, CR_ERR_ARG, "ctx and info must be non-NULL");
+    HIPCHK(c, hipStreamSynchronize(c->user_stream));
+    HIPCHK(c, hipStreamSynchronize(c->cs));
+    HIPCHK(c, hipMemcpy(c->pinned_state, c->st, sizeof(cr::DevState), hipMemcpyDeviceToHost));
+    std::memset(info, 0, sizeof(*info));
+    fill_info(c, *c->pinned_state, info);
+    return CR_OK;
+}
+
+cr_status cr_get_theta(cr_ctx* c, void* theta_dev) {
+    if (!c || !theta_dev) return fail(c, CR_ERR_ARG, "ctx and theta must be non-NULL");
+    HIPCHK(c, cr::launch_theta_export(c->f64, c->P(c->L.off_theta), c->N, c->L.ld, (double*)theta_dev, c->user_stream));
+    return CR_OK;
+}
+
+cr_status cr_set_theta(cr_ctx* c, const void* theta_dev) {
+    if (!c || !theta_dev) return fail(c, CR_ERR_ARG, "ctx and theta must be non-NULL");
+    HIPCHK(c, cr::launch_theta_import(c->f64, (const double*)theta_dev, c->N, c->L.Nrow, c->L.ld, c->P(c->L.off_theta),
+                                      c->user_stream));
+    return CR_OK;
+}
+
+cr_status cr_get_start(cr_ctx* c, void* y_dev, void* xi_dev) {
+    if (!c || !y_dev || !xi_dev) return fail(c, CR_ERR_ARG, "ctx, y and xi must be non-NULL");
+    HIPCHK(c, hipMemcpyAsync(y_dev, c->D(c->L.off_y0), (size_t)c->N * 8, hipMemcpyDeviceToDevice, c->user_stream));
+    HIPCHK(c, hipMemcpyAsync(xi_dev, c->D(c->L.off_xi0), (size_t)c->N * c->n * 8, hipMemcpyDeviceToDevice,
+                             c->user_stream));
+    return CR_OK;
+}
+
+cr_status cr_run(cr_ctx* c, void* y_dev, void* xi_dev, cr_info* info) {
+    if (!c) return fail(nullptr, CR_ERR_ARG, "ctx is NULL");
+    if (!y_dev || !xi_dev) return fail(c, CR_ERR_ARG, "y and xi must be non-NULL");
+    const Layout& L = c->L;
+    const cr_params& p = c->p;
+    hipStream_t cs = c->cs;
+    HIPCHK(c, hipEventRecord(c->ev[0], c->user_stream));
+    HIPCHK(c, hipStreamWaitEvent(cs, c->ev[0], 0));
+    cr_status bs = build_graph(c);
+    if (bs != CR_OK) return bs;
+
+    const auto t0 = std::chrono::steady_clock::now();
+    // theta_1 = 0 and (y_0, xi_0) = the affine fit
+    HIPCHK(c, cr::launch_zero(c->P(L.off_theta), (size_t)L.Nrow * L.ld * L.esz, cs));
+    cr::PointArgs start = point_args(c, c->D(L.off_y0), c->D(L.off_xi0), 1);
+    HIPCHK(c, cr::launch_set_point(c->f64, start, cs));
+
+    const int64_t N = c->N;
+    const double gamma = p.gamma;
+    double mu = p.mu1 > 0 ? p.mu1 : 1.0 / (2.0 * (double)N);
+    double tau = p.tau1;
+    double ay = p.alpha_y1 > 0 ? p.alpha_y1 : 1e-2 * c->Bbar;
+    double axi = p.alpha_xi1 > 0 ? p.alpha_xi1 : 1e-2 * c->Bbar;
+    const bool fixed = p.inner_iters > 0;
+    int64_t total_inner = 0;
+    int outer = 0;
+    bool converged = false;
+    cr_status result = CR_OK;
+    cr::DevState h{};
+    for (int k = 1; k <= p.max_outer; ++k) {
+        outer = k;
+        const double Ly = p.Ly_override > 0 ? p.Ly_override : 1.0 / mu + c->sigma2_A1;
+        const double Lxi = p.Lxi_override > 0 ? p.Lxi_override : gamma / mu + c->sigma2_A2;
+        int64_t lmax;
+        if (fixed) {
+            lmax = p.inner_iters;
+        } else {
+            const double f = std::ceil(4.0 * std::sqrt((Ly * c->By * c->By + Lxi * c->Bxi * c->Bxi) / tau));
+            lmax = (int64_t)std::max(1.0, std::min(f, (double)p.max_inner));
+        }
+        const double mu_next = p.c * mu;
+        cr::OuterArgs oa{};
+        oa.mu = mu; oa.gamma = gamma; oa.sy = p.step_scale / Ly; oa.sxi = p.step_scale / Lxi;
+        oa.alpha_y = ay; oa.alpha_xi = axi; oa.By = c->By; oa.Bxi = c->Bxi;
+        oa.theta_scale = mu / mu_next; oa.lmax = lmax; oa.adaptive = fixed ? 0 : 1;
+        HIPCHK(c, cr::launch_begin_outer(oa, c->oa, c->st, cs));
+
+        // MAPG: replay the captured iterations until the device clears `active`.
+        int64_t launched = 0;
+        int slot = 0, pending = -1;
+        while (launched < lmax) {
+            HIPCHK(c, hipGraphLaunch(c->graph, cs));
+            launched += kGraphIters;
+            if (fixed) continue;
+            HIPCHK(c, hipMemcpyAsync(c->pinned_flag + slot, &c->st->active, 4, hipMemcpyDeviceToHost, cs));
+            HIPCHK(c, hipEventRecord(c->ev[slot], cs));
+            if (pending >= 0) {
+                HIPCHK(c, hipEventSynchronize(c->ev[pending]));
+                if (c->pinned_flag[pending] == 0) break;
+            }
+            pending = slot;
+            slot ^= 1;
+        }
+        // multiplier step at the MAPG output (y_k, xi_k), which also restarts MAPG there
+        cr::PointArgs pt = point_args(c, c->D(L.off_y1p), c->D(L.off_xi1p), 1);
+        HIPCHK(c, cr::launch_set_point(c->f64, pt, cs));
+        cr::PassArgs pa = pass_args(c, 1, mu / mu_next, &c->st->one);
+        HIPCHK(c, cr::launch_pair_pass(c->f64, L.ks, pa, pass_grid(L), cs));
+        cr::ReduceArgs ra = reduce_args(c, 2, c->D(L.off_y1p), c->D(L.off_xi1p), nullptr, nullptr, mu);
+        HIPCHK(c, cr::launch_reduce(c->f64, ra, cs));
+        HIPCHK(c, hipMemcpyAsync(c->pinned_state, c->st, sizeof(cr::DevState), hipMemcpyDeviceToHost, cs));
+        HIPCHK(c, hipStreamSynchronize(cs));
+        h = *c->pinned_state;
+        total_inner += h.it;
+        c->have_kkt = true;
+        if (h.iterate_nonfinite) { result = CR_ERR_NONFINITE; break; }
+        cr_info tmp{};
+        fill_info(c, h, &tmp);
+        if (!fixed && tmp.kkt <= p.kkt_tol) { converged = true; break; }
+        const double decay = std::pow(p.c * std::pow((double)k, 1.0 + p.kappa), 2.0);
+        mu = mu_next;
+        tau /= decay;
+        ay /= decay;
+        axi /= decay;
+    }
+    HIPCHK(c, hipMemcpyAsync(y_dev, c->D(L.off_y1p), (size_t)N * 8, hipMemcpyDeviceToDevice, cs));
+    HIPCHK(c, hipMemcpyAsync(xi_dev, c->D(L.off_xi1p), (size_t)N * c->n * 8, hipMemcpyDeviceToDevice, cs));
+    HIPCHK(c, hipStreamSynchronize(cs));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (result == CR_OK && !fixed && !converged) result = CR_NOT_CONVERGED;
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        fill_info(c, h, info);
+        info->outer_iters = outer;
+        info->inner_iters = total_inner;
+        info->seconds = secs;
+        info->pair_updates = (double)N * (double)(N - 1) * (double)total_inner;
+        info->status = result;
+    }
+    if (result == CR_ERR_NONFINITE) return fail(c, result, "non-finite iterate");
+    return result;
+}
+
+cr_status cr_solve(const void* X_dev, const void* ybar_dev, int64_t N, int32_t n, const cr_params* params,
+                   void* y_dev, void* xi_dev, void* workspace_dev, size_t ws_bytes, cr_info* info, void* stream) {
+    if (!y_dev || !xi_dev) return fail(nullptr, CR_ERR_ARG, "y and xi must be non-NULL");
+    cr_ctx* c = nullptr;
+    cr_status s = cr_init(&c, N, n, params, X_dev, ybar_dev, workspace_dev, ws_bytes, stream);
+    if (s != CR_OK) return s;
+    s = cr_run(c, y_dev, xi_dev, info);
+    if (s != CR_OK && s != CR_NOT_CONVERGED) g_last_error = c->err;
+    hipEvent_t done = nullptr;
+    if (hipEventCreateWithFlags(&done, hipEventDisableTiming) == hipSuccess) {
+        hipEventRecord(done, c->cs);
+        hipStreamWaitEvent((hipStream_t)stream, done, 0);
+        hipEventDestroy(done);
+    }
+    cr_destroy(c);
+    return s;
+}
+
+}  // extern "C"

@@ -1,0 +1,143 @@
+// Shared definitions of the gfx950 kernels and the host driver.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cr {
+
+constexpr int kBlock = 256;          // threads per workgroup of every kernel
+constexpr int kTileRows = 16;        // rows (i) of one MFMA tile
+constexpr int kWaves = 4;            // waves per pair-pass workgroup, split over rows
+constexpr int kMaxDim = 31;          // n + 1 <= 32 output columns of W^T [X 1]
+
+// Scalars the host sets once per ALCC iteration (Fig. 3 steps 1-2, 5-6).
+struct OuterArgs {
+    double mu;            // mu_k
+    double gamma;         // Tikhonov weight
+    double sy, sxi;       // MAPG block steps step_scale / L^y_k, step_scale / L^xi_k
+    double alpha_y, alpha_xi;
+    double By, Bxi;       // ball radii of Q_y (centre ybar) and Q_xi (centre 0)
+    double theta_scale;   // mu_k / mu_{k+1}
+    int64_t lmax;         // l^max_k
+    int32_t adaptive;     // 1: alpha tests of Fig. 4 active
+    int32_t pad;
+};
+
+// Device-side state.  Written by kernels only (the host reads it back).
+struct DevState {
+    // problem constants (set up once)
+    double ybar_mean, ybar_inf, sigma2_A2, Bbar, aff_b, pad_c;
+    int32_t nonfinite, one;           // `one` stays 1: the activity flag of stand-alone passes
+    // MAPG loop
+    double t;                         // momentum scalar t_l
+    int64_t it;                       // MAPG iterations done in this ALCC iteration
+    int32_t active, stopped_by_alpha;
+    double scale_y, scale_xi;         // ball projection factors of the current step
+    double dy, dxi;                   // ||y1 - y2||, ||xi1 - xi2|| of the last step
+    // KKT of the last multiplier step
+    double stat_y, stat_xi, infeas, compl_, infeas_sq, gap, obj, xi_sq;
+    int32_t iterate_nonfinite, pad_k;
+    // arrival counters of the last-block reductions
+    unsigned int cnt[4];
+};
+
+// Packed per-lane X operands of one 16-row tile: for lane l = 16 g + c,
+//   q <  KS           : A operand of R = [X 1] Xi_aug^T, element X_aug[i0 + c][4 q + g]
+//   KS <= q < KS+4NKB : B operand of C = W^T X_aug,      element X_aug[i0 + rmap(g, s)][16 kb + c]
+//                        with s = (q - KS) % 4, kb = (q - KS) / 4
+// where X_aug[i] = [x_i, 1, 0, ...] (zero rows for i >= N) and rmap is the
+// accumulator row map of the pass precision (4 g + s for FP32, g + 4 s for FP64).
+__host__ __device__ constexpr int ks_of(int n) { return (n + 1 + 3) / 4; }
+__host__ __device__ constexpr int nkb_of_ks(int ks) { return ks <= 4 ? 1 : 2; }
+__host__ __device__ constexpr int q_of_ks(int ks) { return ks + 4 * nkb_of_ks(ks); }
+__host__ __device__ constexpr int qp_of_ks(int ks, int elem) {
+    // padded to whole 16-byte vectors
+    return ((q_of_ks(ks) * elem + 15) / 16) * 16 / elem;
+}
+
+struct PassArgs {
+    int64_t N, Nrow, ld;      // points, padded rows (x16), theta row stride (x64)
+    int32_t nc;               // n + 1
+    int32_t rows_per_chunk;   // multiple of 64
+    int32_t mode;             // 0 gradient pass, 1 multiplier (theta) pass
+    int32_t pad;
+    void* theta;              // Nrow x ld, pass precision
+    const void* xp;           // packed X operands, (Nrow/16) x 64 x QP
+    const void* xiaug;        // ld x KP: [-xi_j, d_j - y_j, 0..]
+    const void* ycol;         // Nrow: y_i
+    void* rowpart;            // strips x Nrow
+    void* cpart;              // chunks x ld x nc
+    double* kktpart;          // (strips*chunks) x 4
+    double theta_scale;       // mu_k / mu_{k+1} (multiplier pass)
+    const int32_t* active;
+};
+
+// Sum of the pass partials for point j, then the gradient (mode 1), the MAPG
+// gradient step (mode 0) or the KKT residuals of a multiplier step (mode 2).
+struct ReduceArgs {
+    int64_t N, Nrow, ld;
+    int32_t n, nc, strips, chunks, mode, npass;   // mode 0 MAPG step, 1 gradient out, 2 KKT
+    const void* rowpart;
+    const void* cpart;
+    const double* X;
+    const double* ybar;
+    const double* y;
+    const double* xi;
+    double* out_y;
+    double* out_xi;
+    double* blockpart;        // gridDim.x x 4
+    const double* kktpart;    // npass x 4 (mode 2)
+    const OuterArgs* oa;
+    DevState* st;
+    double mu, gamma;         // modes 1 and 2
+};
+
+// Completion of a MAPG step (Fig. 4): projections, momentum, stopping test.
+struct UpdateArgs {
+    int64_t N, ld;
+    int32_t n, kp;
+    const double* X;
+    const double* ybar;
+    const double* vy;
+    const double* vxi;
+    double* y1p;     // y^(1)_{l-1} in, y^(1)_l out
+    double* y2;      // y^(2)_l in, y^(2)_{l+1} out
+    double* xi1p;
+    double* xi2;
+    void* xiaug;     // pass precision
+    void* ycol;
+    double* blockpart;
+    const OuterArgs* oa;
+    DevState* st;
+};
+
+// Operands of the next pass at (y, xi), optionally restarting MAPG there.
+struct PointArgs {
+    int64_t N, Nrow, ld;
+    int32_t n, kp, write_state, pad;
+    const double* X;
+    const double* y;
+    const double* xi;
+    double* y1p;
+    double* y2;
+    double* xi1p;
+    double* xi2;
+    void* xiaug;
+    void* ycol;
+};
+
+hipError_t launch_pair_pass(bool f64, int ks, const PassArgs& a, dim3 grid, hipStream_t s);
+hipError_t launch_reduce(bool f64, const ReduceArgs& a, hipStream_t s);
+hipError_t launch_update(bool f64, const UpdateArgs& a, hipStream_t s);
+hipError_t launch_set_point(bool f64, const PointArgs& a, hipStream_t s);
+hipError_t launch_begin_outer(const OuterArgs& args, OuterArgs* dst, DevState* st, hipStream_t s);
+hipError_t launch_prep_xp(bool f64, const double* X, int64_t N, int n, int64_t Nrow, int ks, int qp, void* xp,
+                          hipStream_t s);
+hipError_t launch_theta_import(bool f64, const double* src, int64_t N, int64_t Nrow, int64_t ld, void* theta,
+                               hipStream_t s);
+hipError_t launch_theta_export(bool f64, const void* theta, int64_t N, int64_t ld, double* dst, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_setup(const double* X, const double* ybar, int64_t N, int n, double gamma, double* su,
+                        double* part, double* y0, double* xi0, DevState* st, hipStream_t s);
+
+}  // namespace cr

@@ -1,0 +1,864 @@
+// gfx950 kernels of the convex-regression pair engine.
+//
+// Notation (Aybat & Wang, Sec. II): points x_l (rows of X, N x n), data ybar,
+// unknowns y (N) and xi (N x n).  Pair (i, j), i != j, is the constraint
+// y_i >= y_j + xi_j^T (x_i - x_j) (eq. "original"); its residual is
+//   r_ij = y_i - y_j - xi_j^T x_i + xi_j^T x_j = (A1 y + A2 xi)_(i,j).
+// One MAPG iteration (Fig. 4) needs grad P_k (eq. "subproblem"):
+//   w_ij = (r_ij - theta_ij)_- = max(theta_ij - r_ij, 0)
+//   grad_y P  = (y - ybar)/mu - (rowsum(W) - colsum(W))
+//   grad_xi P = (gamma/mu) xi_j + sum_i w_ij x_i - colsum_j(W) x_j
+// and the ALCC multiplier step (Fig. 3 step 4) is
+//   theta <- (mu_k / mu_{k+1}) max(theta - r, 0).
+//
+// The pair pass computes r with one MFMA contraction,
+//   R = [X 1] [-Xi  c]^T + y 1^T,   c_j = x_j^T xi_j - y_j,
+// streams theta once, and reduces W with a second MFMA contraction,
+//   C = W^T [X 1]  (columns 0..n-1: sum_i w_ij x_i, column n: colsum_j),
+// plus wavefront shuffles for the row sums.  Partial sums leave each
+// workgroup once; a separate O(N n) kernel sums them in a fixed order.
+#include "cr_device.h"
+
+namespace cr {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Tr;
+template <> struct Tr<float> {
+    static constexpr int TW = 4;   // j-tiles per wave: 16 lanes x 4 floats = 256 B per row
+    typedef f32x4 acc;
+};
+template <> struct Tr<double> {
+    static constexpr int TW = 2;   // 16 lanes x 2 doubles = 256 B per row
+    typedef f64x4 acc;
+};
+
+// 16x16x4 MFMA.  Operand layout for lane l = 16 g + c (g = l / 16, c = l % 16):
+//   A element (row c, k g), B element (k g, col c); accumulator element v is
+//   (row rmap(g, v), col c) with rmap = 4 g + v for FP32 and g + 4 v for FP64
+//   (measured on gfx950 with a one-wave layout probe).
+__device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 acc) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma4(double a, double b, f64x4 acc) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+}
+
+template <typename T> __host__ __device__ constexpr int rmap(int g, int v) {
+    return sizeof(T) == 4 ? 4 * g + v : g + 4 * v;
+}
+
+template <typename T> struct alignas(16) V16 { T v[16 / sizeof(T)]; };
+
+template <typename T>
+__device__ __forceinline__ V16<T> ld16(const T* p) { return *reinterpret_cast<const V16<T>*>(p); }
+template <typename T>
+__device__ __forceinline__ void st16(T* p, const V16<T>& x) { *reinterpret_cast<V16<T>*>(p) = x; }
+
+// ---------------------------------------------------------------------------
+// Block reductions (256 threads) and the last-arriving-block handshake.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Sum (op 0) or max (op 1) of one double per thread; result valid in every thread.
+__device__ double block_reduce(double v, int op) {
+    __shared__ double red[kBlock / 64];
+    v = op == 0 ? wave_sum(v) : wave_max(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = red[0];
+    for (int w = 1; w < kBlock / 64; ++w) r = op == 0 ? r + red[w] : fmax(r, red[w]);
+    return r;
+}
+
+// Each block calls this once after writing its partial results; it returns
+// true in every thread of the one block that arrives last (that block then
+// sees every other block's partials) and re-arms the counter.
+__device__ bool last_block(unsigned int* counter) {
+    __shared__ int is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int prev = atomicAdd(counter, 1u);
+        is_last = (prev == gridDim.x * gridDim.y - 1) ? 1 : 0;
+        if (is_last) atomicExch(counter, 0u);
+    }
+    __syncthreads();
+    if (is_last) __threadfence();
+    return is_last != 0;
+}
+
+__device__ __forceinline__ double ld_coherent(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// The fused pair pass (gradient or multiplier step).
+//
+// Grid (strips, chunks).  Workgroup (s, h) owns the columns
+// [16 TW s, 16 TW (s+1)) and the rows [h rpc, (h+1) rpc); its 4 waves take
+// alternate 16-row tiles.  Lane (g, c) of a wave covers, for j-tile t and
+// accumulator element v, the pair (i0 + rmap(g, v), J0 + TW c + t), so its
+// TW theta values of one row are contiguous (one 16-byte load per row).
+// ---------------------------------------------------------------------------
+template <typename T, int KS>
+__global__ __launch_bounds__(kBlock) void k_pair_pass(PassArgs a) {
+    constexpr int TW = Tr<T>::TW;
+    constexpr int NKB = nkb_of_ks(KS);
+    constexpr int KP = 4 * KS;
+    constexpr int QP = qp_of_ks(KS, (int)sizeof(T));
+    constexpr int EV = 16 / (int)sizeof(T);
+    typedef typename Tr<T>::acc acc_t;
+
+    if (*a.active == 0) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int64_t J0 = (int64_t)blockIdx.x * (16 * TW);
+    const int64_t I0 = (int64_t)blockIdx.y * a.rows_per_chunk;
+    const int64_t I1 = min(I0 + (int64_t)a.rows_per_chunk, a.Nrow);
+    const int64_t jl = J0 + TW * c;
+    const T* __restrict__ xiaug = (const T*)a.xiaug;
+    const T* __restrict__ xp = (const T*)a.xp;
+    const T* __restrict__ ycol = (const T*)a.ycol;
+    T* __restrict__ theta = (T*)a.theta;
+    const bool theta_mode = a.mode == 1;
+
+    // B operand of R for every j-tile: [-xi_j, c_j, 0...] (k = 4 s + g)
+    T breg[KS][TW];
+#pragma unroll
+    for (int t = 0; t < TW; ++t) {
+        const T* row = xiaug + (jl + t) * KP;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) breg[s][t] = row[4 * s + g];
+    }
+
+    acc_t cacc[TW][NKB];
+#pragma unroll
+    for (int t = 0; t < TW; ++t)
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb) cacc[t][kb] = acc_t{0, 0, 0, 0};
+
+    double k_rneg_max = 0.0, k_rneg_sq = 0.0, k_wr_max = 0.0, k_wr_sum = 0.0;
+
+    for (int64_t i0 = I0 + 16 * wave; i0 < I1; i0 += 16 * kWaves) {
+        T xop[QP];
+#pragma unroll
+        for (int q = 0; q < QP / EV; ++q) {
+            V16<T> tv = ld16(xp + ((i0 >> 4) * 64 + lane) * QP + q * EV);
+#pragma unroll
+            for (int e = 0; e < EV; ++e) xop[q * EV + e] = tv.v[e];
+        }
+        T yv[4];
+        if (sizeof(T) == 4) {
+            V16<T> tv = ld16(ycol + i0 + 4 * g);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) yv[e] = tv.v[e];
+        } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) yv[v] = ycol[i0 + rmap<T>(g, v)];
+        }
+        V16<T> th[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) th[v] = ld16(theta + (i0 + rmap<T>(g, v)) * a.ld + jl);
+
+        // residual tiles R_t (accumulator initialised with y_i)
+        acc_t R[TW];
+#pragma unroll
+        for (int t = 0; t < TW; ++t) {
+            R[t] = acc_t{yv[0], yv[1], yv[2], yv[3]};
+#pragma unroll
+            for (int s = 0; s < KS; ++s) R[t] = mfma4(xop[s], breg[s][t], R[t]);
+        }
+
+        // w = max(theta - r, 0); explicit zero off the constraint set
+        T W[TW][4];
+#pragma unroll
+        for (int t = 0; t < TW; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                T d = th[v].v[t] - R[t][v];
+                W[t][v] = d > (T)0 ? d : (T)0;
+            }
+        const bool edge = (i0 < J0 + 16 * TW && i0 + 16 > J0) || (J0 + 16 * TW > a.N) || (i0 + 16 > a.N);
+        if (edge) {
+#pragma unroll
+            for (int t = 0; t < TW; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t i = i0 + rmap<T>(g, v), j = jl + t;
+                    if (!(i < a.N && j < a.N && i != j)) W[t][v] = (T)0;
+                }
+        }
+
+        if (theta_mode) {
+            // Fig. 3 step 4 in place, and the pair terms of the KKT residual
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                V16<T> o;
+#pragma unroll
+                for (int t = 0; t < TW; ++t) o.v[t] = (T)(a.theta_scale * (double)W[t][v]);
+                st16(theta + (i0 + rmap<T>(g, v)) * a.ld + jl, o);
+            }
+#pragma unroll
+            for (int t = 0; t < TW; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t i = i0 + rmap<T>(g, v), j = jl + t;
+                    if (i < a.N && j < a.N && i != j) {
+                        const double r = (double)R[t][v];
+                        const double rn = r < 0.0 ? -r : 0.0;
+                        const double wr = (double)W[t][v] * r;
+                        k_rneg_max = fmax(k_rneg_max, rn);
+                        k_rneg_sq += rn * rn;
+                        k_wr_max = fmax(k_wr_max, fabs(wr));
+                        k_wr_sum += wr;
+                    }
+                }
+        }
+
+        // C += W^T [X 1]: i-slot g of step s is row i0 + rmap(g, s)
+#pragma unroll
+        for (int t = 0; t < TW; ++t)
+#pragma unroll
+            for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    cacc[t][kb] = mfma4(W[t][s], xop[KS + 4 * kb + s], cacc[t][kb]);
+
+        // row sums over this workgroup's columns
+        T rs[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            T s = W[0][v];
+#pragma unroll
+            for (int t = 1; t < TW; ++t) s += W[t][v];
+            s += __shfl_xor(s, 8);
+            s += __shfl_xor(s, 4);
+            s += __shfl_xor(s, 2);
+            s += __shfl_xor(s, 1);
+            rs[v] = s;
+        }
+        if (c == 0) {
+            T* dst = (T*)a.rowpart + (int64_t)blockIdx.x * a.Nrow + i0;
+            if (sizeof(T) == 4) {
+                V16<T> o;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) o.v[e] = rs[e];
+                st16(dst + 4 * g, o);
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) dst[rmap<T>(g, v)] = rs[v];
+            }
+        }
+    }
+
+    // Combine the 4 waves' column sums (fixed order) and write this chunk's partial.
+    __shared__ T cl[kWaves][TW][NKB][4][64];
+#pragma unroll
+    for (int t = 0; t < TW; ++t)
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cl[wave][t][kb][v][lane] = cacc[t][kb][v];
+    __syncthreads();
+    T* cpart = (T*)a.cpart;
+    for (int e = threadIdx.x; e < TW * NKB * 4 * 64; e += kBlock) {
+        const int ln = e & 63, v = (e >> 6) & 3, rest = e >> 8;
+        const int kb = rest % NKB, t = rest / NKB;
+        const T s = ((cl[0][t][kb][v][ln] + cl[1][t][kb][v][ln]) + cl[2][t][kb][v][ln]) + cl[3][t][kb][v][ln];
+        const int64_t j = J0 + TW * rmap<T>(ln >> 4, v) + t;
+        const int kk = 16 * kb + (ln & 15);
+        if (kk < a.nc) cpart[((int64_t)blockIdx.y * a.ld + j) * a.nc + kk] = s;
+    }
+
+    if (theta_mode) {
+        __shared__ double kr[4][kWaves];
+        double q0 = wave_max(k_rneg_max), q1 = wave_sum(k_rneg_sq);
+        double q2 = wave_max(k_wr_max), q3 = wave_sum(k_wr_sum);
+        if (lane == 0) { kr[0][wave] = q0; kr[1][wave] = q1; kr[2][wave] = q2; kr[3][wave] = q3; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double* o = a.kktpart + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 4;
+            double m0 = kr[0][0], s1 = kr[1][0], m2 = kr[2][0], s3 = kr[3][0];
+            for (int w = 1; w < kWaves; ++w) {
+                m0 = fmax(m0, kr[0][w]); s1 += kr[1][w]; m2 = fmax(m2, kr[2][w]); s3 += kr[3][w];
+            }
+            o[0] = m0; o[1] = s1; o[2] = m2; o[3] = s3;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sum of the pass partials for point j and the gradient / MAPG step / KKT.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) {
+    DevState* st = a.st;
+    if (a.mode == 0 && st->active == 0) return;
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = j < a.N;
+    const T* rowpart = (const T*)a.rowpart;
+    const T* cpart = (const T*)a.cpart;
+    const int n = a.n, nc = a.nc;
+    double mu, gamma, sy = 0.0, sxi = 0.0;
+    if (a.mode == 0) {
+        mu = a.oa->mu; gamma = a.oa->gamma; sy = a.oa->sy; sxi = a.oa->sxi;
+    } else {
+        mu = a.mu; gamma = a.gamma;
+    }
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    if (valid) {
+        double rs = 0.0;
+        for (int s = 0; s < a.strips; ++s) rs += (double)rowpart[(int64_t)s * a.Nrow + j];
+        double cs = 0.0;
+        for (int h = 0; h < a.chunks; ++h) cs += (double)cpart[((int64_t)h * a.ld + j) * nc + n];
+        const double yj = a.y[j], ybj = a.ybar[j];
+        if (a.mode == 0) {
+            const double gy = (yj - ybj) / mu - rs + cs;
+            const double vy = yj - sy * gy;
+            a.out_y[j] = vy;
+            acc0 = (vy - ybj) * (vy - ybj);
+        } else if (a.mode == 1) {
+            a.out_y[j] = (yj - ybj) / mu - rs + cs;
+        } else {
+            const double sty = yj - ybj - mu * (rs - cs);
+            if (a.out_y) a.out_y[j] = sty;
+            acc0 = fabs(sty);
+            acc2 = (yj - ybj) * (yj - ybj);
+        }
+        for (int k = 0; k < n; ++k) {
+            double ck = 0.0;
+            for (int h = 0; h < a.chunks; ++h) ck += (double)cpart[((int64_t)h * a.ld + j) * nc + k];
+            const double xjk = a.X[j * n + k], xik = a.xi[j * n + k];
+            const double aw = ck - cs * xjk;          // -(A2^T w)_j
+            if (a.mode == 0) {
+                const double gx = (gamma / mu) * xik + aw;
+                const double vx = xik - sxi * gx;
+                a.out_xi[j * n + k] = vx;
+                acc1 += vx * vx;
+            } else if (a.mode == 1) {
+                a.out_xi[j * n + k] = (gamma / mu) * xik + aw;
+            } else {
+                const double stx = gamma * xik + mu * aw;
+                if (a.out_xi) a.out_xi[j * n + k] = stx;
+                acc1 = fmax(acc1, fabs(stx));
+                acc3 += xik * xik;
+            }
+        }
+    }
+    if (a.mode == 1) return;
+    if (a.mode == 0) {
+        const double b0 = block_reduce(acc0, 0), b1 = block_reduce(acc1, 0);
+        if (threadIdx.x == 0) { a.blockpart[blockIdx.x * 4 + 0] = b0; a.blockpart[blockIdx.x * 4 + 1] = b1; }
+        if (last_block(&st->cnt[0])) {
+            if (threadIdx.x == 0) {
+                double ny = 0.0, nx = 0.0;
+                for (unsigned b = 0; b < gridDim.x; ++b) {
+                    ny += ld_coherent(a.blockpart + b * 4 + 0);
+                    nx += ld_coherent(a.blockpart + b * 4 + 1);
+                }
+                ny = sqrt(ny); nx = sqrt(nx);
+                st->scale_y = ny > a.oa->By ? a.oa->By / ny : 1.0;
+                st->scale_xi = nx > a.oa->Bxi ? a.oa->Bxi / nx : 1.0;
+            }
+        }
+        return;
+    }
+    // mode 2: KKT residuals of the multiplier step
+    const bool bad = valid && !(isfinite(a.y[j]));
+    const double b0 = block_reduce(acc0, 1), b1 = block_reduce(acc1, 1);
+    const double b2 = block_reduce(acc2, 0), b3 = block_reduce(acc3, 0);
+    const double bb = block_reduce(bad ? 1.0 : 0.0, 1);
+    if (threadIdx.x == 0) {
+        a.blockpart[blockIdx.x * 4 + 0] = fmax(b0, bb > 0 ? INFINITY : 0.0);
+        a.blockpart[blockIdx.x * 4 + 1] = b1;
+        a.blockpart[blockIdx.x * 4 + 2] = b2;
+        a.blockpart[blockIdx.x * 4 + 3] = b3;
+    }
+    if (last_block(&st->cnt[1])) {
+        if (threadIdx.x == 0) {
+            double m0 = 0.0, m1 = 0.0, s2 = 0.0, s3 = 0.0;
+            for (unsigned b = 0; b < gridDim.x; ++b) {
+                m0 = fmax(m0, ld_coherent(a.blockpart + b * 4 + 0));
+                m1 = fmax(m1, ld_coherent(a.blockpart + b * 4 + 1));
+                s2 += ld_coherent(a.blockpart + b * 4 + 2);
+                s3 += ld_coherent(a.blockpart + b * 4 + 3);
+            }
+            double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+            for (int q = 0; q < a.npass; ++q) {
+                p0 = fmax(p0, a.kktpart[q * 4 + 0]);
+                p1 += a.kktpart[q * 4 + 1];
+                p2 = fmax(p2, a.kktpart[q * 4 + 2]);
+                p3 += a.kktpart[q * 4 + 3];
+            }
+            st->stat_y = m0;
+            st->stat_xi = m1;
+            st->obj = 0.5 * s2;
+            st->xi_sq = s3;
+            st->infeas = p0;
+            st->infeas_sq = p1;
+            st->compl_ = mu * p2;
+            st->gap = mu * p3;
+            st->iterate_nonfinite = isfinite(m0) && isfinite(m1) && isfinite(s2) && isfinite(s3) ? 0 : 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// MAPG step completion (Fig. 4 steps 1-9): ball projections, momentum,
+// stopping test, and the pass-precision operands of the next pass.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
+    DevState* st = a.st;
+    if (st->active == 0) return;
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int n = a.n;
+    const double t = st->t;
+    const double t_next = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+    const double beta = (t - 1.0) / t_next;
+    const double sc_y = st->scale_y, sc_xi = st->scale_xi;
+    double dy2 = 0.0, dx2 = 0.0;
+    if (j < a.N) {
+        const double yb = a.ybar[j];
+        const double y1 = yb + sc_y * (a.vy[j] - yb);
+        const double y2o = a.y2[j];
+        dy2 = (y1 - y2o) * (y1 - y2o);
+        const double y2n = y1 + beta * (y1 - a.y1p[j]);
+        a.y1p[j] = y1;
+        a.y2[j] = y2n;
+        T* xa = (T*)a.xiaug + j * a.kp;
+        double d = 0.0;
+        for (int k = 0; k < n; ++k) {
+            const double x1 = sc_xi * a.vxi[j * n + k];
+            const double x2o = a.xi2[j * n + k];
+            dx2 += (x1 - x2o) * (x1 - x2o);
+            const double x2n = x1 + beta * (x1 - a.xi1p[j * n + k]);
+            a.xi1p[j * n + k] = x1;
+            a.xi2[j * n + k] = x2n;
+            xa[k] = (T)(-x2n);
+            d += a.X[j * n + k] * x2n;
+        }
+        xa[n] = (T)(d - y2n);
+        ((T*)a.ycol)[j] = (T)y2n;
+    }
+    const double b0 = block_reduce(dy2, 0), b1 = block_reduce(dx2, 0);
+    if (threadIdx.x == 0) { a.blockpart[blockIdx.x * 4 + 2] = b0; a.blockpart[blockIdx.x * 4 + 3] = b1; }
+    if (last_block(&st->cnt[2])) {
+        if (threadIdx.x == 0) {
+            double sy = 0.0, sx = 0.0;
+            for (unsigned b = 0; b < gridDim.x; ++b) {
+                sy += ld_coherent(a.blockpart + b * 4 + 2);
+                sx += ld_coherent(a.blockpart + b * 4 + 3);
+            }
+            const double dy = sqrt(sy), dxi = sqrt(sx);
+            st->dy = dy;
+            st->dxi = dxi;
+            st->t = t_next;
+            const int64_t it = st->it + 1;
+            st->it = it;
+            const bool alpha_stop = a.oa->adaptive && dy <= a.oa->alpha_y && dxi <= a.oa->alpha_xi;
+            if (alpha_stop || it >= a.oa->lmax) {
+                st->active = 0;
+                st->stopped_by_alpha = alpha_stop ? 1 : 0;
+            }
+        }
+    }
+}
+
+// Set the point of the next pass (and optionally restart MAPG there):
+// pass-precision operands from (y, xi); with write_state, also
+// y^(1)_0 = y^(2)_1 = y and likewise xi.
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_set_point(PointArgs a) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int n = a.n;
+    if (j >= a.ld) return;
+    T* xa = (T*)a.xiaug + j * a.kp;
+    if (j < a.N) {
+        const double yj = a.y[j];
+        double d = 0.0;
+        for (int k = 0; k < n; ++k) {
+            const double x = a.xi[j * n + k];
+            xa[k] = (T)(-x);
+            d += a.X[j * n + k] * x;
+            if (a.write_state) { a.xi1p[j * n + k] = x; a.xi2[j * n + k] = x; }
+        }
+        xa[n] = (T)(d - yj);
+        for (int k = n + 1; k < a.kp; ++k) xa[k] = (T)0;
+        ((T*)a.ycol)[j] = (T)yj;
+        if (a.write_state) { a.y1p[j] = yj; a.y2[j] = yj; }
+    } else {
+        for (int k = 0; k < a.kp; ++k) xa[k] = (T)0;
+        if (j < a.Nrow) ((T*)a.ycol)[j] = (T)0;
+    }
+}
+
+__global__ void k_begin_outer(OuterArgs args, OuterArgs* dst, DevState* st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *dst = args;
+        st->t = 1.0;
+        st->it = 0;
+        st->active = 1;
+        st->stopped_by_alpha = 0;
+        st->one = 1;
+        for (int q = 0; q < 4; ++q) st->cnt[q] = 0u;
+    }
+}
+
+// Packed X operands (see cr_device.h): one thread per (16-row tile, lane).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prep_xp(const double* X, int64_t N, int n, int64_t Nrow, int ks,
+                                                    int qp, T* xp) {
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (gid >= (Nrow / 16) * 64) return;
+    const int64_t tile = gid / 64;
+    const int lane = (int)(gid % 64), g = lane >> 4, c = lane & 15;
+    const int64_t i0 = tile * 16;
+    const int q_used = ks + 4 * nkb_of_ks(ks);
+    for (int q = 0; q < qp; ++q) {
+        int64_t i;
+        int k;
+        if (q < ks) {
+            i = i0 + c; k = 4 * q + g;
+        } else if (q < q_used) {
+            const int s = (q - ks) % 4, kb = (q - ks) / 4;
+            i = i0 + rmap<T>(g, s); k = 16 * kb + c;
+        } else {
+            xp[gid * qp + q] = (T)0;
+            continue;
+        }
+        double val = 0.0;
+        if (i < N) val = k < n ? X[i * n + k] : (k == n ? 1.0 : 0.0);
+        xp[gid * qp + q] = (T)val;
+    }
+}
+
+// theta layout conversions (inspection / tests) and clearing.
+template <typename T>
+__global__ void k_theta_import(const double* src, int64_t N, int64_t Nrow, int64_t ld, T* theta) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= Nrow * ld) return;
+    const int64_t i = e / ld, j = e % ld;
+    theta[e] = (i < N && j < N && i != j) ? (T)src[i * N + j] : (T)0;
+}
+template <typename T>
+__global__ void k_theta_export(const T* theta, int64_t N, int64_t ld, double* dst) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= N * N) return;
+    const int64_t i = e / N, j = e % N;
+    dst[e] = i == j ? 0.0 : (double)theta[i * ld + j];
+}
+__global__ void k_zero16(uint4* p, int64_t n16) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t q = e; q < n16; q += stride) p[q] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// ---------------------------------------------------------------------------
+// Set-up (once per context, FP64): means, centred scatter matrix and its
+// eigen-decomposition, affine least-squares fit, sigma_max(A2)^2, start point.
+// Scratch `su` layout: [0,n) xbar | [n] ybar mean | [n+1,2n+1) a | [2n+1] b |
+//   [2n+2, 3n+2) eigenvalues | [3n+2, 3n+2+n^2) eigenvectors (column k = vector k)
+// ---------------------------------------------------------------------------
+__global__ void k_su_sums(const double* X, const double* ybar, int64_t N, int n, int64_t rows,
+                          const double* su, int phase, double* part) {
+    // phase 0: e < n: sum x_ik; e = n: sum ybar; e = n+1: max |ybar|; e = n+2: # non-finite
+    // phase 1: e < n*n: sum u_ik u_il; n*n <= e < n*n+n: sum u_ik (ybar_i - ybar_mean)
+    const int64_t r0 = (int64_t)blockIdx.x * rows, r1 = min(r0 + rows, N);
+    const int ne = phase == 0 ? n + 3 : n * n + n;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+        double acc = 0.0;
+        if (phase == 0) {
+            for (int64_t i = r0; i < r1; ++i) {
+                if (e < n) acc += X[i * n + e];
+                else if (e == n) acc += ybar[i];
+                else if (e == n + 1) acc = fmax(acc, fabs(ybar[i]));
+                else {
+                    bool bad = !isfinite(ybar[i]);
+                    for (int k = 0; k < n; ++k) bad = bad || !isfinite(X[i * n + k]);
+                    acc += bad ? 1.0 : 0.0;
+                }
+            }
+        } else {
+            const double ym = su[n];
+            if (e < n * n) {
+                const int k = e / n, l = e % n;
+                for (int64_t i = r0; i < r1; ++i) acc += (X[i * n + k] - su[k]) * (X[i * n + l] - su[l]);
+            } else {
+                const int k = e - n * n;
+                for (int64_t i = r0; i < r1; ++i) acc += (X[i * n + k] - su[k]) * (ybar[i] - ym);
+            }
+        }
+        part[(int64_t)blockIdx.x * ne + e] = acc;
+    }
+}
+
+__global__ void k_su_means_final(const double* part, int nblk, int64_t N, int n, double* su, DevState* st) {
+    if (threadIdx.x != 0) return;
+    st->one = 1;
+    const int ne = n + 3;
+    for (int e = 0; e < ne; ++e) {
+        double acc = 0.0;
+        for (int b = 0; b < nblk; ++b) acc = (e == n + 1) ? fmax(acc, part[b * ne + e]) : acc + part[b * ne + e];
+        if (e < n) su[e] = acc / (double)N;
+        else if (e == n) { su[n] = acc / (double)N; st->ybar_mean = su[n]; }
+        else if (e == n + 1) st->ybar_inf = acc;
+        else st->nonfinite = acc > 0.0 ? 1 : 0;
+    }
+}
+
+// Cyclic Jacobi eigen-decomposition of the centred scatter matrix M0 and the
+// affine fit a = M0^+ X_c^T ybar_c, b = mean(ybar) - xbar^T a.
+__global__ void k_su_eig_final(const double* part, int nblk, int n, double* su) {
+    __shared__ double A[kMaxDim * kMaxDim], V[kMaxDim * kMaxDim], q[kMaxDim];
+    const int ne = n * n + n;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+        double acc = 0.0;
+        for (int b = 0; b < nblk; ++b) acc += part[b * ne + e];
+        if (e < n * n) A[e] = acc;
+        else q[e - n * n] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int k = 0; k < n; ++k)
+        for (int l = 0; l < n; ++l) V[k * n + l] = k == l ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, diag = 0.0;
+        for (int p = 0; p < n; ++p) {
+            diag += A[p * n + p] * A[p * n + p];
+            for (int r = p + 1; r < n; ++r) off += A[p * n + r] * A[p * n + r];
+        }
+        if (off <= 1e-32 * diag || off == 0.0) break;
+        for (int p = 0; p < n; ++p)
+            for (int r = p + 1; r < n; ++r) {
+                const double apr = A[p * n + r];
+                if (apr == 0.0) continue;
+                const double tau = (A[r * n + r] - A[p * n + p]) / (2.0 * apr);
+                const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = tt * cs;
+                for (int k = 0; k < n; ++k) {       // columns p, r
+                    const double akp = A[k * n + p], akr = A[k * n + r];
+                    A[k * n + p] = cs * akp - sn * akr;
+                    A[k * n + r] = sn * akp + cs * akr;
+                }
+                for (int k = 0; k < n; ++k) {       // rows p, r
+                    const double apk = A[p * n + k], ark = A[r * n + k];
+                    A[p * n + k] = cs * apk - sn * ark;
+                    A[r * n + k] = sn * apk + cs * ark;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = V[k * n + p], vkr = V[k * n + r];
+                    V[k * n + p] = cs * vkp - sn * vkr;
+                    V[k * n + r] = sn * vkp + cs * vkr;
+                }
+            }
+    }
+    double lmax = 0.0;
+    for (int k = 0; k < n; ++k) lmax = fmax(lmax, A[k * n + k]);
+    double* lam = su + 2 * n + 2;
+    double* vec = su + 3 * n + 2;
+    for (int k = 0; k < n; ++k) lam[k] = A[k * n + k];
+    for (int e = 0; e < n * n; ++e) vec[e] = V[e];
+    // a = sum_k v_k (v_k^T q) / lam_k over eigenvalues above the rank tolerance
+    double* acoef = su + n + 1;
+    for (int l = 0; l < n; ++l) acoef[l] = 0.0;
+    for (int k = 0; k < n; ++k) {
+        if (!(lam[k] > 1e-12 * lmax)) continue;
+        double proj = 0.0;
+        for (int l = 0; l < n; ++l) proj += V[l * n + k] * q[l];
+        proj /= lam[k];
+        for (int l = 0; l < n; ++l) acoef[l] += proj * V[l * n + k];
+    }
+    double b = su[n];
+    for (int l = 0; l < n; ++l) b -= su[l] * acoef[l];
+    su[2 * n + 1] = b;
+}
+
+// lambda_max(S_j) with S_j = M0 + N u u^T, u = x_j - xbar: the largest root of
+// the secular equation 1 = sum_k z_k^2 / (lambda - lam_k), z = sqrt(N) V^T u,
+// found by bisection on [max lam, max lam + |z|^2].
+__global__ __launch_bounds__(kBlock) void k_su_sigma2(const double* X, int64_t N, int n, const double* su,
+                                                      double* part) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double best = 0.0;
+    if (j < N) {
+        const double* lam = su + 2 * n + 2;
+        const double* vec = su + 3 * n + 2;
+        double z[kMaxDim];
+        double zz = 0.0, l1 = lam[0];
+        for (int k = 1; k < n; ++k) l1 = fmax(l1, lam[k]);
+        for (int k = 0; k < n; ++k) {
+            double acc = 0.0;
+            for (int l = 0; l < n; ++l) acc += vec[l * n + k] * (X[j * n + l] - su[l]);
+            z[k] = sqrt((double)N) * acc;
+            zz += z[k] * z[k];
+        }
+        double lo = l1, hi = l1 + zz;
+        for (int itr = 0; itr < 200 && zz > 0.0; ++itr) {
+            const double mid = 0.5 * (lo + hi);
+            if (!(mid > lo && mid < hi)) break;
+            double f = 1.0;
+            for (int k = 0; k < n; ++k) f -= z[k] * z[k] / (mid - lam[k]);
+            if (f < 0.0) lo = mid; else hi = mid;
+        }
+        best = zz > 0.0 ? hi : l1;
+    }
+    const double b = block_reduce(best, 1);
+    if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+
+__global__ void k_su_sigma2_final(const double* part, int nblk, DevState* st) {
+    if (threadIdx.x != 0) return;
+    double m = 0.0;
+    for (int b = 0; b < nblk; ++b) m = fmax(m, part[b]);
+    st->sigma2_A2 = m;
+}
+
+// Start point (Sec. II-E): yhat = X a + b, xihat_l = a; Bbar^2 = |yhat - ybar|^2 + gamma |xihat|^2.
+__global__ __launch_bounds__(kBlock) void k_su_start(const double* X, const double* ybar, int64_t N, int n,
+                                                     const double* su, double* y0, double* xi0, double* part) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const double* acoef = su + n + 1;
+    double r2 = 0.0;
+    if (j < N) {
+        double v = su[2 * n + 1];
+        for (int k = 0; k < n; ++k) {
+            v += X[j * n + k] * acoef[k];
+            xi0[j * n + k] = acoef[k];
+        }
+        y0[j] = v;
+        r2 = (v - ybar[j]) * (v - ybar[j]);
+    }
+    const double b = block_reduce(r2, 0);
+    if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+
+__global__ void k_su_start_final(const double* part, int nblk, int64_t N, int n, double gamma, const double* su,
+                                 DevState* st) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[b];
+    double aa = 0.0;
+    for (int k = 0; k < n; ++k) aa += su[n + 1 + k] * su[n + 1 + k];
+    st->aff_b = su[2 * n + 1];
+    st->Bbar = sqrt(s + gamma * (double)N * aa);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch helpers (called by the driver in cr_api.hip).
+// ---------------------------------------------------------------------------
+template <typename T, int KS>
+static hipError_t launch_pass_ks(const PassArgs& a, dim3 grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_pair_pass<T, KS>), grid, dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_pass_t(int ks, const PassArgs& a, dim3 grid, hipStream_t s) {
+    switch (ks) {
+        case 1: return launch_pass_ks<T, 1>(a, grid, s);
+        case 2: return launch_pass_ks<T, 2>(a, grid, s);
+        case 3: return launch_pass_ks<T, 3>(a, grid, s);
+        case 4: return launch_pass_ks<T, 4>(a, grid, s);
+        case 5: return launch_pass_ks<T, 5>(a, grid, s);
+        case 6: return launch_pass_ks<T, 6>(a, grid, s);
+        case 7: return launch_pass_ks<T, 7>(a, grid, s);
+        case 8: return launch_pass_ks<T, 8>(a, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pair_pass(bool f64, int ks, const PassArgs& a, dim3 grid, hipStream_t s) {
+    return f64 ? launch_pass_t<double>(ks, a, grid, s) : launch_pass_t<float>(ks, a, grid, s);
+}
+
+hipError_t launch_reduce(bool f64, const ReduceArgs& a, hipStream_t s) {
+    const dim3 grid((unsigned)((a.N + kBlock - 1) / kBlock));
+    if (f64) hipLaunchKernelGGL(k_reduce<double>, grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL(k_reduce<float>, grid, dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(bool f64, const UpdateArgs& a, hipStream_t s) {
+    const dim3 grid((unsigned)((a.N + kBlock - 1) / kBlock));
+    if (f64) hipLaunchKernelGGL(k_update<double>, grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL(k_update<float>, grid, dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_point(bool f64, const PointArgs& a, hipStream_t s) {
+    const dim3 grid((unsigned)((a.ld + kBlock - 1) / kBlock));
+    if (f64) hipLaunchKernelGGL(k_set_point<double>, grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL(k_set_point<float>, grid, dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_begin_outer(const OuterArgs& args, OuterArgs* dst, DevState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_begin_outer, dim3(1), dim3(64), 0, s, args, dst, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_xp(bool f64, const double* X, int64_t N, int n, int64_t Nrow, int ks, int qp, void* xp,
+                          hipStream_t s) {
+    const int64_t total = (Nrow / 16) * 64;
+    const dim3 grid((unsigned)((total + kBlock - 1) / kBlock));
+    if (f64) hipLaunchKernelGGL(k_prep_xp<double>, grid, dim3(kBlock), 0, s, X, N, n, Nrow, ks, qp, (double*)xp);
+    else hipLaunchKernelGGL(k_prep_xp<float>, grid, dim3(kBlock), 0, s, X, N, n, Nrow, ks, qp, (float*)xp);
+    return hipGetLastError();
+}
+
+hipError_t launch_theta_import(bool f64, const double* src, int64_t N, int64_t Nrow, int64_t ld, void* theta,
+                               hipStream_t s) {
+    const dim3 grid((unsigned)((Nrow * ld + kBlock - 1) / kBlock));
+    if (f64) hipLaunchKernelGGL(k_theta_import<double>, grid, dim3(kBlock), 0, s, src, N, Nrow, ld, (double*)theta);
+    else hipLaunchKernelGGL(k_theta_import<float>, grid, dim3(kBlock), 0, s, src, N, Nrow, ld, (float*)theta);
+    return hipGetLastError();
+}
+
+hipError_t launch_theta_export(bool f64, const void* theta, int64_t N, int64_t ld, double* dst, hipStream_t s) {
+    const dim3 grid((unsigned)((N * N + kBlock - 1) / kBlock));
+    if (f64) hipLaunchKernelGGL(k_theta_export<double>, grid, dim3(kBlock), 0, s, (const double*)theta, N, ld, dst);
+    else hipLaunchKernelGGL(k_theta_export<float>, grid, dim3(kBlock), 0, s, (const float*)theta, N, ld, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+    const int64_t n16 = (int64_t)(bytes / 16);
+    int64_t blocks = (n16 + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_zero16, dim3((unsigned)blocks), dim3(kBlock), 0, s, (uint4*)p, n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup(const double* X, const double* ybar, int64_t N, int n, double gamma, double* su,
+                        double* part, double* y0, double* xi0, DevState* st, hipStream_t s) {
+    const int64_t rows = 1024;
+    const int nblk = (int)((N + rows - 1) / rows);
+    hipLaunchKernelGGL(k_su_sums, dim3(nblk), dim3(kBlock), 0, s, X, ybar, N, n, rows, (const double*)su, 0, part);
+    hipLaunchKernelGGL(k_su_means_final, dim3(1), dim3(64), 0, s, (const double*)part, nblk, N, n, su, st);
+    hipLaunchKernelGGL(k_su_sums, dim3(nblk), dim3(kBlock), 0, s, X, ybar, N, n, rows, (const double*)su, 1, part);
+    hipLaunchKernelGGL(k_su_eig_final, dim3(1), dim3(kBlock), 0, s, (const double*)part, nblk, n, su);
+    const int nb = (int)((N + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_su_sigma2, dim3(nb), dim3(kBlock), 0, s, X, N, n, (const double*)su, part);
+    hipLaunchKernelGGL(k_su_sigma2_final, dim3(1), dim3(64), 0, s, (const double*)part, nb, st);
+    hipLaunchKernelGGL(k_su_start, dim3(nb), dim3(kBlock), 0, s, X, ybar, N, n, (const double*)su, y0, xi0, part);
+    hipLaunchKernelGGL(k_su_start_final, dim3(1), dim3(64), 0, s, (const double*)part, nb, N, n, gamma,
+                       (const double*)su, st);
+    return hipGetLastError();
+}
+
+}  // namespace cr

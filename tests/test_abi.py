@@ -1,0 +1,91 @@
+"""Host-only checks of the C ABI: the library loads without a GPU, exports every
+symbol include/cr.h declares, and rejects bad arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    import paper_1407_7220_amd as cr
+    return cr, cr._lib
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "cr.h")).read()
+    return sorted(set(re.findall(r"\b(cr_[a-z_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    cr, lib = _lib()
+    names = _declared()
+    assert "cr_solve" in names and "cr_pairwise_step" in names and "cr_init" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(cr.EXPORTED) == set(names)
+
+
+def test_status_strings_and_defaults():
+    cr, lib = _lib()
+    assert lib.cr_status_string(0) == b"CR_OK"
+    assert lib.cr_status_string(5) == b"CR_NOT_CONVERGED"
+    p = cr._CParams()
+    assert lib.cr_params_default(ctypes.byref(p)) == 0
+    assert p.gamma == 1e-3 and p.c == 4.0 and p.step_scale == 0.5 and p.precision == 0
+    assert lib.cr_params_default(None) == cr.ERR_ARG
+
+
+def test_workspace_bytes_validation_and_growth():
+    cr, lib = _lib()
+    b1 = cr.workspace_bytes(1000, 10)
+    b2 = cr.workspace_bytes(2000, 10)
+    assert b1 >= 1000 * 1000 * 8 and b2 >= 2000 * 2000 * 8
+    assert 3.5 < b2 / b1 < 4.5
+    assert cr.workspace_bytes(1000, 10, cr.Params(precision=cr.F32)) < b1
+    for N, n, status in [(1, 2, cr.ERR_ARG), (10, 0, cr.ERR_ARG), (10, 32, cr.ERR_UNSUPPORTED)]:
+        with pytest.raises(cr.CRError) as e:
+            cr.workspace_bytes(N, n)
+        assert e.value.status == status
+    with pytest.raises(cr.CRError):
+        cr.workspace_bytes(10, 2, cr.Params(gamma=0.0))
+    with pytest.raises(cr.CRError):
+        cr.workspace_bytes(10, 2, cr.Params(c=1.0))
+    with pytest.raises(cr.CRError):
+        cr.workspace_bytes(10, 2, cr.Params(step_scale=1.5))
+    with pytest.raises(cr.CRError):
+        cr.workspace_bytes(10, 2, cr.Params(precision=7))
+
+
+def test_init_rejects_before_touching_the_gpu():
+    cr, lib = _lib()
+    p = cr.Params().to_c()
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)
+    need = cr.workspace_bytes(50, 3)
+    # null output handle, null inputs, bad sizes, small workspace
+    assert lib.cr_init(None, 50, 3, ctypes.byref(p), fake, fake, fake, need, None) == cr.ERR_ARG
+    assert lib.cr_init(ctypes.byref(h), 50, 3, ctypes.byref(p), None, fake, fake, need, None) == cr.ERR_ARG
+    assert lib.cr_init(ctypes.byref(h), 1, 3, ctypes.byref(p), fake, fake, fake, need, None) == cr.ERR_ARG
+    assert lib.cr_init(ctypes.byref(h), 50, 40, ctypes.byref(p), fake, fake, fake, need, None) == cr.ERR_UNSUPPORTED
+    assert lib.cr_init(ctypes.byref(h), 50, 3, ctypes.byref(p), fake, fake, fake, need - 1, None) == cr.ERR_NOMEM
+    assert b"workspace" in lib.cr_last_error(None)
+    assert h.value is None
+    bad = cr.Params(tau1=-1.0).to_c()
+    assert lib.cr_init(ctypes.byref(h), 50, 3, ctypes.byref(bad), fake, fake, fake, need, None) == cr.ERR_ARG
+    # entry points that take a context reject NULL
+    assert lib.cr_pairwise_step(None, 0, fake, fake, fake, fake, 1.0, 2.0) == cr.ERR_ARG
+    assert lib.cr_run(None, fake, fake, None) == cr.ERR_ARG
+    assert lib.cr_destroy(None) == cr.OK
+    assert lib.cr_solve(fake, fake, 50, 3, ctypes.byref(p), None, fake, fake, need, None, None) == cr.ERR_ARG
+
+
+def test_product_package_has_no_oracle_dependency():
+    pkg = os.path.join(ROOT, "paper_1407_7220_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in text.lower() or f == "__init__.py" and "import oracle" not in text, f

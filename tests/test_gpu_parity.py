@@ -1,0 +1,203 @@
+"""GPU parity of the HIP pair engine against the FP64 oracle (through the C ABI).
+
+Every case prints its name, sizes and seed before touching the GPU."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1407_7220_amd as cr
+    return cr
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+# Tolerances: FP64 pass vs FP64 oracle differs only by summation order (~1e-15
+# per term); the FP32 pass rounds theta, r and every in-tile sum to 24 bits.
+TOL_PASS = {0: 1e-12, 1: 3e-5}
+TOL_SOLVE = {0: 1e-9, 1: 1e-5}
+PREC_NAME = {0: "f64", 1: "f32"}
+
+
+def _random_state(N, n, seed, theta_scale=0.3):
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-1, 1, size=(N, n))
+    ybar = np.sum(X * X, axis=1) + 0.1 * rng.normal(size=N)
+    y = ybar + 0.2 * rng.normal(size=N)
+    xi = rng.normal(size=(N, n))
+    theta = theta_scale * np.abs(rng.normal(size=(N, N)))
+    np.fill_diagonal(theta, 0.0)
+    return X, ybar, y, xi, theta
+
+
+SHAPES = [(2, 1), (37, 3), (64, 2), (200, 2), (333, 10), (1000, 5), (517, 20), (300, 31)]
+
+
+@pytest.mark.parametrize("N,n", [(37, 3), (200, 2), (1000, 10), (517, 20), (300, 31)])
+def test_setup_constants(cr, N, n):
+    say("setup_constants N=%d n=%d" % (N, n))
+    p = synth.quadratic_uniform(N, n, seed=N + n)
+    ctx = cr.Context(dev(p.X), dev(p.ybar), cr.Params(gamma=1e-3))
+    info = ctx.info()
+    yhat, xihat, Bbar, By, Bxi = oracle.affine_fit(p.X, p.ybar, 1e-3)
+    assert info.sigma2_A1 == 2.0 * N
+    assert abs(info.sigma2_A2 - oracle.sigma2_A2(p.X)) <= 1e-11 * oracle.sigma2_A2(p.X)
+    assert abs(info.Bbar_y - By) <= 1e-10 * By
+    assert abs(info.Bbar_xi - Bxi) <= 1e-10 * Bxi
+    y0, xi0 = ctx.get_start()
+    assert rel(host(y0), yhat) < 1e-11
+    assert rel(host(xi0), xihat) < 1e-10
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+@pytest.mark.parametrize("N,n", SHAPES)
+def test_grad_pass(cr, prec, N, n):
+    say("grad_pass %s N=%d n=%d" % (PREC_NAME[prec], N, n))
+    X, ybar, y, xi, theta = _random_state(N, n, seed=10 * N + n)
+    gamma, mu = 1e-2, 0.37
+    ctx = cr.Context(dev(X), dev(ybar), cr.Params(gamma=gamma, precision=prec))
+    ctx.set_theta(dev(theta))
+    gy, gxi = ctx.pairwise_step(cr.GRAD, dev(y), dev(xi), mu)
+    ey, exi = oracle.grad_P(X, ybar, gamma, mu, theta, y, xi)
+    # compare the pair part (the (y - ybar)/mu term is exact on both sides)
+    hy, hxi = host(gy), host(gxi)
+    assert rel(hy - (y - ybar) / mu, ey - (y - ybar) / mu) < TOL_PASS[prec]
+    assert rel(hxi - gamma / mu * xi, exi - gamma / mu * xi) < TOL_PASS[prec]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+@pytest.mark.parametrize("N,n", [(37, 3), (200, 2), (640, 10), (517, 20)])
+def test_theta_pass(cr, prec, N, n):
+    say("theta_pass %s N=%d n=%d" % (PREC_NAME[prec], N, n))
+    X, ybar, y, xi, theta = _random_state(N, n, seed=7 * N + n)
+    gamma, mu, mu_next = 1e-2, 0.25, 1.0
+    ctx = cr.Context(dev(X), dev(ybar), cr.Params(gamma=gamma, precision=prec))
+    ctx.set_theta(dev(theta))
+    sy, sxi = ctx.pairwise_step(cr.THETA_UPDATE, dev(y), dev(xi), mu, mu_next)
+    th_new = host(ctx.get_theta())
+    W = oracle.penalty_weights(X, y, xi, theta)
+    assert rel(th_new, (mu / mu_next) * W) < TOL_PASS[prec]
+    lam = mu * W
+    u, v = oracle.adjoint(X, lam)
+    assert rel(host(sy), y - ybar - u) < TOL_PASS[prec] * 10
+    assert rel(host(sxi), gamma * xi - v) < TOL_PASS[prec] * 10
+    m = oracle.kkt_measures(X, ybar, gamma, y, xi, lam)
+    info = ctx.info()
+    t = 1e-10 if prec == 0 else 1e-4
+    assert abs(info.infeas - m["infeas"]) <= t * max(1.0, m["infeas"])
+    assert abs(info.compl - m["compl"]) <= t * max(1.0, m["compl"])
+    assert abs(info.stat_y - m["stat_y"]) <= 10 * t * max(1.0, m["stat_y"])
+    assert abs(info.stat_xi - m["stat_xi"]) <= 10 * t * max(1.0, m["stat_xi"])
+    assert abs(info.infeas_norm - m["infeas_norm"]) <= t * max(1.0, m["infeas_norm"])
+    assert abs(info.gap_norm - m["gap_norm"]) <= t * max(1e-3, abs(m["gap_norm"]))
+
+
+def test_pass_is_deterministic(cr):
+    say("deterministic N=700 n=10")
+    X, ybar, y, xi, theta = _random_state(700, 10, seed=3)
+    ctx = cr.Context(dev(X), dev(ybar), cr.Params(precision=1))
+    ctx.set_theta(dev(theta))
+    a = [host(t) for t in ctx.pairwise_step(cr.GRAD, dev(y), dev(xi), 0.5)]
+    b = [host(t) for t in ctx.pairwise_step(cr.GRAD, dev(y), dev(xi), 0.5)]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+FIXED_C1 = dict(inner_iters=50, max_outer=10)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+def test_fixed_schedule_small_quadratic(cr, prec):
+    say("fixed schedule small_quadratic N=200 n=2 10x50 %s" % PREC_NAME[prec])
+    p = synth.workload("small_quadratic")
+    ref = oracle.alcc(p.X, p.ybar, oracle.Params(**FIXED_C1), record_kkt=False)
+    y, xi, info = cr.solve(dev(p.X), dev(p.ybar), cr.Params(precision=prec, **FIXED_C1))
+    assert info.inner_iters == 500 and info.outer_iters == 10
+    assert rel(host(y), ref.y) < TOL_SOLVE[prec]
+    assert rel(host(xi), ref.xi) < TOL_SOLVE[prec] * 10
+
+
+@pytest.mark.parametrize("N,n,seed", [(37, 3, 1), (130, 5, 2), (96, 20, 3)])
+def test_fixed_schedule_ragged(cr, N, n, seed):
+    say("fixed schedule ragged N=%d n=%d seed=%d" % (N, n, seed))
+    p = synth.quad_l1_gaussian(N, n, seed=seed)
+    sched = dict(inner_iters=20, max_outer=4)
+    ref = oracle.alcc(p.X, p.ybar, oracle.Params(**sched), record_kkt=False)
+    y, xi, info = cr.solve(dev(p.X), dev(p.ybar), cr.Params(precision=0, **sched))
+    assert rel(host(y), ref.y) < 1e-9
+    assert rel(host(xi), ref.xi) < 1e-8
+
+
+def test_constant_data_fixed_point(cr):
+    say("constant data N=50 n=3")
+    p = synth.constant_data(50, 3, value=1.5)
+    y, xi, info = cr.solve(dev(p.X), dev(p.ybar), cr.Params(inner_iters=10, max_outer=2))
+    assert np.max(np.abs(host(y) - 1.5)) < 1e-12
+    assert np.max(np.abs(host(xi))) < 1e-12
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+def test_adaptive_reaches_kkt(cr, prec):
+    say("adaptive N=60 n=2 %s" % PREC_NAME[prec])
+    p = synth.workload("small_quadratic")
+    X, ybar = p.X[:60], p.ybar[:60]
+    y, xi, info = cr.solve(dev(X), dev(ybar), cr.Params(precision=prec, kkt_tol=1e-4))
+    assert info.status == 0 and info.kkt <= 1e-4
+    ref = oracle.alcc(X, ybar, oracle.Params(kkt_tol=1e-6))
+    assert rel(host(y), ref.y) < 1e-3
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+def test_full_size_pass_sampled(cr, prec):
+    """One gradient pass at the 5000-point, n=10 workload, in the launch
+    configuration the benchmark uses; sampled outputs recomputed by the oracle."""
+    say("full-size sampled logsumexp_5000 %s" % PREC_NAME[prec])
+    p = synth.workload("logsumexp_5000")
+    N, n = p.N, p.n
+    rng = np.random.default_rng(5)
+    y = p.ybar + 0.05 * rng.normal(size=N)
+    xi = 0.3 * rng.normal(size=(N, n))
+    theta = 0.02 * np.abs(rng.normal(size=(N, N)))
+    np.fill_diagonal(theta, 0.0)
+    gamma, mu = 1e-3, 1e-4
+    ctx = cr.Context(dev(p.X), dev(p.ybar), cr.Params(gamma=gamma, precision=prec))
+    ctx.set_theta(dev(theta))
+    gy, gxi = ctx.pairwise_step(cr.GRAD, dev(y), dev(xi), mu)
+    hy, hxi = host(gy), host(gxi)
+    tol = 1e-11 if prec == 0 else 2e-4
+    for m in [0, 1, 17, 2500, 4095, 4096, 4998, 4999]:
+        row, col = oracle.residual_row_col(p.X, y, xi, m)
+        wrow = np.maximum(theta[m] - row, 0.0); wrow[m] = 0.0
+        wcol = np.maximum(theta[:, m] - col, 0.0); wcol[m] = 0.0
+        u, v = oracle.adjoint_one(p.X, m, wrow, wcol)
+        scale = wrow.sum() + wcol.sum()
+        assert abs((hy[m] - (y[m] - p.ybar[m]) / mu) - (-u)) <= tol * scale
+        assert np.max(np.abs((hxi[m] - gamma / mu * xi[m]) - (-v))) <= tol * scale * (1 + np.abs(p.X).max())
