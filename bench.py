@@ -1,0 +1,146 @@
+"""Throughput benchmark: constraint-pair updates per second of the ALCC/MAPG
+solve run to KKT <= 1e-4, on one MI355X.
+
+A step is one whole solve (every stage of the hot path: pair passes, MAPG
+steps, multiplier steps and KKT checks) of the 5000-point, n = 10 workload
+(x ~ N(0, I), f0 = log-sum-exp of 20 random affine maps, noise N(0, 0.05^2)),
+with the inputs already resident in device memory.  value = sum over the timed
+steps of N (N - 1) x MAPG iterations / wall seconds.
+
+Also reported on the same JSON line:
+  roofline      the dominant kernel (the gradient pair pass): algorithmic bytes
+                (one theta read per pair) / its average device time, measured
+                with HIP events on the library's stream, against 8 TB/s HBM;
+  cpu_baseline  the FP64 CPU oracle timed on the host cores on a bounded
+                sample of the same workload (a fixed number of MAPG iterations).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision f32|f64]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "constraint-pair updates/s (N(N-1)·iters/s) at KKT<=1e-4, plain vs mixed/batched"
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "logsumexp_5000"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("cr_kernels.hip", "cr_device.h", "cr_api.hip"):
+        with open(os.path.join(ROOT, "paper_1407_7220_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(prec_name: str):
+    """HBM bytes per pass launch from the committed rocprofv3 counter summary,
+    only if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "pair_pass_%s_%s_counters.json" % (prec_name, WORKLOAD))
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(p, budget_s: float):
+    """Oracle MAPG iterations (FP64, C operators + numpy) on the same workload,
+    from the same starting point, until about budget_s seconds have passed."""
+    import numpy as np
+    import oracle
+    gamma = 1e-3
+    yhat, xihat, Bbar, By, Bxi = oracle.affine_fit(p.X, p.ybar, gamma)
+    N = p.N
+    mu = 1.0 / (2.0 * N)
+    Ly = 1.0 / mu + oracle.sigma2_A1(N)
+    Lxi = gamma / mu + oracle.sigma2_A2(p.X)
+    theta = np.zeros((N, N))
+    oracle.mapg(p.X, p.ybar, gamma, mu, theta, Ly, Lxi, yhat, xihat, By, Bxi, 0, 0, 1, adaptive=False)
+    t0 = time.perf_counter()
+    iters = 0
+    y, xi = yhat, xihat
+    while time.perf_counter() - t0 < budget_s:
+        y, xi, _ = oracle.mapg(p.X, p.ybar, gamma, mu, theta, Ly, Lxi, y, xi, By, Bxi, 0, 0, 1, adaptive=False)
+        iters += 1
+    secs = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return {"value": N * (N - 1) * iters / secs, "unit": "pair-updates/s", "cores": cores, "kind": "oracle",
+            "sample": "%d MAPG iterations of the FP64 oracle on %s (N=%d, n=%d), %.1f s" % (
+                iters, WORKLOAD, N, p.n, secs)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=("f32", "f64"), default="f32")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the pair engine runs on a single device "
+              "(the multi-GPU sharding is described in the design notes, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1407_7220_amd as cr
+    import synth
+
+    p = synth.workload(WORKLOAD)
+    prec = cr.F32 if args.precision == "f32" else cr.F64
+    X = torch.from_numpy(p.X).cuda()
+    yb = torch.from_numpy(p.ybar).cuda()
+    params = cr.Params(precision=prec, kkt_tol=1e-4)
+    ctx = cr.Context(X, yb, params)
+
+    for _ in range(args.warmup):
+        ctx.run()
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, info = ctx.run()
+        infos.append(info)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pair_updates = sum(i.pair_updates for i in infos)
+    value = pair_updates / wall
+    converged = all(i.status == 0 and i.kkt <= 1e-4 for i in infos)
+
+    # dominant kernel: the gradient pair pass, timed with HIP events on its own stream
+    pass_ms = ctx.time_pass(50)
+    esz = 4 if prec == cr.F32 else 8
+    alg_bytes = p.N * (p.N - 1) * esz
+    achieved = alg_bytes / (pass_ms * 1e-3) / 1e9
+    traffic = load_traffic(args.precision)
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "k_pair_pass", "avg_ms": pass_ms, "bytes_per_launch": alg_bytes}
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "pair-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": WORKLOAD, "N": p.N, "n": p.n, "precision": args.precision, "kkt_tol": 1e-4,
+                   "mapg_iters_per_solve": infos[-1].inner_iters, "alcc_iters_per_solve": infos[-1].outer_iters,
+                   "final_kkt": infos[-1].kkt, "converged": converged, "gamma": 1e-3},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(p, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

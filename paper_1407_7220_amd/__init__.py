@@ -72,6 +72,7 @@ def _load():
         "cr_set_theta": (i32, [vp, vp]),
         "cr_get_start": (i32, [vp, vp, vp]),
         "cr_get_info": (i32, [vp, pi]),
+        "cr_time_pass": (i32, [vp, i32, i32, ctypes.POINTER(dbl)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -84,7 +85,7 @@ _lib = _load()
 
 EXPORTED = ("cr_params_default", "cr_status_string", "cr_last_error", "cr_workspace_bytes", "cr_init",
             "cr_destroy", "cr_pairwise_step", "cr_run", "cr_solve", "cr_get_theta", "cr_set_theta",
-            "cr_get_start", "cr_get_info")
+            "cr_get_start", "cr_get_info", "cr_time_pass")
 
 
 class CRError(RuntimeError):
@@ -246,6 +247,12 @@ class Context:
         y, xi = self._new(self.N), self._new(self.N, self.n)
         _check(_lib.cr_get_start(self._h, ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(xi.data_ptr())), self._h)
         return y, xi
+
+    def time_pass(self, reps: int = 20) -> float:
+        """Average device milliseconds of one gradient pair pass (HIP events)."""
+        out = ctypes.c_double(0.0)
+        _check(_lib.cr_time_pass(self._h, GRAD, int(reps), ctypes.byref(out)), self._h)
+        return float(out.value)
 
     def info(self) -> Info:
         ci = _CInfo()

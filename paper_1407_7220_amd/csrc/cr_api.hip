@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -29,13 +30,14 @@ struct Layout {
     int strips = 0, chunks = 0, rpc = 0, nb = 0, nsu = 0;
     size_t off_theta, off_xp, off_xiaug, off_ycol, off_rowpart, off_cpart, off_kkt;
     size_t off_y1p, off_y2, off_vy, off_y0, off_xi1p, off_xi2, off_vxi, off_xi0;
-    size_t off_blockpart, off_supart, off_su, off_oa, off_st;
+    size_t off_blockpart, off_supart, off_su, off_oa, off_st, off_beta;
+    int64_t nbeta = 0;
     size_t total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-Layout make_layout(int64_t N, int n, int precision) {
+Layout make_layout(int64_t N, int n, int precision, int64_t max_iters) {
     Layout L;
     L.N = N;
     L.n = n;
@@ -50,14 +52,15 @@ Layout make_layout(int64_t N, int n, int precision) {
     L.strips = (int)(L.ld / (16 * L.tw));
     // Enough workgroups to fill 256 CUs several times over, but long enough
     // row chunks that the per-chunk column partials stay small.
-    const int64_t target = 2048;
+    int64_t target = 768;
+    if (const char* tw = std::getenv("CR_TARGET_WGS")) target = std::max(1L, std::atol(tw));
     int64_t chunks = (target + L.strips - 1) / L.strips;
     chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, L.Nrow / 64));
     int64_t rpc = (L.Nrow + chunks - 1) / chunks;
     rpc = ((rpc + 63) / 64) * 64;
     L.rpc = (int)rpc;
     L.chunks = (int)((L.Nrow + rpc - 1) / rpc);
-    L.nb = (int)((L.ld + cr::kBlock - 1) / cr::kBlock);
+    L.nb = (int)((L.ld * 32 + cr::kBlock - 1) / cr::kBlock);  // blocks of the O(N n) kernels (32 lanes per point)
     L.nsu = (int)((N + 1023) / 1024);
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
@@ -81,6 +84,8 @@ Layout make_layout(int64_t N, int n, int precision) {
     L.off_su = take((size_t)(3 * n + 2 + n * n + 8) * 8);
     L.off_oa = take(sizeof(cr::OuterArgs));
     L.off_st = take(sizeof(cr::DevState));
+    L.nbeta = max_iters + 2 * kGraphIters + 2;
+    L.off_beta = take((size_t)L.nbeta * 8);
     L.total = o + 256;  // slack for re-aligning an unaligned base
     return L;
 }
@@ -103,6 +108,9 @@ bool check_params(const cr_params* p, std::string& msg) {
     if (p->precision == CR_MIXED_BF16) { msg = "CR_MIXED_BF16 is not available in this build"; return false; }
     return true;
 }
+
+// Longest MAPG run of any ALCC iteration: the length of the momentum table.
+int64_t max_mapg_iters(const cr_params& p) { return p.inner_iters > 0 ? p.inner_iters : p.max_inner; }
 
 cr_status check_dims(int64_t N, int32_t n, std::string& msg) {
     if (N < 2) { msg = "N must be >= 2"; return CR_ERR_ARG; }
@@ -135,6 +143,7 @@ struct cr_ctx {
     std::string err;
     cr::DevState last{};
     bool have_kkt = false;
+    bool verbose = false;
     char* P(size_t off) const { return ws + off; }
     double* D(size_t off) const { return reinterpret_cast<double*>(ws + off); }
 };
@@ -191,23 +200,27 @@ static cr::UpdateArgs update_args(cr_ctx* c) {
     const Layout& L = c->L;
     cr::UpdateArgs a{};
     a.N = L.N; a.ld = L.ld; a.n = L.n; a.kp = L.kp;
-    a.X = c->X; a.ybar = c->ybar; a.vy = c->D(L.off_vy); a.vxi = c->D(L.off_vxi);
+    a.X = c->X; a.ybar = c->ybar; a.vy = c->D(L.off_vy); a.vxi = c->D(L.off_vxi); a.beta = c->D(L.off_beta);
     a.y1p = c->D(L.off_y1p); a.y2 = c->D(L.off_y2); a.xi1p = c->D(L.off_xi1p); a.xi2 = c->D(L.off_xi2);
     a.xiaug = c->P(L.off_xiaug); a.ycol = c->P(L.off_ycol);
     a.blockpart = c->D(L.off_blockpart); a.oa = c->oa; a.st = c->st;
     return a;
 }
 
-// One MAPG iteration: pair pass at (y2, xi2), gradient step, projection and momentum.
-static hipError_t enqueue_mapg_iteration(cr_ctx* c, hipStream_t s) {
+// One MAPG iteration (position q of a replay): pair pass at (y2, xi2), the
+// stopping test of the previous iteration plus the gradient step, then
+// projection and momentum.
+static hipError_t enqueue_mapg_iteration(cr_ctx* c, int q, hipStream_t s) {
     const Layout& L = c->L;
     cr::PassArgs pa = pass_args(c, 0, 0.0, &c->st->active);
     hipError_t e = cr::launch_pair_pass(c->f64, L.ks, pa, pass_grid(L), s);
     if (e != hipSuccess) return e;
     cr::ReduceArgs ra = reduce_args(c, 0, c->D(L.off_y2), c->D(L.off_xi2), c->D(L.off_vy), c->D(L.off_vxi), 0.0);
+    ra.q = q;
     e = cr::launch_reduce(c->f64, ra, s);
     if (e != hipSuccess) return e;
     cr::UpdateArgs ua = update_args(c);
+    ua.q = q;
     return cr::launch_update(c->f64, ua, s);
 }
 
@@ -216,7 +229,8 @@ static cr_status build_graph(cr_ctx* c) {
     hipGraph_t g = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->cs, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int q = 0; q < kGraphIters && e == hipSuccess; ++q) e = enqueue_mapg_iteration(c, c->cs);
+    for (int q = 0; q < kGraphIters && e == hipSuccess; ++q) e = enqueue_mapg_iteration(c, q, c->cs);
+    if (e == hipSuccess) e = cr::launch_replay_end(c->st, kGraphIters, c->cs);
     hipError_t e2 = hipStreamEndCapture(c->cs, &g);
     if (e != hipSuccess) return fail(c, CR_ERR_HIP, std::string("capture: ") + hipGetErrorString(e));
     if (e2 != hipSuccess) return fail(c, CR_ERR_HIP, std::string("end capture: ") + hipGetErrorString(e2));
@@ -269,7 +283,7 @@ cr_status cr_workspace_bytes(int64_t N, int32_t n, const cr_params* params, size
     cr_status s = check_dims(N, n, msg);
     if (s != CR_OK) return fail(nullptr, s, msg);
     if (!check_params(params, msg)) return fail(nullptr, CR_ERR_ARG, msg);
-    *bytes = make_layout(N, n, params->precision).total;
+    *bytes = make_layout(N, n, params->precision, max_mapg_iters(*params)).total;
     return CR_OK;
 }
 
@@ -282,7 +296,7 @@ cr_status cr_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params, c
     if (s != CR_OK) return fail(nullptr, s, msg);
     if (!check_params(params, msg)) return fail(nullptr, CR_ERR_ARG, msg);
     if (!X_dev || !ybar_dev || !workspace_dev) return fail(nullptr, CR_ERR_ARG, "X, ybar and workspace must be non-NULL");
-    Layout L = make_layout(N, n, params->precision);
+    Layout L = make_layout(N, n, params->precision, max_mapg_iters(*params));
     if (ws_bytes < L.total) return fail(nullptr, CR_ERR_NOMEM, "workspace smaller than cr_workspace_bytes()");
 
     cr_ctx* c = new (std::nothrow) cr_ctx();
@@ -293,6 +307,10 @@ cr_status cr_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params, c
     c->n = n;
     c->f64 = params->precision == CR_F64;
     c->user_stream = (hipStream_t)stream;
+    {
+        const char* v = std::getenv("CR_VERBOSE");
+        c->verbose = v && v[0] && v[0] != '0';
+    }
     c->X = (const double*)X_dev;
     c->ybar = (const double*)ybar_dev;
     c->ws = (char*)align256((size_t)workspace_dev);
@@ -324,6 +342,24 @@ cr_status cr_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params, c
         e = cr::launch_setup(c->X, c->ybar, N, n, params->gamma, c->D(L.off_su), c->D(L.off_supart), c->D(L.off_y0),
                              c->D(L.off_xi0), c->st, cs);
     if (e == hipSuccess) e = cr::launch_prep_xp(c->f64, c->X, N, n, L.Nrow, L.ks, L.qp, c->P(L.off_xp), cs);
+    if (e == hipSuccess) {
+        // momentum weights of Fig. 4: t_1 = 1, t_{l+1} = (1 + sqrt(1 + 4 t_l^2)) / 2,
+        // beta_l = (t_l - 1) / t_{l+1}; entry 0 is unused
+        double* hb = nullptr;
+        e = hipHostMalloc((void**)&hb, (size_t)L.nbeta * 8, hipHostMallocDefault);
+        if (e == hipSuccess) {
+            double t = 1.0;
+            hb[0] = 0.0;
+            for (int64_t l = 1; l < L.nbeta; ++l) {
+                const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+                hb[l] = (t - 1.0) / tn;
+                t = tn;
+            }
+            e = hipMemcpyAsync(c->P(L.off_beta), hb, (size_t)L.nbeta * 8, hipMemcpyHostToDevice, cs);
+            if (e == hipSuccess) e = hipStreamSynchronize(cs);
+            hipHostFree(hb);
+        }
+    }
     if (e == hipSuccess) {
         cr::PointArgs pa = point_args(c, c->D(L.off_y0), c->D(L.off_xi0), 1);
         e = cr::launch_set_point(c->f64, pa, cs);
@@ -493,6 +529,7 @@ cr_status cr_run(cr_ctx* c, void* y_dev, void* xi_dev, cr_info* info) {
             pending = slot;
             slot ^= 1;
         }
+        HIPCHK(c, cr::launch_mapg_end(c->D(L.off_blockpart), cr::reduce_blocks(N, c->n), launched, c->st, cs));
         // multiplier step at the MAPG output (y_k, xi_k), which also restarts MAPG there
         cr::PointArgs pt = point_args(c, c->D(L.off_y1p), c->D(L.off_xi1p), 1);
         HIPCHK(c, cr::launch_set_point(c->f64, pt, cs));
@@ -508,6 +545,11 @@ cr_status cr_run(cr_ctx* c, void* y_dev, void* xi_dev, cr_info* info) {
         if (h.iterate_nonfinite) { result = CR_ERR_NONFINITE; break; }
         cr_info tmp{};
         fill_info(c, h, &tmp);
+        if (c->verbose)
+            std::fprintf(stderr, "[cr] outer %d mu %.3e inner %lld (alpha stop %d) kkt %.3e stat_y %.2e stat_xi %.2e "
+                         "infeas %.2e compl %.2e obj %.6e t %.3fs\n",
+                         k, mu, (long long)h.it, h.stopped_by_alpha, tmp.kkt, h.stat_y, h.stat_xi, h.infeas, h.compl_,
+                         h.obj, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
         if (!fixed && tmp.kkt <= p.kkt_tol) { converged = true; break; }
         const double decay = std::pow(p.c * std::pow((double)k, 1.0 + p.kappa), 2.0);
         mu = mu_next;
@@ -531,6 +573,27 @@ cr_status cr_run(cr_ctx* c, void* y_dev, void* xi_dev, cr_info* info) {
     }
     if (result == CR_ERR_NONFINITE) return fail(c, result, "non-finite iterate");
     return result;
+}
+
+cr_status cr_time_pass(cr_ctx* c, int32_t mode, int32_t reps, double* avg_ms) {
+    if (!c || !avg_ms) return fail(c, CR_ERR_ARG, "ctx and avg_ms must be non-NULL");
+    if (reps < 1 || mode != CR_GRAD) return fail(c, CR_ERR_ARG, "reps must be >= 1 and mode CR_GRAD");
+    const Layout& L = c->L;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    cr::PassArgs pa = pass_args(c, 0, 0.0, &c->st->one);
+    hipError_t e = hipEventRecord(e0, c->cs);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = cr::launch_pair_pass(c->f64, L.ks, pa, pass_grid(L), c->cs);
+    if (e == hipSuccess) e = hipEventRecord(e1, c->cs);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(c, CR_ERR_HIP, std::string("time pass: ") + hipGetErrorString(e));
+    *avg_ms = (double)ms / reps;
+    return CR_OK;
 }
 
 cr_status cr_solve(const void* X_dev, const void* ybar_dev, int64_t N, int32_t n, const cr_params* params,

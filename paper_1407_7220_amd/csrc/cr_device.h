@@ -29,10 +29,9 @@ struct DevState {
     double ybar_mean, ybar_inf, sigma2_A2, Bbar, aff_b, pad_c;
     int32_t nonfinite, one;           // `one` stays 1: the activity flag of stand-alone passes
     // MAPG loop
-    double t;                         // momentum scalar t_l
-    int64_t it;                       // MAPG iterations done in this ALCC iteration
+    int64_t base;                     // iterations launched before the current graph replay
+    int64_t it;                       // MAPG iterations done in this ALCC iteration (set at the stop)
     int32_t active, stopped_by_alpha;
-    double scale_y, scale_xi;         // ball projection factors of the current step
     double dy, dxi;                   // ||y1 - y2||, ||xi1 - xi2|| of the last step
     // KKT of the last multiplier step
     double stat_y, stat_xi, infeas, compl_, infeas_sq, gap, obj, xi_sq;
@@ -77,6 +76,7 @@ struct PassArgs {
 struct ReduceArgs {
     int64_t N, Nrow, ld;
     int32_t n, nc, strips, chunks, mode, npass;   // mode 0 MAPG step, 1 gradient out, 2 KKT
+    int32_t q, pad;           // mode 0: position of the iteration in the captured replay
     const void* rowpart;
     const void* cpart;
     const double* X;
@@ -85,7 +85,7 @@ struct ReduceArgs {
     const double* xi;
     double* out_y;
     double* out_xi;
-    double* blockpart;        // gridDim.x x 4
+    double* blockpart;        // gridDim.x x 4 (one record per block)
     const double* kktpart;    // npass x 4 (mode 2)
     const OuterArgs* oa;
     DevState* st;
@@ -96,6 +96,8 @@ struct ReduceArgs {
 struct UpdateArgs {
     int64_t N, ld;
     int32_t n, kp;
+    int32_t q, pad;           // position of the iteration in the captured replay
+    const double* beta;       // beta[l] = (t_l - 1) / t_{l+1}, l = 1, 2, ... (momentum of Fig. 4)
     const double* X;
     const double* ybar;
     const double* vy;
@@ -131,6 +133,9 @@ hipError_t launch_reduce(bool f64, const ReduceArgs& a, hipStream_t s);
 hipError_t launch_update(bool f64, const UpdateArgs& a, hipStream_t s);
 hipError_t launch_set_point(bool f64, const PointArgs& a, hipStream_t s);
 hipError_t launch_begin_outer(const OuterArgs& args, OuterArgs* dst, DevState* st, hipStream_t s);
+hipError_t launch_replay_end(DevState* st, int iters, hipStream_t s);
+hipError_t launch_mapg_end(const double* blockpart, int nblk, int64_t launched, DevState* st, hipStream_t s);
+int reduce_blocks(int64_t N, int n);
 hipError_t launch_prep_xp(bool f64, const double* X, int64_t N, int n, int64_t Nrow, int ks, int qp, void* xp,
                           hipStream_t s);
 hipError_t launch_theta_import(bool f64, const double* src, int64_t N, int64_t Nrow, int64_t ld, void* theta,

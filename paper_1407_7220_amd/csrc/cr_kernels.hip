@@ -51,6 +51,29 @@ template <typename T> __host__ __device__ constexpr int rmap(int g, int v) {
 
 template <typename T> struct alignas(16) V16 { T v[16 / sizeof(T)]; };
 
+// Sum over each 16-lane row of the wave with DPP moves (every lane of the row
+// receives the total): pairs (quad_perm 1,0,3,2), quads (quad_perm 2,3,0,1),
+// half rows (row_half_mirror), full row (row_mirror).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T>
+__device__ __forceinline__ T row16_sum(T v) {
+    v += dpp_f<0xB1>(v);
+    v += dpp_f<0x4E>(v);
+    v += dpp_f<0x141>(v);
+    v += dpp_f<0x140>(v);
+    return v;
+}
+
 template <typename T>
 __device__ __forceinline__ V16<T> ld16(const T* p) { return *reinterpret_cast<const V16<T>*>(p); }
 template <typename T>
@@ -149,15 +172,16 @@ __global__ __launch_bounds__(kBlock) void k_pair_pass(PassArgs a) {
 
     double k_rneg_max = 0.0, k_rneg_sq = 0.0, k_wr_max = 0.0, k_wr_sum = 0.0;
 
-    for (int64_t i0 = I0 + 16 * wave; i0 < I1; i0 += 16 * kWaves) {
-        T xop[QP];
+    // Operands of one 16-row tile: packed X (L2-resident), y_i, and the
+    // wave's 16 x 16TW block of theta (HBM stream).  NSET register sets rotate
+    // so that each tile's loads are issued NSET - 1 tiles ahead of its use.
+    auto load_tile = [&](int64_t i0, T* xop, T* yv, V16<T>* th) {
 #pragma unroll
         for (int q = 0; q < QP / EV; ++q) {
             V16<T> tv = ld16(xp + ((i0 >> 4) * 64 + lane) * QP + q * EV);
 #pragma unroll
             for (int e = 0; e < EV; ++e) xop[q * EV + e] = tv.v[e];
         }
-        T yv[4];
         if (sizeof(T) == 4) {
             V16<T> tv = ld16(ycol + i0 + 4 * g);
 #pragma unroll
@@ -166,98 +190,116 @@ __global__ __launch_bounds__(kBlock) void k_pair_pass(PassArgs a) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) yv[v] = ycol[i0 + rmap<T>(g, v)];
         }
-        V16<T> th[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) th[v] = ld16(theta + (i0 + rmap<T>(g, v)) * a.ld + jl);
+    };
 
-        // residual tiles R_t (accumulator initialised with y_i)
-        acc_t R[TW];
-#pragma unroll
-        for (int t = 0; t < TW; ++t) {
-            R[t] = acc_t{yv[0], yv[1], yv[2], yv[3]};
-#pragma unroll
-            for (int s = 0; s < KS; ++s) R[t] = mfma4(xop[s], breg[s][t], R[t]);
-        }
-
-        // w = max(theta - r, 0); explicit zero off the constraint set
-        T W[TW][4];
-#pragma unroll
-        for (int t = 0; t < TW; ++t)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                T d = th[v].v[t] - R[t][v];
-                W[t][v] = d > (T)0 ? d : (T)0;
+    auto process = [&](const int64_t i0, const T* xop, const T* yv, const V16<T>* th) {
+            // residual tiles R_t (accumulator initialised with y_i)
+            acc_t R[TW];
+    #pragma unroll
+            for (int t = 0; t < TW; ++t) {
+                R[t] = acc_t{yv[0], yv[1], yv[2], yv[3]};
+    #pragma unroll
+                for (int s = 0; s < KS; ++s) R[t] = mfma4(xop[s], breg[s][t], R[t]);
             }
-        const bool edge = (i0 < J0 + 16 * TW && i0 + 16 > J0) || (J0 + 16 * TW > a.N) || (i0 + 16 > a.N);
-        if (edge) {
-#pragma unroll
+
+            // w = max(theta - r, 0); explicit zero off the constraint set
+            T W[TW][4];
+    #pragma unroll
             for (int t = 0; t < TW; ++t)
-#pragma unroll
+    #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int64_t i = i0 + rmap<T>(g, v), j = jl + t;
-                    if (!(i < a.N && j < a.N && i != j)) W[t][v] = (T)0;
+                    T d = th[v].v[t] - R[t][v];
+                    W[t][v] = d > (T)0 ? d : (T)0;
                 }
-        }
-
-        if (theta_mode) {
-            // Fig. 3 step 4 in place, and the pair terms of the KKT residual
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                V16<T> o;
-#pragma unroll
-                for (int t = 0; t < TW; ++t) o.v[t] = (T)(a.theta_scale * (double)W[t][v]);
-                st16(theta + (i0 + rmap<T>(g, v)) * a.ld + jl, o);
-            }
-#pragma unroll
-            for (int t = 0; t < TW; ++t)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int64_t i = i0 + rmap<T>(g, v), j = jl + t;
-                    if (i < a.N && j < a.N && i != j) {
-                        const double r = (double)R[t][v];
-                        const double rn = r < 0.0 ? -r : 0.0;
-                        const double wr = (double)W[t][v] * r;
-                        k_rneg_max = fmax(k_rneg_max, rn);
-                        k_rneg_sq += rn * rn;
-                        k_wr_max = fmax(k_wr_max, fabs(wr));
-                        k_wr_sum += wr;
+            const bool edge = (i0 < J0 + 16 * TW && i0 + 16 > J0) || (J0 + 16 * TW > a.N) || (i0 + 16 > a.N);
+            if (edge) {
+    #pragma unroll
+                for (int t = 0; t < TW; ++t)
+    #pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int64_t i = i0 + rmap<T>(g, v), j = jl + t;
+                        if (!(i < a.N && j < a.N && i != j)) W[t][v] = (T)0;
                     }
-                }
-        }
-
-        // C += W^T [X 1]: i-slot g of step s is row i0 + rmap(g, s)
-#pragma unroll
-        for (int t = 0; t < TW; ++t)
-#pragma unroll
-            for (int kb = 0; kb < NKB; ++kb)
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    cacc[t][kb] = mfma4(W[t][s], xop[KS + 4 * kb + s], cacc[t][kb]);
-
-        // row sums over this workgroup's columns
-        T rs[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            T s = W[0][v];
-#pragma unroll
-            for (int t = 1; t < TW; ++t) s += W[t][v];
-            s += __shfl_xor(s, 8);
-            s += __shfl_xor(s, 4);
-            s += __shfl_xor(s, 2);
-            s += __shfl_xor(s, 1);
-            rs[v] = s;
-        }
-        if (c == 0) {
-            T* dst = (T*)a.rowpart + (int64_t)blockIdx.x * a.Nrow + i0;
-            if (sizeof(T) == 4) {
-                V16<T> o;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) o.v[e] = rs[e];
-                st16(dst + 4 * g, o);
-            } else {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) dst[rmap<T>(g, v)] = rs[v];
             }
+
+            if (theta_mode) {
+                // Fig. 3 step 4 in place, and the pair terms of the KKT residual
+    #pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    V16<T> o;
+    #pragma unroll
+                    for (int t = 0; t < TW; ++t) o.v[t] = (T)(a.theta_scale * (double)W[t][v]);
+                    st16(theta + (i0 + rmap<T>(g, v)) * a.ld + jl, o);
+                }
+    #pragma unroll
+                for (int t = 0; t < TW; ++t)
+    #pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int64_t i = i0 + rmap<T>(g, v), j = jl + t;
+                        if (i < a.N && j < a.N && i != j) {
+                            const double r = (double)R[t][v];
+                            const double rn = r < 0.0 ? -r : 0.0;
+                            const double wr = (double)W[t][v] * r;
+                            k_rneg_max = fmax(k_rneg_max, rn);
+                            k_rneg_sq += rn * rn;
+                            k_wr_max = fmax(k_wr_max, fabs(wr));
+                            k_wr_sum += wr;
+                        }
+                    }
+            }
+
+            // C += W^T [X 1]: i-slot g of step s is row i0 + rmap(g, s)
+    #pragma unroll
+            for (int t = 0; t < TW; ++t)
+    #pragma unroll
+                for (int kb = 0; kb < NKB; ++kb)
+    #pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        cacc[t][kb] = mfma4(W[t][s], xop[KS + 4 * kb + s], cacc[t][kb]);
+
+            // row sums over this workgroup's columns (16-lane DPP reduction)
+            T rs[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                T s = W[0][v];
+#pragma unroll
+                for (int t = 1; t < TW; ++t) s += W[t][v];
+                rs[v] = row16_sum(s);
+            }
+            if (c == 0) {
+                // rowpart[strip][i]: the 16 row sums of a tile are contiguous
+                T* dst = (T*)a.rowpart + (int64_t)blockIdx.x * a.Nrow + i0;
+                if (sizeof(T) == 4) {
+                    V16<T> o;
+    #pragma unroll
+                    for (int e = 0; e < 4; ++e) o.v[e] = rs[e];
+                    st16(dst + 4 * g, o);
+                } else {
+    #pragma unroll
+                    for (int v = 0; v < 4; ++v) dst[rmap<T>(g, v)] = rs[v];
+                }
+            }
+    };
+
+    constexpr int64_t step = 16 * kWaves;
+    constexpr int NSET = sizeof(T) == 4 ? 3 : 2;   // staging sets (tiles in flight per wave)
+    // Tiles of this wave: rows I0 + 16 wave + step m < I1 (at least one, since
+    // I1 - I0 >= 64).  Prefetches are unconditional, clamped to the last tile,
+    // so the compiler can count outstanding loads exactly.
+    const int64_t first = I0 + 16 * wave;
+    const int ntile = (int)((I1 - first + step - 1) / step);
+    auto row_of = [&](int m) { return first + step * (int64_t)(m < ntile ? m : ntile - 1); };
+    T xs[NSET][QP], ys[NSET][4];
+    V16<T> ts[NSET][4];
+#pragma unroll
+    for (int b = 0; b < NSET; ++b) load_tile(row_of(b), xs[b], ys[b], ts[b]);
+    for (int m = 0; m < ntile; m += NSET) {
+#pragma unroll
+        for (int b = 0; b < NSET; ++b) {
+            if (m + b < ntile) process(row_of(m + b), xs[b], ys[b], ts[b]);
+            load_tile(row_of(m + b + NSET), xs[b], ys[b], ts[b]);
         }
     }
 
@@ -277,6 +319,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_pass(PassArgs a) {
         const T s = ((cl[0][t][kb][v][ln] + cl[1][t][kb][v][ln]) + cl[2][t][kb][v][ln]) + cl[3][t][kb][v][ln];
         const int64_t j = J0 + TW * rmap<T>(ln >> 4, v) + t;
         const int kk = 16 * kb + (ln & 15);
+        // cpart[chunk][j][k]: this workgroup's columns are one contiguous range
         if (kk < a.nc) cpart[((int64_t)blockIdx.y * a.ld + j) * a.nc + kk] = s;
     }
 
@@ -301,11 +344,54 @@ __global__ __launch_bounds__(kBlock) void k_pair_pass(PassArgs a) {
 // Sum of the pass partials for point j and the gradient / MAPG step / KKT.
 // ---------------------------------------------------------------------------
 
-template <typename T>
+// A group of G lanes (G >= n + 1, a power of two dividing 64) owns one point j:
+// lane k < n handles xi_jk, lane n handles y_j; the partial sums of point j are
+// contiguous, so every group reads them with unit stride.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Sum (op 0) or max (op 1) of field q of the first `count` 4-double records,
+// by all threads of the block in a fixed order.
+__device__ double block_gather(const double* part, int count, int q, int op) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < count; b += kBlock) {
+        const double x = ld_coherent(part + (int64_t)b * 4 + q);
+        v = op == 0 ? v + x : fmax(v, x);
+    }
+    return block_reduce(v, op);
+}
+
+template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) {
     DevState* st = a.st;
-    if (a.mode == 0 && st->active == 0) return;
-    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (a.mode == 0) {
+        if (st->active == 0) return;
+        // Fig. 4 steps 6-9 for the previous iteration l - 1, from the block
+        // pieces that k_update left: every block takes the same decision.
+        const int64_t l = st->base + a.q + 1;
+        if (l > 1) {
+            const double dy = sqrt(block_gather(a.blockpart, gridDim.x, 2, 0));
+            const double dxi = sqrt(block_gather(a.blockpart, gridDim.x, 3, 0));
+            const bool alpha_stop = a.oa->adaptive && dy <= a.oa->alpha_y && dxi <= a.oa->alpha_xi;
+            if (alpha_stop || l - 1 >= a.oa->lmax) {
+                if (blockIdx.x == 0 && threadIdx.x == 0) {
+                    st->active = 0;
+                    st->it = l - 1;
+                    st->stopped_by_alpha = alpha_stop ? 1 : 0;
+                    st->dy = dy;
+                    st->dxi = dxi;
+                }
+                return;
+            }
+        }
+    }
+    constexpr int PER = kBlock / G;
+    const int k = threadIdx.x % G;
+    const int64_t j = (int64_t)blockIdx.x * PER + threadIdx.x / G;
     const bool valid = j < a.N;
     const T* rowpart = (const T*)a.rowpart;
     const T* cpart = (const T*)a.cpart;
@@ -316,12 +402,22 @@ __global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) {
     } else {
         mu = a.mu; gamma = a.gamma;
     }
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    double rs = 0.0, ck = 0.0;
     if (valid) {
-        double rs = 0.0;
-        for (int s = 0; s < a.strips; ++s) rs += (double)rowpart[(int64_t)s * a.Nrow + j];
-        double cs = 0.0;
-        for (int h = 0; h < a.chunks; ++h) cs += (double)cpart[((int64_t)h * a.ld + j) * nc + n];
+#pragma unroll 4
+        for (int q = k; q < a.strips; q += G) rs += (double)rowpart[(int64_t)q * a.Nrow + j];
+        if (k < nc) {
+            const T* cp = cpart + j * nc + k;
+#pragma unroll 4
+            for (int h = 0; h < a.chunks; ++h) ck += (double)cp[(int64_t)h * a.ld * nc];
+        }
+    }
+    rs = group_sum<G>(rs);
+    const int base = (threadIdx.x & 63) & ~(G - 1);
+    const double cs = __shfl(ck, base + n);      // colsum_j = sum_i w_ij
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    bool bad = false;
+    if (valid && k == n) {
         const double yj = a.y[j], ybj = a.ybar[j];
         if (a.mode == 0) {
             const double gy = (yj - ybj) / mu - rs + cs;
@@ -335,72 +431,53 @@ __global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) {
             if (a.out_y) a.out_y[j] = sty;
             acc0 = fabs(sty);
             acc2 = (yj - ybj) * (yj - ybj);
+            bad = !isfinite(yj);
         }
-        for (int k = 0; k < n; ++k) {
-            double ck = 0.0;
-            for (int h = 0; h < a.chunks; ++h) ck += (double)cpart[((int64_t)h * a.ld + j) * nc + k];
-            const double xjk = a.X[j * n + k], xik = a.xi[j * n + k];
-            const double aw = ck - cs * xjk;          // -(A2^T w)_j
-            if (a.mode == 0) {
-                const double gx = (gamma / mu) * xik + aw;
-                const double vx = xik - sxi * gx;
-                a.out_xi[j * n + k] = vx;
-                acc1 += vx * vx;
-            } else if (a.mode == 1) {
-                a.out_xi[j * n + k] = (gamma / mu) * xik + aw;
-            } else {
-                const double stx = gamma * xik + mu * aw;
-                if (a.out_xi) a.out_xi[j * n + k] = stx;
-                acc1 = fmax(acc1, fabs(stx));
-                acc3 += xik * xik;
-            }
+    } else if (valid && k < n) {
+        const double xjk = a.X[j * n + k], xik = a.xi[j * n + k];
+        const double aw = ck - cs * xjk;          // -(A2^T w)_jk
+        if (a.mode == 0) {
+            const double gx = (gamma / mu) * xik + aw;
+            const double vx = xik - sxi * gx;
+            a.out_xi[j * n + k] = vx;
+            acc1 = vx * vx;
+        } else if (a.mode == 1) {
+            a.out_xi[j * n + k] = (gamma / mu) * xik + aw;
+        } else {
+            const double stx = gamma * xik + mu * aw;
+            if (a.out_xi) a.out_xi[j * n + k] = stx;
+            acc1 = fabs(stx);
+            acc3 = xik * xik;
+            bad = !isfinite(xik);
         }
     }
     if (a.mode == 1) return;
     if (a.mode == 0) {
+        // per-block pieces of ||v_y - ybar||^2 and ||v_xi||^2; k_update combines them
         const double b0 = block_reduce(acc0, 0), b1 = block_reduce(acc1, 0);
         if (threadIdx.x == 0) { a.blockpart[blockIdx.x * 4 + 0] = b0; a.blockpart[blockIdx.x * 4 + 1] = b1; }
-        if (last_block(&st->cnt[0])) {
-            if (threadIdx.x == 0) {
-                double ny = 0.0, nx = 0.0;
-                for (unsigned b = 0; b < gridDim.x; ++b) {
-                    ny += ld_coherent(a.blockpart + b * 4 + 0);
-                    nx += ld_coherent(a.blockpart + b * 4 + 1);
-                }
-                ny = sqrt(ny); nx = sqrt(nx);
-                st->scale_y = ny > a.oa->By ? a.oa->By / ny : 1.0;
-                st->scale_xi = nx > a.oa->Bxi ? a.oa->Bxi / nx : 1.0;
-            }
-        }
         return;
     }
     // mode 2: KKT residuals of the multiplier step
-    const bool bad = valid && !(isfinite(a.y[j]));
     const double b0 = block_reduce(acc0, 1), b1 = block_reduce(acc1, 1);
     const double b2 = block_reduce(acc2, 0), b3 = block_reduce(acc3, 0);
     const double bb = block_reduce(bad ? 1.0 : 0.0, 1);
     if (threadIdx.x == 0) {
-        a.blockpart[blockIdx.x * 4 + 0] = fmax(b0, bb > 0 ? INFINITY : 0.0);
+        a.blockpart[blockIdx.x * 4 + 0] = b0;
         a.blockpart[blockIdx.x * 4 + 1] = b1;
         a.blockpart[blockIdx.x * 4 + 2] = b2;
-        a.blockpart[blockIdx.x * 4 + 3] = b3;
+        a.blockpart[blockIdx.x * 4 + 3] = bb > 0.0 ? INFINITY : b3;
     }
     if (last_block(&st->cnt[1])) {
+        const double m0 = block_gather(a.blockpart, gridDim.x, 0, 1);
+        const double m1 = block_gather(a.blockpart, gridDim.x, 1, 1);
+        const double s2 = block_gather(a.blockpart, gridDim.x, 2, 0);
+        const double s3 = block_gather(a.blockpart, gridDim.x, 3, 0);
+        const double p0 = block_gather(a.kktpart, a.npass, 0, 1);
+        const double p1 = block_gather(a.kktpart, a.npass, 1, 0);
+        const double p2 = block_gather(a.kktpart, a.npass, 2, 1);
+        const double p3 = block_gather(a.kktpart, a.npass, 3, 0);
         if (threadIdx.x == 0) {
-            double m0 = 0.0, m1 = 0.0, s2 = 0.0, s3 = 0.0;
-            for (unsigned b = 0; b < gridDim.x; ++b) {
-                m0 = fmax(m0, ld_coherent(a.blockpart + b * 4 + 0));
-                m1 = fmax(m1, ld_coherent(a.blockpart + b * 4 + 1));
-                s2 += ld_coherent(a.blockpart + b * 4 + 2);
-                s3 += ld_coherent(a.blockpart + b * 4 + 3);
-            }
-            double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
-            for (int q = 0; q < a.npass; ++q) {
-                p0 = fmax(p0, a.kktpart[q * 4 + 0]);
-                p1 += a.kktpart[q * 4 + 1];
-                p2 = fmax(p2, a.kktpart[q * 4 + 2]);
-                p3 += a.kktpart[q * 4 + 3];
-            }
             st->stat_y = m0;
             st->stat_xi = m1;
             st->obj = 0.5 * s2;
@@ -419,61 +496,69 @@ __global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) {
 // stopping test, and the pass-precision operands of the next pass.
 // ---------------------------------------------------------------------------
 
-template <typename T>
+template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
     DevState* st = a.st;
     if (st->active == 0) return;
-    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    constexpr int PER = kBlock / G;
+    const int k = threadIdx.x % G;
+    const int64_t j = (int64_t)blockIdx.x * PER + threadIdx.x / G;
+    const bool valid = j < a.N;
     const int n = a.n;
-    const double t = st->t;
-    const double t_next = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
-    const double beta = (t - 1.0) / t_next;
-    const double sc_y = st->scale_y, sc_xi = st->scale_xi;
-    double dy2 = 0.0, dx2 = 0.0;
-    if (j < a.N) {
+    const double beta = a.beta[st->base + a.q + 1];   // (t_l - 1) / t_{l+1}
+    // ball projections (Fig. 4 steps 1-2): every block forms the same norms
+    const double ny = sqrt(block_gather(a.blockpart, gridDim.x, 0, 0));
+    const double nx = sqrt(block_gather(a.blockpart, gridDim.x, 1, 0));
+    const double sc_y = ny > a.oa->By ? a.oa->By / ny : 1.0;
+    const double sc_xi = nx > a.oa->Bxi ? a.oa->Bxi / nx : 1.0;
+    double dy2 = 0.0, dx2 = 0.0, prod = 0.0, y2n = 0.0;
+    T* xa = (T*)a.xiaug + j * a.kp;
+    if (valid && k == n) {
         const double yb = a.ybar[j];
-        const double y1 = yb + sc_y * (a.vy[j] - yb);
+        const double y1 = yb + sc_y * (a.vy[j] - yb);       // projection onto Q_y
         const double y2o = a.y2[j];
         dy2 = (y1 - y2o) * (y1 - y2o);
-        const double y2n = y1 + beta * (y1 - a.y1p[j]);
+        y2n = y1 + beta * (y1 - a.y1p[j]);                  // extrapolation
         a.y1p[j] = y1;
         a.y2[j] = y2n;
-        T* xa = (T*)a.xiaug + j * a.kp;
-        double d = 0.0;
-        for (int k = 0; k < n; ++k) {
-            const double x1 = sc_xi * a.vxi[j * n + k];
-            const double x2o = a.xi2[j * n + k];
-            dx2 += (x1 - x2o) * (x1 - x2o);
-            const double x2n = x1 + beta * (x1 - a.xi1p[j * n + k]);
-            a.xi1p[j * n + k] = x1;
-            a.xi2[j * n + k] = x2n;
-            xa[k] = (T)(-x2n);
-            d += a.X[j * n + k] * x2n;
-        }
+    } else if (valid && k < n) {
+        const int64_t e = j * n + k;
+        const double x1 = sc_xi * a.vxi[e];                 // projection onto Q_xi
+        const double x2o = a.xi2[e];
+        dx2 = (x1 - x2o) * (x1 - x2o);
+        const double x2n = x1 + beta * (x1 - a.xi1p[e]);
+        a.xi1p[e] = x1;
+        a.xi2[e] = x2n;
+        xa[k] = (T)(-x2n);
+        prod = a.X[e] * x2n;
+    }
+    const double d = group_sum<G>(prod);                    // x_j^T xi_j
+    if (valid && k == n) {
         xa[n] = (T)(d - y2n);
         ((T*)a.ycol)[j] = (T)y2n;
     }
     const double b0 = block_reduce(dy2, 0), b1 = block_reduce(dx2, 0);
     if (threadIdx.x == 0) { a.blockpart[blockIdx.x * 4 + 2] = b0; a.blockpart[blockIdx.x * 4 + 3] = b1; }
-    if (last_block(&st->cnt[2])) {
-        if (threadIdx.x == 0) {
-            double sy = 0.0, sx = 0.0;
-            for (unsigned b = 0; b < gridDim.x; ++b) {
-                sy += ld_coherent(a.blockpart + b * 4 + 2);
-                sx += ld_coherent(a.blockpart + b * 4 + 3);
-            }
-            const double dy = sqrt(sy), dxi = sqrt(sx);
-            st->dy = dy;
-            st->dxi = dxi;
-            st->t = t_next;
-            const int64_t it = st->it + 1;
-            st->it = it;
-            const bool alpha_stop = a.oa->adaptive && dy <= a.oa->alpha_y && dxi <= a.oa->alpha_xi;
-            if (alpha_stop || it >= a.oa->lmax) {
-                st->active = 0;
-                st->stopped_by_alpha = alpha_stop ? 1 : 0;
-            }
-        }
+}
+
+// After each graph replay: advance the iteration base by the replay length.
+__global__ void k_replay_end(DevState* st, int iters) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) st->base += iters;
+}
+
+// After the last replay of an ALCC iteration: if no reduce kernel has stopped
+// MAPG yet, the run ended at exactly `launched` = l_max iterations.
+__global__ __launch_bounds__(kBlock) void k_mapg_end(const double* blockpart, int nblk, int64_t launched,
+                                                     DevState* st) {
+    if (st->active == 0) return;
+    const double dy = sqrt(block_gather(blockpart, nblk, 2, 0));
+    const double dxi = sqrt(block_gather(blockpart, nblk, 3, 0));
+    if (threadIdx.x == 0) {
+        st->active = 0;
+        st->it = launched;
+        st->stopped_by_alpha = 0;
+        st->dy = dy;
+        st->dxi = dxi;
     }
 }
 
@@ -481,35 +566,39 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
 // pass-precision operands from (y, xi); with write_state, also
 // y^(1)_0 = y^(2)_1 = y and likewise xi.
 
-template <typename T>
+template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_set_point(PointArgs a) {
-    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    constexpr int PER = kBlock / G;
+    const int k = threadIdx.x % G;
+    const int64_t j = (int64_t)blockIdx.x * PER + threadIdx.x / G;
     const int n = a.n;
-    if (j >= a.ld) return;
+    double prod = 0.0, x = 0.0;
+    const bool valid = j < a.N;
+    if (valid && k < n) {
+        x = a.xi[j * n + k];
+        prod = a.X[j * n + k] * x;
+        if (a.write_state) { a.xi1p[j * n + k] = x; a.xi2[j * n + k] = x; }
+    }
+    const double d = group_sum<G>(prod);
+    if (j >= a.ld || k >= a.kp) return;
     T* xa = (T*)a.xiaug + j * a.kp;
-    if (j < a.N) {
+    if (valid) {
         const double yj = a.y[j];
-        double d = 0.0;
-        for (int k = 0; k < n; ++k) {
-            const double x = a.xi[j * n + k];
-            xa[k] = (T)(-x);
-            d += a.X[j * n + k] * x;
-            if (a.write_state) { a.xi1p[j * n + k] = x; a.xi2[j * n + k] = x; }
+        xa[k] = k < n ? (T)(-x) : (k == n ? (T)(d - yj) : (T)0);
+        if (k == n) {
+            ((T*)a.ycol)[j] = (T)yj;
+            if (a.write_state) { a.y1p[j] = yj; a.y2[j] = yj; }
         }
-        xa[n] = (T)(d - yj);
-        for (int k = n + 1; k < a.kp; ++k) xa[k] = (T)0;
-        ((T*)a.ycol)[j] = (T)yj;
-        if (a.write_state) { a.y1p[j] = yj; a.y2[j] = yj; }
     } else {
-        for (int k = 0; k < a.kp; ++k) xa[k] = (T)0;
-        if (j < a.Nrow) ((T*)a.ycol)[j] = (T)0;
+        xa[k] = (T)0;
+        if (k == 0 && j < a.Nrow) ((T*)a.ycol)[j] = (T)0;
     }
 }
 
 __global__ void k_begin_outer(OuterArgs args, OuterArgs* dst, DevState* st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         *dst = args;
-        st->t = 1.0;
+        st->base = 0;
         st->it = 0;
         st->active = 1;
         st->stopped_by_alpha = 0;
@@ -785,24 +874,50 @@ hipError_t launch_pair_pass(bool f64, int ks, const PassArgs& a, dim3 grid, hipS
     return f64 ? launch_pass_t<double>(ks, a, grid, s) : launch_pass_t<float>(ks, a, grid, s);
 }
 
+// Threads per point of the O(N n) kernels: the smallest of 16, 32 that holds n + 1.
+static int group_of(int n) { return n + 1 <= 16 ? 16 : 32; }
+static dim3 points_grid(int64_t points, int G) { return dim3((unsigned)((points * G + kBlock - 1) / kBlock)); }
+
+template <typename T>
+static void reduce_t(const ReduceArgs& a, hipStream_t s) {
+    if (group_of(a.n) == 16) hipLaunchKernelGGL((k_reduce<T, 16>), points_grid(a.N, 16), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_reduce<T, 32>), points_grid(a.N, 32), dim3(kBlock), 0, s, a);
+}
+template <typename T>
+static void update_t(const UpdateArgs& a, hipStream_t s) {
+    if (group_of(a.n) == 16) hipLaunchKernelGGL((k_update<T, 16>), points_grid(a.N, 16), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_update<T, 32>), points_grid(a.N, 32), dim3(kBlock), 0, s, a);
+}
+template <typename T>
+static void set_point_t(const PointArgs& a, hipStream_t s) {
+    if (group_of(a.n) == 16) hipLaunchKernelGGL((k_set_point<T, 16>), points_grid(a.ld, 16), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_set_point<T, 32>), points_grid(a.ld, 32), dim3(kBlock), 0, s, a);
+}
+
 hipError_t launch_reduce(bool f64, const ReduceArgs& a, hipStream_t s) {
-    const dim3 grid((unsigned)((a.N + kBlock - 1) / kBlock));
-    if (f64) hipLaunchKernelGGL(k_reduce<double>, grid, dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL(k_reduce<float>, grid, dim3(kBlock), 0, s, a);
+    if (f64) reduce_t<double>(a, s); else reduce_t<float>(a, s);
     return hipGetLastError();
 }
 
 hipError_t launch_update(bool f64, const UpdateArgs& a, hipStream_t s) {
-    const dim3 grid((unsigned)((a.N + kBlock - 1) / kBlock));
-    if (f64) hipLaunchKernelGGL(k_update<double>, grid, dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL(k_update<float>, grid, dim3(kBlock), 0, s, a);
+    if (f64) update_t<double>(a, s); else update_t<float>(a, s);
+    return hipGetLastError();
+}
+
+int reduce_blocks(int64_t N, int n) { return (int)points_grid(N, group_of(n)).x; }
+
+hipError_t launch_replay_end(DevState* st, int iters, hipStream_t s) {
+    hipLaunchKernelGGL(k_replay_end, dim3(1), dim3(64), 0, s, st, iters);
+    return hipGetLastError();
+}
+
+hipError_t launch_mapg_end(const double* blockpart, int nblk, int64_t launched, DevState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_mapg_end, dim3(1), dim3(kBlock), 0, s, blockpart, nblk, launched, st);
     return hipGetLastError();
 }
 
 hipError_t launch_set_point(bool f64, const PointArgs& a, hipStream_t s) {
-    const dim3 grid((unsigned)((a.ld + kBlock - 1) / kBlock));
-    if (f64) hipLaunchKernelGGL(k_set_point<double>, grid, dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL(k_set_point<float>, grid, dim3(kBlock), 0, s, a);
+    if (f64) set_point_t<double>(a, s); else set_point_t<float>(a, s);
     return hipGetLastError();
 }
 

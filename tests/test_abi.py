@@ -88,4 +88,5 @@ def test_product_package_has_no_oracle_dependency():
         for f in files:
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
-                assert "oracle" not in text.lower() or f == "__init__.py" and "import oracle" not in text, f
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "cr_oracle" not in text and "libcr_oracle" not in text, f
