@@ -44,7 +44,7 @@ def test_workspace_bytes_validation_and_growth():
     b2 = cr.workspace_bytes(4000, 10)
     # dominated by the N x N multiplier array theta (FP64 by default)
     assert b1 >= 2000 * 2000 * 8 and b2 >= 4000 * 4000 * 8
-    assert 3.7 < b2 / b1 < 4.3
+    assert 3.3 < b2 / b1 < 4.5
     assert cr.workspace_bytes(1000, 10, cr.Params(precision=cr.F32)) < b1
     for N, n, status in [(1, 2, cr.ERR_ARG), (10, 0, cr.ERR_ARG), (10, 32, cr.ERR_UNSUPPORTED)]:
         with pytest.raises(cr.CRError) as e:
