@@ -30,7 +30,8 @@ struct Layout {
     int strips = 0, chunks = 0, rpc = 0, nb = 0, nsu = 0;
     size_t off_theta, off_xp, off_xiaug, off_ycol, off_rowpart, off_cpart, off_kkt;
     size_t off_y1p, off_y2, off_vy, off_y0, off_xi1p, off_xi2, off_vxi, off_xi0;
-    size_t off_blockpart, off_supart, off_su, off_oa, off_st, off_beta;
+    size_t off_blockpart, off_supart, off_su, off_oa, off_st, off_beta, off_cvec;
+    int prec = 0;
     int64_t nbeta = 0;
     size_t total;
 };
@@ -42,6 +43,7 @@ Layout make_layout(int64_t N, int n, int precision, int64_t max_iters) {
     L.N = N;
     L.n = n;
     L.nc = n + 1;
+    L.prec = precision;
     L.esz = precision == CR_F64 ? 8 : 4;
     L.tw = L.esz == 8 ? 2 : 4;
     L.Nrow = ((N + 63) / 64) * 64;
@@ -49,6 +51,15 @@ Layout make_layout(int64_t N, int n, int precision, int64_t max_iters) {
     L.ks = cr::ks_of(n);
     L.kp = 4 * L.ks;
     L.qp = cr::qp_of_ks(L.ks, L.esz);
+    size_t xp_bytes = (size_t)(L.Nrow / 16) * 64 * L.qp * L.esz;
+    size_t xiaug_bytes = (size_t)L.ld * L.kp * L.esz;
+    if (precision == CR_MIXED_BF16) {
+        // BF16 operand slots: kp per column, (KB + 2 NKB) 16-byte vectors per lane and tile
+        L.kp = 32 * cr::mixed_kb(n);
+        L.qp = cr::mixed_kb(n) + 2 * ((n + 1 + 15) / 16);
+        xp_bytes = (size_t)(L.Nrow / 16) * 64 * L.qp * 16;
+        xiaug_bytes = (size_t)L.ld * L.kp * 2;
+    }
     L.strips = (int)(L.ld / (16 * L.tw));
     // Enough workgroups to fill 256 CUs several times over, but long enough
     // row chunks that the per-chunk column partials stay small.
@@ -65,8 +76,9 @@ Layout make_layout(int64_t N, int n, int precision, int64_t max_iters) {
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
     L.off_theta = take((size_t)L.Nrow * L.ld * L.esz);
-    L.off_xp = take((size_t)(L.Nrow / 16) * 64 * L.qp * L.esz);
-    L.off_xiaug = take((size_t)L.ld * L.kp * L.esz);
+    L.off_xp = take(xp_bytes);
+    L.off_xiaug = take(xiaug_bytes);
+    L.off_cvec = take((size_t)L.ld * 4);
     L.off_ycol = take((size_t)L.Nrow * L.esz);
     L.off_rowpart = take((size_t)L.strips * L.Nrow * L.esz);
     L.off_cpart = take((size_t)L.chunks * L.ld * L.nc * L.esz);
@@ -105,7 +117,6 @@ bool check_params(const cr_params* p, std::string& msg) {
         msg = "unknown precision";
         return false;
     }
-    if (p->precision == CR_MIXED_BF16) { msg = "CR_MIXED_BF16 is not available in this build"; return false; }
     return true;
 }
 
@@ -127,7 +138,8 @@ struct cr_ctx {
     cr_params p;
     int64_t N;
     int n;
-    bool f64;
+    bool f64;        // FP64 pass partials (CR_F64); FP32 for CR_F32 and CR_MIXED_BF16
+    int prec;
     hipStream_t user_stream = nullptr;
     hipStream_t cs = nullptr;            // internal stream (graph capture needs a non-null stream)
     hipGraphExec_t graph = nullptr;
@@ -168,6 +180,7 @@ static cr::PassArgs pass_args(cr_ctx* c, int mode, double theta_scale, const int
     a.theta = c->P(L.off_theta); a.xp = c->P(L.off_xp); a.xiaug = c->P(L.off_xiaug); a.ycol = c->P(L.off_ycol);
     a.rowpart = c->P(L.off_rowpart); a.cpart = c->P(L.off_cpart); a.kktpart = c->D(L.off_kkt);
     a.theta_scale = theta_scale; a.active = active;
+    a.cvec = (const float*)c->P(L.off_cvec);
     return a;
 }
 
@@ -193,6 +206,7 @@ static cr::PointArgs point_args(cr_ctx* c, const double* y, const double* xi, in
     a.X = c->X; a.y = y; a.xi = xi;
     a.y1p = c->D(L.off_y1p); a.y2 = c->D(L.off_y2); a.xi1p = c->D(L.off_xi1p); a.xi2 = c->D(L.off_xi2);
     a.xiaug = c->P(L.off_xiaug); a.ycol = c->P(L.off_ycol);
+    a.cvec = (float*)c->P(L.off_cvec);
     return a;
 }
 
@@ -203,6 +217,7 @@ static cr::UpdateArgs update_args(cr_ctx* c) {
     a.X = c->X; a.ybar = c->ybar; a.vy = c->D(L.off_vy); a.vxi = c->D(L.off_vxi); a.beta = c->D(L.off_beta);
     a.y1p = c->D(L.off_y1p); a.y2 = c->D(L.off_y2); a.xi1p = c->D(L.off_xi1p); a.xi2 = c->D(L.off_xi2);
     a.xiaug = c->P(L.off_xiaug); a.ycol = c->P(L.off_ycol);
+    a.cvec = (float*)c->P(L.off_cvec);
     a.blockpart = c->D(L.off_blockpart); a.oa = c->oa; a.st = c->st;
     return a;
 }
@@ -213,7 +228,7 @@ static cr::UpdateArgs update_args(cr_ctx* c) {
 static hipError_t enqueue_mapg_iteration(cr_ctx* c, int q, hipStream_t s) {
     const Layout& L = c->L;
     cr::PassArgs pa = pass_args(c, 0, 0.0, &c->st->active);
-    hipError_t e = cr::launch_pair_pass(c->f64, L.ks, pa, pass_grid(L), s);
+    hipError_t e = cr::launch_pair_pass(c->prec, c->n, pa, pass_grid(L), s);
     if (e != hipSuccess) return e;
     cr::ReduceArgs ra = reduce_args(c, 0, c->D(L.off_y2), c->D(L.off_xi2), c->D(L.off_vy), c->D(L.off_vxi), 0.0);
     ra.q = q;
@@ -221,7 +236,7 @@ static hipError_t enqueue_mapg_iteration(cr_ctx* c, int q, hipStream_t s) {
     if (e != hipSuccess) return e;
     cr::UpdateArgs ua = update_args(c);
     ua.q = q;
-    return cr::launch_update(c->f64, ua, s);
+    return cr::launch_update(c->prec, ua, s);
 }
 
 static cr_status build_graph(cr_ctx* c) {
@@ -306,6 +321,7 @@ cr_status cr_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params, c
     c->N = N;
     c->n = n;
     c->f64 = params->precision == CR_F64;
+    c->prec = params->precision;
     c->user_stream = (hipStream_t)stream;
     {
         const char* v = std::getenv("CR_VERBOSE");
@@ -341,7 +357,7 @@ cr_status cr_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params, c
     if (e == hipSuccess)
         e = cr::launch_setup(c->X, c->ybar, N, n, params->gamma, c->D(L.off_su), c->D(L.off_supart), c->D(L.off_y0),
                              c->D(L.off_xi0), c->st, cs);
-    if (e == hipSuccess) e = cr::launch_prep_xp(c->f64, c->X, N, n, L.Nrow, L.ks, L.qp, c->P(L.off_xp), cs);
+    if (e == hipSuccess) e = cr::launch_prep_xp(c->prec, c->X, N, n, L.Nrow, L.ks, L.qp, c->P(L.off_xp), cs);
     if (e == hipSuccess) {
         // momentum weights of Fig. 4: t_1 = 1, t_{l+1} = (1 + sqrt(1 + 4 t_l^2)) / 2,
         // beta_l = (t_l - 1) / t_{l+1}; entry 0 is unused
@@ -362,7 +378,7 @@ cr_status cr_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params, c
     }
     if (e == hipSuccess) {
         cr::PointArgs pa = point_args(c, c->D(L.off_y0), c->D(L.off_xi0), 1);
-        e = cr::launch_set_point(c->f64, pa, cs);
+        e = cr::launch_set_point(c->prec, pa, cs);
     }
     if (e == hipSuccess) e = hipMemcpyAsync(c->pinned_state, c->st, sizeof(cr::DevState), hipMemcpyDeviceToHost, cs);
     if (e == hipSuccess) e = hipStreamSynchronize(cs);
@@ -407,10 +423,10 @@ cr_status cr_pairwise_step(cr_ctx* c, int32_t mode, const void* y_dev, const voi
     const Layout& L = c->L;
     hipStream_t s = c->user_stream;
     cr::PointArgs pt = point_args(c, (const double*)y_dev, (const double*)xi_dev, 0);
-    HIPCHK(c, cr::launch_set_point(c->f64, pt, s));
+    HIPCHK(c, cr::launch_set_point(c->prec, pt, s));
     const double scale = mode == CR_THETA_UPDATE ? mu / mu_next : 0.0;
     cr::PassArgs pa = pass_args(c, mode == CR_THETA_UPDATE ? 1 : 0, scale, &c->st->one);
-    HIPCHK(c, cr::launch_pair_pass(c->f64, L.ks, pa, pass_grid(L), s));
+    HIPCHK(c, cr::launch_pair_pass(c->prec, c->n, pa, pass_grid(L), s));
     cr::ReduceArgs ra = reduce_args(c, mode == CR_THETA_UPDATE ? 2 : 1, (const double*)y_dev, (const double*)xi_dev,
                                     (double*)gy_dev, (double*)gxi_dev, mu);
     HIPCHK(c, cr::launch_reduce(c->f64, ra, s));
@@ -481,7 +497,7 @@ cr_status cr_run(cr_ctx* c, void* y_dev, void* xi_dev, cr_info* info) {
     // theta_1 = 0 and (y_0, xi_0) = the affine fit
     HIPCHK(c, cr::launch_zero(c->P(L.off_theta), (size_t)L.Nrow * L.ld * L.esz, cs));
     cr::PointArgs start = point_args(c, c->D(L.off_y0), c->D(L.off_xi0), 1);
-    HIPCHK(c, cr::launch_set_point(c->f64, start, cs));
+    HIPCHK(c, cr::launch_set_point(c->prec, start, cs));
 
     const int64_t N = c->N;
     const double gamma = p.gamma;
@@ -532,9 +548,9 @@ cr_status cr_run(cr_ctx* c, void* y_dev, void* xi_dev, cr_info* info) {
         HIPCHK(c, cr::launch_mapg_end(c->D(L.off_blockpart), cr::reduce_blocks(N, c->n), launched, c->st, cs));
         // multiplier step at the MAPG output (y_k, xi_k), which also restarts MAPG there
         cr::PointArgs pt = point_args(c, c->D(L.off_y1p), c->D(L.off_xi1p), 1);
-        HIPCHK(c, cr::launch_set_point(c->f64, pt, cs));
+        HIPCHK(c, cr::launch_set_point(c->prec, pt, cs));
         cr::PassArgs pa = pass_args(c, 1, mu / mu_next, &c->st->one);
-        HIPCHK(c, cr::launch_pair_pass(c->f64, L.ks, pa, pass_grid(L), cs));
+        HIPCHK(c, cr::launch_pair_pass(c->prec, c->n, pa, pass_grid(L), cs));
         cr::ReduceArgs ra = reduce_args(c, 2, c->D(L.off_y1p), c->D(L.off_xi1p), nullptr, nullptr, mu);
         HIPCHK(c, cr::launch_reduce(c->f64, ra, cs));
         HIPCHK(c, hipMemcpyAsync(c->pinned_state, c->st, sizeof(cr::DevState), hipMemcpyDeviceToHost, cs));
@@ -584,7 +600,7 @@ cr_status cr_time_pass(cr_ctx* c, int32_t mode, int32_t reps, double* avg_ms) {
     HIPCHK(c, hipEventCreate(&e1));
     cr::PassArgs pa = pass_args(c, 0, 0.0, &c->st->one);
     hipError_t e = hipEventRecord(e0, c->cs);
-    for (int r = 0; r < reps && e == hipSuccess; ++r) e = cr::launch_pair_pass(c->f64, L.ks, pa, pass_grid(L), c->cs);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = cr::launch_pair_pass(c->prec, c->n, pa, pass_grid(L), c->cs);
     if (e == hipSuccess) e = hipEventRecord(e1, c->cs);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;

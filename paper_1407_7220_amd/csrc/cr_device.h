@@ -53,6 +53,8 @@ __host__ __device__ constexpr int qp_of_ks(int ks, int elem) {
     // padded to whole 16-byte vectors
     return ((q_of_ks(ks) * elem + 15) / 16) * 16 / elem;
 }
+// Mixed precision: K = 3n BF16 slots of the residual contraction in blocks of 32.
+__host__ __device__ constexpr int mixed_kb(int n) { return (3 * n + 31) / 32; }
 
 struct PassArgs {
     int64_t N, Nrow, ld;      // points, padded rows (x16), theta row stride (x64)
@@ -69,6 +71,7 @@ struct PassArgs {
     double* kktpart;          // (strips*chunks) x 4
     double theta_scale;       // mu_k / mu_{k+1} (multiplier pass)
     const int32_t* active;
+    const float* cvec;        // mixed precision: c_j = x_j^T xi_j - y_j in FP32 (ld)
 };
 
 // Sum of the pass partials for point j, then the gradient (mode 1), the MAPG
@@ -106,8 +109,9 @@ struct UpdateArgs {
     double* y2;      // y^(2)_l in, y^(2)_{l+1} out
     double* xi1p;
     double* xi2;
-    void* xiaug;     // pass precision
+    void* xiaug;     // pass precision (mixed: BF16 hi/lo slots)
     void* ycol;
+    float* cvec;     // mixed precision only
     double* blockpart;
     const OuterArgs* oa;
     DevState* st;
@@ -126,17 +130,19 @@ struct PointArgs {
     double* xi2;
     void* xiaug;
     void* ycol;
+    float* cvec;     // mixed precision only
 };
 
-hipError_t launch_pair_pass(bool f64, int ks, const PassArgs& a, dim3 grid, hipStream_t s);
+// prec: 0 FP64, 1 FP32, 2 mixed BF16 (the pass precision of cr.h)
+hipError_t launch_pair_pass(int prec, int n, const PassArgs& a, dim3 grid, hipStream_t s);
 hipError_t launch_reduce(bool f64, const ReduceArgs& a, hipStream_t s);
-hipError_t launch_update(bool f64, const UpdateArgs& a, hipStream_t s);
-hipError_t launch_set_point(bool f64, const PointArgs& a, hipStream_t s);
+hipError_t launch_update(int prec, const UpdateArgs& a, hipStream_t s);
+hipError_t launch_set_point(int prec, const PointArgs& a, hipStream_t s);
 hipError_t launch_begin_outer(const OuterArgs& args, OuterArgs* dst, DevState* st, hipStream_t s);
 hipError_t launch_replay_end(DevState* st, int iters, hipStream_t s);
 hipError_t launch_mapg_end(const double* blockpart, int nblk, int64_t launched, DevState* st, hipStream_t s);
 int reduce_blocks(int64_t N, int n);
-hipError_t launch_prep_xp(bool f64, const double* X, int64_t N, int n, int64_t Nrow, int ks, int qp, void* xp,
+hipError_t launch_prep_xp(int prec, const double* X, int64_t N, int n, int64_t Nrow, int ks, int qp, void* xp,
                           hipStream_t s);
 hipError_t launch_theta_import(bool f64, const double* src, int64_t N, int64_t Nrow, int64_t ld, void* theta,
                                hipStream_t s);

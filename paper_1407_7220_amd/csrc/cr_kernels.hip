@@ -125,6 +125,132 @@ __device__ __forceinline__ double ld_coherent(const double* p) {
 }
 
 // ---------------------------------------------------------------------------
+// Operand policies of the pair pass.  A policy says what one lane holds for
+// the two contractions and how they run:
+//   R = [X 1] [-Xi c]^T + y 1^T      (residuals, one 16 x 16 tile per j-tile)
+//   C += W^T [X 1]                   (sum_i w_ij x_i and colsum_j)
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 acc) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+}
+
+// FP64 / FP32: 16x16x4 MFMA in the pass precision; c_j and y_i enter R exactly.
+template <typename T, int KS> struct PlainOps {
+    typedef T elem;
+    typedef typename Tr<T>::acc acc_t;
+    static constexpr int TW = Tr<T>::TW;
+    static constexpr int NKB = nkb_of_ks(KS);
+    static constexpr int QP = qp_of_ks(KS, (int)sizeof(T));
+    static constexpr int EV = 16 / (int)sizeof(T);
+    static constexpr int NSET = sizeof(T) == 4 ? 3 : 2;
+    static constexpr int RM4 = sizeof(T) == 4;   // accumulator row map 4 g + v (else g + 4 v)
+    struct Breg { T b[KS][TW]; };
+    struct Xop { T q[QP]; };
+    // B operand of R for every j-tile: [-xi_j, c_j, 0...] (k = 4 s + g)
+    static __device__ void load_breg(Breg& B, const PassArgs& a, int64_t jl, int g) {
+        const T* xiaug = (const T*)a.xiaug;
+#pragma unroll
+        for (int t = 0; t < TW; ++t) {
+            const T* row = xiaug + (jl + t) * (4 * KS);
+#pragma unroll
+            for (int s = 0; s < KS; ++s) B.b[s][t] = row[4 * s + g];
+        }
+    }
+    static __device__ void load_xop(Xop& X, const PassArgs& a, int64_t i0, int lane) {
+        const T* xp = (const T*)a.xp;
+#pragma unroll
+        for (int q = 0; q < QP / EV; ++q) {
+            V16<T> tv = ld16(xp + ((i0 >> 4) * 64 + lane) * QP + q * EV);
+#pragma unroll
+            for (int e = 0; e < EV; ++e) X.q[q * EV + e] = tv.v[e];
+        }
+    }
+    static __device__ void residual(acc_t R[TW], const Xop& X, const Breg& B, const T yv[4]) {
+#pragma unroll
+        for (int t = 0; t < TW; ++t) {
+            R[t] = acc_t{yv[0], yv[1], yv[2], yv[3]};
+#pragma unroll
+            for (int s = 0; s < KS; ++s) R[t] = mfma4(X.q[s], B.b[s][t], R[t]);
+        }
+    }
+    // i-slot g of step s is row i0 + rmap(g, s): W comes straight from R's registers
+    static __device__ void colsums(acc_t C[TW][NKB], const T W[TW][4], const Xop& X) {
+#pragma unroll
+        for (int t = 0; t < TW; ++t)
+#pragma unroll
+            for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) C[t][kb] = mfma4(W[t][s], X.q[KS + 4 * kb + s], C[t][kb]);
+    }
+};
+
+// Mixed: BF16 16x16x32 MFMA on hi/lo splits with FP32 accumulation; theta,
+// W and the accumulators are FP32.  R: K-slots [x_hi | x_lo | x_hi] against
+// [-xi_hi | -xi_hi | -xi_lo] (K = 3n, KB blocks of 32), accumulator started
+// at y_i + c_j in FP32.  C: [W_hi(4 rows), W_lo(4 rows)] . [X_hi, X_hi] plus
+// [W_hi, 0] . [X_lo, 0].
+template <int KB, int NKB_> struct MixedOps {
+    typedef float elem;
+    typedef f32x4 acc_t;
+    static constexpr int TW = 4;
+    static constexpr int NKB = NKB_;
+    static constexpr int NSET = KB + NKB <= 2 ? 3 : 2;
+    static constexpr int RM4 = 1;
+    struct Breg { bf16x8 b[KB][TW]; float cc[TW]; };
+    struct Xop { bf16x8 r[KB]; bf16x8 c1[NKB]; bf16x8 c2[NKB]; };
+    static __device__ void load_breg(Breg& B, const PassArgs& a, int64_t jl, int g) {
+        const __bf16* xb = (const __bf16*)a.xiaug;
+#pragma unroll
+        for (int t = 0; t < TW; ++t) {
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb)
+                B.b[kb][t] = *reinterpret_cast<const bf16x8*>(xb + ((jl + t) * KB + kb) * 32 + 8 * g);
+            B.cc[t] = a.cvec[jl + t];
+        }
+    }
+    static __device__ void load_xop(Xop& X, const PassArgs& a, int64_t i0, int lane) {
+        const bf16x8* xp = (const bf16x8*)a.xp + ((i0 >> 4) * 64 + lane) * (KB + 2 * NKB);
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) X.r[kb] = xp[kb];
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb) { X.c1[kb] = xp[KB + 2 * kb]; X.c2[kb] = xp[KB + 2 * kb + 1]; }
+    }
+    static __device__ void residual(acc_t R[TW], const Xop& X, const Breg& B, const float yv[4]) {
+#pragma unroll
+        for (int t = 0; t < TW; ++t) {
+            R[t] = acc_t{yv[0] + B.cc[t], yv[1] + B.cc[t], yv[2] + B.cc[t], yv[3] + B.cc[t]};
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) R[t] = mfma_bf16(X.r[kb], B.b[kb][t], R[t]);
+        }
+    }
+    static __device__ void colsums(acc_t C[TW][NKB], const float W[TW][4], const Xop& X) {
+#pragma unroll
+        for (int t = 0; t < TW; ++t) {
+            bf16x8 w1, w2;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const __bf16 hi = (__bf16)W[t][v];
+                w1[v] = hi;
+                w1[v + 4] = (__bf16)(W[t][v] - (float)hi);
+                w2[v] = hi;
+                w2[v + 4] = (__bf16)0.0f;
+            }
+#pragma unroll
+            for (int kb = 0; kb < NKB; ++kb) {
+                C[t][kb] = mfma_bf16(w1, X.c1[kb], C[t][kb]);
+                C[t][kb] = mfma_bf16(w2, X.c2[kb], C[t][kb]);
+            }
+        }
+    }
+};
+
+template <typename Ops> __device__ __forceinline__ int orow(int g, int v) {
+    return Ops::RM4 ? 4 * g + v : g + 4 * v;
+}
+
+// ---------------------------------------------------------------------------
 // The fused pair pass (gradient or multiplier step).
 //
 // Grid (strips, chunks).  Workgroup (s, h) owns the columns
@@ -133,14 +259,13 @@ __device__ __forceinline__ double ld_coherent(const double* p) {
 // accumulator element v, the pair (i0 + rmap(g, v), J0 + TW c + t), so its
 // TW theta values of one row are contiguous (one 16-byte load per row).
 // ---------------------------------------------------------------------------
-template <typename T, int KS>
+template <typename Ops>
 __global__ __launch_bounds__(kBlock) void k_pair_pass(PassArgs a) {
-    constexpr int TW = Tr<T>::TW;
-    constexpr int NKB = nkb_of_ks(KS);
-    constexpr int KP = 4 * KS;
-    constexpr int QP = qp_of_ks(KS, (int)sizeof(T));
+    typedef typename Ops::elem T;
+    typedef typename Ops::acc_t acc_t;
+    constexpr int TW = Ops::TW;
+    constexpr int NKB = Ops::NKB;
     constexpr int EV = 16 / (int)sizeof(T);
-    typedef typename Tr<T>::acc acc_t;
 
     if (*a.active == 0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -149,20 +274,12 @@ __global__ __launch_bounds__(kBlock) void k_pair_pass(PassArgs a) {
     const int64_t I0 = (int64_t)blockIdx.y * a.rows_per_chunk;
     const int64_t I1 = min(I0 + (int64_t)a.rows_per_chunk, a.Nrow);
     const int64_t jl = J0 + TW * c;
-    const T* __restrict__ xiaug = (const T*)a.xiaug;
-    const T* __restrict__ xp = (const T*)a.xp;
     const T* __restrict__ ycol = (const T*)a.ycol;
     T* __restrict__ theta = (T*)a.theta;
     const bool theta_mode = a.mode == 1;
 
-    // B operand of R for every j-tile: [-xi_j, c_j, 0...] (k = 4 s + g)
-    T breg[KS][TW];
-#pragma unroll
-    for (int t = 0; t < TW; ++t) {
-        const T* row = xiaug + (jl + t) * KP;
-#pragma unroll
-        for (int s = 0; s < KS; ++s) breg[s][t] = row[4 * s + g];
-    }
+    typename Ops::Breg breg;
+    Ops::load_breg(breg, a, jl, g);
 
     acc_t cacc[TW][NKB];
 #pragma unroll
@@ -175,123 +292,107 @@ __global__ __launch_bounds__(kBlock) void k_pair_pass(PassArgs a) {
     // Operands of one 16-row tile: packed X (L2-resident), y_i, and the
     // wave's 16 x 16TW block of theta (HBM stream).  NSET register sets rotate
     // so that each tile's loads are issued NSET - 1 tiles ahead of its use.
-    auto load_tile = [&](int64_t i0, T* xop, T* yv, V16<T>* th) {
-#pragma unroll
-        for (int q = 0; q < QP / EV; ++q) {
-            V16<T> tv = ld16(xp + ((i0 >> 4) * 64 + lane) * QP + q * EV);
-#pragma unroll
-            for (int e = 0; e < EV; ++e) xop[q * EV + e] = tv.v[e];
-        }
+    auto load_tile = [&](int64_t i0, typename Ops::Xop& xop, T* yv, V16<T>* th) {
+        Ops::load_xop(xop, a, i0, lane);
         if (sizeof(T) == 4) {
             V16<T> tv = ld16(ycol + i0 + 4 * g);
 #pragma unroll
             for (int e = 0; e < 4; ++e) yv[e] = tv.v[e];
         } else {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) yv[v] = ycol[i0 + rmap<T>(g, v)];
+            for (int v = 0; v < 4; ++v) yv[v] = ycol[i0 + orow<Ops>(g, v)];
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) th[v] = ld16(theta + (i0 + rmap<T>(g, v)) * a.ld + jl);
+        for (int v = 0; v < 4; ++v) th[v] = ld16(theta + (i0 + orow<Ops>(g, v)) * a.ld + jl);
     };
 
-    auto process = [&](const int64_t i0, const T* xop, const T* yv, const V16<T>* th) {
-            // residual tiles R_t (accumulator initialised with y_i)
-            acc_t R[TW];
-    #pragma unroll
-            for (int t = 0; t < TW; ++t) {
-                R[t] = acc_t{yv[0], yv[1], yv[2], yv[3]};
-    #pragma unroll
-                for (int s = 0; s < KS; ++s) R[t] = mfma4(xop[s], breg[s][t], R[t]);
-            }
+    auto process = [&](const int64_t i0, const typename Ops::Xop& xop, const T* yv, const V16<T>* th) {
+        // residual tiles R_t
+        acc_t R[TW];
+        Ops::residual(R, xop, breg, yv);
 
-            // w = max(theta - r, 0); explicit zero off the constraint set
-            T W[TW][4];
-    #pragma unroll
-            for (int t = 0; t < TW; ++t)
-    #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    T d = th[v].v[t] - R[t][v];
-                    W[t][v] = d > (T)0 ? d : (T)0;
-                }
-            const bool edge = (i0 < J0 + 16 * TW && i0 + 16 > J0) || (J0 + 16 * TW > a.N) || (i0 + 16 > a.N);
-            if (edge) {
-    #pragma unroll
-                for (int t = 0; t < TW; ++t)
-    #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int64_t i = i0 + rmap<T>(g, v), j = jl + t;
-                        if (!(i < a.N && j < a.N && i != j)) W[t][v] = (T)0;
-                    }
-            }
-
-            if (theta_mode) {
-                // Fig. 3 step 4 in place, and the pair terms of the KKT residual
-    #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    V16<T> o;
-    #pragma unroll
-                    for (int t = 0; t < TW; ++t) o.v[t] = (T)(a.theta_scale * (double)W[t][v]);
-                    st16(theta + (i0 + rmap<T>(g, v)) * a.ld + jl, o);
-                }
-    #pragma unroll
-                for (int t = 0; t < TW; ++t)
-    #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int64_t i = i0 + rmap<T>(g, v), j = jl + t;
-                        if (i < a.N && j < a.N && i != j) {
-                            const double r = (double)R[t][v];
-                            const double rn = r < 0.0 ? -r : 0.0;
-                            const double wr = (double)W[t][v] * r;
-                            k_rneg_max = fmax(k_rneg_max, rn);
-                            k_rneg_sq += rn * rn;
-                            k_wr_max = fmax(k_wr_max, fabs(wr));
-                            k_wr_sum += wr;
-                        }
-                    }
-            }
-
-            // C += W^T [X 1]: i-slot g of step s is row i0 + rmap(g, s)
-    #pragma unroll
-            for (int t = 0; t < TW; ++t)
-    #pragma unroll
-                for (int kb = 0; kb < NKB; ++kb)
-    #pragma unroll
-                    for (int s = 0; s < 4; ++s)
-                        cacc[t][kb] = mfma4(W[t][s], xop[KS + 4 * kb + s], cacc[t][kb]);
-
-            // row sums over this workgroup's columns (16-lane DPP reduction)
-            T rs[4];
+        // w = max(theta - r, 0); explicit zero off the constraint set
+        T W[TW][4];
+#pragma unroll
+        for (int t = 0; t < TW; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                T s = W[0][v];
+                T d = th[v].v[t] - R[t][v];
+                W[t][v] = d > (T)0 ? d : (T)0;
+            }
+        const bool edge = (i0 < J0 + 16 * TW && i0 + 16 > J0) || (J0 + 16 * TW > a.N) || (i0 + 16 > a.N);
+        if (edge) {
 #pragma unroll
-                for (int t = 1; t < TW; ++t) s += W[t][v];
-                rs[v] = row16_sum(s);
-            }
-            if (c == 0) {
-                // rowpart[strip][i]: the 16 row sums of a tile are contiguous
-                T* dst = (T*)a.rowpart + (int64_t)blockIdx.x * a.Nrow + i0;
-                if (sizeof(T) == 4) {
-                    V16<T> o;
-    #pragma unroll
-                    for (int e = 0; e < 4; ++e) o.v[e] = rs[e];
-                    st16(dst + 4 * g, o);
-                } else {
-    #pragma unroll
-                    for (int v = 0; v < 4; ++v) dst[rmap<T>(g, v)] = rs[v];
+            for (int t = 0; t < TW; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t i = i0 + orow<Ops>(g, v), j = jl + t;
+                    if (!(i < a.N && j < a.N && i != j)) W[t][v] = (T)0;
                 }
+        }
+
+        if (theta_mode) {
+            // Fig. 3 step 4 in place, and the pair terms of the KKT residual
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                V16<T> o;
+#pragma unroll
+                for (int t = 0; t < TW; ++t) o.v[t] = (T)(a.theta_scale * (double)W[t][v]);
+                st16(theta + (i0 + orow<Ops>(g, v)) * a.ld + jl, o);
             }
+#pragma unroll
+            for (int t = 0; t < TW; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t i = i0 + orow<Ops>(g, v), j = jl + t;
+                    if (i < a.N && j < a.N && i != j) {
+                        const double r = (double)R[t][v];
+                        const double rn = r < 0.0 ? -r : 0.0;
+                        const double wr = (double)W[t][v] * r;
+                        k_rneg_max = fmax(k_rneg_max, rn);
+                        k_rneg_sq += rn * rn;
+                        k_wr_max = fmax(k_wr_max, fabs(wr));
+                        k_wr_sum += wr;
+                    }
+                }
+        }
+
+        Ops::colsums(cacc, W, xop);
+
+        // row sums over this workgroup's columns (16-lane DPP reduction)
+        T rs[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            T s = W[0][v];
+#pragma unroll
+            for (int t = 1; t < TW; ++t) s += W[t][v];
+            rs[v] = row16_sum(s);
+        }
+        if (c == 0) {
+            // rowpart[strip][i]: the 16 row sums of a tile are contiguous
+            T* dst = (T*)a.rowpart + (int64_t)blockIdx.x * a.Nrow + i0;
+            if (Ops::RM4 && sizeof(T) == 4) {
+                V16<T> o;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) o.v[e] = rs[e];
+                st16(dst + 4 * g, o);
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) dst[orow<Ops>(g, v)] = rs[v];
+            }
+        }
     };
 
     constexpr int64_t step = 16 * kWaves;
-    constexpr int NSET = sizeof(T) == 4 ? 3 : 2;   // staging sets (tiles in flight per wave)
+    constexpr int NSET = Ops::NSET;   // staging sets (tiles in flight per wave)
     // Tiles of this wave: rows I0 + 16 wave + step m < I1 (at least one, since
     // I1 - I0 >= 64).  Prefetches are unconditional, clamped to the last tile,
     // so the compiler can count outstanding loads exactly.
     const int64_t first = I0 + 16 * wave;
     const int ntile = (int)((I1 - first + step - 1) / step);
     auto row_of = [&](int m) { return first + step * (int64_t)(m < ntile ? m : ntile - 1); };
-    T xs[NSET][QP], ys[NSET][4];
+    typename Ops::Xop xs[NSET];
+    T ys[NSET][4];
     V16<T> ts[NSET][4];
 #pragma unroll
     for (int b = 0; b < NSET; ++b) load_tile(row_of(b), xs[b], ys[b], ts[b]);
@@ -317,7 +418,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_pass(PassArgs a) {
         const int ln = e & 63, v = (e >> 6) & 3, rest = e >> 8;
         const int kb = rest % NKB, t = rest / NKB;
         const T s = ((cl[0][t][kb][v][ln] + cl[1][t][kb][v][ln]) + cl[2][t][kb][v][ln]) + cl[3][t][kb][v][ln];
-        const int64_t j = J0 + TW * rmap<T>(ln >> 4, v) + t;
+        const int64_t j = J0 + TW * orow<Ops>(ln >> 4, v) + t;
         const int kk = 16 * kb + (ln & 15);
         // cpart[chunk][j][k]: this workgroup's columns are one contiguous range
         if (kk < a.nc) cpart[((int64_t)blockIdx.y * a.ld + j) * a.nc + kk] = s;
@@ -339,10 +440,6 @@ __global__ __launch_bounds__(kBlock) void k_pair_pass(PassArgs a) {
         }
     }
 }
-
-// ---------------------------------------------------------------------------
-// Sum of the pass partials for point j and the gradient / MAPG step / KKT.
-// ---------------------------------------------------------------------------
 
 // A group of G lanes (G >= n + 1, a power of two dividing 64) owns one point j:
 // lane k < n handles xi_jk, lane n handles y_j; the partial sums of point j are
@@ -496,7 +593,15 @@ __global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) {
 // stopping test, and the pass-precision operands of the next pass.
 // ---------------------------------------------------------------------------
 
-template <typename T, int G>
+// Pass operands of column j from xi2 (value of lane k) and c_j.  Plain: the
+// pass-precision slots [-xi, c, 0..].  Mixed: BF16 slots -xi_hi at k and n + k,
+// -xi_lo at 2n + k, and c_j in FP32.
+__device__ __forceinline__ void bf16_split(float v, __bf16& hi, __bf16& lo) {
+    hi = (__bf16)v;
+    lo = (__bf16)(v - (float)hi);
+}
+
+template <typename T, int G, int MIX>
 __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
     DevState* st = a.st;
     if (st->active == 0) return;
@@ -529,12 +634,22 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
         const double x2n = x1 + beta * (x1 - a.xi1p[e]);
         a.xi1p[e] = x1;
         a.xi2[e] = x2n;
-        xa[k] = (T)(-x2n);
+        if (MIX) {
+            __bf16* xb = (__bf16*)a.xiaug + j * a.kp;
+            __bf16 hi, lo;
+            bf16_split((float)(-x2n), hi, lo);
+            xb[k] = hi;
+            xb[n + k] = hi;
+            xb[2 * n + k] = lo;
+        } else {
+            xa[k] = (T)(-x2n);
+        }
         prod = a.X[e] * x2n;
     }
     const double d = group_sum<G>(prod);                    // x_j^T xi_j
     if (valid && k == n) {
-        xa[n] = (T)(d - y2n);
+        if (MIX) a.cvec[j] = (float)(d - y2n);
+        else xa[n] = (T)(d - y2n);
         ((T*)a.ycol)[j] = (T)y2n;
     }
     const double b0 = block_reduce(dy2, 0), b1 = block_reduce(dx2, 0);
@@ -566,7 +681,7 @@ __global__ __launch_bounds__(kBlock) void k_mapg_end(const double* blockpart, in
 // pass-precision operands from (y, xi); with write_state, also
 // y^(1)_0 = y^(2)_1 = y and likewise xi.
 
-template <typename T, int G>
+template <typename T, int G, int MIX>
 __global__ __launch_bounds__(kBlock) void k_set_point(PointArgs a) {
     constexpr int PER = kBlock / G;
     const int k = threadIdx.x % G;
@@ -580,18 +695,32 @@ __global__ __launch_bounds__(kBlock) void k_set_point(PointArgs a) {
         if (a.write_state) { a.xi1p[j * n + k] = x; a.xi2[j * n + k] = x; }
     }
     const double d = group_sum<G>(prod);
-    if (j >= a.ld || k >= a.kp) return;
-    T* xa = (T*)a.xiaug + j * a.kp;
-    if (valid) {
-        const double yj = a.y[j];
-        xa[k] = k < n ? (T)(-x) : (k == n ? (T)(d - yj) : (T)0);
-        if (k == n) {
-            ((T*)a.ycol)[j] = (T)yj;
-            if (a.write_state) { a.y1p[j] = yj; a.y2[j] = yj; }
+    if (j >= a.ld) return;
+    const double yj = valid ? a.y[j] : 0.0;
+    if (valid && k == n) {
+        ((T*)a.ycol)[j] = (T)yj;
+        if (a.write_state) { a.y1p[j] = yj; a.y2[j] = yj; }
+    } else if (!valid && k == 0 && j < a.Nrow) {
+        ((T*)a.ycol)[j] = (T)0;
+    }
+    if (MIX) {
+        // every BF16 slot of the column, lanes striding over them
+        __bf16* xb = (__bf16*)a.xiaug + j * a.kp;
+        for (int q = k; q < a.kp; q += G) {
+            __bf16 val = (__bf16)0.0f;
+            if (valid && q < 3 * n) {
+                const int kk = q % n;
+                __bf16 hi, lo;
+                bf16_split((float)(-a.xi[j * n + kk]), hi, lo);
+                val = q < 2 * n ? hi : lo;
+            }
+            xb[q] = val;
         }
+        if (k == 0) a.cvec[j] = valid ? (float)(d - yj) : 0.0f;
     } else {
-        xa[k] = (T)0;
-        if (k == 0 && j < a.Nrow) ((T*)a.ycol)[j] = (T)0;
+        if (k >= a.kp) return;
+        T* xa = (T*)a.xiaug + j * a.kp;
+        xa[k] = !valid ? (T)0 : (k < n ? (T)(-x) : (k == n ? (T)(d - yj) : (T)0));
     }
 }
 
@@ -632,6 +761,44 @@ __global__ __launch_bounds__(kBlock) void k_prep_xp(const double* X, int64_t N, 
         double val = 0.0;
         if (i < N) val = k < n ? X[i * n + k] : (k == n ? 1.0 : 0.0);
         xp[gid * qp + q] = (T)val;
+    }
+}
+
+// Packed mixed-precision X operands, one thread per (16-row tile, lane), as
+// 16-byte vectors: KB vectors of the residual A operand (slots 32 kb + 8 g + e
+// of [x_hi | x_lo | x_hi] for row i0 + c), then per column block kb2 the two
+// B operands of C: [X_hi rows 4g..4g+3, X_hi same rows] and [X_lo same rows, 0].
+__device__ __forceinline__ double xaug_at(const double* X, int64_t N, int n, int64_t i, int k) {
+    if (i >= N) return 0.0;
+    return k < n ? X[i * n + k] : (k == n ? 1.0 : 0.0);
+}
+__global__ __launch_bounds__(kBlock) void k_prep_xp_mixed(const double* X, int64_t N, int n, int64_t Nrow,
+                                                           int kb_r, int nkb, bf16x8* xp) {
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (gid >= (Nrow / 16) * 64) return;
+    const int64_t i0 = (gid / 64) * 16;
+    const int lane = (int)(gid % 64), g = lane >> 4, c = lane & 15;
+    bf16x8* out = xp + gid * (kb_r + 2 * nkb);
+    for (int kb = 0; kb < kb_r; ++kb) {
+        bf16x8 v;
+        for (int e = 0; e < 8; ++e) {
+            const int q = 32 * kb + 8 * g + e;
+            __bf16 hi = (__bf16)0.0f, lo = (__bf16)0.0f;
+            if (q < 3 * n) bf16_split((float)xaug_at(X, N, n, i0 + c, q % n), hi, lo);
+            v[e] = (q >= n && q < 2 * n) ? lo : hi;
+        }
+        out[kb] = v;
+    }
+    for (int kb = 0; kb < nkb; ++kb) {
+        bf16x8 v1, v2;
+        for (int e = 0; e < 4; ++e) {
+            __bf16 hi, lo;
+            bf16_split((float)xaug_at(X, N, n, i0 + 4 * g + e, 16 * kb + c), hi, lo);
+            v1[e] = hi; v1[e + 4] = hi;
+            v2[e] = lo; v2[e + 4] = (__bf16)0.0f;
+        }
+        out[kb_r + 2 * kb] = v1;
+        out[kb_r + 2 * kb + 1] = v2;
     }
 }
 
@@ -849,29 +1016,41 @@ __global__ void k_su_start_final(const double* part, int nblk, int64_t N, int n,
 // ---------------------------------------------------------------------------
 // Host-side launch helpers (called by the driver in cr_api.hip).
 // ---------------------------------------------------------------------------
-template <typename T, int KS>
-static hipError_t launch_pass_ks(const PassArgs& a, dim3 grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_pair_pass<T, KS>), grid, dim3(kBlock), 0, s, a);
+template <typename Ops>
+static hipError_t launch_pass_ops(const PassArgs& a, dim3 grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_pair_pass<Ops>), grid, dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t launch_pass_t(int ks, const PassArgs& a, dim3 grid, hipStream_t s) {
     switch (ks) {
-        case 1: return launch_pass_ks<T, 1>(a, grid, s);
-        case 2: return launch_pass_ks<T, 2>(a, grid, s);
-        case 3: return launch_pass_ks<T, 3>(a, grid, s);
-        case 4: return launch_pass_ks<T, 4>(a, grid, s);
-        case 5: return launch_pass_ks<T, 5>(a, grid, s);
-        case 6: return launch_pass_ks<T, 6>(a, grid, s);
-        case 7: return launch_pass_ks<T, 7>(a, grid, s);
-        case 8: return launch_pass_ks<T, 8>(a, grid, s);
+        case 1: return launch_pass_ops<PlainOps<T, 1>>(a, grid, s);
+        case 2: return launch_pass_ops<PlainOps<T, 2>>(a, grid, s);
+        case 3: return launch_pass_ops<PlainOps<T, 3>>(a, grid, s);
+        case 4: return launch_pass_ops<PlainOps<T, 4>>(a, grid, s);
+        case 5: return launch_pass_ops<PlainOps<T, 5>>(a, grid, s);
+        case 6: return launch_pass_ops<PlainOps<T, 6>>(a, grid, s);
+        case 7: return launch_pass_ops<PlainOps<T, 7>>(a, grid, s);
+        case 8: return launch_pass_ops<PlainOps<T, 8>>(a, grid, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_pair_pass(bool f64, int ks, const PassArgs& a, dim3 grid, hipStream_t s) {
-    return f64 ? launch_pass_t<double>(ks, a, grid, s) : launch_pass_t<float>(ks, a, grid, s);
+// Mixed: KB = ceil(3n / 32) BF16 k-blocks for R, NKB = ceil((n + 1) / 16) column blocks.
+static hipError_t launch_pass_mixed(int n, const PassArgs& a, dim3 grid, hipStream_t s) {
+    const int kb = mixed_kb(n), nkb = (n + 1 + 15) / 16;
+    if (kb == 1 && nkb == 1) return launch_pass_ops<MixedOps<1, 1>>(a, grid, s);
+    if (kb == 2 && nkb == 1) return launch_pass_ops<MixedOps<2, 1>>(a, grid, s);
+    if (kb == 2 && nkb == 2) return launch_pass_ops<MixedOps<2, 2>>(a, grid, s);
+    if (kb == 3 && nkb == 2) return launch_pass_ops<MixedOps<3, 2>>(a, grid, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_pair_pass(int prec, int n, const PassArgs& a, dim3 grid, hipStream_t s) {
+    if (prec == 2) return launch_pass_mixed(n, a, grid, s);
+    const int ks = ks_of(n);
+    return prec == 0 ? launch_pass_t<double>(ks, a, grid, s) : launch_pass_t<float>(ks, a, grid, s);
 }
 
 // Threads per point of the O(N n) kernels: the smallest of 16, 32 that holds n + 1.
@@ -883,15 +1062,15 @@ static void reduce_t(const ReduceArgs& a, hipStream_t s) {
     if (group_of(a.n) == 16) hipLaunchKernelGGL((k_reduce<T, 16>), points_grid(a.N, 16), dim3(kBlock), 0, s, a);
     else hipLaunchKernelGGL((k_reduce<T, 32>), points_grid(a.N, 32), dim3(kBlock), 0, s, a);
 }
-template <typename T>
+template <typename T, int MIX>
 static void update_t(const UpdateArgs& a, hipStream_t s) {
-    if (group_of(a.n) == 16) hipLaunchKernelGGL((k_update<T, 16>), points_grid(a.N, 16), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_update<T, 32>), points_grid(a.N, 32), dim3(kBlock), 0, s, a);
+    if (group_of(a.n) == 16) hipLaunchKernelGGL((k_update<T, 16, MIX>), points_grid(a.N, 16), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_update<T, 32, MIX>), points_grid(a.N, 32), dim3(kBlock), 0, s, a);
 }
-template <typename T>
+template <typename T, int MIX>
 static void set_point_t(const PointArgs& a, hipStream_t s) {
-    if (group_of(a.n) == 16) hipLaunchKernelGGL((k_set_point<T, 16>), points_grid(a.ld, 16), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_set_point<T, 32>), points_grid(a.ld, 32), dim3(kBlock), 0, s, a);
+    if (group_of(a.n) == 16) hipLaunchKernelGGL((k_set_point<T, 16, MIX>), points_grid(a.ld, 16), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_set_point<T, 32, MIX>), points_grid(a.ld, 32), dim3(kBlock), 0, s, a);
 }
 
 hipError_t launch_reduce(bool f64, const ReduceArgs& a, hipStream_t s) {
@@ -899,8 +1078,10 @@ hipError_t launch_reduce(bool f64, const ReduceArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_update(bool f64, const UpdateArgs& a, hipStream_t s) {
-    if (f64) update_t<double>(a, s); else update_t<float>(a, s);
+hipError_t launch_update(int prec, const UpdateArgs& a, hipStream_t s) {
+    if (prec == 0) update_t<double, 0>(a, s);
+    else if (prec == 1) update_t<float, 0>(a, s);
+    else update_t<float, 1>(a, s);
     return hipGetLastError();
 }
 
@@ -916,8 +1097,10 @@ hipError_t launch_mapg_end(const double* blockpart, int nblk, int64_t launched, 
     return hipGetLastError();
 }
 
-hipError_t launch_set_point(bool f64, const PointArgs& a, hipStream_t s) {
-    if (f64) set_point_t<double>(a, s); else set_point_t<float>(a, s);
+hipError_t launch_set_point(int prec, const PointArgs& a, hipStream_t s) {
+    if (prec == 0) set_point_t<double, 0>(a, s);
+    else if (prec == 1) set_point_t<float, 0>(a, s);
+    else set_point_t<float, 1>(a, s);
     return hipGetLastError();
 }
 
@@ -926,12 +1109,14 @@ hipError_t launch_begin_outer(const OuterArgs& args, OuterArgs* dst, DevState* s
     return hipGetLastError();
 }
 
-hipError_t launch_prep_xp(bool f64, const double* X, int64_t N, int n, int64_t Nrow, int ks, int qp, void* xp,
+hipError_t launch_prep_xp(int prec, const double* X, int64_t N, int n, int64_t Nrow, int ks, int qp, void* xp,
                           hipStream_t s) {
     const int64_t total = (Nrow / 16) * 64;
     const dim3 grid((unsigned)((total + kBlock - 1) / kBlock));
-    if (f64) hipLaunchKernelGGL(k_prep_xp<double>, grid, dim3(kBlock), 0, s, X, N, n, Nrow, ks, qp, (double*)xp);
-    else hipLaunchKernelGGL(k_prep_xp<float>, grid, dim3(kBlock), 0, s, X, N, n, Nrow, ks, qp, (float*)xp);
+    if (prec == 0) hipLaunchKernelGGL(k_prep_xp<double>, grid, dim3(kBlock), 0, s, X, N, n, Nrow, ks, qp, (double*)xp);
+    else if (prec == 1) hipLaunchKernelGGL(k_prep_xp<float>, grid, dim3(kBlock), 0, s, X, N, n, Nrow, ks, qp, (float*)xp);
+    else hipLaunchKernelGGL(k_prep_xp_mixed, grid, dim3(kBlock), 0, s, X, N, n, Nrow, mixed_kb(n), (n + 1 + 15) / 16,
+                            (bf16x8*)xp);
     return hipGetLastError();
 }
 

@@ -43,9 +43,9 @@ def rel(a, b):
 
 # Tolerances: FP64 pass vs FP64 oracle differs only by summation order (~1e-15
 # per term); the FP32 pass rounds theta, r and every in-tile sum to 24 bits.
-TOL_PASS = {0: 1e-12, 1: 3e-5}
-TOL_SOLVE = {0: 1e-9, 1: 1e-5}
-PREC_NAME = {0: "f64", 1: "f32"}
+TOL_PASS = {0: 1e-12, 1: 3e-5, 2: 3e-4}
+TOL_SOLVE = {0: 1e-9, 1: 1e-5, 2: 1e-3}
+PREC_NAME = {0: "f64", 1: "f32", 2: "mixed_bf16"}
 
 
 def _random_state(N, n, seed, theta_scale=0.3):
@@ -78,7 +78,7 @@ def test_setup_constants(cr, N, n):
     assert rel(host(xi0), xihat) < 1e-10
 
 
-@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "mixed"])
 @pytest.mark.parametrize("N,n", SHAPES)
 def test_grad_pass(cr, prec, N, n):
     say("grad_pass %s N=%d n=%d" % (PREC_NAME[prec], N, n))
@@ -90,11 +90,14 @@ def test_grad_pass(cr, prec, N, n):
     ey, exi = oracle.grad_P(X, ybar, gamma, mu, theta, y, xi)
     # compare the pair part (the (y - ybar)/mu term is exact on both sides)
     hy, hxi = host(gy), host(gxi)
-    assert rel(hy - (y - ybar) / mu, ey - (y - ybar) / mu) < TOL_PASS[prec]
-    assert rel(hxi - gamma / mu * xi, exi - gamma / mu * xi) < TOL_PASS[prec]
+    e1 = rel(hy - (y - ybar) / mu, ey - (y - ybar) / mu)
+    e2 = rel(hxi - gamma / mu * xi, exi - gamma / mu * xi)
+    say("  pass relative error: grad_y %.3e  grad_xi %.3e" % (e1, e2))
+    assert e1 < TOL_PASS[prec]
+    assert e2 < TOL_PASS[prec]
 
 
-@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "mixed"])
 @pytest.mark.parametrize("N,n", [(37, 3), (200, 2), (640, 10), (517, 20)])
 def test_theta_pass(cr, prec, N, n):
     say("theta_pass %s N=%d n=%d" % (PREC_NAME[prec], N, n))
@@ -112,7 +115,7 @@ def test_theta_pass(cr, prec, N, n):
     assert rel(host(sxi), gamma * xi - v) < TOL_PASS[prec] * 10
     m = oracle.kkt_measures(X, ybar, gamma, y, xi, lam)
     info = ctx.info()
-    t = 1e-10 if prec == 0 else 1e-4
+    t = {0: 1e-10, 1: 1e-4, 2: 1e-3}[prec]
     assert abs(info.infeas - m["infeas"]) <= t * max(1.0, m["infeas"])
     assert abs(info.compl - m["compl"]) <= t * max(1.0, m["compl"])
     assert abs(info.stat_y - m["stat_y"]) <= 10 * t * max(1.0, m["stat_y"])
@@ -134,15 +137,17 @@ def test_pass_is_deterministic(cr):
 FIXED_C1 = dict(inner_iters=50, max_outer=10)
 
 
-@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "mixed"])
 def test_fixed_schedule_small_quadratic(cr, prec):
     say("fixed schedule small_quadratic N=200 n=2 10x50 %s" % PREC_NAME[prec])
     p = synth.workload("small_quadratic")
     ref = oracle.alcc(p.X, p.ybar, oracle.Params(**FIXED_C1), record_kkt=False)
     y, xi, info = cr.solve(dev(p.X), dev(p.ybar), cr.Params(precision=prec, **FIXED_C1))
     assert info.inner_iters == 500 and info.outer_iters == 10
-    assert rel(host(y), ref.y) < TOL_SOLVE[prec]
-    assert rel(host(xi), ref.xi) < TOL_SOLVE[prec] * 10
+    ey, exi = rel(host(y), ref.y), rel(host(xi), ref.xi)
+    say("  relative error vs FP64 oracle: y %.3e  xi %.3e" % (ey, exi))
+    assert ey < TOL_SOLVE[prec]
+    assert exi < TOL_SOLVE[prec] * 10
 
 
 @pytest.mark.parametrize("N,n,seed", [(37, 3, 1), (130, 5, 2), (96, 20, 3)])
@@ -175,7 +180,7 @@ def test_adaptive_reaches_kkt(cr, prec):
     assert rel(host(y), ref.y) < 1e-3
 
 
-@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "mixed"])
 def test_full_size_pass_sampled(cr, prec):
     """One gradient pass at the 5000-point, n=10 workload, in the launch
     configuration the benchmark uses; sampled outputs recomputed by the oracle."""
@@ -192,7 +197,7 @@ def test_full_size_pass_sampled(cr, prec):
     ctx.set_theta(dev(theta))
     gy, gxi = ctx.pairwise_step(cr.GRAD, dev(y), dev(xi), mu)
     hy, hxi = host(gy), host(gxi)
-    tol = 1e-11 if prec == 0 else 2e-4
+    tol = {0: 1e-11, 1: 2e-4, 2: 2e-3}[prec]
     for m in [0, 1, 17, 2500, 4095, 4096, 4998, 4999]:
         row, col = oracle.residual_row_col(p.X, y, xi, m)
         wrow = np.maximum(theta[m] - row, 0.0); wrow[m] = 0.0
