@@ -197,6 +197,53 @@ cr_status cr_solve(const void* X_dev, const void* ybar_dev, int64_t N, int32_t n
                    const cr_params* params, void* y_dev, void* xi_dev,
                    void* workspace_dev, size_t ws_bytes, cr_info* info, void* stream);
 
+/* Batched form --------------------------------------------------------- */
+
+/*
+ * One of P independent problems of the batched form: N points of dimension n,
+ * device pointers to its FP64 inputs X (N x n), ybar (N) and outputs y (N),
+ * xi (N x n), all owned by the caller.
+ */
+typedef struct {
+    int64_t N;
+    int32_t n, pad;
+    const void* X_dev;
+    const void* ybar_dev;
+    void* y_dev;
+    void* xi_dev;
+} cr_problem;
+
+typedef struct cr_batch cr_batch;
+
+/* Bytes of device workspace for the batch (the sum of the single-problem
+ * workspaces plus argument tables).  Errors as cr_workspace_bytes, and
+ * CR_ERR_UNSUPPORTED for CR_MIXED_BF16 (the batched form runs CR_F64 and
+ * CR_F32). */
+cr_status cr_batch_workspace_bytes(const cr_problem* probs, int32_t P, const cr_params* params, size_t* bytes);
+
+/*
+ * Solve P independent instances of eq. "regularize" (Sec. II-C) with ALCC/MAPG
+ * (Fig. 3, Fig. 4), all problems advanced together: each MAPG iteration of
+ * every problem still running is one replay step of a captured graph made of
+ * one persistent pair pass per operand class (problems with equal
+ * ceil((n + 1) / 4)), one batched reduction and one batched update.  Every
+ * problem keeps its own schedule, multipliers and stopping tests (the same
+ * as cr_run), and a problem that reaches kkt_tol is frozen while the others
+ * continue.  The ALCC iterations of all problems advance in lockstep.
+ * cr_batch_init borrows the problems' buffers and the workspace until
+ * cr_batch_destroy; it runs every problem's set-up (host-synchronous).
+ * cr_batch_run is host-synchronous, writes every problem's y and xi, fills
+ * infos[0..P-1] when not NULL and the wall seconds when not NULL; returns
+ * CR_OK, CR_NOT_CONVERGED (some problem not converged), CR_ERR_NONFINITE or
+ * CR_ERR_HIP.  cr_solve_batched = init + run + destroy.
+ */
+cr_status cr_batch_init(cr_batch** out, const cr_problem* probs, int32_t P, const cr_params* params,
+                        void* workspace_dev, size_t ws_bytes, void* stream);
+cr_status cr_batch_run(cr_batch* batch, cr_info* infos, double* seconds);
+cr_status cr_batch_destroy(cr_batch* batch);
+cr_status cr_solve_batched(const cr_problem* probs, int32_t P, const cr_params* params, void* workspace_dev,
+                           size_t ws_bytes, cr_info* infos, void* stream);
+
 /* Inspection and test hooks --------------------------------------------- */
 
 /* Copy the context's theta to / from an N x N FP64 device array (diagonal

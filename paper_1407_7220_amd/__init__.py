@@ -19,7 +19,7 @@ from typing import Optional
 
 __all__ = [
     "Params", "Info", "CRError", "Context", "solve", "workspace_bytes", "lib_path",
-    "F64", "F32", "MIXED_BF16", "GRAD", "THETA_UPDATE", "MAX_DIM",
+    "F64", "F32", "MIXED_BF16", "GRAD", "THETA_UPDATE", "MAX_DIM", "Batch", "solve_batched",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -37,6 +37,12 @@ class _CParams(ctypes.Structure):
                 ("gamma", "mu1", "c", "kappa", "tau1", "alpha_y1", "alpha_xi1", "step_scale", "kkt_tol")] + \
                [(k, ctypes.c_int32) for k in ("max_outer", "inner_iters", "max_inner", "precision")] + \
                [(k, ctypes.c_double) for k in ("Ly_override", "Lxi_override", "By_override", "Bxi_override")]
+
+
+class _CProblem(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("n", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("X_dev", ctypes.c_void_p), ("ybar_dev", ctypes.c_void_p),
+                ("y_dev", ctypes.c_void_p), ("xi_dev", ctypes.c_void_p)]
 
 
 class _CInfo(ctypes.Structure):
@@ -73,6 +79,11 @@ def _load():
         "cr_get_start": (i32, [vp, vp, vp]),
         "cr_get_info": (i32, [vp, pi]),
         "cr_time_pass": (i32, [vp, i32, i32, ctypes.POINTER(dbl)]),
+        "cr_batch_workspace_bytes": (i32, [ctypes.POINTER(_CProblem), i32, pp, ctypes.POINTER(ctypes.c_size_t)]),
+        "cr_batch_init": (i32, [ctypes.POINTER(vp), ctypes.POINTER(_CProblem), i32, pp, vp, ctypes.c_size_t, vp]),
+        "cr_batch_run": (i32, [vp, pi, ctypes.POINTER(dbl)]),
+        "cr_batch_destroy": (i32, [vp]),
+        "cr_solve_batched": (i32, [ctypes.POINTER(_CProblem), i32, pp, vp, ctypes.c_size_t, pi, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -85,7 +96,8 @@ _lib = _load()
 
 EXPORTED = ("cr_params_default", "cr_status_string", "cr_last_error", "cr_workspace_bytes", "cr_init",
             "cr_destroy", "cr_pairwise_step", "cr_run", "cr_solve", "cr_get_theta", "cr_set_theta",
-            "cr_get_start", "cr_get_info", "cr_time_pass")
+            "cr_get_start", "cr_get_info", "cr_time_pass", "cr_batch_workspace_bytes", "cr_batch_init",
+            "cr_batch_run", "cr_batch_destroy", "cr_solve_batched")
 
 
 class CRError(RuntimeError):
@@ -277,3 +289,62 @@ def solve(X, ybar, params: Optional[Params] = None):
                          ctypes.c_void_p(xi.data_ptr()), ctypes.c_void_p(ws.data_ptr()), nbytes,
                          ctypes.byref(ci), _stream()), None, allow=(OK, NOT_CONVERGED))
     return y, xi, Info.from_c(ci)
+
+
+class Batch:
+    """Many independent problems solved together (cr_batch_*): problems is a list
+    of (X, ybar) float64 CUDA tensor pairs with their own N and n."""
+
+    def __init__(self, problems, params: Optional[Params] = None):
+        torch = _torch()
+        self.params = params or Params()
+        self._keep = []
+        self.P = len(problems)
+        arr = (_CProblem * self.P)()
+        self.outputs = []
+        for p, (X, ybar) in enumerate(problems):
+            N, n = int(X.shape[0]), int(X.shape[1])
+            px = _dev_f64(X, (N, n), "X[%d]" % p)
+            py = _dev_f64(ybar, (N,), "ybar[%d]" % p)
+            y = torch.empty(N, dtype=torch.float64, device=X.device)
+            xi = torch.empty(N, n, dtype=torch.float64, device=X.device)
+            self._keep += [X, ybar]
+            self.outputs.append((y, xi))
+            arr[p] = _CProblem(N, n, 0, px.value, py.value, y.data_ptr(), xi.data_ptr())
+        self._arr = arr
+        self._cp = self.params.to_c()
+        nbytes = ctypes.c_size_t(0)
+        _check(_lib.cr_batch_workspace_bytes(arr, self.P, ctypes.byref(self._cp), ctypes.byref(nbytes)))
+        self._ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=problems[0][0].device)
+        h = ctypes.c_void_p()
+        _check(_lib.cr_batch_init(ctypes.byref(h), arr, self.P, ctypes.byref(self._cp),
+                                  ctypes.c_void_p(self._ws.data_ptr()), int(nbytes.value), _stream()))
+        self._h = h
+
+    def run(self):
+        """Solve every problem; returns ([(y, xi), ...], [Info, ...], wall seconds)."""
+        infos = (_CInfo * self.P)()
+        secs = ctypes.c_double(0.0)
+        _check(_lib.cr_batch_run(self._h, infos, ctypes.byref(secs)), None, allow=(OK, NOT_CONVERGED))
+        return self.outputs, [Info.from_c(infos[p]) for p in range(self.P)], float(secs.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.cr_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batched(problems, params: Optional[Params] = None):
+    """cr_solve_batched: returns ([(y, xi), ...], [Info, ...]) for a list of (X, ybar) pairs."""
+    b = Batch(problems, params)
+    try:
+        outs, infos, _ = b.run()
+    finally:
+        b.close()
+    return outs, infos

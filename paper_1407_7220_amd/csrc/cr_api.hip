@@ -255,6 +255,72 @@ static cr_status build_graph(cr_ctx* c) {
     return CR_OK;
 }
 
+// ALCC schedule of one problem (Fig. 3 steps 1-2 and 5-6).
+struct Schedule {
+    double mu, tau, ay, axi;
+    int k = 0;
+    bool done = false, converged = false;
+    int64_t total_inner = 0;
+    cr::DevState last{};
+    void start(const cr_ctx* c) {
+        const cr_params& p = c->p;
+        mu = p.mu1 > 0 ? p.mu1 : 1.0 / (2.0 * (double)c->N);
+        tau = p.tau1;
+        ay = p.alpha_y1 > 0 ? p.alpha_y1 : 1e-2 * c->Bbar;
+        axi = p.alpha_xi1 > 0 ? p.alpha_xi1 : 1e-2 * c->Bbar;
+        k = 0;
+        done = converged = false;
+        total_inner = 0;
+        last = cr::DevState{};
+    }
+    // Arguments of ALCC iteration k + 1: L^y, L^xi, l^max and the steps.
+    cr::OuterArgs next(const cr_ctx* c) {
+        const cr_params& p = c->p;
+        ++k;
+        const double Ly = p.Ly_override > 0 ? p.Ly_override : 1.0 / mu + c->sigma2_A1;
+        const double Lxi = p.Lxi_override > 0 ? p.Lxi_override : p.gamma / mu + c->sigma2_A2;
+        int64_t lmax;
+        if (p.inner_iters > 0) {
+            lmax = p.inner_iters;
+        } else {
+            const double f = std::ceil(4.0 * std::sqrt((Ly * c->By * c->By + Lxi * c->Bxi * c->Bxi) / tau));
+            lmax = (int64_t)std::max(1.0, std::min(f, (double)p.max_inner));
+        }
+        cr::OuterArgs oa{};
+        oa.mu = mu; oa.gamma = p.gamma; oa.sy = p.step_scale / Ly; oa.sxi = p.step_scale / Lxi;
+        oa.alpha_y = ay; oa.alpha_xi = axi; oa.By = c->By; oa.Bxi = c->Bxi;
+        oa.theta_scale = 1.0 / p.c; oa.lmax = lmax; oa.adaptive = p.inner_iters > 0 ? 0 : 1; oa.skip = 0;
+        return oa;
+    }
+    double mu_next(const cr_ctx* c) const { return c->p.c * mu; }
+    // after the multiplier step of iteration k
+    void advance(const cr_ctx* c) {
+        const cr_params& p = c->p;
+        const double decay = std::pow(p.c * std::pow((double)k, 1.0 + p.kappa), 2.0);
+        mu = p.c * mu;
+        tau /= decay;
+        ay /= decay;
+        axi /= decay;
+    }
+};
+
+// The multiplier step at the MAPG output (y_k, xi_k) of one problem, which also
+// restarts MAPG there, followed by the KKT residuals; then a state read-back.
+// nblk: number of blocks of the update kernel that wrote the last step's norms.
+static hipError_t enqueue_multiplier_step(cr_ctx* c, double mu, double mu_next, int64_t launched, int nblk,
+                                          hipStream_t cs) {
+    const Layout& L = c->L;
+    hipError_t e = cr::launch_mapg_end(c->D(L.off_blockpart), nblk, launched, c->st, cs);
+    if (e != hipSuccess) return e;
+    cr::PointArgs pt = point_args(c, c->D(L.off_y1p), c->D(L.off_xi1p), 1);
+    if ((e = cr::launch_set_point(c->prec, pt, cs)) != hipSuccess) return e;
+    cr::PassArgs pa = pass_args(c, 1, mu / mu_next, &c->st->one);
+    if ((e = cr::launch_pair_pass(c->prec, c->n, pa, pass_grid(L), cs)) != hipSuccess) return e;
+    cr::ReduceArgs ra = reduce_args(c, 2, c->D(L.off_y1p), c->D(L.off_xi1p), nullptr, nullptr, mu);
+    if ((e = cr::launch_reduce(c->f64, ra, cs)) != hipSuccess) return e;
+    return hipMemcpyAsync(c->pinned_state, c->st, sizeof(cr::DevState), hipMemcpyDeviceToHost, cs);
+}
+
 extern "C" {
 
 cr_status cr_params_default(cr_params* p) {
@@ -500,33 +566,15 @@ cr_status cr_run(cr_ctx* c, void* y_dev, void* xi_dev, cr_info* info) {
     HIPCHK(c, cr::launch_set_point(c->prec, start, cs));
 
     const int64_t N = c->N;
-    const double gamma = p.gamma;
-    double mu = p.mu1 > 0 ? p.mu1 : 1.0 / (2.0 * (double)N);
-    double tau = p.tau1;
-    double ay = p.alpha_y1 > 0 ? p.alpha_y1 : 1e-2 * c->Bbar;
-    double axi = p.alpha_xi1 > 0 ? p.alpha_xi1 : 1e-2 * c->Bbar;
     const bool fixed = p.inner_iters > 0;
-    int64_t total_inner = 0;
-    int outer = 0;
-    bool converged = false;
+    Schedule sch;
+    sch.start(c);
     cr_status result = CR_OK;
     cr::DevState h{};
     for (int k = 1; k <= p.max_outer; ++k) {
-        outer = k;
-        const double Ly = p.Ly_override > 0 ? p.Ly_override : 1.0 / mu + c->sigma2_A1;
-        const double Lxi = p.Lxi_override > 0 ? p.Lxi_override : gamma / mu + c->sigma2_A2;
-        int64_t lmax;
-        if (fixed) {
-            lmax = p.inner_iters;
-        } else {
-            const double f = std::ceil(4.0 * std::sqrt((Ly * c->By * c->By + Lxi * c->Bxi * c->Bxi) / tau));
-            lmax = (int64_t)std::max(1.0, std::min(f, (double)p.max_inner));
-        }
-        const double mu_next = p.c * mu;
-        cr::OuterArgs oa{};
-        oa.mu = mu; oa.gamma = gamma; oa.sy = p.step_scale / Ly; oa.sxi = p.step_scale / Lxi;
-        oa.alpha_y = ay; oa.alpha_xi = axi; oa.By = c->By; oa.Bxi = c->Bxi;
-        oa.theta_scale = mu / mu_next; oa.lmax = lmax; oa.adaptive = fixed ? 0 : 1;
+        const cr::OuterArgs oa = sch.next(c);
+        const double mu = sch.mu, mu_next = sch.mu_next(c);
+        const int64_t lmax = oa.lmax;
         HIPCHK(c, cr::launch_begin_outer(oa, c->oa, c->st, cs));
 
         // MAPG: replay the captured iterations until the device clears `active`.
@@ -545,18 +593,10 @@ cr_status cr_run(cr_ctx* c, void* y_dev, void* xi_dev, cr_info* info) {
             pending = slot;
             slot ^= 1;
         }
-        HIPCHK(c, cr::launch_mapg_end(c->D(L.off_blockpart), cr::reduce_blocks(N, c->n), launched, c->st, cs));
-        // multiplier step at the MAPG output (y_k, xi_k), which also restarts MAPG there
-        cr::PointArgs pt = point_args(c, c->D(L.off_y1p), c->D(L.off_xi1p), 1);
-        HIPCHK(c, cr::launch_set_point(c->prec, pt, cs));
-        cr::PassArgs pa = pass_args(c, 1, mu / mu_next, &c->st->one);
-        HIPCHK(c, cr::launch_pair_pass(c->prec, c->n, pa, pass_grid(L), cs));
-        cr::ReduceArgs ra = reduce_args(c, 2, c->D(L.off_y1p), c->D(L.off_xi1p), nullptr, nullptr, mu);
-        HIPCHK(c, cr::launch_reduce(c->f64, ra, cs));
-        HIPCHK(c, hipMemcpyAsync(c->pinned_state, c->st, sizeof(cr::DevState), hipMemcpyDeviceToHost, cs));
+        HIPCHK(c, enqueue_multiplier_step(c, mu, mu_next, launched, cr::reduce_blocks(N, c->n), cs));
         HIPCHK(c, hipStreamSynchronize(cs));
         h = *c->pinned_state;
-        total_inner += h.it;
+        sch.total_inner += h.it;
         c->have_kkt = true;
         if (h.iterate_nonfinite) { result = CR_ERR_NONFINITE; break; }
         cr_info tmp{};
@@ -566,13 +606,12 @@ cr_status cr_run(cr_ctx* c, void* y_dev, void* xi_dev, cr_info* info) {
                          "infeas %.2e compl %.2e obj %.6e t %.3fs\n",
                          k, mu, (long long)h.it, h.stopped_by_alpha, tmp.kkt, h.stat_y, h.stat_xi, h.infeas, h.compl_,
                          h.obj, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
-        if (!fixed && tmp.kkt <= p.kkt_tol) { converged = true; break; }
-        const double decay = std::pow(p.c * std::pow((double)k, 1.0 + p.kappa), 2.0);
-        mu = mu_next;
-        tau /= decay;
-        ay /= decay;
-        axi /= decay;
+        if (!fixed && tmp.kkt <= p.kkt_tol) { sch.converged = true; break; }
+        sch.advance(c);
     }
+    const int outer = sch.k;
+    const int64_t total_inner = sch.total_inner;
+    const bool converged = sch.converged;
     HIPCHK(c, hipMemcpyAsync(y_dev, c->D(L.off_y1p), (size_t)N * 8, hipMemcpyDeviceToDevice, cs));
     HIPCHK(c, hipMemcpyAsync(xi_dev, c->D(L.off_xi1p), (size_t)N * c->n * 8, hipMemcpyDeviceToDevice, cs));
     HIPCHK(c, hipStreamSynchronize(cs));
@@ -627,6 +666,366 @@ cr_status cr_solve(const void* X_dev, const void* ybar_dev, int64_t N, int32_t n
         hipEventDestroy(done);
     }
     cr_destroy(c);
+    return s;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched form: many independent problems advanced in lockstep.  Each problem
+// owns a single-problem context in a slice of the batch workspace; one MAPG
+// iteration of every problem is [persistent pass per operand class,
+// batched reduce, batched update], captured kGraphIters times in one graph.
+// Converged problems are frozen (their activity flag stays 0).
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BatchItemH { int32_t p, strip, chunk, pad; };
+
+struct BatchPlan {
+    std::vector<Layout> L;
+    std::vector<size_t> off;     // sub-workspace offsets
+    size_t hdr = 0, total = 0;
+    int G = 16, nblocks = 0;
+    std::vector<int32_t> nblk;
+    std::vector<int> ks_classes;
+    std::vector<BatchItemH> items;          // grouped by class
+    std::vector<int> class_off, class_cnt;
+    size_t off_pass, off_red, off_upd, off_nstrips, off_blocks, off_nblk, off_sts, off_any, off_items;
+};
+
+cr_status check_batch(const cr_problem* probs, int32_t P, const cr_params* params, std::string& msg) {
+    if (!probs || P < 1) { msg = "probs must be non-NULL and P >= 1"; return CR_ERR_ARG; }
+    if (!check_params(params, msg)) return CR_ERR_ARG;
+    if (params->precision == CR_MIXED_BF16) { msg = "the batched form supports CR_F64 and CR_F32"; return CR_ERR_UNSUPPORTED; }
+    for (int p = 0; p < P; ++p) {
+        cr_status s = check_dims(probs[p].N, probs[p].n, msg);
+        if (s != CR_OK) { msg = "problem " + std::to_string(p) + ": " + msg; return s; }
+    }
+    return CR_OK;
+}
+
+BatchPlan plan_batch(const cr_problem* probs, int32_t P, const cr_params* params) {
+    BatchPlan B;
+    int nmax = 0;
+    for (int p = 0; p < P; ++p) nmax = std::max(nmax, (int)probs[p].n);
+    B.G = nmax + 1 <= 16 ? 16 : 32;
+    for (int p = 0; p < P; ++p) {
+        B.L.push_back(make_layout(probs[p].N, probs[p].n, params->precision, max_mapg_iters(*params)));
+        const int nb = (int)((probs[p].N * B.G + cr::kBlock - 1) / cr::kBlock);
+        B.nblk.push_back(nb);
+        B.nblocks += nb;
+        const int ks = cr::ks_of(probs[p].n);
+        if (std::find(B.ks_classes.begin(), B.ks_classes.end(), ks) == B.ks_classes.end()) B.ks_classes.push_back(ks);
+    }
+    std::sort(B.ks_classes.begin(), B.ks_classes.end());
+    for (int ks : B.ks_classes) {
+        B.class_off.push_back((int)B.items.size());
+        for (int p = 0; p < P; ++p) {
+            if (cr::ks_of(probs[p].n) != ks) continue;
+            for (int h = 0; h < B.L[p].chunks; ++h)
+                for (int st = 0; st < B.L[p].strips; ++st) B.items.push_back(BatchItemH{p, st, h, 0});
+        }
+        B.class_cnt.push_back((int)B.items.size() - B.class_off.back());
+    }
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    B.off_pass = take((size_t)P * sizeof(cr::PassArgs));
+    B.off_red = take((size_t)P * sizeof(cr::ReduceArgs));
+    B.off_upd = take((size_t)P * sizeof(cr::UpdateArgs));
+    B.off_nstrips = take((size_t)P * 4);
+    B.off_blocks = take((size_t)B.nblocks * 8);
+    B.off_nblk = take((size_t)P * 4);
+    B.off_sts = take((size_t)P * sizeof(void*));
+    B.off_any = take(64);
+    B.off_items = take(B.items.size() * sizeof(BatchItemH));
+    B.hdr = o;
+    for (int p = 0; p < P; ++p) B.off.push_back(take(B.L[p].total));
+    B.total = o + 256;
+    return B;
+}
+
+}  // namespace
+
+struct cr_batch {
+    int P = 0;
+    cr_params p{};
+    BatchPlan plan;
+    std::vector<cr_problem> probs;
+    std::vector<cr_ctx*> sub;
+    hipStream_t user_stream = nullptr, cs = nullptr;
+    hipGraphExec_t graph = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int32_t* pinned_flag = nullptr;
+    char* ws = nullptr;
+    bool f64 = false;
+    int grid = 512;
+    std::string err;
+};
+
+static cr_status bfail(cr_batch* b, cr_status s, const std::string& msg) {
+    if (b) b->err = msg;
+    g_last_error = msg;
+    return s;
+}
+
+#define BHIPCHK(b, call)                                                                         \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return bfail(b, CR_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+static cr_status build_batch_graph(cr_batch* b) {
+    if (b->graph) return CR_OK;
+    const BatchPlan& B = b->plan;
+    char* h = b->ws;
+    hipGraph_t g = nullptr;
+    BHIPCHK(b, hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < kGraphIters && e == hipSuccess; ++q) {
+        for (size_t ci = 0; ci < B.ks_classes.size() && e == hipSuccess; ++ci) {
+            const int grid = std::max(1, std::min(b->grid, B.class_cnt[ci]));
+            e = cr::launch_pass_batched(b->f64, B.ks_classes[ci], (const cr::PassArgs*)(h + B.off_pass),
+                                        (const int32_t*)(h + B.off_nstrips),
+                                        h + B.off_items + (size_t)B.class_off[ci] * sizeof(BatchItemH),
+                                        B.class_cnt[ci], grid, b->cs);
+        }
+        if (e == hipSuccess)
+            e = cr::launch_reduce_batched(b->f64, B.G, (const cr::ReduceArgs*)(h + B.off_red), h + B.off_blocks,
+                                          (const int32_t*)(h + B.off_nblk), B.nblocks, q, b->cs);
+        if (e == hipSuccess)
+            e = cr::launch_update_batched(b->f64, B.G, (const cr::UpdateArgs*)(h + B.off_upd), h + B.off_blocks,
+                                          (const int32_t*)(h + B.off_nblk), B.nblocks, q, b->cs);
+    }
+    if (e == hipSuccess)
+        e = cr::launch_replay_end_batched((cr::DevState* const*)(h + B.off_sts), b->P, kGraphIters,
+                                          (int32_t*)(h + B.off_any), b->cs);
+    hipError_t e2 = hipStreamEndCapture(b->cs, &g);
+    if (e != hipSuccess) return bfail(b, CR_ERR_HIP, std::string("batch capture: ") + hipGetErrorString(e));
+    if (e2 != hipSuccess) return bfail(b, CR_ERR_HIP, std::string("batch end capture: ") + hipGetErrorString(e2));
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) { b->graph = nullptr; return bfail(b, CR_ERR_HIP, std::string("batch instantiate: ") + hipGetErrorString(e)); }
+    return CR_OK;
+}
+
+extern "C" {
+
+cr_status cr_batch_workspace_bytes(const cr_problem* probs, int32_t P, const cr_params* params, size_t* bytes) {
+    std::string msg;
+    if (!bytes) return fail(nullptr, CR_ERR_ARG, "bytes is NULL");
+    cr_status s = check_batch(probs, P, params, msg);
+    if (s != CR_OK) return fail(nullptr, s, msg);
+    *bytes = plan_batch(probs, P, params).total;
+    return CR_OK;
+}
+
+cr_status cr_batch_destroy(cr_batch* b) {
+    if (!b) return CR_OK;
+    if (b->cs) hipStreamSynchronize(b->cs);
+    if (b->graph) hipGraphExecDestroy(b->graph);
+    for (cr_ctx* c : b->sub) cr_destroy(c);
+    for (int q = 0; q < 2; ++q)
+        if (b->ev[q]) hipEventDestroy(b->ev[q]);
+    if (b->pinned_flag) hipHostFree(b->pinned_flag);
+    if (b->cs) hipStreamDestroy(b->cs);
+    delete b;
+    return CR_OK;
+}
+
+cr_status cr_batch_init(cr_batch** out, const cr_problem* probs, int32_t P, const cr_params* params,
+                        void* workspace_dev, size_t ws_bytes, void* stream) {
+    std::string msg;
+    if (!out) return fail(nullptr, CR_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    cr_status s = check_batch(probs, P, params, msg);
+    if (s != CR_OK) return fail(nullptr, s, msg);
+    if (!workspace_dev) return fail(nullptr, CR_ERR_ARG, "workspace must be non-NULL");
+    for (int p = 0; p < P; ++p)
+        if (!probs[p].X_dev || !probs[p].ybar_dev || !probs[p].y_dev || !probs[p].xi_dev)
+            return fail(nullptr, CR_ERR_ARG, "problem " + std::to_string(p) + ": X, ybar, y and xi must be non-NULL");
+    BatchPlan B = plan_batch(probs, P, params);
+    if (ws_bytes < B.total) return fail(nullptr, CR_ERR_NOMEM, "workspace smaller than cr_batch_workspace_bytes()");
+    cr_batch* b = new (std::nothrow) cr_batch();
+    if (!b) return fail(nullptr, CR_ERR_NOMEM, "host allocation failed");
+    b->P = P;
+    b->p = *params;
+    b->plan = B;
+    b->probs.assign(probs, probs + P);
+    b->user_stream = (hipStream_t)stream;
+    b->ws = (char*)align256((size_t)workspace_dev);
+    b->f64 = params->precision == CR_F64;
+    auto bad = [&](cr_status st) { std::string m = g_last_error; cr_batch_destroy(b); g_last_error = m; return st; };
+    hipError_t e = hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking);
+    for (int q = 0; q < 2 && e == hipSuccess; ++q) e = hipEventCreateWithFlags(&b->ev[q], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b->pinned_flag, 64, hipHostMallocDefault);
+    if (e != hipSuccess) { fail(nullptr, CR_ERR_HIP, std::string("batch resources: ") + hipGetErrorString(e)); return bad(CR_ERR_HIP); }
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            b->grid = 2 * cus;
+    }
+    // per-problem contexts (set-up of each problem on its own slice)
+    for (int p = 0; p < P; ++p) {
+        cr_ctx* c = nullptr;
+        cr_status st = cr_init(&c, probs[p].N, probs[p].n, params, probs[p].X_dev, probs[p].ybar_dev,
+                               b->ws + B.off[p], B.L[p].total, stream);
+        if (st != CR_OK) { g_last_error = "problem " + std::to_string(p) + ": " + g_last_error; return bad(st); }
+        b->sub.push_back(c);
+    }
+    // device argument tables
+    std::vector<cr::PassArgs> pa(P);
+    std::vector<cr::ReduceArgs> ra(P);
+    std::vector<cr::UpdateArgs> ua(P);
+    std::vector<int32_t> nstrips(P);
+    std::vector<int32_t> blocks;
+    std::vector<void*> sts(P);
+    for (int p = 0; p < P; ++p) {
+        cr_ctx* c = b->sub[p];
+        const Layout& L = c->L;
+        pa[p] = pass_args(c, 0, 0.0, &c->st->active);
+        ra[p] = reduce_args(c, 0, c->D(L.off_y2), c->D(L.off_xi2), c->D(L.off_vy), c->D(L.off_vxi), 0.0);
+        ua[p] = update_args(c);
+        nstrips[p] = L.strips;
+        sts[p] = c->st;
+        for (int q = 0; q < B.nblk[p]; ++q) { blocks.push_back(p); blocks.push_back(q); }
+    }
+    char* h = b->ws;
+    e = hipMemcpy(h + B.off_pass, pa.data(), P * sizeof(cr::PassArgs), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h + B.off_red, ra.data(), P * sizeof(cr::ReduceArgs), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h + B.off_upd, ua.data(), P * sizeof(cr::UpdateArgs), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h + B.off_nstrips, nstrips.data(), P * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h + B.off_blocks, blocks.data(), blocks.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h + B.off_nblk, B.nblk.data(), P * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h + B.off_sts, sts.data(), P * sizeof(void*), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !B.items.empty())
+        e = hipMemcpy(h + B.off_items, B.items.data(), B.items.size() * sizeof(BatchItemH), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { fail(nullptr, CR_ERR_HIP, std::string("batch tables: ") + hipGetErrorString(e)); return bad(CR_ERR_HIP); }
+    *out = b;
+    return CR_OK;
+}
+
+cr_status cr_batch_run(cr_batch* b, cr_info* infos, double* seconds) {
+    if (!b) return fail(nullptr, CR_ERR_ARG, "batch is NULL");
+    const int P = b->P;
+    const cr_params& p = b->p;
+    const bool fixed = p.inner_iters > 0;
+    hipStream_t cs = b->cs;
+    BHIPCHK(b, hipEventRecord(b->ev[0], b->user_stream));
+    BHIPCHK(b, hipStreamWaitEvent(cs, b->ev[0], 0));
+    cr_status bs = build_batch_graph(b);
+    if (bs != CR_OK) return bs;
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<Schedule> sch(P);
+    for (int q = 0; q < P; ++q) {
+        cr_ctx* c = b->sub[q];
+        const Layout& L = c->L;
+        BHIPCHK(b, cr::launch_zero(c->P(L.off_theta), (size_t)L.Nrow * L.ld * L.esz, cs));
+        cr::PointArgs start = point_args(c, c->D(L.off_y0), c->D(L.off_xi0), 1);
+        BHIPCHK(b, cr::launch_set_point(c->prec, start, cs));
+        sch[q].start(c);
+    }
+    cr_status result = CR_OK;
+    std::vector<double> mus(P), mun(P);
+    for (int k = 1; k <= p.max_outer; ++k) {
+        int64_t lmax_all = 0;
+        for (int q = 0; q < P; ++q) {
+            cr_ctx* c = b->sub[q];
+            cr::OuterArgs oa{};
+            if (!sch[q].done) {
+                oa = sch[q].next(c);
+                mus[q] = sch[q].mu;
+                mun[q] = sch[q].mu_next(c);
+                lmax_all = std::max(lmax_all, oa.lmax);
+            } else {
+                oa.skip = 1;
+                oa.lmax = 0;
+            }
+            BHIPCHK(b, cr::launch_begin_outer(oa, c->oa, c->st, cs));
+        }
+        if (lmax_all == 0) break;
+        int64_t launched = 0;
+        int slot = 0, pending = -1;
+        int32_t* any = (int32_t*)(b->ws + b->plan.off_any);
+        while (launched < lmax_all) {
+            BHIPCHK(b, hipGraphLaunch(b->graph, cs));
+            launched += kGraphIters;
+            if (fixed) continue;
+            BHIPCHK(b, hipMemcpyAsync(b->pinned_flag + slot, any, 4, hipMemcpyDeviceToHost, cs));
+            BHIPCHK(b, hipEventRecord(b->ev[slot], cs));
+            if (pending >= 0) {
+                BHIPCHK(b, hipEventSynchronize(b->ev[pending]));
+                if (b->pinned_flag[pending] == 0) break;
+            }
+            pending = slot;
+            slot ^= 1;
+        }
+        for (int q = 0; q < P; ++q)
+            if (!sch[q].done)
+                BHIPCHK(b, enqueue_multiplier_step(b->sub[q], mus[q], mun[q], launched, b->plan.nblk[q], cs));
+        BHIPCHK(b, hipStreamSynchronize(cs));
+        bool all_done = true;
+        for (int q = 0; q < P; ++q) {
+            if (sch[q].done) continue;
+            cr_ctx* c = b->sub[q];
+            const cr::DevState h = *c->pinned_state;
+            sch[q].total_inner += h.it;
+            sch[q].last = h;
+            if (h.iterate_nonfinite) { result = CR_ERR_NONFINITE; sch[q].done = true; continue; }
+            cr_info tmp{};
+            fill_info(c, h, &tmp);
+            if (!fixed && tmp.kkt <= p.kkt_tol) { sch[q].converged = true; sch[q].done = true; continue; }
+            sch[q].advance(c);
+            all_done = false;
+        }
+        if (all_done) break;
+    }
+    for (int q = 0; q < P; ++q) {
+        cr_ctx* c = b->sub[q];
+        const Layout& L = c->L;
+        BHIPCHK(b, hipMemcpyAsync(b->probs[q].y_dev, c->D(L.off_y1p), (size_t)c->N * 8, hipMemcpyDeviceToDevice, cs));
+        BHIPCHK(b, hipMemcpyAsync(b->probs[q].xi_dev, c->D(L.off_xi1p), (size_t)c->N * c->n * 8,
+                                  hipMemcpyDeviceToDevice, cs));
+    }
+    BHIPCHK(b, hipStreamSynchronize(cs));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (seconds) *seconds = secs;
+    bool all_conv = true;
+    for (int q = 0; q < P; ++q) all_conv = all_conv && (fixed || sch[q].converged);
+    if (result == CR_OK && !all_conv) result = CR_NOT_CONVERGED;
+    if (infos) {
+        for (int q = 0; q < P; ++q) {
+            cr_ctx* c = b->sub[q];
+            cr_info& info = infos[q];
+            std::memset(&info, 0, sizeof(info));
+            fill_info(c, sch[q].last, &info);
+            info.outer_iters = sch[q].k;
+            info.inner_iters = sch[q].total_inner;
+            info.seconds = secs;
+            info.pair_updates = (double)c->N * (double)(c->N - 1) * (double)sch[q].total_inner;
+            info.status = sch[q].last.iterate_nonfinite ? CR_ERR_NONFINITE
+                          : (fixed || sch[q].converged ? CR_OK : CR_NOT_CONVERGED);
+        }
+    }
+    if (result == CR_ERR_NONFINITE) return bfail(b, result, "non-finite iterate");
+    return result;
+}
+
+cr_status cr_solve_batched(const cr_problem* probs, int32_t P, const cr_params* params, void* workspace_dev,
+                           size_t ws_bytes, cr_info* infos, void* stream) {
+    cr_batch* b = nullptr;
+    cr_status s = cr_batch_init(&b, probs, P, params, workspace_dev, ws_bytes, stream);
+    if (s != CR_OK) return s;
+    s = cr_batch_run(b, infos, nullptr);
+    if (s != CR_OK && s != CR_NOT_CONVERGED) g_last_error = b->err;
+    hipEvent_t done = nullptr;
+    if (hipEventCreateWithFlags(&done, hipEventDisableTiming) == hipSuccess) {
+        hipEventRecord(done, b->cs);
+        hipStreamWaitEvent((hipStream_t)stream, done, 0);
+        hipEventDestroy(done);
+    }
+    cr_batch_destroy(b);
     return s;
 }
 

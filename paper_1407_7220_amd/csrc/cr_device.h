@@ -20,7 +20,7 @@ struct OuterArgs {
     double theta_scale;   // mu_k / mu_{k+1}
     int64_t lmax;         // l^max_k
     int32_t adaptive;     // 1: alpha tests of Fig. 4 active
-    int32_t pad;
+    int32_t skip;         // 1: problem already converged (batched form); MAPG does not run
 };
 
 // Device-side state.  Written by kernels only (the host reads it back).
@@ -142,6 +142,16 @@ hipError_t launch_begin_outer(const OuterArgs& args, OuterArgs* dst, DevState* s
 hipError_t launch_replay_end(DevState* st, int iters, hipStream_t s);
 hipError_t launch_mapg_end(const double* blockpart, int nblk, int64_t launched, DevState* st, hipStream_t s);
 int reduce_blocks(int64_t N, int n);
+int reduce_blocks_g(int64_t N, int G);
+// Batched form (plain precisions): see cr_batch.hip.
+// One persistent pass per operand class ks = ceil((n + 1) / 4) over that class's items.
+hipError_t launch_pass_batched(bool f64, int ks, const PassArgs* args, const int32_t* nstrips, const void* items,
+                               int nitems, int grid, hipStream_t s);
+hipError_t launch_reduce_batched(bool f64, int G, const ReduceArgs* args, const void* blocks, const int32_t* nblk,
+                                 int nblocks, int q, hipStream_t s);
+hipError_t launch_update_batched(bool f64, int G, const UpdateArgs* args, const void* blocks, const int32_t* nblk,
+                                 int nblocks, int q, hipStream_t s);
+hipError_t launch_replay_end_batched(DevState* const* sts, int P, int iters, int32_t* any_active, hipStream_t s);
 hipError_t launch_prep_xp(int prec, const double* X, int64_t N, int n, int64_t Nrow, int ks, int qp, void* xp,
                           hipStream_t s);
 hipError_t launch_theta_import(bool f64, const double* src, int64_t N, int64_t Nrow, int64_t ld, void* theta,

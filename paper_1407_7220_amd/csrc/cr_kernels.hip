@@ -137,14 +137,14 @@ __device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 acc) {
 }
 
 // FP64 / FP32: 16x16x4 MFMA in the pass precision; c_j and y_i enter R exactly.
-template <typename T, int KS> struct PlainOps {
+template <typename T, int KS, int NSET_ = 0> struct PlainOps {
     typedef T elem;
     typedef typename Tr<T>::acc acc_t;
     static constexpr int TW = Tr<T>::TW;
     static constexpr int NKB = nkb_of_ks(KS);
     static constexpr int QP = qp_of_ks(KS, (int)sizeof(T));
     static constexpr int EV = 16 / (int)sizeof(T);
-    static constexpr int NSET = sizeof(T) == 4 ? 3 : 2;
+    static constexpr int NSET = NSET_ > 0 ? NSET_ : (sizeof(T) == 4 ? 3 : 2);
     static constexpr int RM4 = sizeof(T) == 4;   // accumulator row map 4 g + v (else g + 4 v)
     struct Breg { T b[KS][TW]; };
     struct Xop { T q[QP]; };
@@ -259,24 +259,28 @@ template <typename Ops> __device__ __forceinline__ int orow(int g, int v) {
 // accumulator element v, the pair (i0 + rmap(g, v), J0 + TW c + t), so its
 // TW theta values of one row are contiguous (one 16-byte load per row).
 // ---------------------------------------------------------------------------
-template <typename Ops>
-__global__ __launch_bounds__(kBlock) void k_pair_pass(PassArgs a) {
+// LDS of one pass workgroup: the 4 waves' column-sum accumulators (at most
+// 4 x TW x NKB x 4 x 64 elements = 32 KiB in every precision) and 4 x 4 KKT doubles.
+constexpr int kPassLds = 32768 + 256;
+
+template <typename Ops, int THETA_MODE>
+__device__ void pair_pass_item(const PassArgs& a, const int strip, const int chunk, const int nstrips,
+                               char* __restrict__ lds) {
     typedef typename Ops::elem T;
     typedef typename Ops::acc_t acc_t;
     constexpr int TW = Ops::TW;
     constexpr int NKB = Ops::NKB;
     constexpr int EV = 16 / (int)sizeof(T);
 
-    if (*a.active == 0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, c = lane & 15;
-    const int64_t J0 = (int64_t)blockIdx.x * (16 * TW);
-    const int64_t I0 = (int64_t)blockIdx.y * a.rows_per_chunk;
+    const int64_t J0 = (int64_t)strip * (16 * TW);
+    const int64_t I0 = (int64_t)chunk * a.rows_per_chunk;
     const int64_t I1 = min(I0 + (int64_t)a.rows_per_chunk, a.Nrow);
     const int64_t jl = J0 + TW * c;
     const T* __restrict__ ycol = (const T*)a.ycol;
     T* __restrict__ theta = (T*)a.theta;
-    const bool theta_mode = a.mode == 1;
+    constexpr bool theta_mode = THETA_MODE != 0;
 
     typename Ops::Breg breg;
     Ops::load_breg(breg, a, jl, g);
@@ -331,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_pass(PassArgs a) {
                 }
         }
 
-        if (theta_mode) {
+        if constexpr (theta_mode) {
             // Fig. 3 step 4 in place, and the pair terms of the KKT residual
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -370,7 +374,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_pass(PassArgs a) {
         }
         if (c == 0) {
             // rowpart[strip][i]: the 16 row sums of a tile are contiguous
-            T* dst = (T*)a.rowpart + (int64_t)blockIdx.x * a.Nrow + i0;
+            T* dst = (T*)a.rowpart + (int64_t)strip * a.Nrow + i0;
             if (Ops::RM4 && sizeof(T) == 4) {
                 V16<T> o;
 #pragma unroll
@@ -405,7 +409,9 @@ __global__ __launch_bounds__(kBlock) void k_pair_pass(PassArgs a) {
     }
 
     // Combine the 4 waves' column sums (fixed order) and write this chunk's partial.
-    __shared__ T cl[kWaves][TW][NKB][4][64];
+    static_assert(sizeof(T) * kWaves * TW * NKB * 4 * 64 <= 32768, "pass LDS");
+    typedef T cl_t[TW][NKB][4][64];
+    cl_t* cl = reinterpret_cast<cl_t*>(lds);
 #pragma unroll
     for (int t = 0; t < TW; ++t)
 #pragma unroll
@@ -421,23 +427,50 @@ __global__ __launch_bounds__(kBlock) void k_pair_pass(PassArgs a) {
         const int64_t j = J0 + TW * orow<Ops>(ln >> 4, v) + t;
         const int kk = 16 * kb + (ln & 15);
         // cpart[chunk][j][k]: this workgroup's columns are one contiguous range
-        if (kk < a.nc) cpart[((int64_t)blockIdx.y * a.ld + j) * a.nc + kk] = s;
+        if (kk < a.nc) cpart[((int64_t)chunk * a.ld + j) * a.nc + kk] = s;
     }
 
-    if (theta_mode) {
-        __shared__ double kr[4][kWaves];
+    if constexpr (theta_mode) {
+        double (*kr)[kWaves] = reinterpret_cast<double (*)[kWaves]>(lds + 32768);
         double q0 = wave_max(k_rneg_max), q1 = wave_sum(k_rneg_sq);
         double q2 = wave_max(k_wr_max), q3 = wave_sum(k_wr_sum);
         if (lane == 0) { kr[0][wave] = q0; kr[1][wave] = q1; kr[2][wave] = q2; kr[3][wave] = q3; }
         __syncthreads();
         if (threadIdx.x == 0) {
-            double* o = a.kktpart + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 4;
+            double* o = a.kktpart + ((int64_t)chunk * nstrips + strip) * 4;
             double m0 = kr[0][0], s1 = kr[1][0], m2 = kr[2][0], s3 = kr[3][0];
             for (int w = 1; w < kWaves; ++w) {
                 m0 = fmax(m0, kr[0][w]); s1 += kr[1][w]; m2 = fmax(m2, kr[2][w]); s3 += kr[3][w];
             }
             o[0] = m0; o[1] = s1; o[2] = m2; o[3] = s3;
         }
+    }
+}
+
+// WAVES: minimum waves per SIMD the register allocation must allow (3 for the
+// plain gradient passes with KS <= 4, which then need no spills; 2 otherwise).
+template <typename Ops, int THETA_MODE, int WAVES>
+__global__ __launch_bounds__(kBlock, WAVES) void k_pair_pass(PassArgs a) {
+    if (*a.active == 0) return;
+    __shared__ __align__(16) char lds[kPassLds];
+    pair_pass_item<Ops, THETA_MODE>(a, blockIdx.x, blockIdx.y, gridDim.x, lds);
+}
+
+// Batched pass: a persistent grid walks the (problem, strip, chunk) items of
+// every problem in a fixed round-robin order, skipping problems whose MAPG has
+// stopped.  Each item is one workgroup tile of the single-problem pass.
+struct BatchItem { int32_t p, strip, chunk, pad; };
+
+template <typename T, int KS>
+__global__ __launch_bounds__(kBlock) void k_pair_pass_batched(const PassArgs* args, const int32_t* nstrips_of_p,
+                                                              const BatchItem* items, int nitems) {
+    __shared__ __align__(16) char lds[kPassLds];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const BatchItem item = items[it];
+        const PassArgs& a = args[item.p];
+        if (*a.active == 0) continue;
+        pair_pass_item<PlainOps<T, KS>, 0>(a, item.strip, item.chunk, nstrips_of_p[item.p], lds);
+        __syncthreads();   // the next item reuses this workgroup's LDS
     }
 }
 
@@ -463,7 +496,7 @@ __device__ double block_gather(const double* part, int count, int q, int op) {
 }
 
 template <typename T, int G>
-__global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) {
+__device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk) {
     DevState* st = a.st;
     if (a.mode == 0) {
         if (st->active == 0) return;
@@ -471,11 +504,11 @@ __global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) {
         // pieces that k_update left: every block takes the same decision.
         const int64_t l = st->base + a.q + 1;
         if (l > 1) {
-            const double dy = sqrt(block_gather(a.blockpart, gridDim.x, 2, 0));
-            const double dxi = sqrt(block_gather(a.blockpart, gridDim.x, 3, 0));
+            const double dy = sqrt(block_gather(a.blockpart, nblk, 2, 0));
+            const double dxi = sqrt(block_gather(a.blockpart, nblk, 3, 0));
             const bool alpha_stop = a.oa->adaptive && dy <= a.oa->alpha_y && dxi <= a.oa->alpha_xi;
             if (alpha_stop || l - 1 >= a.oa->lmax) {
-                if (blockIdx.x == 0 && threadIdx.x == 0) {
+                if (blk == 0 && threadIdx.x == 0) {
                     st->active = 0;
                     st->it = l - 1;
                     st->stopped_by_alpha = alpha_stop ? 1 : 0;
@@ -488,7 +521,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) {
     }
     constexpr int PER = kBlock / G;
     const int k = threadIdx.x % G;
-    const int64_t j = (int64_t)blockIdx.x * PER + threadIdx.x / G;
+    const int64_t j = (int64_t)blk * PER + threadIdx.x / G;
     const bool valid = j < a.N;
     const T* rowpart = (const T*)a.rowpart;
     const T* cpart = (const T*)a.cpart;
@@ -552,7 +585,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) {
     if (a.mode == 0) {
         // per-block pieces of ||v_y - ybar||^2 and ||v_xi||^2; k_update combines them
         const double b0 = block_reduce(acc0, 0), b1 = block_reduce(acc1, 0);
-        if (threadIdx.x == 0) { a.blockpart[blockIdx.x * 4 + 0] = b0; a.blockpart[blockIdx.x * 4 + 1] = b1; }
+        if (threadIdx.x == 0) { a.blockpart[blk * 4 + 0] = b0; a.blockpart[blk * 4 + 1] = b1; }
         return;
     }
     // mode 2: KKT residuals of the multiplier step
@@ -560,16 +593,16 @@ __global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) {
     const double b2 = block_reduce(acc2, 0), b3 = block_reduce(acc3, 0);
     const double bb = block_reduce(bad ? 1.0 : 0.0, 1);
     if (threadIdx.x == 0) {
-        a.blockpart[blockIdx.x * 4 + 0] = b0;
-        a.blockpart[blockIdx.x * 4 + 1] = b1;
-        a.blockpart[blockIdx.x * 4 + 2] = b2;
-        a.blockpart[blockIdx.x * 4 + 3] = bb > 0.0 ? INFINITY : b3;
+        a.blockpart[blk * 4 + 0] = b0;
+        a.blockpart[blk * 4 + 1] = b1;
+        a.blockpart[blk * 4 + 2] = b2;
+        a.blockpart[blk * 4 + 3] = bb > 0.0 ? INFINITY : b3;
     }
     if (last_block(&st->cnt[1])) {
-        const double m0 = block_gather(a.blockpart, gridDim.x, 0, 1);
-        const double m1 = block_gather(a.blockpart, gridDim.x, 1, 1);
-        const double s2 = block_gather(a.blockpart, gridDim.x, 2, 0);
-        const double s3 = block_gather(a.blockpart, gridDim.x, 3, 0);
+        const double m0 = block_gather(a.blockpart, nblk, 0, 1);
+        const double m1 = block_gather(a.blockpart, nblk, 1, 1);
+        const double s2 = block_gather(a.blockpart, nblk, 2, 0);
+        const double s3 = block_gather(a.blockpart, nblk, 3, 0);
         const double p0 = block_gather(a.kktpart, a.npass, 0, 1);
         const double p1 = block_gather(a.kktpart, a.npass, 1, 0);
         const double p2 = block_gather(a.kktpart, a.npass, 2, 1);
@@ -602,18 +635,18 @@ __device__ __forceinline__ void bf16_split(float v, __bf16& hi, __bf16& lo) {
 }
 
 template <typename T, int G, int MIX>
-__global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
+__device__ void update_block(const UpdateArgs& a, const int blk, const int nblk) {
     DevState* st = a.st;
     if (st->active == 0) return;
     constexpr int PER = kBlock / G;
     const int k = threadIdx.x % G;
-    const int64_t j = (int64_t)blockIdx.x * PER + threadIdx.x / G;
+    const int64_t j = (int64_t)blk * PER + threadIdx.x / G;
     const bool valid = j < a.N;
     const int n = a.n;
     const double beta = a.beta[st->base + a.q + 1];   // (t_l - 1) / t_{l+1}
     // ball projections (Fig. 4 steps 1-2): every block forms the same norms
-    const double ny = sqrt(block_gather(a.blockpart, gridDim.x, 0, 0));
-    const double nx = sqrt(block_gather(a.blockpart, gridDim.x, 1, 0));
+    const double ny = sqrt(block_gather(a.blockpart, nblk, 0, 0));
+    const double nx = sqrt(block_gather(a.blockpart, nblk, 1, 0));
     const double sc_y = ny > a.oa->By ? a.oa->By / ny : 1.0;
     const double sc_xi = nx > a.oa->Bxi ? a.oa->Bxi / nx : 1.0;
     double dy2 = 0.0, dx2 = 0.0, prod = 0.0, y2n = 0.0;
@@ -653,7 +686,54 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
         ((T*)a.ycol)[j] = (T)y2n;
     }
     const double b0 = block_reduce(dy2, 0), b1 = block_reduce(dx2, 0);
-    if (threadIdx.x == 0) { a.blockpart[blockIdx.x * 4 + 2] = b0; a.blockpart[blockIdx.x * 4 + 3] = b1; }
+    if (threadIdx.x == 0) { a.blockpart[blk * 4 + 2] = b0; a.blockpart[blk * 4 + 3] = b1; }
+}
+
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) {
+    reduce_block<T, G>(a, blockIdx.x, gridDim.x);
+}
+
+template <typename T, int G, int MIX>
+__global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
+    update_block<T, G, MIX>(a, blockIdx.x, gridDim.x);
+}
+
+// Batched O(N n) kernels: block b of the launch is local block blocks[b].y of
+// problem blocks[b].x (blocks never straddle problems), nblk_of_p its count.
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_reduce_batched(const ReduceArgs* args, const int2* blocks,
+                                                           const int32_t* nblk_of_p, int q) {
+    const int2 bp = blocks[blockIdx.x];
+    ReduceArgs a = args[bp.x];
+    a.q = q;
+    reduce_block<T, G>(a, bp.y, nblk_of_p[bp.x]);
+}
+
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_update_batched(const UpdateArgs* args, const int2* blocks,
+                                                           const int32_t* nblk_of_p, int q) {
+    const int2 bp = blocks[blockIdx.x];
+    UpdateArgs a = args[bp.x];
+    a.q = q;
+    update_block<T, G, 0>(a, bp.y, nblk_of_p[bp.x]);
+}
+
+// After each batched graph replay: advance every problem's iteration base and
+// record whether any problem's MAPG is still running.
+__global__ void k_replay_end_batched(DevState* const* sts, int P, int iters, int32_t* any_active) {
+    if (blockIdx.x != 0) return;
+    int any = 0;
+    for (int p = threadIdx.x; p < P; p += blockDim.x) {
+        sts[p]->base += iters;
+        any |= sts[p]->active;
+    }
+    __shared__ int s_any;
+    if (threadIdx.x == 0) s_any = 0;
+    __syncthreads();
+    if (any) atomicOr(&s_any, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) *any_active = s_any;
 }
 
 // After each graph replay: advance the iteration base by the replay length.
@@ -729,7 +809,7 @@ __global__ void k_begin_outer(OuterArgs args, OuterArgs* dst, DevState* st) {
         *dst = args;
         st->base = 0;
         st->it = 0;
-        st->active = 1;
+        st->active = args.skip ? 0 : 1;
         st->stopped_by_alpha = 0;
         st->one = 1;
         for (int q = 0; q < 4; ++q) st->cnt[q] = 0u;
@@ -1016,18 +1096,19 @@ __global__ void k_su_start_final(const double* part, int nblk, int64_t N, int n,
 // ---------------------------------------------------------------------------
 // Host-side launch helpers (called by the driver in cr_api.hip).
 // ---------------------------------------------------------------------------
-template <typename Ops>
+template <typename Ops, int GRAD_WAVES = 2>
 static hipError_t launch_pass_ops(const PassArgs& a, dim3 grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_pair_pass<Ops>), grid, dim3(kBlock), 0, s, a);
+    if (a.mode == 1) hipLaunchKernelGGL((k_pair_pass<Ops, 1, 2>), grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_pair_pass<Ops, 0, GRAD_WAVES>), grid, dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t launch_pass_t(int ks, const PassArgs& a, dim3 grid, hipStream_t s) {
     switch (ks) {
-        case 1: return launch_pass_ops<PlainOps<T, 1>>(a, grid, s);
-        case 2: return launch_pass_ops<PlainOps<T, 2>>(a, grid, s);
-        case 3: return launch_pass_ops<PlainOps<T, 3>>(a, grid, s);
+        case 1: return launch_pass_ops<PlainOps<T, 1>, 3>(a, grid, s);
+        case 2: return launch_pass_ops<PlainOps<T, 2>, 3>(a, grid, s);
+        case 3: return launch_pass_ops<PlainOps<T, 3>, 3>(a, grid, s);
         case 4: return launch_pass_ops<PlainOps<T, 4>>(a, grid, s);
         case 5: return launch_pass_ops<PlainOps<T, 5>>(a, grid, s);
         case 6: return launch_pass_ops<PlainOps<T, 6>>(a, grid, s);
@@ -1086,6 +1167,67 @@ hipError_t launch_update(int prec, const UpdateArgs& a, hipStream_t s) {
 }
 
 int reduce_blocks(int64_t N, int n) { return (int)points_grid(N, group_of(n)).x; }
+int reduce_blocks_g(int64_t N, int G) { return (int)points_grid(N, G).x; }
+
+template <typename T, int KS>
+static void pass_batched_ks(const PassArgs* args, const int32_t* nstrips, const BatchItem* it, int nitems, int grid,
+                            hipStream_t s) {
+    hipLaunchKernelGGL((k_pair_pass_batched<T, KS>), dim3(grid), dim3(kBlock), 0, s, args, nstrips, it, nitems);
+}
+template <typename T>
+static hipError_t pass_batched_t(int ks, const PassArgs* args, const int32_t* nstrips, const BatchItem* it,
+                                 int nitems, int grid, hipStream_t s) {
+    switch (ks) {
+        case 1: pass_batched_ks<T, 1>(args, nstrips, it, nitems, grid, s); break;
+        case 2: pass_batched_ks<T, 2>(args, nstrips, it, nitems, grid, s); break;
+        case 3: pass_batched_ks<T, 3>(args, nstrips, it, nitems, grid, s); break;
+        case 4: pass_batched_ks<T, 4>(args, nstrips, it, nitems, grid, s); break;
+        case 5: pass_batched_ks<T, 5>(args, nstrips, it, nitems, grid, s); break;
+        case 6: pass_batched_ks<T, 6>(args, nstrips, it, nitems, grid, s); break;
+        case 7: pass_batched_ks<T, 7>(args, nstrips, it, nitems, grid, s); break;
+        case 8: pass_batched_ks<T, 8>(args, nstrips, it, nitems, grid, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pass_batched(bool f64, int ks, const PassArgs* args, const int32_t* nstrips, const void* items,
+                               int nitems, int grid, hipStream_t s) {
+    const BatchItem* it = (const BatchItem*)items;
+    return f64 ? pass_batched_t<double>(ks, args, nstrips, it, nitems, grid, s)
+               : pass_batched_t<float>(ks, args, nstrips, it, nitems, grid, s);
+}
+
+hipError_t launch_reduce_batched(bool f64, int G, const ReduceArgs* args, const void* blocks, const int32_t* nblk,
+                                 int nblocks, int q, hipStream_t s) {
+    const int2* b = (const int2*)blocks;
+    if (f64) {
+        if (G == 16) hipLaunchKernelGGL((k_reduce_batched<double, 16>), dim3(nblocks), dim3(kBlock), 0, s, args, b, nblk, q);
+        else hipLaunchKernelGGL((k_reduce_batched<double, 32>), dim3(nblocks), dim3(kBlock), 0, s, args, b, nblk, q);
+    } else {
+        if (G == 16) hipLaunchKernelGGL((k_reduce_batched<float, 16>), dim3(nblocks), dim3(kBlock), 0, s, args, b, nblk, q);
+        else hipLaunchKernelGGL((k_reduce_batched<float, 32>), dim3(nblocks), dim3(kBlock), 0, s, args, b, nblk, q);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_update_batched(bool f64, int G, const UpdateArgs* args, const void* blocks, const int32_t* nblk,
+                                 int nblocks, int q, hipStream_t s) {
+    const int2* b = (const int2*)blocks;
+    if (f64) {
+        if (G == 16) hipLaunchKernelGGL((k_update_batched<double, 16>), dim3(nblocks), dim3(kBlock), 0, s, args, b, nblk, q);
+        else hipLaunchKernelGGL((k_update_batched<double, 32>), dim3(nblocks), dim3(kBlock), 0, s, args, b, nblk, q);
+    } else {
+        if (G == 16) hipLaunchKernelGGL((k_update_batched<float, 16>), dim3(nblocks), dim3(kBlock), 0, s, args, b, nblk, q);
+        else hipLaunchKernelGGL((k_update_batched<float, 32>), dim3(nblocks), dim3(kBlock), 0, s, args, b, nblk, q);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_replay_end_batched(DevState* const* sts, int P, int iters, int32_t* any_active, hipStream_t s) {
+    hipLaunchKernelGGL(k_replay_end_batched, dim3(1), dim3(kBlock), 0, s, sts, P, iters, any_active);
+    return hipGetLastError();
+}
 
 hipError_t launch_replay_end(DevState* st, int iters, hipStream_t s) {
     hipLaunchKernelGGL(k_replay_end, dim3(1), dim3(64), 0, s, st, iters);

@@ -91,3 +91,25 @@ def test_product_package_has_no_oracle_dependency():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "cr_oracle" not in text and "libcr_oracle" not in text, f
+
+
+def test_batch_arguments_rejected_on_host():
+    cr, lib = _lib()
+    p = cr.Params().to_c()
+    arr = (cr._CProblem * 2)()
+    arr[0] = cr._CProblem(100, 3, 0, 0x1000, 0x1000, 0x1000, 0x1000)
+    arr[1] = cr._CProblem(50, 40, 0, 0x1000, 0x1000, 0x1000, 0x1000)
+    out = ctypes.c_size_t(0)
+    assert lib.cr_batch_workspace_bytes(arr, 0, ctypes.byref(p), ctypes.byref(out)) == cr.ERR_ARG
+    assert lib.cr_batch_workspace_bytes(arr, 2, ctypes.byref(p), ctypes.byref(out)) == cr.ERR_UNSUPPORTED
+    assert lib.cr_batch_workspace_bytes(arr, 1, ctypes.byref(p), ctypes.byref(out)) == cr.OK
+    one = out.value
+    assert one >= cr.workspace_bytes(100, 3)
+    mixed = cr.Params(precision=cr.MIXED_BF16).to_c()
+    assert lib.cr_batch_workspace_bytes(arr, 1, ctypes.byref(mixed), ctypes.byref(out)) == cr.ERR_UNSUPPORTED
+    h = ctypes.c_void_p()
+    assert lib.cr_batch_init(ctypes.byref(h), arr, 1, ctypes.byref(p), ctypes.c_void_p(0x1000), one - 1, None) == cr.ERR_NOMEM
+    arr[0].y_dev = None
+    assert lib.cr_batch_init(ctypes.byref(h), arr, 1, ctypes.byref(p), ctypes.c_void_p(0x1000), one, None) == cr.ERR_ARG
+    assert lib.cr_batch_run(None, None, None) == cr.ERR_ARG
+    assert lib.cr_batch_destroy(None) == cr.OK

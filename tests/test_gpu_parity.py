@@ -206,3 +206,53 @@ def test_full_size_pass_sampled(cr, prec):
         scale = wrow.sum() + wcol.sum()
         assert abs((hy[m] - (y[m] - p.ybar[m]) / mu) - (-u)) <= tol * scale
         assert np.max(np.abs((hxi[m] - gamma / mu * xi[m]) - (-v))) <= tol * scale * (1 + np.abs(p.X).max())
+
+
+# --------------------------------------------------------------------------
+# Batched form
+# --------------------------------------------------------------------------
+
+BATCH_SHAPES = [(37, 3), (150, 5), (300, 10), (64, 2), (513, 20), (90, 10)]
+
+
+def _batch_problems(shapes, seed0=100):
+    return [synth.quad_l1_gaussian(N, n, 0.1, seed=seed0 + i) for i, (N, n) in enumerate(shapes)]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+def test_batched_fixed_schedule_matches_oracle(cr, prec):
+    say("batched fixed schedule %s shapes %s" % (PREC_NAME[prec], BATCH_SHAPES))
+    probs = _batch_problems(BATCH_SHAPES)
+    sched = dict(inner_iters=20, max_outer=3)
+    outs, infos = cr.solve_batched([(dev(p.X), dev(p.ybar)) for p in probs], cr.Params(precision=prec, **sched))
+    for p, (y, xi), info in zip(probs, outs, infos):
+        ref = oracle.alcc(p.X, p.ybar, oracle.Params(**sched), record_kkt=False)
+        assert info.inner_iters == 60 and info.outer_iters == 3
+        ey, exi = rel(host(y), ref.y), rel(host(xi), ref.xi)
+        say("  N=%d n=%d: y %.2e xi %.2e" % (p.N, p.n, ey, exi))
+        assert ey < TOL_SOLVE[prec]
+        assert exi < TOL_SOLVE[prec] * 10
+
+
+def test_batched_equals_single_problem_solves(cr):
+    say("batched vs single-problem solves, f64")
+    probs = _batch_problems(BATCH_SHAPES[:4], seed0=200)
+    sched = dict(inner_iters=25, max_outer=2)
+    outs, _ = cr.solve_batched([(dev(p.X), dev(p.ybar)) for p in probs], cr.Params(precision=0, **sched))
+    for p, (y, xi) in zip(probs, outs):
+        ys, xis, _ = cr.solve(dev(p.X), dev(p.ybar), cr.Params(precision=0, **sched))
+        assert rel(host(y), host(ys)) < 1e-12
+        assert rel(host(xi), host(xis)) < 1e-11
+
+
+def test_batched_adaptive_converges_and_freezes(cr):
+    say("batched adaptive f32")
+    probs = _batch_problems([(40, 2), (60, 3), (80, 5)], seed0=300)
+    outs, infos = cr.solve_batched([(dev(p.X), dev(p.ybar)) for p in probs], cr.Params(precision=1, kkt_tol=1e-4))
+    outers = []
+    for p, (y, xi), info in zip(probs, outs, infos):
+        assert info.status == 0 and info.kkt <= 1e-4, info
+        outers.append(info.outer_iters)
+        ref = oracle.alcc(p.X, p.ybar, oracle.Params(kkt_tol=1e-6))
+        assert rel(host(y), ref.y) < 1e-3
+    say("  ALCC iterations per problem: %s" % outers)
