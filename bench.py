@@ -12,7 +12,12 @@ Also reported on the same JSON line:
                 (one theta read per pair) / its average device time, measured
                 with HIP events on the library's stream, against 8 TB/s HBM;
   cpu_baseline  the FP64 CPU oracle timed on the host cores on a bounded
-                sample of the same workload (a fixed number of MAPG iterations).
+                sample of the same workload (a fixed number of MAPG iterations);
+  variants      the same metric for the FP64 solve of the same workload, and the
+                steady-state MAPG throughput (fixed iteration count, stated) of
+                the mixed BF16 form on the 20000-point workload and of the
+                64-problem batched form.
+The pass tile height comes from the autotuner (paper_1407_7220_amd.autotune).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision f32|f64]
 """
@@ -79,6 +84,61 @@ def cpu_baseline(p, budget_s: float):
                 iters, WORKLOAD, N, p.n, secs)}
 
 
+def solve_rate(cr, p, prec, tile_rows, steps=1, warmup=0):
+    """Pair-updates/s of whole solves to KKT <= 1e-4 on workload p."""
+    import torch
+    X = torch.from_numpy(p.X).cuda()
+    yb = torch.from_numpy(p.ybar).cuda()
+    ctx = cr.Context(X, yb, cr.Params(precision=prec, kkt_tol=1e-4, tile_rows=tile_rows))
+    for _ in range(warmup):
+        ctx.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [ctx.run()[2] for _ in range(steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pass_ms = ctx.time_pass(20)
+    ctx.close()
+    return {"value": sum(i.pair_updates for i in infos) / wall, "unit": "pair-updates/s",
+            "mapg_iters_per_solve": infos[-1].inner_iters, "final_kkt": infos[-1].kkt,
+            "converged": all(i.status == 0 for i in infos), "pass_us": pass_ms * 1e3, "tile_rows": tile_rows}
+
+
+def fixed_rate(cr, p, prec, tile_rows, inner=100, outer=2):
+    """Steady-state pair-updates/s over a fixed schedule (outer x inner MAPG iterations)."""
+    import torch
+    X = torch.from_numpy(p.X).cuda()
+    yb = torch.from_numpy(p.ybar).cuda()
+    ctx = cr.Context(X, yb, cr.Params(precision=prec, inner_iters=inner, max_outer=outer, tile_rows=tile_rows))
+    ctx.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, info = ctx.run()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pass_ms = ctx.time_pass(10)
+    ctx.close()
+    esz = 8 if prec == cr.F64 else 4
+    return {"value": info.pair_updates / wall, "unit": "pair-updates/s", "schedule": "%d x %d MAPG" % (outer, inner),
+            "N": p.N, "n": p.n, "pass_us": pass_ms * 1e3, "tile_rows": tile_rows,
+            "pass_hbm_frac": p.N * (p.N - 1) * esz / (pass_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def batched_rate(cr, autotune, inner=100, outer=2):
+    import torch
+    import synth
+    probs = synth.batched_workload()
+    pairs = [(torch.from_numpy(q.X).cuda(), torch.from_numpy(q.ybar).cuda()) for q in probs]
+    tiles = [autotune.tile_rows_for(X, yb, cr.F32) for X, yb in pairs]
+    b = cr.Batch(pairs, cr.Params(precision=cr.F32, inner_iters=inner, max_outer=outer), tile_rows=tiles)
+    b.run()
+    _, infos, secs = b.run()
+    b.close()
+    return {"value": sum(i.pair_updates for i in infos) / secs, "unit": "pair-updates/s",
+            "schedule": "%d x %d MAPG, every problem" % (outer, inner), "problems": len(probs),
+            "pairs_per_iteration": float(sum(q.N * (q.N - 1) for q in probs))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +147,7 @@ def main():
     ap.add_argument("--precision", choices=("f32", "f64"), default="f32")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the pair engine runs on a single device "
@@ -95,13 +156,15 @@ def main():
 
     import torch
     import paper_1407_7220_amd as cr
+    from paper_1407_7220_amd import autotune
     import synth
 
     p = synth.workload(WORKLOAD)
     prec = cr.F32 if args.precision == "f32" else cr.F64
     X = torch.from_numpy(p.X).cuda()
     yb = torch.from_numpy(p.ybar).cuda()
-    params = cr.Params(precision=prec, kkt_tol=1e-4)
+    tile_rows = autotune.tile_rows_for(X, yb, prec)
+    params = cr.Params(precision=prec, kkt_tol=1e-4, tile_rows=tile_rows)
     ctx = cr.Context(X, yb, params)
 
     for _ in range(args.warmup):
@@ -134,9 +197,23 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
         "config": {"workload": WORKLOAD, "N": p.N, "n": p.n, "precision": args.precision, "kkt_tol": 1e-4,
                    "mapg_iters_per_solve": infos[-1].inner_iters, "alcc_iters_per_solve": infos[-1].outer_iters,
-                   "final_kkt": infos[-1].kkt, "converged": converged, "gamma": 1e-3},
+                   "final_kkt": infos[-1].kkt, "converged": converged, "gamma": 1e-3, "tile_rows": tile_rows},
         "roofline": roof,
     }
+    ctx.close()
+    if not args.no_variants:
+        other = cr.F64 if prec == cr.F32 else cr.F32
+        v = {("f64" if other == cr.F64 else "f32") + "_" + WORKLOAD:
+             solve_rate(cr, p, other, autotune.tile_rows_for(X, yb, other))}
+        big = synth.workload("maxaffine_20000")
+        Xb, ybb = torch.from_numpy(big.X).cuda(), torch.from_numpy(big.ybar).cuda()
+        v["mixed_bf16_maxaffine_20000"] = fixed_rate(cr, big, cr.MIXED_BF16,
+                                                     autotune.tile_rows_for(Xb, ybb, cr.MIXED_BF16))
+        v["f32_maxaffine_20000"] = fixed_rate(cr, big, cr.F32, autotune.tile_rows_for(Xb, ybb, cr.F32))
+        del Xb, ybb
+        torch.cuda.empty_cache()
+        v["batched_f32_64_problems"] = batched_rate(cr, autotune)
+        line["variants"] = v
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_budget)
     print(json.dumps(line), flush=True)

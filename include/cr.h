@@ -87,11 +87,15 @@ enum {
  *               iterations per ALCC iteration and no early stops    [0]
  *   max_inner   cap on l_max_k in the adaptive schedule             [20000]
  *   precision   CR_F64, CR_F32 or CR_MIXED_BF16                     [CR_F64]
+ *   tile_rows   rows of theta per pass workgroup (rounded up to 64);
+ *               0 selects a heuristic; an autotuner picks it per
+ *               (n, precision, N bucket) in the Python layer         [0]
  *   *_override  > 0 replaces the computed L^y, L^xi, Bbar_y, Bbar_xi [0]
  */
 typedef struct {
     double gamma, mu1, c, kappa, tau1, alpha_y1, alpha_xi1, step_scale, kkt_tol;
     int32_t max_outer, inner_iters, max_inner, precision;
+    int32_t tile_rows, reserved;
     double Ly_override, Lxi_override, By_override, Bxi_override;
 } cr_params;
 
@@ -206,7 +210,7 @@ cr_status cr_solve(const void* X_dev, const void* ybar_dev, int64_t N, int32_t n
  */
 typedef struct {
     int64_t N;
-    int32_t n, pad;
+    int32_t n, tile_rows;    /* tile_rows as in cr_params; 0 = the batch's params value */
     const void* X_dev;
     const void* ybar_dev;
     void* y_dev;

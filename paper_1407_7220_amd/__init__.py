@@ -35,12 +35,13 @@ OK, ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_NONFINITE, NOT_CONVERGED, ERR_STATE, ERR_UN
 class _CParams(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in
                 ("gamma", "mu1", "c", "kappa", "tau1", "alpha_y1", "alpha_xi1", "step_scale", "kkt_tol")] + \
-               [(k, ctypes.c_int32) for k in ("max_outer", "inner_iters", "max_inner", "precision")] + \
+               [(k, ctypes.c_int32) for k in ("max_outer", "inner_iters", "max_inner", "precision",
+                                              "tile_rows", "reserved")] + \
                [(k, ctypes.c_double) for k in ("Ly_override", "Lxi_override", "By_override", "Bxi_override")]
 
 
 class _CProblem(ctypes.Structure):
-    _fields_ = [("N", ctypes.c_int64), ("n", ctypes.c_int32), ("pad", ctypes.c_int32),
+    _fields_ = [("N", ctypes.c_int64), ("n", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("X_dev", ctypes.c_void_p), ("ybar_dev", ctypes.c_void_p),
                 ("y_dev", ctypes.c_void_p), ("xi_dev", ctypes.c_void_p)]
 
@@ -61,6 +62,9 @@ def _load():
         raise ImportError(
             "libcr.so is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
             "or `python paper_1407_7220_amd/build.py` first")
+    # torch first: its HIP runtime then serves this library too (one runtime per
+    # process; loading the library first binds a second copy that sees no device)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(_LIB_PATH)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     pp, pi = ctypes.POINTER(_CParams), ctypes.POINTER(_CInfo)
@@ -128,6 +132,7 @@ class Params:
     inner_iters: Optional[int] = None
     max_inner: Optional[int] = None
     precision: Optional[int] = None
+    tile_rows: Optional[int] = None
     Ly_override: Optional[float] = None
     Lxi_override: Optional[float] = None
     By_override: Optional[float] = None
@@ -295,7 +300,7 @@ class Batch:
     """Many independent problems solved together (cr_batch_*): problems is a list
     of (X, ybar) float64 CUDA tensor pairs with their own N and n."""
 
-    def __init__(self, problems, params: Optional[Params] = None):
+    def __init__(self, problems, params: Optional[Params] = None, tile_rows=None):
         torch = _torch()
         self.params = params or Params()
         self._keep = []
@@ -310,7 +315,8 @@ class Batch:
             xi = torch.empty(N, n, dtype=torch.float64, device=X.device)
             self._keep += [X, ybar]
             self.outputs.append((y, xi))
-            arr[p] = _CProblem(N, n, 0, px.value, py.value, y.data_ptr(), xi.data_ptr())
+            tr = int(tile_rows[p]) if tile_rows is not None else 0
+            arr[p] = _CProblem(N, n, tr, px.value, py.value, y.data_ptr(), xi.data_ptr())
         self._arr = arr
         self._cp = self.params.to_c()
         nbytes = ctypes.c_size_t(0)

@@ -1,0 +1,137 @@
+"""Tile autotuner of the pair pass.
+
+The one free tile dimension of the pass is the number of theta rows a
+workgroup sweeps (``tile_rows``): taller tiles amortise the per-workgroup
+prologue and the column-partial writes, shorter ones give the scheduler more
+workgroups.  The tuner times the gradient pass (HIP events inside the library,
+``Context.time_pass``) for a set of candidates on the caller's own data and
+keeps the fastest.  Choices are cached in a JSON file keyed on
+(n, precision, N bucket), the bucket being N rounded to the nearest quarter
+octave.  The cache path is ``tile_cache.json`` next to this file unless
+``CR_TILE_CACHE`` names another.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Dict, Optional
+
+if __package__ in (None, ""):
+    import sys as _sys
+    _sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    from paper_1407_7220_amd import Context, Params, F64, F32, MIXED_BF16
+else:
+    from . import Context, Params, F64, F32, MIXED_BF16
+
+CANDIDATES = (128, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096)
+_PREC = {F64: "f64", F32: "f32", MIXED_BF16: "mixed_bf16"}
+
+
+def cache_path() -> str:
+    return os.environ.get("CR_TILE_CACHE", os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                        "tile_cache.json"))
+
+
+def bucket(N: int) -> int:
+    """N rounded to the nearest quarter octave, 2^(k/4)."""
+    return int(round(2.0 ** (round(4.0 * math.log2(max(2, int(N)))) / 4.0)))
+
+
+def key(N: int, n: int, precision: int) -> str:
+    return "n%d-%s-N%d" % (int(n), _PREC[int(precision)], bucket(N))
+
+
+def load_cache() -> Dict[str, dict]:
+    try:
+        with open(cache_path()) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(cache: Dict[str, dict]) -> None:
+    path = cache_path()
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def lookup(N: int, n: int, precision: int) -> Optional[int]:
+    entry = load_cache().get(key(N, n, precision))
+    return int(entry["tile_rows"]) if entry else None
+
+
+def tune(X, ybar, precision: int, reps: int = 20, candidates=CANDIDATES, save: bool = True) -> int:
+    """Time the gradient pass for each candidate tile height on (X, ybar); return
+    and cache the fastest."""
+    N, n = int(X.shape[0]), int(X.shape[1])
+    rows = ((N + 63) // 64) * 64
+    timings = {}
+    for r in candidates:
+        if r > rows and timings:
+            continue
+        ctx = Context(X, ybar, Params(precision=precision, tile_rows=int(r)))
+        ctx.time_pass(3)
+        timings[int(r)] = ctx.time_pass(reps)
+        ctx.close()
+        del ctx
+    best = min(timings, key=timings.get)
+    if save:
+        cache = load_cache()
+        cache[key(N, n, precision)] = {"tile_rows": best, "pass_ms": timings[best], "N": N,
+                                       "timings_ms": {str(k): v for k, v in sorted(timings.items())}}
+        save_cache(cache)
+    return best
+
+
+def tile_rows_for(X, ybar, precision: int, tune_if_missing: bool = True) -> int:
+    """Cached tile height for this (n, precision, N bucket), tuning on (X, ybar) if absent
+    (0, the library's heuristic, when tuning is not allowed)."""
+    N, n = int(X.shape[0]), int(X.shape[1])
+    found = lookup(N, n, precision)
+    if found is not None:
+        return found
+    return tune(X, ybar, precision) if tune_if_missing else 0
+
+
+def _main(argv=None) -> int:
+    """Tune the named synthetic workloads (the seeded generators beside the
+    package) and write their entries to the cache:
+    python paper_1407_7220_amd/autotune.py logsumexp_5000:f32 maxaffine_20000:mixed_bf16 batched:f32"""
+    import argparse
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import torch
+    import synth
+    ap = argparse.ArgumentParser()
+    ap.add_argument("targets", nargs="+", help="workload:precision, workload 'batched' = the 64-problem set")
+    ap.add_argument("--reps", type=int, default=20)
+    args = ap.parse_args(argv)
+    names = {v: k for k, v in _PREC.items()}
+    for t in args.targets:
+        wl, pn = t.split(":")
+        prec = names[pn]
+        probs = synth.batched_workload() if wl == "batched" else [synth.workload(wl)]
+        done = set()
+        for p in probs:
+            k = key(p.N, p.n, prec)
+            if k in done:
+                continue
+            done.add(k)
+            X = torch.from_numpy(p.X).cuda()
+            yb = torch.from_numpy(p.ybar).cuda()
+            best = tune(X, yb, prec, reps=args.reps)
+            e = load_cache()[k]
+            print("%-28s N=%-6d tile_rows=%-5d pass %.4f ms  (%s)" % (
+                k, p.N, best, e["pass_ms"], " ".join("%s:%.4f" % kv for kv in e["timings_ms"].items())),
+                flush=True)
+            del X, yb
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(_main())

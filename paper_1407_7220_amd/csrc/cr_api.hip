@@ -38,7 +38,7 @@ struct Layout {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-Layout make_layout(int64_t N, int n, int precision, int64_t max_iters) {
+Layout make_layout(int64_t N, int n, int precision, int64_t max_iters, int tile_rows) {
     Layout L;
     L.N = N;
     L.n = n;
@@ -63,12 +63,17 @@ Layout make_layout(int64_t N, int n, int precision, int64_t max_iters) {
     L.strips = (int)(L.ld / (16 * L.tw));
     // Enough workgroups to fill 256 CUs several times over, but long enough
     // row chunks that the per-chunk column partials stay small.
-    int64_t target = 768;
-    if (const char* tw = std::getenv("CR_TARGET_WGS")) target = std::max(1L, std::atol(tw));
-    int64_t chunks = (target + L.strips - 1) / L.strips;
-    chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, L.Nrow / 64));
-    int64_t rpc = (L.Nrow + chunks - 1) / chunks;
-    rpc = ((rpc + 63) / 64) * 64;
+    int64_t rpc;
+    if (tile_rows > 0) {
+        rpc = std::min<int64_t>(((int64_t)tile_rows + 63) / 64 * 64, L.Nrow);
+    } else {
+        int64_t target = 768;
+        if (const char* tw = std::getenv("CR_TARGET_WGS")) target = std::max(1L, std::atol(tw));
+        int64_t chunks = (target + L.strips - 1) / L.strips;
+        chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, L.Nrow / 64));
+        rpc = (L.Nrow + chunks - 1) / chunks;
+        rpc = ((rpc + 63) / 64) * 64;
+    }
     L.rpc = (int)rpc;
     L.chunks = (int)((L.Nrow + rpc - 1) / rpc);
     L.nb = (int)((L.ld * 32 + cr::kBlock - 1) / cr::kBlock);  // blocks of the O(N n) kernels (32 lanes per point)
@@ -113,6 +118,7 @@ bool check_params(const cr_params* p, std::string& msg) {
     if (p->inner_iters < 0) { msg = "inner_iters must be >= 0"; return false; }
     if (p->inner_iters == 0 && p->max_inner < 1) { msg = "max_inner must be >= 1"; return false; }
     if (!(p->kkt_tol >= 0)) { msg = "kkt_tol must be >= 0"; return false; }
+    if (p->tile_rows < 0) { msg = "tile_rows must be >= 0"; return false; }
     if (p->precision != CR_F64 && p->precision != CR_F32 && p->precision != CR_MIXED_BF16) {
         msg = "unknown precision";
         return false;
@@ -364,7 +370,7 @@ cr_status cr_workspace_bytes(int64_t N, int32_t n, const cr_params* params, size
     cr_status s = check_dims(N, n, msg);
     if (s != CR_OK) return fail(nullptr, s, msg);
     if (!check_params(params, msg)) return fail(nullptr, CR_ERR_ARG, msg);
-    *bytes = make_layout(N, n, params->precision, max_mapg_iters(*params)).total;
+    *bytes = make_layout(N, n, params->precision, max_mapg_iters(*params), params->tile_rows).total;
     return CR_OK;
 }
 
@@ -377,7 +383,7 @@ cr_status cr_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params, c
     if (s != CR_OK) return fail(nullptr, s, msg);
     if (!check_params(params, msg)) return fail(nullptr, CR_ERR_ARG, msg);
     if (!X_dev || !ybar_dev || !workspace_dev) return fail(nullptr, CR_ERR_ARG, "X, ybar and workspace must be non-NULL");
-    Layout L = make_layout(N, n, params->precision, max_mapg_iters(*params));
+    Layout L = make_layout(N, n, params->precision, max_mapg_iters(*params), params->tile_rows);
     if (ws_bytes < L.total) return fail(nullptr, CR_ERR_NOMEM, "workspace smaller than cr_workspace_bytes()");
 
     cr_ctx* c = new (std::nothrow) cr_ctx();
@@ -701,6 +707,7 @@ cr_status check_batch(const cr_problem* probs, int32_t P, const cr_params* param
     for (int p = 0; p < P; ++p) {
         cr_status s = check_dims(probs[p].N, probs[p].n, msg);
         if (s != CR_OK) { msg = "problem " + std::to_string(p) + ": " + msg; return s; }
+        if (probs[p].tile_rows < 0) { msg = "problem " + std::to_string(p) + ": tile_rows must be >= 0"; return CR_ERR_ARG; }
     }
     return CR_OK;
 }
@@ -711,7 +718,8 @@ BatchPlan plan_batch(const cr_problem* probs, int32_t P, const cr_params* params
     for (int p = 0; p < P; ++p) nmax = std::max(nmax, (int)probs[p].n);
     B.G = nmax + 1 <= 16 ? 16 : 32;
     for (int p = 0; p < P; ++p) {
-        B.L.push_back(make_layout(probs[p].N, probs[p].n, params->precision, max_mapg_iters(*params)));
+        const int tr = probs[p].tile_rows > 0 ? probs[p].tile_rows : params->tile_rows;
+        B.L.push_back(make_layout(probs[p].N, probs[p].n, params->precision, max_mapg_iters(*params), tr));
         const int nb = (int)((probs[p].N * B.G + cr::kBlock - 1) / cr::kBlock);
         B.nblk.push_back(nb);
         B.nblocks += nb;
@@ -869,7 +877,9 @@ cr_status cr_batch_init(cr_batch** out, const cr_problem* probs, int32_t P, cons
     // per-problem contexts (set-up of each problem on its own slice)
     for (int p = 0; p < P; ++p) {
         cr_ctx* c = nullptr;
-        cr_status st = cr_init(&c, probs[p].N, probs[p].n, params, probs[p].X_dev, probs[p].ybar_dev,
+        cr_params pp = *params;
+        if (probs[p].tile_rows > 0) pp.tile_rows = probs[p].tile_rows;
+        cr_status st = cr_init(&c, probs[p].N, probs[p].n, &pp, probs[p].X_dev, probs[p].ybar_dev,
                                b->ws + B.off[p], B.L[p].total, stream);
         if (st != CR_OK) { g_last_error = "problem " + std::to_string(p) + ": " + g_last_error; return bad(st); }
         b->sub.push_back(c);

@@ -113,3 +113,24 @@ def test_batch_arguments_rejected_on_host():
     assert lib.cr_batch_init(ctypes.byref(h), arr, 1, ctypes.byref(p), ctypes.c_void_p(0x1000), one, None) == cr.ERR_ARG
     assert lib.cr_batch_run(None, None, None) == cr.ERR_ARG
     assert lib.cr_batch_destroy(None) == cr.OK
+
+
+def test_autotune_cache_roundtrip(tmp_path, monkeypatch):
+    """Tuner cache: keys on (n, precision, power-of-two N bucket), JSON round trip,
+    lookup misses give None and tile_rows_for falls back to 0 when tuning is off."""
+    import paper_1407_7220_amd as cr
+    from paper_1407_7220_amd import autotune as at
+    import numpy as np
+    monkeypatch.setenv("CR_TILE_CACHE", str(tmp_path / "cache.json"))
+    assert at.bucket(5000) == 4871 and at.bucket(4334) == 4096 and at.bucket(2) == 2
+    assert at.bucket(4096) == 4096 and at.bucket(6000) == 5793
+    assert at.key(5000, 10, cr.F32) == "n10-f32-N4871"
+    assert at.key(20000, 4, cr.MIXED_BF16) == "n4-mixed_bf16-N19484"
+    assert at.lookup(5000, 10, cr.F32) is None
+    at.save_cache({at.key(5000, 10, cr.F32): {"tile_rows": 512}})
+    assert at.lookup(4900, 10, cr.F32) == 512
+    assert at.lookup(4300, 10, cr.F32) is None
+    assert at.lookup(5000, 10, cr.F64) is None
+    X = np.zeros((5000, 10))
+    assert at.tile_rows_for(X, None, cr.F32, tune_if_missing=False) == 512
+    assert at.tile_rows_for(X, None, cr.F64, tune_if_missing=False) == 0
