@@ -248,6 +248,69 @@ cr_status cr_batch_destroy(cr_batch* batch);
 cr_status cr_solve_batched(const cr_problem* probs, int32_t P, const cr_params* params, void* workspace_dev,
                            size_t ws_bytes, cr_info* infos, void* stream);
 
+/* Differentiable form --------------------------------------------------- */
+
+typedef struct cr_diff cr_diff;
+
+/*
+ * The fixed-schedule map of ALCC (Fig. 3) with MAPG (Fig. 4): from a given
+ * start (y0, xi0) and theta_1 = 0, exactly params->max_outer ALCC iterations
+ * of params->inner_iters MAPG steps each, with the constants of cr_run's fixed
+ * schedule (mu_k, L^y_k, L^xi_k, the ball radii, the momentum weights); the
+ * output is the last ALCC iterate (y_K, xi_K).  The reverse pass gives the
+ * vector-Jacobian product of this map with respect to X, ybar, y0 and xi0,
+ * holding the step constants and radii fixed (they depend on the data only
+ * through sigma_max(A2)^2 and Bbar; the *_override fields fix them).  The
+ * derivative of (v)_- is taken as -[v < 0], of the ball projections as that
+ * of the branch the forward took.
+ *
+ * Memory: theta_k of every ALCC iteration k >= 2 is kept (max_outer - 1 pair
+ * arrays of the pass precision), the iterate state every checkpoint_every
+ * MAPG steps (and at each ALCC iteration's start); the reverse pass recomputes
+ * each segment of checkpoint_every steps from its checkpoint.
+ *
+ * cr_diff_workspace_bytes: bytes of device workspace.  CR_ERR_ARG when
+ * inner_iters < 1 (the map needs a fixed schedule) or checkpoint_every < 1,
+ * CR_ERR_UNSUPPORTED for CR_MIXED_BF16 (the adjoint runs CR_F64 and CR_F32),
+ * and the errors of cr_workspace_bytes.
+ */
+cr_status cr_diff_workspace_bytes(int64_t N, int32_t n, const cr_params* params, int32_t checkpoint_every,
+                                  size_t* bytes);
+
+/*
+ * Borrows X (N x n) and ybar (N), FP64 device arrays, and the workspace until
+ * cr_diff_destroy; runs the set-up of cr_init (host-synchronous).  stream
+ * orders the work as in cr_init.  Errors as cr_diff_workspace_bytes and
+ * cr_init.
+ */
+cr_status cr_diff_init(cr_diff** out, int64_t N, int32_t n, const cr_params* params, int32_t checkpoint_every,
+                       const void* X_dev, const void* ybar_dev, void* workspace_dev, size_t ws_bytes,
+                       void* stream);
+
+/*
+ * Forward map from the start y0_dev (N), xi0_dev (N x n), FP64 device arrays
+ * (y0 NULL: y0 = ybar; xi0 NULL: xi0 = 0), writing (y_K, xi_K) to y_dev (N)
+ * and xi_dev (N x n) and the checkpoints to the workspace.  info (may be
+ * NULL): the KKT scalars of the last multiplier step, inner/outer counts,
+ * seconds and pair updates.  Host-synchronous.  CR_OK, CR_ERR_ARG,
+ * CR_ERR_NONFINITE, CR_ERR_HIP.
+ */
+cr_status cr_diff_forward(cr_diff* d, const void* y0_dev, const void* xi0_dev, void* y_dev, void* xi_dev,
+                          cr_info* info);
+
+/*
+ * Reverse pass of the last forward: for the cotangents gy_dev (N) and gxi_dev
+ * (N x n, NULL = 0) of (y_K, xi_K), writes the gradients of
+ * <gy, y_K> + <gxi, xi_K> to dX_dev (N x n), dybar_dev (N), dy0_dev (N) and
+ * dxi0_dev (N x n), FP64 device arrays owned by the caller.  May be called
+ * again for other cotangents.  Host-synchronous.  CR_ERR_STATE before a
+ * forward; CR_ERR_ARG, CR_ERR_HIP.
+ */
+cr_status cr_diff_backward(cr_diff* d, const void* gy_dev, const void* gxi_dev, void* dX_dev, void* dybar_dev,
+                           void* dy0_dev, void* dxi0_dev);
+
+cr_status cr_diff_destroy(cr_diff* d);
+
 /* Inspection and test hooks --------------------------------------------- */
 
 /* Copy the context's theta to / from an N x N FP64 device array (diagonal

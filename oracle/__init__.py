@@ -157,16 +157,21 @@ def sigma2_A2(X) -> float:
 def affine_fit(X, ybar, gamma: float):
     """Feasible starting point and bounding radii (Sec. II-E, first paragraph).
 
-    The least-squares affine fit yhat = X a + b (numpy lstsq) with xi_l = a for
-    every l has A1 yhat + A2 xihat = 0, so it is feasible.  Then
+    The least-squares affine fit yhat = X a + b with xi_l = a for every l has
+    A1 yhat + A2 xihat = 0, so it is feasible.  The slope a is the
+    minimum-norm least-squares solution of the centred problem (numpy lstsq on
+    X - mean(X) against ybar - mean(ybar)) and b = mean(ybar) - mean(X)^T a;
+    when the fit is not unique (N <= n, or collinear points) this picks the
+    shortest slope, the intercept being free.  Then
     Bbar = sqrt(||yhat - ybar||^2 + gamma ||xihat||^2), Bbar_y = Bbar and
     Bbar_xi = Bbar / sqrt(gamma).
     """
     X, ybar = _f64(X), _f64(ybar)
     N, n = X.shape
-    M = np.hstack([X, np.ones((N, 1))])
-    coef, *_ = np.linalg.lstsq(M, ybar, rcond=None)
-    a, b = coef[:n], coef[n]
+    xm = X.mean(axis=0)
+    ym = float(ybar.mean())
+    a, *_ = np.linalg.lstsq(X - xm, ybar - ym, rcond=None)
+    b = ym - float(xm @ a)
     yhat = X @ a + b
     xihat = np.tile(a, (N, 1))
     Bbar = math.sqrt(float(np.sum((yhat - ybar) ** 2)) + gamma * float(np.sum(xihat ** 2)))

@@ -25,11 +25,11 @@ the overrides when comparing with finite differences).
 
 The gradient is the plain definition: reverse-mode automatic differentiation
 (torch autograd, CPU, float64) of the map written out with dense N x N pair
-arrays.  The pair map (v)_- has derivative 1 where its argument is negative
-and 0 elsewhere (the subgradient convention of the HIP path too), which
-matters only on a set of measure zero.  The forward is checked against
+arrays.  The pair map (v)_- has derivative -1 where its argument is negative
+and 0 elsewhere (the HIP path takes the same branch at v = 0), which matters
+only on a set of measure zero.  The forward is checked against
 ``oracle.alcc`` and the gradient against central finite differences of
-``oracle.alcc`` in ``tests/test_oracle_pins.py``.
+``oracle.alcc`` in ``tests/test_oracle_diff_pins.py``.
 """
 from __future__ import annotations
 

@@ -20,6 +20,7 @@ from typing import Optional
 __all__ = [
     "Params", "Info", "CRError", "Context", "solve", "workspace_bytes", "lib_path",
     "F64", "F32", "MIXED_BF16", "GRAD", "THETA_UPDATE", "MAX_DIM", "Batch", "solve_batched",
+    "Diff", "diff_workspace_bytes", "solve_unrolled",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -88,6 +89,11 @@ def _load():
         "cr_batch_run": (i32, [vp, pi, ctypes.POINTER(dbl)]),
         "cr_batch_destroy": (i32, [vp]),
         "cr_solve_batched": (i32, [ctypes.POINTER(_CProblem), i32, pp, vp, ctypes.c_size_t, pi, vp]),
+        "cr_diff_workspace_bytes": (i32, [i64, i32, pp, i32, ctypes.POINTER(ctypes.c_size_t)]),
+        "cr_diff_init": (i32, [ctypes.POINTER(vp), i64, i32, pp, i32, vp, vp, vp, ctypes.c_size_t, vp]),
+        "cr_diff_forward": (i32, [vp, vp, vp, vp, vp, pi]),
+        "cr_diff_backward": (i32, [vp, vp, vp, vp, vp, vp, vp]),
+        "cr_diff_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -101,7 +107,8 @@ _lib = _load()
 EXPORTED = ("cr_params_default", "cr_status_string", "cr_last_error", "cr_workspace_bytes", "cr_init",
             "cr_destroy", "cr_pairwise_step", "cr_run", "cr_solve", "cr_get_theta", "cr_set_theta",
             "cr_get_start", "cr_get_info", "cr_time_pass", "cr_batch_workspace_bytes", "cr_batch_init",
-            "cr_batch_run", "cr_batch_destroy", "cr_solve_batched")
+            "cr_batch_run", "cr_batch_destroy", "cr_solve_batched", "cr_diff_workspace_bytes", "cr_diff_init",
+            "cr_diff_forward", "cr_diff_backward", "cr_diff_destroy")
 
 
 class CRError(RuntimeError):
@@ -354,3 +361,114 @@ def solve_batched(problems, params: Optional[Params] = None):
     finally:
         b.close()
     return outs, infos
+
+
+# ---------------------------------------------------------------------------
+# Differentiable form (cr_diff_*)
+# ---------------------------------------------------------------------------
+
+def diff_workspace_bytes(N: int, n: int, params: Params, checkpoint_every: int = 20) -> int:
+    out = ctypes.c_size_t(0)
+    cp = params.to_c()
+    _check(_lib.cr_diff_workspace_bytes(int(N), int(n), ctypes.byref(cp), int(checkpoint_every), ctypes.byref(out)))
+    return int(out.value)
+
+
+class Diff:
+    """The fixed-schedule ALCC/MAPG map (params.max_outer ALCC iterations of
+    params.inner_iters MAPG steps) and its reverse pass, bound to (X, ybar).
+    forward(y0, xi0) -> (y_K, xi_K, Info); backward(gy, gxi) -> (dX, dybar, dy0, dxi0),
+    the gradients of <gy, y_K> + <gxi, xi_K> for the last forward."""
+
+    def __init__(self, X, ybar, params: Params, checkpoint_every: int = 20):
+        torch = _torch()
+        self.N, self.n = int(X.shape[0]), int(X.shape[1])
+        self.params = params
+        self._X, self._ybar = X, ybar
+        px = _dev_f64(X, (self.N, self.n), "X")
+        py = _dev_f64(ybar, (self.N,), "ybar")
+        nbytes = diff_workspace_bytes(self.N, self.n, params, checkpoint_every)
+        self._ws = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
+        self._cp = params.to_c()
+        h = ctypes.c_void_p()
+        _check(_lib.cr_diff_init(ctypes.byref(h), self.N, self.n, ctypes.byref(self._cp), int(checkpoint_every),
+                                 px, py, ctypes.c_void_p(self._ws.data_ptr()), nbytes, _stream()))
+        self._h = h
+
+    def _new(self, *shape):
+        torch = _torch()
+        return torch.empty(*shape, dtype=torch.float64, device=self._X.device)
+
+    def forward(self, y0=None, xi0=None):
+        y, xi = self._new(self.N), self._new(self.N, self.n)
+        py0 = _dev_f64(y0, (self.N,), "y0") if y0 is not None else None
+        pxi0 = _dev_f64(xi0, (self.N, self.n), "xi0") if xi0 is not None else None
+        self._start = (y0, xi0)
+        ci = _CInfo()
+        _check(_lib.cr_diff_forward(self._h, py0, pxi0, ctypes.c_void_p(y.data_ptr()),
+                                    ctypes.c_void_p(xi.data_ptr()), ctypes.byref(ci)), None)
+        return y, xi, Info.from_c(ci)
+
+    def backward(self, gy, gxi=None):
+        dX, dyb = self._new(self.N, self.n), self._new(self.N)
+        dy0, dxi0 = self._new(self.N), self._new(self.N, self.n)
+        pgxi = _dev_f64(gxi, (self.N, self.n), "gxi") if gxi is not None else None
+        _check(_lib.cr_diff_backward(self._h, _dev_f64(gy, (self.N,), "gy"), pgxi,
+                                     ctypes.c_void_p(dX.data_ptr()), ctypes.c_void_p(dyb.data_ptr()),
+                                     ctypes.c_void_p(dy0.data_ptr()), ctypes.c_void_p(dxi0.data_ptr())), None)
+        return dX, dyb, dy0, dxi0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.cr_diff_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _unrolled_function():
+    torch = _torch()
+
+    class UnrolledSolve(torch.autograd.Function):
+        """torch.autograd.Function over cr_diff: forward runs the map, backward
+        the library's reverse pass (checkpointed recomputation + adjoint kernels)."""
+
+        @staticmethod
+        def forward(ctx, X, ybar, y0, xi0, params, checkpoint_every):
+            d = Diff(X.detach().contiguous(), ybar.detach().contiguous(), params, checkpoint_every)
+            y, xi, info = d.forward(y0.detach().contiguous(), xi0.detach().contiguous())
+            ctx.diff = d
+            ctx.info = info
+            return y, xi
+
+        @staticmethod
+        def backward(ctx, gy, gxi):
+            d = ctx.diff
+            if gy is None:
+                gy = torch.zeros(d.N, dtype=torch.float64, device=d._X.device)
+            dX, dyb, dy0, dxi0 = d.backward(gy.contiguous(), gxi.contiguous() if gxi is not None else None)
+            return dX, dyb, dy0, dxi0, None, None
+
+    return UnrolledSolve
+
+
+_UNROLLED = None
+
+
+def solve_unrolled(X, ybar, params: Params, y0=None, xi0=None, checkpoint_every: int = 20):
+    """(y_K, xi_K) of the fixed-schedule map, differentiable with respect to X,
+    ybar, y0 and xi0 through torch autograd.  y0 defaults to ybar itself (so its
+    gradient reaches ybar), xi0 to zeros."""
+    global _UNROLLED
+    torch = _torch()
+    if _UNROLLED is None:
+        _UNROLLED = _unrolled_function()
+    if y0 is None:
+        y0 = ybar
+    if xi0 is None:
+        xi0 = torch.zeros(X.shape[0], X.shape[1], dtype=torch.float64, device=X.device)
+    return _UNROLLED.apply(X, ybar, y0, xi0, params, int(checkpoint_every))

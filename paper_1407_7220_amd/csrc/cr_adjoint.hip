@@ -1,0 +1,465 @@
+// gfx950 kernels of the reverse-mode (adjoint) pass through the fixed-schedule
+// ALCC/MAPG map (Fig. 3 with a fixed number of Fig. 4 steps per iteration).
+//
+// One MAPG step maps (y^(1)_{l-1}, y^(2)_l) to (y^(1)_l, y^(2)_{l+1}):
+//   v   = y^(2) - S grad P_k(y^(2)),       S = diag(s^y, s^xi)
+//   y^(1)_l = Proj(v),  y^(2)_{l+1} = (1 + beta_l) y^(1)_l - beta_l y^(1)_{l-1}
+// (the same for xi).  grad P_k = (z-part)/mu - A^T (A z - theta)_- has the
+// Jacobian H = diag(1/mu, gamma/mu) + A^T M A with the pair mask
+// M = diag(m_ij), m_ij = [theta_ij - r_ij > 0].  Its adjoint, for the adjoint
+// v-bar of v, is
+//   y^(2)-bar = v-bar - H S v-bar,
+//   theta-bar += M A S v-bar,   ybar-bar += s^y vy-bar / mu,
+// and the derivative of <S v-bar, grad P_k> in X.  With (a, b) = S v-bar,
+// rho = A1 a + A2 b and z = m rho, this is one pass over the pairs:
+//   (A^T z)        rowsum(z) - colsum(z);  -sum_i z_ij x_i + colsum_j(z) x_j
+//   X-bar_m       += sum_j z_mj xi_j - sum_j w_mj b_j - colsum_m(z) xi_m + colsum_m(W) b_m
+// and the multiplier step theta_{k+1} = s (A y_k + A2 xi_k - theta_k)_- gives
+// the same structure with z = s m thetabar_{k+1} and W = 0.
+//
+// The pass keeps the forward pass's tiling and operands: the residual tile R is
+// recomputed with the same MFMA chain on the same operands, so the mask is
+// bit-identical to the forward's; rho is a second MFMA chain on the direction
+// operands; Z^T [X 1] is the forward's column contraction with W replaced by
+// Z.  The row-direction terms sum over the column index, which the MFMA
+// accumulator layout does not contract: each lane forms its four columns'
+// products against the staged xi_j and b_j (LDS, [k][column]) and a 16-lane
+// DPP sum finishes the row.
+#include "cr_device.h"
+#include "cr_ops.h"
+
+namespace cr {
+
+template <typename T> struct AdjTile {
+    static constexpr int TW = Tr<T>::TW;
+    static constexpr int NW = 16 * TW;            // columns of one workgroup
+    static constexpr int kCsum = 32768;           // wave column-sum accumulators (as in the forward pass)
+    static constexpr int kCw = kWaves * 4 * NW * (int)sizeof(T);
+    static constexpr int kStage = 2 * 32 * NW * (int)sizeof(T);
+    static constexpr int kLds = kCsum + kCw + kStage;
+};
+
+template <typename T, int KS, int MODE>
+__global__ __launch_bounds__(kBlock, 2) void k_adj_pass(AdjPassArgs a) {
+    typedef PlainOps<T, KS, 1> Ops;
+    typedef typename Ops::acc_t acc_t;
+    constexpr int TW = Ops::TW;
+    constexpr int NKB = Ops::NKB;
+    constexpr int NW = AdjTile<T>::NW;
+    constexpr int KX = 4 * KS;                    // staged k slots (>= n + 1)
+    __shared__ __align__(16) char lds[AdjTile<T>::kLds];
+    T* sx = reinterpret_cast<T*>(lds + AdjTile<T>::kCsum + AdjTile<T>::kCw);   // [KX][NW]  -xi_jk
+    T* sb = sx + KX * NW;                                                          // [KX][NW]  -b_jk
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int strip = blockIdx.x, chunk = blockIdx.y;
+    const int64_t J0 = (int64_t)strip * NW;
+    const int64_t I0 = (int64_t)chunk * a.rows_per_chunk;
+    const int64_t I1 = min(I0 + (int64_t)a.rows_per_chunk, a.Nrow);
+    const int64_t jl = J0 + TW * c;
+    const int n = a.n;
+
+    // stage -xi_j (and -b_j) of this workgroup's columns, k-major
+    {
+        const T* xa = (const T*)a.xiaug;
+        const T* da = (const T*)a.diraug;
+        for (int e = threadIdx.x; e < KX * NW; e += kBlock) {
+            const int k = e / NW, jj = e - k * NW;
+            const int64_t j = J0 + jj;
+            T vx = (T)0, vb = (T)0;
+            if (k < n) {
+                vx = xa[j * a.kp + k];
+                if (MODE == 0) vb = da[j * a.kp + k];
+            }
+            sx[k * NW + jj] = vx;
+            sb[k * NW + jj] = vb;
+        }
+    }
+
+    PassArgs pa{};
+    pa.xp = a.xp;
+    pa.xiaug = a.xiaug;
+    typename Ops::Breg breg, dreg;
+    Ops::load_breg(breg, pa, jl, g);
+    if (MODE == 0) {
+        pa.xiaug = a.diraug;
+        Ops::load_breg(dreg, pa, jl, g);
+    }
+
+    acc_t cacc[TW][NKB];
+#pragma unroll
+    for (int t = 0; t < TW; ++t)
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb) cacc[t][kb] = acc_t{0, 0, 0, 0};
+    T cw[TW];
+#pragma unroll
+    for (int t = 0; t < TW; ++t) cw[t] = (T)0;
+
+    const T* __restrict__ ycol = (const T*)a.ycol;
+    const T* __restrict__ acol = (const T*)a.acol;
+    const T* __restrict__ theta = (const T*)a.theta;
+    T* __restrict__ thetabar = (T*)a.thetabar;
+    const bool tb_read = (MODE == 1) || a.tb_mode == 1;
+    const bool tb_write = a.tb_mode != 0;
+    const T scale = (T)a.scale;
+    __syncthreads();
+
+    for (int64_t i0 = I0 + 16 * wave; i0 < I1; i0 += 16 * kWaves) {
+        typename Ops::Xop xop;
+        Ops::load_xop(xop, pa, i0, lane);
+        T yv[4], av[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            yv[v] = ycol[i0 + orow<Ops>(g, v)];
+            av[v] = MODE == 0 ? acol[i0 + orow<Ops>(g, v)] : (T)0;
+        }
+        V16<T> th[4], tb[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t off = (i0 + orow<Ops>(g, v)) * a.ld + jl;
+            th[v] = ld16(theta + off);
+            if (tb_read) tb[v] = ld16(thetabar + off);
+            else {
+#pragma unroll
+                for (int t = 0; t < TW; ++t) tb[v].v[t] = (T)0;
+            }
+        }
+
+        acc_t R[TW];
+        Ops::residual(R, xop, breg, yv);
+        acc_t P[TW];
+        if (MODE == 0) Ops::residual(P, xop, dreg, av);
+
+        const bool edge = (i0 < J0 + NW && i0 + 16 > J0) || (J0 + NW > a.N) || (i0 + 16 > a.N);
+        T W[TW][4], Z[TW][4];
+#pragma unroll
+        for (int t = 0; t < TW; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const T d = th[v].v[t] - R[t][v];
+                bool m = d > (T)0;
+                if (edge) {
+                    const int64_t i = i0 + orow<Ops>(g, v), j = jl + t;
+                    m = m && i < a.N && j < a.N && i != j;
+                }
+                if (MODE == 0) {
+                    W[t][v] = m ? d : (T)0;
+                    Z[t][v] = m ? P[t][v] : (T)0;
+                } else {
+                    W[t][v] = (T)0;
+                    Z[t][v] = m ? scale * tb[v].v[t] : (T)0;
+                }
+            }
+        if (tb_write) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                V16<T> o;
+#pragma unroll
+                for (int t = 0; t < TW; ++t) o.v[t] = MODE == 0 ? tb[v].v[t] + Z[t][v] : Z[t][v];
+                st16(thetabar + (i0 + orow<Ops>(g, v)) * a.ld + jl, o);
+            }
+        }
+
+        Ops::colsums(cacc, Z, xop);
+        if (MODE == 0) {
+#pragma unroll
+            for (int t = 0; t < TW; ++t) cw[t] += (W[t][0] + W[t][1]) + (W[t][2] + W[t][3]);
+        }
+
+        // row sums of z
+        T rs[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            T s = Z[0][v];
+#pragma unroll
+            for (int t = 1; t < TW; ++t) s += Z[t][v];
+            rs[v] = row16_sum(s);
+        }
+        if (c == 0) {
+            T* dst = (T*)a.rowpart + (int64_t)strip * a.Nrow + i0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dst[orow<Ops>(g, v)] = rs[v];
+        }
+
+        // row-direction terms sum_j (w_ij (-b_jk) - z_ij (-xi_jk)); lane c keeps k = c and k = 16 + c
+        T keep[2][4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) keep[h][v] = (T)0;
+#pragma unroll
+        for (int k = 0; k < KX; ++k) {
+            if (k >= n) break;
+            const V16<T> xv = *reinterpret_cast<const V16<T>*>(sx + k * NW + TW * c);
+            V16<T> bv;
+            if (MODE == 0) bv = *reinterpret_cast<const V16<T>*>(sb + k * NW + TW * c);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                T s = (T)0;
+#pragma unroll
+                for (int t = 0; t < TW; ++t) {
+                    if (MODE == 0) s += W[t][v] * bv.v[t];
+                    s -= Z[t][v] * xv.v[t];
+                }
+                s = row16_sum(s);
+                if (c == (k & 15)) keep[k >> 4][v] = s;
+            }
+        }
+        T* rv = (T*)a.rowvpart;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = 16 * h + c;
+            if (k < n) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    rv[((int64_t)strip * a.Nrow + i0 + orow<Ops>(g, v)) * n + k] = keep[h][v];
+            }
+        }
+    }
+
+    // combine the 4 waves' column sums (fixed order) and write this chunk's partials
+    typedef T cl_t[TW][NKB][4][64];
+    cl_t* cl = reinterpret_cast<cl_t*>(lds);
+#pragma unroll
+    for (int t = 0; t < TW; ++t)
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cl[wave][t][kb][v][lane] = cacc[t][kb][v];
+    T* cwl = reinterpret_cast<T*>(lds + AdjTile<T>::kCsum);   // [wave][g][NW]
+    if (MODE == 0) {
+#pragma unroll
+        for (int t = 0; t < TW; ++t) cwl[(wave * 4 + g) * NW + TW * c + t] = cw[t];
+    }
+    __syncthreads();
+    T* cpart = (T*)a.cpart;
+    for (int e = threadIdx.x; e < TW * NKB * 4 * 64; e += kBlock) {
+        const int ln = e & 63, v = (e >> 6) & 3, rest = e >> 8;
+        const int kb = rest % NKB, t = rest / NKB;
+        const T s = ((cl[0][t][kb][v][ln] + cl[1][t][kb][v][ln]) + cl[2][t][kb][v][ln]) + cl[3][t][kb][v][ln];
+        const int64_t j = J0 + TW * orow<Ops>(ln >> 4, v) + t;
+        const int kk = 16 * kb + (ln & 15);
+        if (kk < a.nc) cpart[((int64_t)chunk * a.ld + j) * a.nc + kk] = s;
+    }
+    if (MODE == 0) {
+        T* cwp = (T*)a.cwpart + (int64_t)chunk * a.ld + J0;
+        for (int e = threadIdx.x; e < NW; e += kBlock) {
+            T s = (T)0;
+            for (int q = 0; q < kWaves * 4; ++q) s += cwl[q * NW + e];
+            cwp[e] = s;
+        }
+    }
+}
+
+template <int G>
+__device__ __forceinline__ double adj_group_sum(double v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Sums of the pass partials for point m, then the adjoint formulas (header).
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_adj_reduce(AdjReduceArgs a) {
+    constexpr int PER = kBlock / G;
+    const int k = threadIdx.x % G;
+    const int64_t m = (int64_t)blockIdx.x * PER + threadIdx.x / G;
+    const bool valid = m < a.N;
+    const int n = a.n, nc = a.nc;
+    const T* rowpart = (const T*)a.rowpart;
+    const T* rowvpart = (const T*)a.rowvpart;
+    const T* cpart = (const T*)a.cpart;
+    const T* cwpart = (const T*)a.cwpart;
+    double rs = 0.0, rv = 0.0, ck = 0.0, cw = 0.0;
+    if (valid) {
+        for (int q = k; q < a.strips; q += G) rs += (double)rowpart[(int64_t)q * a.Nrow + m];
+        if (k < n)
+            for (int q = 0; q < a.strips; ++q) rv += (double)rowvpart[((int64_t)q * a.Nrow + m) * n + k];
+        if (k < nc)
+            for (int h = 0; h < a.chunks; ++h) ck += (double)cpart[((int64_t)h * a.ld + m) * nc + k];
+        if (a.mode == 0 && k == n)
+            for (int h = 0; h < a.chunks; ++h) cw += (double)cwpart[(int64_t)h * a.ld + m];
+    }
+    rs = adj_group_sum<G>(rs);
+    const int base = (threadIdx.x & 63) & ~(G - 1);
+    const double czn = __shfl(ck, base + n);      // colsum_m(z)
+    const double cwn = __shfl(cw, base + n);      // colsum_m(W)
+    if (!valid) return;
+    if (k == n) {
+        if (a.mode == 0) {
+            const double vb = a.vb_y[m];
+            const double at = a.sy * vb;
+            a.out_y[m] = vb - at / a.mu - (rs - czn);
+            a.dybar[m] += at / a.mu;
+        } else {
+            a.out_y[m] += -(rs - czn);
+        }
+    } else if (k < n) {
+        const int64_t e = m * n + k;
+        const double xmk = a.X[e];
+        if (a.mode == 0) {
+            const double vb = a.vb_xi[e];
+            const double bt = a.sxi * vb;
+            a.out_xi[e] = vb - a.gamma * bt / a.mu + ck - czn * xmk;
+            a.dX[e] += rv - czn * a.xi[e] + cwn * bt;
+        } else {
+            a.out_xi[e] += ck - czn * xmk;
+            a.dX[e] += rv - czn * a.xi[e];
+        }
+    }
+}
+
+// Momentum adjoint: g1 = pb + (1 + beta) qb, pb <- -beta qb, and per-block
+// pieces of <v_y - ybar, g1_y> and <v_xi, g1_xi> for the projection adjoint.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_adj_momentum(AdjVecArgs a) {
+    constexpr int PER = kBlock / G;
+    const int k = threadIdx.x % G;
+    const int64_t m = (int64_t)blockIdx.x * PER + threadIdx.x / G;
+    const bool valid = m < a.N;
+    const int n = a.n;
+    double dy = 0.0, dx = 0.0;
+    if (valid && k == n) {
+        const double q = a.qb_y[m];
+        const double g1 = a.pb_y[m] + (1.0 + a.beta) * q;
+        a.g1_y[m] = g1;
+        a.pb_y[m] = -a.beta * q;
+        dy = (a.v_y[m] - a.ybar[m]) * g1;
+    } else if (valid && k < n) {
+        const int64_t e = m * n + k;
+        const double q = a.qb_xi[e];
+        const double g1 = a.pb_xi[e] + (1.0 + a.beta) * q;
+        a.g1_xi[e] = g1;
+        a.pb_xi[e] = -a.beta * q;
+        dx = a.v_xi[e] * g1;
+    }
+    const double b0 = block_reduce(dy, 0), b1 = block_reduce(dx, 0);
+    if (threadIdx.x == 0) { a.blockpart[blockIdx.x * 4 + 0] = b0; a.blockpart[blockIdx.x * 4 + 1] = b1; }
+}
+
+// Projection adjoint (ball of radius B around the centre, active when the
+// forward norm exceeded B): vb = (B/|d|) (g1 - d <d, g1> / |d|^2), centre
+// adjoint g1 - vb; then the direction operands (a, b) = (s^y vb_y, s^xi vb_xi).
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_adj_project(AdjVecArgs a, int nblk) {
+    constexpr int PER = kBlock / G;
+    const int k = threadIdx.x % G;
+    const int64_t m = (int64_t)blockIdx.x * PER + threadIdx.x / G;
+    const bool valid = m < a.N;
+    const int n = a.n;
+    double sdy = 0.0, sdx = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) {
+        sdy += a.blockpart[(int64_t)b * 4 + 0];
+        sdx += a.blockpart[(int64_t)b * 4 + 1];
+    }
+    const double dy = block_reduce(sdy, 0), dx = block_reduce(sdx, 0);
+    const double ny = a.nrm[0], nx = a.nrm[1];
+    double prod = 0.0, at = 0.0;
+    if (valid && k == n) {
+        const double g1 = a.g1_y[m];
+        double vb = g1;
+        if (ny > a.By) {
+            const double d = a.v_y[m] - a.ybar[m];
+            vb = (a.By / ny) * (g1 - d * (dy / (ny * ny)));
+            a.dybar[m] += g1 - vb;
+        }
+        a.vb_y[m] = vb;
+        at = a.sy * vb;
+        ((T*)a.acol)[m] = (T)at;
+    } else if (valid && k < n) {
+        const int64_t e = m * n + k;
+        const double g1 = a.g1_xi[e];
+        double vb = g1;
+        if (nx > a.Bxi) vb = (a.Bxi / nx) * (g1 - a.v_xi[e] * (dx / (nx * nx)));
+        a.vb_xi[e] = vb;
+        const double bt = a.sxi * vb;
+        ((T*)a.diraug)[m * a.kp + k] = (T)(-bt);
+        prod = a.X[e] * bt;
+    }
+    const double d = adj_group_sum<G>(prod);         // x_m^T b_m
+    if (valid && k == n) ((T*)a.diraug)[m * a.kp + n] = (T)(d - at);
+}
+
+__global__ __launch_bounds__(kBlock) void k_add(double* out, const double* x, const double* y, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < count) out[i] = x[i] + y[i];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static int adj_group(int n) { return n + 1 <= 16 ? 16 : 32; }
+
+int adj_vec_blocks(int64_t N, int n) {
+    const int G = adj_group(n);
+    return (int)((N * G + kBlock - 1) / kBlock);
+}
+
+template <typename T, int KS>
+static void adj_pass_ks(const AdjPassArgs& a, dim3 grid, hipStream_t s) {
+    if (a.mode == 0) hipLaunchKernelGGL((k_adj_pass<T, KS, 0>), grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_adj_pass<T, KS, 1>), grid, dim3(kBlock), 0, s, a);
+}
+
+template <typename T>
+static hipError_t adj_pass_t(int ks, const AdjPassArgs& a, dim3 grid, hipStream_t s) {
+    switch (ks) {
+        case 1: adj_pass_ks<T, 1>(a, grid, s); break;
+        case 2: adj_pass_ks<T, 2>(a, grid, s); break;
+        case 3: adj_pass_ks<T, 3>(a, grid, s); break;
+        case 4: adj_pass_ks<T, 4>(a, grid, s); break;
+        case 5: adj_pass_ks<T, 5>(a, grid, s); break;
+        case 6: adj_pass_ks<T, 6>(a, grid, s); break;
+        case 7: adj_pass_ks<T, 7>(a, grid, s); break;
+        case 8: adj_pass_ks<T, 8>(a, grid, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_pass(bool f64, int n, const AdjPassArgs& a, dim3 grid, hipStream_t s) {
+    const int ks = ks_of(n);
+    return f64 ? adj_pass_t<double>(ks, a, grid, s) : adj_pass_t<float>(ks, a, grid, s);
+}
+
+hipError_t launch_adj_reduce(bool f64, const AdjReduceArgs& a, hipStream_t s) {
+    const int G = adj_group(a.n);
+    const dim3 grid((unsigned)adj_vec_blocks(a.N, a.n));
+    if (f64) {
+        if (G == 16) hipLaunchKernelGGL((k_adj_reduce<double, 16>), grid, dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL((k_adj_reduce<double, 32>), grid, dim3(kBlock), 0, s, a);
+    } else {
+        if (G == 16) hipLaunchKernelGGL((k_adj_reduce<float, 16>), grid, dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL((k_adj_reduce<float, 32>), grid, dim3(kBlock), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_momentum(const AdjVecArgs& a, hipStream_t s) {
+    const dim3 grid((unsigned)adj_vec_blocks(a.N, a.n));
+    if (adj_group(a.n) == 16) hipLaunchKernelGGL(k_adj_momentum<16>, grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL(k_adj_momentum<32>, grid, dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_project(bool f64, const AdjVecArgs& a, int nblk, hipStream_t s) {
+    const dim3 grid((unsigned)adj_vec_blocks(a.N, a.n));
+    const int G = adj_group(a.n);
+    if (f64) {
+        if (G == 16) hipLaunchKernelGGL((k_adj_project<double, 16>), grid, dim3(kBlock), 0, s, a, nblk);
+        else hipLaunchKernelGGL((k_adj_project<double, 32>), grid, dim3(kBlock), 0, s, a, nblk);
+    } else {
+        if (G == 16) hipLaunchKernelGGL((k_adj_project<float, 16>), grid, dim3(kBlock), 0, s, a, nblk);
+        else hipLaunchKernelGGL((k_adj_project<float, 32>), grid, dim3(kBlock), 0, s, a, nblk);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_add(double* out, const double* x, const double* y, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add, dim3((unsigned)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, out, x, y, count);
+    return hipGetLastError();
+}
+
+}  // namespace cr

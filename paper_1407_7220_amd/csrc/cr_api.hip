@@ -14,6 +14,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/cr.h"
 #include "cr_device.h"
@@ -1037,6 +1038,382 @@ cr_status cr_solve_batched(const cr_problem* probs, int32_t P, const cr_params* 
     }
     cr_batch_destroy(b);
     return s;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Differentiable form: the fixed-schedule map and its reverse pass.  The
+// forward is cr_run's fixed schedule launched iteration by iteration, keeping
+// theta_k of every ALCC iteration and the MAPG state every C iterations.  The
+// reverse pass walks the ALCC iterations backwards; for each segment of C MAPG
+// steps it recomputes the segment from its checkpoint (saving each step's pass
+// point, unprojected step and norms), then applies the step adjoints in
+// reverse: momentum, projection, pair pass, reduction.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct DiffLayout {
+    int K = 0, Lin = 0, C = 0, nseg = 0;
+    size_t vecN = 0;                 // doubles of one (y, xi) pair of vectors: Nrow (n + 1)
+    size_t off_thst, off_thbar, off_ckpt, off_sv, off_svn, off_vec, off_diraug, off_acol, off_rowv, off_cw, off_bp;
+    size_t total;
+};
+
+enum DiffVec { kPB = 0, kQB, kG1, kVB, kYA, kACC, kZERO, kNumVec };
+
+DiffLayout make_diff_layout(const Layout& L, const cr_params& p, int C) {
+    DiffLayout D;
+    D.K = p.max_outer;
+    D.Lin = p.inner_iters;
+    D.C = std::max(1, std::min(C, D.Lin));
+    D.nseg = (D.Lin + D.C - 1) / D.C;
+    D.vecN = (size_t)L.Nrow * (L.n + 1);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    const size_t th = (size_t)L.Nrow * L.ld * L.esz;
+    D.off_thst = take(th * (size_t)(D.K - 1));
+    D.off_thbar = take(D.K > 1 ? th : 0);
+    D.off_ckpt = take((size_t)D.K * D.nseg * 2 * D.vecN * 8);
+    D.off_sv = take((size_t)D.C * 2 * D.vecN * 8);
+    D.off_svn = take((size_t)D.C * 4 * 8);
+    D.off_vec = take((size_t)kNumVec * D.vecN * 8);
+    D.off_diraug = take((size_t)L.ld * L.kp * L.esz);
+    D.off_acol = take((size_t)L.Nrow * L.esz);
+    D.off_rowv = take((size_t)L.strips * L.Nrow * L.n * L.esz);
+    D.off_cw = take((size_t)L.chunks * L.ld * L.esz);
+    D.off_bp = take((size_t)(cr::adj_vec_blocks(L.Nrow, L.n) + 1) * 4 * 8);
+    D.total = o + 256;
+    return D;
+}
+
+bool check_diff(const cr_params* p, int32_t C, std::string& msg, cr_status& st) {
+    st = CR_ERR_ARG;
+    if (!check_params(p, msg)) return false;
+    if (p->inner_iters < 1) { msg = "the differentiable form needs a fixed schedule (inner_iters >= 1)"; return false; }
+    if (C < 1) { msg = "checkpoint_every must be >= 1"; return false; }
+    if (p->precision == CR_MIXED_BF16) {
+        msg = "the differentiable form runs CR_F64 and CR_F32";
+        st = CR_ERR_UNSUPPORTED;
+        return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+struct cr_diff {
+    cr_ctx* c = nullptr;
+    DiffLayout D;
+    size_t base_bytes = 0;
+    char* ws = nullptr;
+    bool have_fwd = false;
+    std::vector<cr::OuterArgs> oas;
+    std::vector<double> beta;        // beta_l, l = 1..Lin (index l)
+    double* Dp(size_t off) const { return reinterpret_cast<double*>(ws + off); }
+    char* Pp(size_t off) const { return ws + off; }
+    // pair of vectors: y part (Nrow), then xi part (Nrow n)
+    double* vy(int which) const { return Dp(D.off_vec) + (size_t)which * D.vecN; }
+    double* vxi(int which) const { return vy(which) + c->L.Nrow; }
+    double* ck(int k, int s, int part) const {          // part 0: (y1p, xi1p), 1: (y2, xi2)
+        return Dp(D.off_ckpt) + (((size_t)(k - 1) * D.nseg + s) * 2 + part) * D.vecN;
+    }
+    double* sv(int slot, int part) const {              // part 0: (y2, xi2), 1: (v_y, v_xi)
+        return Dp(D.off_sv) + ((size_t)slot * 2 + part) * D.vecN;
+    }
+    double* svn(int slot) const { return Dp(D.off_svn) + (size_t)slot * 4; }
+    void* thst(int k) const {                            // theta_k, k >= 2
+        return Pp(D.off_thst + (size_t)(k - 2) * c->L.Nrow * c->L.ld * c->L.esz);
+    }
+};
+
+static cr_status dfail(cr_diff* d, cr_status s, const std::string& msg) { return fail(d ? d->c : nullptr, s, msg); }
+
+#define DHIPCHK(d, call)                                                                         \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return dfail(d, CR_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+static hipError_t copy_pair(cr_diff* d, double* dst_y, double* dst_xi, const double* src_y, const double* src_xi,
+                            hipStream_t s) {
+    const cr_ctx* c = d->c;
+    hipError_t e = hipMemcpyAsync(dst_y, src_y, (size_t)c->N * 8, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dst_xi, src_xi, (size_t)c->N * c->n * 8, hipMemcpyDeviceToDevice, s);
+    return e;
+}
+
+static cr::AdjPassArgs adj_pass_args(cr_diff* d, int mode, int tb_mode, double scale) {
+    cr_ctx* c = d->c;
+    const Layout& L = c->L;
+    cr::AdjPassArgs a{};
+    a.N = L.N; a.Nrow = L.Nrow; a.ld = L.ld; a.n = L.n; a.nc = L.nc; a.rows_per_chunk = L.rpc; a.kp = L.kp;
+    a.mode = mode; a.tb_mode = tb_mode;
+    a.theta = c->P(L.off_theta); a.thetabar = d->D.K > 1 ? d->Pp(d->D.off_thbar) : nullptr;
+    a.xp = c->P(L.off_xp); a.xiaug = c->P(L.off_xiaug); a.ycol = c->P(L.off_ycol);
+    a.diraug = d->Pp(d->D.off_diraug); a.acol = d->Pp(d->D.off_acol);
+    a.rowpart = c->P(L.off_rowpart); a.rowvpart = d->Pp(d->D.off_rowv);
+    a.cpart = c->P(L.off_cpart); a.cwpart = d->Pp(d->D.off_cw);
+    a.scale = scale;
+    return a;
+}
+
+static cr::AdjReduceArgs adj_reduce_args(cr_diff* d, int mode, const double* xi, const cr::OuterArgs& oa) {
+    cr_ctx* c = d->c;
+    const Layout& L = c->L;
+    cr::AdjReduceArgs a{};
+    a.N = L.N; a.Nrow = L.Nrow; a.ld = L.ld; a.n = L.n; a.nc = L.nc; a.strips = L.strips; a.chunks = L.chunks;
+    a.mode = mode;
+    a.rowpart = c->P(L.off_rowpart); a.rowvpart = d->Pp(d->D.off_rowv);
+    a.cpart = c->P(L.off_cpart); a.cwpart = d->Pp(d->D.off_cw);
+    a.X = c->X; a.xi = xi;
+    a.vb_y = d->vy(kVB); a.vb_xi = d->vxi(kVB);
+    a.sy = oa.sy; a.sxi = oa.sxi; a.mu = oa.mu; a.gamma = oa.gamma;
+    if (mode == 0) { a.out_y = d->vy(kQB); a.out_xi = d->vxi(kQB); }
+    else { a.out_y = d->vy(kYA); a.out_xi = d->vxi(kYA); }
+    a.dybar = d->vy(kACC); a.dX = d->vxi(kACC);
+    return a;
+}
+
+static cr::AdjVecArgs adj_vec_args(cr_diff* d, const cr::OuterArgs& oa, double beta, int slot) {
+    cr_ctx* c = d->c;
+    const Layout& L = c->L;
+    cr::AdjVecArgs a{};
+    a.N = L.N; a.Nrow = L.Nrow; a.ld = L.ld; a.n = L.n; a.kp = L.kp;
+    a.beta = beta; a.sy = oa.sy; a.sxi = oa.sxi; a.By = oa.By; a.Bxi = oa.Bxi;
+    a.X = c->X; a.ybar = c->ybar;
+    a.pb_y = d->vy(kPB); a.pb_xi = d->vxi(kPB);
+    a.qb_y = d->vy(kQB); a.qb_xi = d->vxi(kQB);
+    a.g1_y = d->vy(kG1); a.g1_xi = d->vxi(kG1);
+    a.v_y = d->sv(slot, 1); a.v_xi = d->sv(slot, 1) + L.Nrow;
+    a.nrm = d->svn(slot);
+    a.vb_y = d->vy(kVB); a.vb_xi = d->vxi(kVB);
+    a.dybar = d->vy(kACC);
+    a.diraug = d->Pp(d->D.off_diraug); a.acol = d->Pp(d->D.off_acol);
+    a.blockpart = d->Dp(d->D.off_bp);
+    return a;
+}
+
+extern "C" {
+
+cr_status cr_diff_workspace_bytes(int64_t N, int32_t n, const cr_params* params, int32_t checkpoint_every,
+                                  size_t* bytes) {
+    std::string msg;
+    if (!bytes) return fail(nullptr, CR_ERR_ARG, "bytes is NULL");
+    cr_status s = check_dims(N, n, msg);
+    if (s != CR_OK) return fail(nullptr, s, msg);
+    if (!check_diff(params, checkpoint_every, msg, s)) return fail(nullptr, s, msg);
+    Layout L = make_layout(N, n, params->precision, max_mapg_iters(*params), params->tile_rows);
+    *bytes = L.total + make_diff_layout(L, *params, checkpoint_every).total;
+    return CR_OK;
+}
+
+cr_status cr_diff_init(cr_diff** out, int64_t N, int32_t n, const cr_params* params, int32_t checkpoint_every,
+                       const void* X_dev, const void* ybar_dev, void* workspace_dev, size_t ws_bytes,
+                       void* stream) {
+    std::string msg;
+    if (!out) return fail(nullptr, CR_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    cr_status s = check_dims(N, n, msg);
+    if (s != CR_OK) return fail(nullptr, s, msg);
+    if (!check_diff(params, checkpoint_every, msg, s)) return fail(nullptr, s, msg);
+    if (!X_dev || !ybar_dev || !workspace_dev) return fail(nullptr, CR_ERR_ARG, "X, ybar and workspace must be non-NULL");
+    Layout L = make_layout(N, n, params->precision, max_mapg_iters(*params), params->tile_rows);
+    DiffLayout D = make_diff_layout(L, *params, checkpoint_every);
+    if (ws_bytes < L.total + D.total) return fail(nullptr, CR_ERR_NOMEM, "workspace smaller than cr_diff_workspace_bytes()");
+    cr_diff* d = new (std::nothrow) cr_diff();
+    if (!d) return fail(nullptr, CR_ERR_NOMEM, "host allocation failed");
+    s = cr_init(&d->c, N, n, params, X_dev, ybar_dev, workspace_dev, L.total, stream);
+    if (s != CR_OK) { delete d; return s; }
+    d->D = D;
+    d->base_bytes = L.total;
+    d->ws = (char*)align256((size_t)workspace_dev + L.total);
+    d->beta.assign((size_t)D.Lin + 2, 0.0);
+    double t = 1.0;
+    for (int l = 1; l <= D.Lin + 1; ++l) {
+        const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+        d->beta[l] = (t - 1.0) / tn;
+        t = tn;
+    }
+    hipStream_t cs = d->c->cs;
+    hipError_t e = cr::launch_zero(d->Pp(D.off_diraug), (size_t)L.ld * L.kp * L.esz, cs);
+    if (e == hipSuccess) e = cr::launch_zero(d->Pp(D.off_acol), (size_t)L.Nrow * L.esz, cs);
+    if (e == hipSuccess) e = cr::launch_zero(d->Pp(D.off_vec), (size_t)kNumVec * D.vecN * 8, cs);
+    if (e == hipSuccess) e = hipStreamSynchronize(cs);
+    if (e != hipSuccess) {
+        fail(nullptr, CR_ERR_HIP, std::string("diff set-up: ") + hipGetErrorString(e));
+        cr_diff_destroy(d);
+        return CR_ERR_HIP;
+    }
+    *out = d;
+    return CR_OK;
+}
+
+cr_status cr_diff_destroy(cr_diff* d) {
+    if (!d) return CR_OK;
+    cr_destroy(d->c);
+    delete d;
+    return CR_OK;
+}
+
+cr_status cr_diff_forward(cr_diff* d, const void* y0_dev, const void* xi0_dev, void* y_dev, void* xi_dev,
+                          cr_info* info) {
+    if (!d) return fail(nullptr, CR_ERR_ARG, "diff is NULL");
+    if (!y_dev || !xi_dev) return dfail(d, CR_ERR_ARG, "y and xi must be non-NULL");
+    cr_ctx* c = d->c;
+    const Layout& L = c->L;
+    const DiffLayout& D = d->D;
+    hipStream_t cs = c->cs;
+    d->have_fwd = false;
+    DHIPCHK(d, hipEventRecord(c->ev[0], c->user_stream));
+    DHIPCHK(d, hipStreamWaitEvent(cs, c->ev[0], 0));
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t th_bytes = (size_t)L.Nrow * L.ld * L.esz;
+
+    DHIPCHK(d, cr::launch_zero(c->P(L.off_theta), th_bytes, cs));
+    const double* y0 = y0_dev ? (const double*)y0_dev : c->ybar;
+    const double* xi0 = xi0_dev ? (const double*)xi0_dev : d->vxi(kZERO);
+    cr::PointArgs start = point_args(c, y0, xi0, 1);
+    DHIPCHK(d, cr::launch_set_point(c->prec, start, cs));
+
+    Schedule sch;
+    sch.start(c);
+    d->oas.clear();
+    cr::DevState h{};
+    for (int k = 1; k <= D.K; ++k) {
+        const cr::OuterArgs oa = sch.next(c);
+        d->oas.push_back(oa);
+        const double mu = sch.mu, mu_next = sch.mu_next(c);
+        if (k >= 2) DHIPCHK(d, hipMemcpyAsync(d->thst(k), c->P(L.off_theta), th_bytes, hipMemcpyDeviceToDevice, cs));
+        DHIPCHK(d, cr::launch_begin_outer(oa, c->oa, c->st, cs, 0));
+        for (int l = 1; l <= D.Lin; ++l) {
+            if ((l - 1) % D.C == 0) {
+                const int sg = (l - 1) / D.C;
+                double* c0 = d->ck(k, sg, 0);
+                double* c1 = d->ck(k, sg, 1);
+                DHIPCHK(d, copy_pair(d, c0, c0 + L.Nrow, c->D(L.off_y1p), c->D(L.off_xi1p), cs));
+                DHIPCHK(d, copy_pair(d, c1, c1 + L.Nrow, c->D(L.off_y2), c->D(L.off_xi2), cs));
+            }
+            DHIPCHK(d, enqueue_mapg_iteration(c, l - 1, cs));
+        }
+        DHIPCHK(d, enqueue_multiplier_step(c, mu, mu_next, D.Lin, cr::reduce_blocks(c->N, c->n), cs));
+        DHIPCHK(d, hipStreamSynchronize(cs));
+        h = *c->pinned_state;
+        if (h.iterate_nonfinite) return dfail(d, CR_ERR_NONFINITE, "non-finite iterate");
+        sch.total_inner += D.Lin;
+        sch.advance(c);
+    }
+    DHIPCHK(d, copy_pair(d, (double*)y_dev, (double*)xi_dev, c->D(L.off_y1p), c->D(L.off_xi1p), cs));
+    DHIPCHK(d, hipStreamSynchronize(cs));
+    c->have_kkt = true;
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        fill_info(c, h, info);
+        info->outer_iters = D.K;
+        info->inner_iters = sch.total_inner;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        info->pair_updates = (double)c->N * (double)(c->N - 1) * (double)sch.total_inner;
+        info->status = CR_OK;
+    }
+    d->have_fwd = true;
+    return CR_OK;
+}
+
+cr_status cr_diff_backward(cr_diff* d, const void* gy_dev, const void* gxi_dev, void* dX_dev, void* dybar_dev,
+                           void* dy0_dev, void* dxi0_dev) {
+    if (!d) return fail(nullptr, CR_ERR_ARG, "diff is NULL");
+    if (!gy_dev || !dX_dev || !dybar_dev || !dy0_dev || !dxi0_dev)
+        return dfail(d, CR_ERR_ARG, "gy, dX, dybar, dy0 and dxi0 must be non-NULL");
+    if (!d->have_fwd) return dfail(d, CR_ERR_STATE, "cr_diff_backward needs a completed cr_diff_forward");
+    cr_ctx* c = d->c;
+    const Layout& L = c->L;
+    const DiffLayout& D = d->D;
+    hipStream_t cs = c->cs;
+    DHIPCHK(d, hipEventRecord(c->ev[0], c->user_stream));
+    DHIPCHK(d, hipStreamWaitEvent(cs, c->ev[0], 0));
+    const size_t th_bytes = (size_t)L.Nrow * L.ld * L.esz;
+    const size_t pair_bytes = D.vecN * 8;
+    const bool f64 = c->f64;
+    const dim3 grid = pass_grid(L);
+    const int nvb = cr::adj_vec_blocks(c->N, c->n);
+
+    DHIPCHK(d, cr::launch_zero(d->vy(kACC), pair_bytes, cs));
+    DHIPCHK(d, cr::launch_zero(d->vy(kYA), pair_bytes, cs));
+    DHIPCHK(d, hipMemcpyAsync(d->vy(kYA), gy_dev, (size_t)c->N * 8, hipMemcpyDeviceToDevice, cs));
+    if (gxi_dev)
+        DHIPCHK(d, hipMemcpyAsync(d->vxi(kYA), gxi_dev, (size_t)c->N * c->n * 8, hipMemcpyDeviceToDevice, cs));
+    if (D.K > 1) DHIPCHK(d, cr::launch_zero(d->Pp(D.off_thbar), th_bytes, cs));
+
+    for (int k = D.K; k >= 1; --k) {
+        const cr::OuterArgs& oa = d->oas[k - 1];
+        if (k >= 2) DHIPCHK(d, hipMemcpyAsync(c->P(L.off_theta), d->thst(k), th_bytes, hipMemcpyDeviceToDevice, cs));
+        else DHIPCHK(d, cr::launch_zero(c->P(L.off_theta), th_bytes, cs));
+
+        if (k < D.K) {
+            // multiplier step k: theta_{k+1} = s (A1 y_k + A2 xi_k - theta_k)_-, at (y_k, xi_k)
+            const double* yk = d->ck(k + 1, 0, 0);
+            const double* xik = yk + L.Nrow;
+            cr::PointArgs pt = point_args(c, yk, xik, 0);
+            DHIPCHK(d, cr::launch_set_point(c->prec, pt, cs));
+            cr::AdjPassArgs pa = adj_pass_args(d, 1, k >= 2 ? 2 : 0, oa.theta_scale);
+            DHIPCHK(d, cr::launch_adj_pass(f64, c->n, pa, grid, cs));
+            cr::AdjReduceArgs ra = adj_reduce_args(d, 1, xik, oa);
+            DHIPCHK(d, cr::launch_adj_reduce(f64, ra, cs));
+        }
+
+        // MAPG of iteration k, backwards: pb = adjoint of y_k = y^(1)_L, qb = 0
+        DHIPCHK(d, hipMemcpyAsync(d->vy(kPB), d->vy(kYA), pair_bytes, hipMemcpyDeviceToDevice, cs));
+        DHIPCHK(d, cr::launch_zero(d->vy(kQB), pair_bytes, cs));
+        for (int sg = D.nseg - 1; sg >= 0; --sg) {
+            const int l0 = sg * D.C + 1, l1 = std::min(D.Lin, l0 + D.C - 1);
+            // recompute the segment from its checkpoint, saving every step
+            const double* c0 = d->ck(k, sg, 0);
+            const double* c1 = d->ck(k, sg, 1);
+            DHIPCHK(d, copy_pair(d, c->D(L.off_y1p), c->D(L.off_xi1p), c0, c0 + L.Nrow, cs));
+            DHIPCHK(d, copy_pair(d, c->D(L.off_y2), c->D(L.off_xi2), c1, c1 + L.Nrow, cs));
+            cr::PointArgs pt = point_args(c, c->D(L.off_y2), c->D(L.off_xi2), 0);
+            DHIPCHK(d, cr::launch_set_point(c->prec, pt, cs));
+            DHIPCHK(d, cr::launch_begin_outer(oa, c->oa, c->st, cs, l0 - 1));
+            for (int l = l0; l <= l1; ++l) {
+                const int q = l - l0;
+                cr::PassArgs pa = pass_args(c, 0, 0.0, &c->st->active);
+                DHIPCHK(d, cr::launch_pair_pass(c->prec, c->n, pa, grid, cs));
+                cr::ReduceArgs ra = reduce_args(c, 0, c->D(L.off_y2), c->D(L.off_xi2), c->D(L.off_vy),
+                                                c->D(L.off_vxi), 0.0);
+                ra.q = q;
+                DHIPCHK(d, cr::launch_reduce(c->f64, ra, cs));
+                cr::UpdateArgs ua = update_args(c);
+                ua.q = q;
+                ua.sv_y2 = d->sv(q, 0); ua.sv_xi2 = d->sv(q, 0) + L.Nrow;
+                ua.sv_vy = d->sv(q, 1); ua.sv_vxi = d->sv(q, 1) + L.Nrow;
+                ua.sv_nrm = d->svn(q);
+                DHIPCHK(d, cr::launch_update(c->prec, ua, cs));
+            }
+            // step adjoints in reverse
+            for (int l = l1; l >= l0; --l) {
+                const int q = l - l0;
+                cr::AdjVecArgs va = adj_vec_args(d, oa, d->beta[l], q);
+                DHIPCHK(d, cr::launch_adj_momentum(va, cs));
+                DHIPCHK(d, cr::launch_adj_project(f64, va, nvb, cs));
+                const double* qy = d->sv(q, 0);
+                const double* qxi = qy + L.Nrow;
+                cr::PointArgs pq = point_args(c, qy, qxi, 0);
+                DHIPCHK(d, cr::launch_set_point(c->prec, pq, cs));
+                cr::AdjPassArgs pa = adj_pass_args(d, 0, k >= 2 ? 1 : 0, 0.0);
+                DHIPCHK(d, cr::launch_adj_pass(f64, c->n, pa, grid, cs));
+                cr::AdjReduceArgs ra = adj_reduce_args(d, 0, qxi, oa);
+                DHIPCHK(d, cr::launch_adj_reduce(f64, ra, cs));
+            }
+        }
+        // adjoint of y_{k-1} = y^(1)_0 = y^(2)_1
+        DHIPCHK(d, cr::launch_add(d->vy(kYA), d->vy(kPB), d->vy(kQB), (int64_t)D.vecN, cs));
+    }
+    DHIPCHK(d, copy_pair(d, (double*)dy0_dev, (double*)dxi0_dev, d->vy(kYA), d->vxi(kYA), cs));
+    DHIPCHK(d, copy_pair(d, (double*)dybar_dev, (double*)dX_dev, d->vy(kACC), d->vxi(kACC), cs));
+    DHIPCHK(d, hipStreamSynchronize(cs));
+    return CR_OK;
 }
 
 }  // extern "C"

@@ -115,6 +115,13 @@ struct UpdateArgs {
     double* blockpart;
     const OuterArgs* oa;
     DevState* st;
+    // optional copies for the adjoint (null otherwise): the pass point y^(2)_l,
+    // xi^(2)_l, the unprojected step v_l, and the two norms ||v - centre||
+    double* sv_y2;
+    double* sv_xi2;
+    double* sv_vy;
+    double* sv_vxi;
+    double* sv_nrm;
 };
 
 // Operands of the next pass at (y, xi), optionally restarting MAPG there.
@@ -138,7 +145,8 @@ hipError_t launch_pair_pass(int prec, int n, const PassArgs& a, dim3 grid, hipSt
 hipError_t launch_reduce(bool f64, const ReduceArgs& a, hipStream_t s);
 hipError_t launch_update(int prec, const UpdateArgs& a, hipStream_t s);
 hipError_t launch_set_point(int prec, const PointArgs& a, hipStream_t s);
-hipError_t launch_begin_outer(const OuterArgs& args, OuterArgs* dst, DevState* st, hipStream_t s);
+hipError_t launch_begin_outer(const OuterArgs& args, OuterArgs* dst, DevState* st, hipStream_t s,
+                              int64_t base = 0);
 hipError_t launch_replay_end(DevState* st, int iters, hipStream_t s);
 hipError_t launch_mapg_end(const double* blockpart, int nblk, int64_t launched, DevState* st, hipStream_t s);
 int reduce_blocks(int64_t N, int n);
@@ -160,5 +168,85 @@ hipError_t launch_theta_export(bool f64, const void* theta, int64_t N, int64_t l
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_setup(const double* X, const double* ybar, int64_t N, int n, double gamma, double* su,
                         double* part, double* y0, double* xi0, DevState* st, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Adjoint (reverse-mode) kernels of the fixed-schedule map (cr_adjoint.hip).
+// ---------------------------------------------------------------------------
+// Pair pass of the adjoint.  Mode 0 (MAPG step): at the pass point (operands
+// xiaug, ycol) with theta_k, mask m_ij = [theta_ij - r_ij > 0] (valid pairs),
+// W = m (theta - r), and the direction (a, b) (operands diraug, acol) gives
+// rho = A1 a + A2 b and z = m rho.  Mode 1 (multiplier step): z = scale m thetabar.
+// Outputs (partials, summed by k_adj_reduce):
+//   rowpart [strip][i]     sum_j z_ij
+//   rowvpart[strip][i][k]  sum_j (W_ij (-b_jk) - z_ij (-xi_jk))
+//   cpart   [chunk][j][k]  Z^T [X 1]  (k < n: sum_i z_ij x_ik, k = n: sum_i z_ij)
+//   cwpart  [chunk][j]     sum_i W_ij  (mode 0)
+// thetabar: mode 0 with tb_mode 1: thetabar += z; mode 1 with tb_mode 2: thetabar = z.
+struct AdjPassArgs {
+    int64_t N, Nrow, ld;
+    int32_t n, nc, rows_per_chunk, kp;
+    int32_t mode, tb_mode;
+    const void* theta;
+    void* thetabar;
+    const void* xp;
+    const void* xiaug;
+    const void* ycol;
+    const void* diraug;
+    const void* acol;
+    void* rowpart;
+    void* rowvpart;
+    void* cpart;
+    void* cwpart;
+    double scale;
+};
+
+struct AdjReduceArgs {
+    int64_t N, Nrow, ld;
+    int32_t n, nc, strips, chunks, mode, pad;
+    const void* rowpart;
+    const void* rowvpart;
+    const void* cpart;
+    const void* cwpart;
+    const double* X;
+    const double* xi;          // xi of the pass point
+    const double* vb_y;        // mode 0: projected adjoint (v-bar)
+    const double* vb_xi;
+    double sy, sxi, mu, gamma;
+    double* out_y;             // mode 0: q-bar (written); mode 1: adjoint of (y_k, xi_k) (added to)
+    double* out_xi;
+    double* dybar;             // mode 0: += a / mu
+    double* dX;
+};
+
+// Momentum and projection adjoints of one MAPG step (vector kernels).
+struct AdjVecArgs {
+    int64_t N, Nrow, ld;
+    int32_t n, kp;
+    double beta, sy, sxi, By, Bxi;
+    const double* X;
+    const double* ybar;
+    double* pb_y;              // adjoint of y^(1)_l (in), of y^(1)_{l-1} (out)
+    double* pb_xi;
+    const double* qb_y;        // adjoint of y^(2)_{l+1}
+    const double* qb_xi;
+    double* g1_y;              // adjoint of y^(1)_l
+    double* g1_xi;
+    const double* v_y;         // saved unprojected step v_l
+    const double* v_xi;
+    const double* nrm;         // saved ||v_y - ybar||, ||v_xi||
+    double* vb_y;              // projected adjoint v-bar (out)
+    double* vb_xi;
+    double* dybar;             // += adjoint of the ball centre
+    void* diraug;              // direction operands [-b_j, x_j^T b_j - a_j, 0..], b = sxi vb_xi
+    void* acol;                // a = sy vb_y
+    double* blockpart;         // per block: dot products (y, xi)
+};
+
+hipError_t launch_adj_pass(bool f64, int n, const AdjPassArgs& a, dim3 grid, hipStream_t s);
+hipError_t launch_adj_reduce(bool f64, const AdjReduceArgs& a, hipStream_t s);
+hipError_t launch_adj_momentum(const AdjVecArgs& a, hipStream_t s);
+hipError_t launch_adj_project(bool f64, const AdjVecArgs& a, int nblk, hipStream_t s);
+hipError_t launch_add(double* out, const double* a, const double* b, int64_t count, hipStream_t s);
+int adj_vec_blocks(int64_t N, int n);
 
 }  // namespace cr

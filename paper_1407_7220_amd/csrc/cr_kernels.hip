@@ -18,237 +18,10 @@
 // plus wavefront shuffles for the row sums.  Partial sums leave each
 // workgroup once; a separate O(N n) kernel sums them in a fixed order.
 #include "cr_device.h"
+#include "cr_ops.h"
 
 namespace cr {
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-template <typename T> struct Tr;
-template <> struct Tr<float> {
-    static constexpr int TW = 4;   // j-tiles per wave: 16 lanes x 4 floats = 256 B per row
-    typedef f32x4 acc;
-};
-template <> struct Tr<double> {
-    static constexpr int TW = 2;   // 16 lanes x 2 doubles = 256 B per row
-    typedef f64x4 acc;
-};
-
-// 16x16x4 MFMA.  Operand layout for lane l = 16 g + c (g = l / 16, c = l % 16):
-//   A element (row c, k g), B element (k g, col c); accumulator element v is
-//   (row rmap(g, v), col c) with rmap = 4 g + v for FP32 and g + 4 v for FP64
-//   (measured on gfx950 with a one-wave layout probe).
-__device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 acc) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
-}
-__device__ __forceinline__ f64x4 mfma4(double a, double b, f64x4 acc) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-}
-
-template <typename T> __host__ __device__ constexpr int rmap(int g, int v) {
-    return sizeof(T) == 4 ? 4 * g + v : g + 4 * v;
-}
-
-template <typename T> struct alignas(16) V16 { T v[16 / sizeof(T)]; };
-
-// Sum over each 16-lane row of the wave with DPP moves (every lane of the row
-// receives the total): pairs (quad_perm 1,0,3,2), quads (quad_perm 2,3,0,1),
-// half rows (row_half_mirror), full row (row_mirror).
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_f(double v) {
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-template <typename T>
-__device__ __forceinline__ T row16_sum(T v) {
-    v += dpp_f<0xB1>(v);
-    v += dpp_f<0x4E>(v);
-    v += dpp_f<0x141>(v);
-    v += dpp_f<0x140>(v);
-    return v;
-}
-
-template <typename T>
-__device__ __forceinline__ V16<T> ld16(const T* p) { return *reinterpret_cast<const V16<T>*>(p); }
-template <typename T>
-__device__ __forceinline__ void st16(T* p, const V16<T>& x) { *reinterpret_cast<V16<T>*>(p) = x; }
-
-// ---------------------------------------------------------------------------
-// Block reductions (256 threads) and the last-arriving-block handshake.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    return v;
-}
-
-// Sum (op 0) or max (op 1) of one double per thread; result valid in every thread.
-__device__ double block_reduce(double v, int op) {
-    __shared__ double red[kBlock / 64];
-    v = op == 0 ? wave_sum(v) : wave_max(v);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double r = red[0];
-    for (int w = 1; w < kBlock / 64; ++w) r = op == 0 ? r + red[w] : fmax(r, red[w]);
-    return r;
-}
-
-// Each block calls this once after writing its partial results; it returns
-// true in every thread of the one block that arrives last (that block then
-// sees every other block's partials) and re-arms the counter.
-__device__ bool last_block(unsigned int* counter) {
-    __shared__ int is_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned int prev = atomicAdd(counter, 1u);
-        is_last = (prev == gridDim.x * gridDim.y - 1) ? 1 : 0;
-        if (is_last) atomicExch(counter, 0u);
-    }
-    __syncthreads();
-    if (is_last) __threadfence();
-    return is_last != 0;
-}
-
-__device__ __forceinline__ double ld_coherent(const double* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// ---------------------------------------------------------------------------
-// Operand policies of the pair pass.  A policy says what one lane holds for
-// the two contractions and how they run:
-//   R = [X 1] [-Xi c]^T + y 1^T      (residuals, one 16 x 16 tile per j-tile)
-//   C += W^T [X 1]                   (sum_i w_ij x_i and colsum_j)
-// ---------------------------------------------------------------------------
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-__device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 acc) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-}
-
-// FP64 / FP32: 16x16x4 MFMA in the pass precision; c_j and y_i enter R exactly.
-template <typename T, int KS, int NSET_ = 0> struct PlainOps {
-    typedef T elem;
-    typedef typename Tr<T>::acc acc_t;
-    static constexpr int TW = Tr<T>::TW;
-    static constexpr int NKB = nkb_of_ks(KS);
-    static constexpr int QP = qp_of_ks(KS, (int)sizeof(T));
-    static constexpr int EV = 16 / (int)sizeof(T);
-    static constexpr int NSET = NSET_ > 0 ? NSET_ : (sizeof(T) == 4 ? 3 : 2);
-    static constexpr int RM4 = sizeof(T) == 4;   // accumulator row map 4 g + v (else g + 4 v)
-    struct Breg { T b[KS][TW]; };
-    struct Xop { T q[QP]; };
-    // B operand of R for every j-tile: [-xi_j, c_j, 0...] (k = 4 s + g)
-    static __device__ void load_breg(Breg& B, const PassArgs& a, int64_t jl, int g) {
-        const T* xiaug = (const T*)a.xiaug;
-#pragma unroll
-        for (int t = 0; t < TW; ++t) {
-            const T* row = xiaug + (jl + t) * (4 * KS);
-#pragma unroll
-            for (int s = 0; s < KS; ++s) B.b[s][t] = row[4 * s + g];
-        }
-    }
-    static __device__ void load_xop(Xop& X, const PassArgs& a, int64_t i0, int lane) {
-        const T* xp = (const T*)a.xp;
-#pragma unroll
-        for (int q = 0; q < QP / EV; ++q) {
-            V16<T> tv = ld16(xp + ((i0 >> 4) * 64 + lane) * QP + q * EV);
-#pragma unroll
-            for (int e = 0; e < EV; ++e) X.q[q * EV + e] = tv.v[e];
-        }
-    }
-    static __device__ void residual(acc_t R[TW], const Xop& X, const Breg& B, const T yv[4]) {
-#pragma unroll
-        for (int t = 0; t < TW; ++t) {
-            R[t] = acc_t{yv[0], yv[1], yv[2], yv[3]};
-#pragma unroll
-            for (int s = 0; s < KS; ++s) R[t] = mfma4(X.q[s], B.b[s][t], R[t]);
-        }
-    }
-    // i-slot g of step s is row i0 + rmap(g, s): W comes straight from R's registers
-    static __device__ void colsums(acc_t C[TW][NKB], const T W[TW][4], const Xop& X) {
-#pragma unroll
-        for (int t = 0; t < TW; ++t)
-#pragma unroll
-            for (int kb = 0; kb < NKB; ++kb)
-#pragma unroll
-                for (int s = 0; s < 4; ++s) C[t][kb] = mfma4(W[t][s], X.q[KS + 4 * kb + s], C[t][kb]);
-    }
-};
-
-// Mixed: BF16 16x16x32 MFMA on hi/lo splits with FP32 accumulation; theta,
-// W and the accumulators are FP32.  R: K-slots [x_hi | x_lo | x_hi] against
-// [-xi_hi | -xi_hi | -xi_lo] (K = 3n, KB blocks of 32), accumulator started
-// at y_i + c_j in FP32.  C: [W_hi(4 rows), W_lo(4 rows)] . [X_hi, X_hi] plus
-// [W_hi, 0] . [X_lo, 0].
-template <int KB, int NKB_> struct MixedOps {
-    typedef float elem;
-    typedef f32x4 acc_t;
-    static constexpr int TW = 4;
-    static constexpr int NKB = NKB_;
-    static constexpr int NSET = KB + NKB <= 2 ? 3 : 2;
-    static constexpr int RM4 = 1;
-    struct Breg { bf16x8 b[KB][TW]; float cc[TW]; };
-    struct Xop { bf16x8 r[KB]; bf16x8 c1[NKB]; bf16x8 c2[NKB]; };
-    static __device__ void load_breg(Breg& B, const PassArgs& a, int64_t jl, int g) {
-        const __bf16* xb = (const __bf16*)a.xiaug;
-#pragma unroll
-        for (int t = 0; t < TW; ++t) {
-#pragma unroll
-            for (int kb = 0; kb < KB; ++kb)
-                B.b[kb][t] = *reinterpret_cast<const bf16x8*>(xb + ((jl + t) * KB + kb) * 32 + 8 * g);
-            B.cc[t] = a.cvec[jl + t];
-        }
-    }
-    static __device__ void load_xop(Xop& X, const PassArgs& a, int64_t i0, int lane) {
-        const bf16x8* xp = (const bf16x8*)a.xp + ((i0 >> 4) * 64 + lane) * (KB + 2 * NKB);
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) X.r[kb] = xp[kb];
-#pragma unroll
-        for (int kb = 0; kb < NKB; ++kb) { X.c1[kb] = xp[KB + 2 * kb]; X.c2[kb] = xp[KB + 2 * kb + 1]; }
-    }
-    static __device__ void residual(acc_t R[TW], const Xop& X, const Breg& B, const float yv[4]) {
-#pragma unroll
-        for (int t = 0; t < TW; ++t) {
-            R[t] = acc_t{yv[0] + B.cc[t], yv[1] + B.cc[t], yv[2] + B.cc[t], yv[3] + B.cc[t]};
-#pragma unroll
-            for (int kb = 0; kb < KB; ++kb) R[t] = mfma_bf16(X.r[kb], B.b[kb][t], R[t]);
-        }
-    }
-    static __device__ void colsums(acc_t C[TW][NKB], const float W[TW][4], const Xop& X) {
-#pragma unroll
-        for (int t = 0; t < TW; ++t) {
-            bf16x8 w1, w2;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const __bf16 hi = (__bf16)W[t][v];
-                w1[v] = hi;
-                w1[v + 4] = (__bf16)(W[t][v] - (float)hi);
-                w2[v] = hi;
-                w2[v + 4] = (__bf16)0.0f;
-            }
-#pragma unroll
-            for (int kb = 0; kb < NKB; ++kb) {
-                C[t][kb] = mfma_bf16(w1, X.c1[kb], C[t][kb]);
-                C[t][kb] = mfma_bf16(w2, X.c2[kb], C[t][kb]);
-            }
-        }
-    }
-};
-
-template <typename Ops> __device__ __forceinline__ int orow(int g, int v) {
-    return Ops::RM4 ? 4 * g + v : g + 4 * v;
-}
 
 // ---------------------------------------------------------------------------
 // The fused pair pass (gradient or multiplier step).
@@ -651,10 +424,12 @@ __device__ void update_block(const UpdateArgs& a, const int blk, const int nblk)
     const double sc_xi = nx > a.oa->Bxi ? a.oa->Bxi / nx : 1.0;
     double dy2 = 0.0, dx2 = 0.0, prod = 0.0, y2n = 0.0;
     T* xa = (T*)a.xiaug + j * a.kp;
+    if (a.sv_nrm && blk == 0 && threadIdx.x == 0) { a.sv_nrm[0] = ny; a.sv_nrm[1] = nx; }
     if (valid && k == n) {
         const double yb = a.ybar[j];
         const double y1 = yb + sc_y * (a.vy[j] - yb);       // projection onto Q_y
         const double y2o = a.y2[j];
+        if (a.sv_y2) { a.sv_y2[j] = y2o; a.sv_vy[j] = a.vy[j]; }
         dy2 = (y1 - y2o) * (y1 - y2o);
         y2n = y1 + beta * (y1 - a.y1p[j]);                  // extrapolation
         a.y1p[j] = y1;
@@ -663,6 +438,7 @@ __device__ void update_block(const UpdateArgs& a, const int blk, const int nblk)
         const int64_t e = j * n + k;
         const double x1 = sc_xi * a.vxi[e];                 // projection onto Q_xi
         const double x2o = a.xi2[e];
+        if (a.sv_y2) { a.sv_xi2[e] = x2o; a.sv_vxi[e] = a.vxi[e]; }
         dx2 = (x1 - x2o) * (x1 - x2o);
         const double x2n = x1 + beta * (x1 - a.xi1p[e]);
         a.xi1p[e] = x1;
@@ -804,10 +580,10 @@ __global__ __launch_bounds__(kBlock) void k_set_point(PointArgs a) {
     }
 }
 
-__global__ void k_begin_outer(OuterArgs args, OuterArgs* dst, DevState* st) {
+__global__ void k_begin_outer(OuterArgs args, OuterArgs* dst, DevState* st, int64_t base) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         *dst = args;
-        st->base = 0;
+        st->base = base;
         st->it = 0;
         st->active = args.skip ? 0 : 1;
         st->stopped_by_alpha = 0;
@@ -1246,8 +1022,8 @@ hipError_t launch_set_point(int prec, const PointArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_begin_outer(const OuterArgs& args, OuterArgs* dst, DevState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_begin_outer, dim3(1), dim3(64), 0, s, args, dst, st);
+hipError_t launch_begin_outer(const OuterArgs& args, OuterArgs* dst, DevState* st, hipStream_t s, int64_t base) {
+    hipLaunchKernelGGL(k_begin_outer, dim3(1), dim3(64), 0, s, args, dst, st, base);
     return hipGetLastError();
 }
 

@@ -134,3 +134,27 @@ def test_autotune_cache_roundtrip(tmp_path, monkeypatch):
     X = np.zeros((5000, 10))
     assert at.tile_rows_for(X, None, cr.F32, tune_if_missing=False) == 512
     assert at.tile_rows_for(X, None, cr.F64, tune_if_missing=False) == 0
+
+
+def test_diff_workspace_and_argument_checks():
+    """cr_diff_workspace_bytes: host-side checks of the differentiable form and
+    the theta store's growth with the number of ALCC iterations."""
+    import paper_1407_7220_amd as cr
+    p = cr.Params(precision=cr.F32, inner_iters=20, max_outer=10)
+    b10 = cr.diff_workspace_bytes(2000, 10, p, 20)
+    b2 = cr.diff_workspace_bytes(2000, 10, cr.Params(precision=cr.F32, inner_iters=20, max_outer=2), 20)
+    theta_bytes = 2048 * 2048 * 4
+    assert b10 - b2 >= 8 * theta_bytes
+    assert b10 - b2 < 8 * theta_bytes + 64 * 2048 * 11 * 8 + (1 << 20)
+    # finer checkpoints cost only O(N n) per checkpoint
+    b1 = cr.diff_workspace_bytes(2000, 10, p, 1)
+    assert b10 < b1 < b10 + 10 * 20 * 2 * 2048 * 11 * 8 + (1 << 20)
+    with pytest.raises(cr.CRError) as e:
+        cr.diff_workspace_bytes(2000, 10, cr.Params(precision=cr.F32, inner_iters=0), 20)
+    assert e.value.status == 1
+    with pytest.raises(cr.CRError) as e:
+        cr.diff_workspace_bytes(2000, 10, p, 0)
+    assert e.value.status == 1
+    with pytest.raises(cr.CRError) as e:
+        cr.diff_workspace_bytes(2000, 10, cr.Params(precision=cr.MIXED_BF16, inner_iters=5), 20)
+    assert e.value.status == 7

@@ -302,3 +302,31 @@ def test_mapg_rate_bound():
         gap = oracle.P_value(X, ybar, gamma, mu, theta, yl, xl) - Pstar
         assert gap >= -1e-9
         assert gap <= 4 * d0 / (l + 1) ** 2 + 1e-9
+
+
+def test_affine_fit_full_rank_and_degenerate():
+    """The start point: with N > n and points in general position the fit is
+    the ordinary least-squares fit on [X 1] (numpy's solver on the uncentred
+    system); with N <= n it interpolates, and its slope is the shortest one,
+    i.e. it lies in the span of the centred points."""
+    rng = np.random.default_rng(0)
+    X = rng.normal(size=(30, 4))
+    ybar = rng.normal(size=30)
+    yhat, xihat, Bbar, By, Bxi = oracle.affine_fit(X, ybar, 1e-3)
+    M = np.hstack([X, np.ones((30, 1))])
+    coef = np.linalg.lstsq(M, ybar, rcond=None)[0]
+    np.testing.assert_allclose(yhat, M @ coef, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(xihat[7], coef[:4], rtol=0, atol=1e-12)
+    # feasibility: every residual of the affine point is zero
+    assert np.abs(oracle.forward(X, yhat, xihat)).max() < 1e-12
+    # degenerate: 3 points in 5 dimensions
+    X = rng.normal(size=(3, 5))
+    ybar = rng.normal(size=3)
+    yhat, xihat, Bbar, By, Bxi = oracle.affine_fit(X, ybar, 1e-3)
+    np.testing.assert_allclose(yhat, ybar, rtol=0, atol=1e-12)
+    Xc = X - X.mean(axis=0)
+    a = xihat[0]
+    # a is in the row space of Xc: its component orthogonal to it vanishes
+    P = np.linalg.pinv(Xc) @ Xc
+    np.testing.assert_allclose(P @ a, a, rtol=0, atol=1e-12)
+    assert abs(Bbar - np.sqrt(1e-3 * 3 * a @ a)) < 1e-12
