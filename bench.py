@@ -16,7 +16,8 @@ Also reported on the same JSON line:
   variants      the same metric for the FP64 solve of the same workload, and the
                 steady-state MAPG throughput (fixed iteration count, stated) of
                 the mixed BF16 form on the 20000-point workload and of the
-                64-problem batched form.
+                64-problem batched form, and the differentiable form (10000
+                points, 10 x 20 unrolled iterations, forward + reverse pass).
 The pass tile height comes from the autotuner (paper_1407_7220_amd.autotune).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision f32|f64]
@@ -139,6 +140,41 @@ def batched_rate(cr, autotune, inner=100, outer=2):
             "pairs_per_iteration": float(sum(q.N * (q.N - 1) for q in probs))}
 
 
+def diff_rate(cr, K=10, L=20, C=20):
+    """The differentiable workload: N = 10000, n = 10, x ~ U[-1,1]^10,
+    f0 = ||x||^2, noise N(0, 0.1^2), FP32, K x L unrolled MAPG iterations
+    checkpointed every C, gradient of sum_l w_l y_l (w ~ N(0, 1))."""
+    import torch
+    import synth
+    p = synth.workload("quadratic_10000")
+    X = torch.from_numpy(p.X).cuda()
+    yb = torch.from_numpy(p.ybar).cuda()
+    w = torch.from_numpy(synth.weights(p.N)).cuda()
+    params = cr.Params(precision=cr.F32, inner_iters=L, max_outer=K)
+    d = cr.Diff(X, yb, params, checkpoint_every=C)
+    d.forward(yb, None)
+    d.backward(w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d.forward(yb, None)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    d.backward(w)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    adj_ms = d.time_adjoint_pass(10)
+    d.close()
+    pairs = p.N * (p.N - 1)
+    iters = K * L
+    adj_bytes = pairs * 4 * 3          # theta read, theta-bar read and write
+    return {"value": pairs * iters / (t2 - t0), "unit": "pair-updates/s (forward + reverse, per unrolled iteration)",
+            "N": p.N, "n": p.n, "schedule": "%d x %d MAPG, checkpoint every %d" % (K, L, C),
+            "forward_s": t1 - t0, "backward_s": t2 - t1,
+            "adjoint_pass": {"avg_ms": adj_ms, "bytes_per_launch": adj_bytes,
+                             "achieved_GBs": adj_bytes / (adj_ms * 1e-3) / 1e9,
+                             "frac": adj_bytes / (adj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,6 +249,8 @@ def main():
         del Xb, ybb
         torch.cuda.empty_cache()
         v["batched_f32_64_problems"] = batched_rate(cr, autotune)
+        torch.cuda.empty_cache()
+        v["differentiable_f32_quadratic_10000"] = diff_rate(cr)
         line["variants"] = v
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_budget)

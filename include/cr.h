@@ -311,6 +311,14 @@ cr_status cr_diff_backward(cr_diff* d, const void* gy_dev, const void* gxi_dev, 
 
 cr_status cr_diff_destroy(cr_diff* d);
 
+/* Host-synchronous: average device time in milliseconds of one adjoint pair
+ * pass of a MAPG step (with the theta-bar accumulation when max_outer >= 2),
+ * at the operands left by the last cr_diff_backward, launched reps times back
+ * to back with the reverse pass's launch configuration and bracketed by HIP
+ * events.  It only adds to the theta-bar scratch array, which the next
+ * backward clears.  CR_ERR_STATE before a backward; CR_ERR_ARG, CR_ERR_HIP. */
+cr_status cr_diff_time_adjoint_pass(cr_diff* d, int32_t reps, double* avg_ms);
+
 /* Inspection and test hooks --------------------------------------------- */
 
 /* Copy the context's theta to / from an N x N FP64 device array (diagonal

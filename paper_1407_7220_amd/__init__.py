@@ -94,6 +94,7 @@ def _load():
         "cr_diff_forward": (i32, [vp, vp, vp, vp, vp, pi]),
         "cr_diff_backward": (i32, [vp, vp, vp, vp, vp, vp, vp]),
         "cr_diff_destroy": (i32, [vp]),
+        "cr_diff_time_adjoint_pass": (i32, [vp, i32, ctypes.POINTER(dbl)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -108,7 +109,7 @@ EXPORTED = ("cr_params_default", "cr_status_string", "cr_last_error", "cr_worksp
             "cr_destroy", "cr_pairwise_step", "cr_run", "cr_solve", "cr_get_theta", "cr_set_theta",
             "cr_get_start", "cr_get_info", "cr_time_pass", "cr_batch_workspace_bytes", "cr_batch_init",
             "cr_batch_run", "cr_batch_destroy", "cr_solve_batched", "cr_diff_workspace_bytes", "cr_diff_init",
-            "cr_diff_forward", "cr_diff_backward", "cr_diff_destroy")
+            "cr_diff_forward", "cr_diff_backward", "cr_diff_destroy", "cr_diff_time_adjoint_pass")
 
 
 class CRError(RuntimeError):
@@ -417,6 +418,13 @@ class Diff:
                                      ctypes.c_void_p(dX.data_ptr()), ctypes.c_void_p(dyb.data_ptr()),
                                      ctypes.c_void_p(dy0.data_ptr()), ctypes.c_void_p(dxi0.data_ptr())), None)
         return dX, dyb, dy0, dxi0
+
+    def time_adjoint_pass(self, reps: int = 20) -> float:
+        """Average device milliseconds of one adjoint pair pass (HIP events),
+        at the operands of the last backward."""
+        out = ctypes.c_double(0.0)
+        _check(_lib.cr_diff_time_adjoint_pass(self._h, int(reps), ctypes.byref(out)), None)
+        return float(out.value)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -1107,7 +1107,7 @@ struct cr_diff {
     DiffLayout D;
     size_t base_bytes = 0;
     char* ws = nullptr;
-    bool have_fwd = false;
+    bool have_fwd = false, have_bwd = false;
     std::vector<cr::OuterArgs> oas;
     std::vector<double> beta;        // beta_l, l = 1..Lin (index l)
     double* Dp(size_t off) const { return reinterpret_cast<double*>(ws + off); }
@@ -1267,6 +1267,7 @@ cr_status cr_diff_forward(cr_diff* d, const void* y0_dev, const void* xi0_dev, v
     const DiffLayout& D = d->D;
     hipStream_t cs = c->cs;
     d->have_fwd = false;
+    d->have_bwd = false;
     DHIPCHK(d, hipEventRecord(c->ev[0], c->user_stream));
     DHIPCHK(d, hipStreamWaitEvent(cs, c->ev[0], 0));
     const auto t0 = std::chrono::steady_clock::now();
@@ -1413,6 +1414,29 @@ cr_status cr_diff_backward(cr_diff* d, const void* gy_dev, const void* gxi_dev, 
     DHIPCHK(d, copy_pair(d, (double*)dy0_dev, (double*)dxi0_dev, d->vy(kYA), d->vxi(kYA), cs));
     DHIPCHK(d, copy_pair(d, (double*)dybar_dev, (double*)dX_dev, d->vy(kACC), d->vxi(kACC), cs));
     DHIPCHK(d, hipStreamSynchronize(cs));
+    d->have_bwd = true;
+    return CR_OK;
+}
+
+cr_status cr_diff_time_adjoint_pass(cr_diff* d, int32_t reps, double* avg_ms) {
+    if (!d || !avg_ms) return fail(d ? d->c : nullptr, CR_ERR_ARG, "diff and avg_ms must be non-NULL");
+    if (reps < 1) return dfail(d, CR_ERR_ARG, "reps must be >= 1");
+    if (!d->have_bwd) return dfail(d, CR_ERR_STATE, "cr_diff_time_adjoint_pass needs a completed cr_diff_backward");
+    cr_ctx* c = d->c;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    DHIPCHK(d, hipEventCreate(&e0));
+    DHIPCHK(d, hipEventCreate(&e1));
+    cr::AdjPassArgs pa = adj_pass_args(d, 0, d->D.K > 1 ? 1 : 0, 0.0);
+    hipError_t e = hipEventRecord(e0, c->cs);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = cr::launch_adj_pass(c->f64, c->n, pa, pass_grid(c->L), c->cs);
+    if (e == hipSuccess) e = hipEventRecord(e1, c->cs);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess) return dfail(d, CR_ERR_HIP, std::string("time adjoint pass: ") + hipGetErrorString(e));
+    *avg_ms = (double)ms / reps;
     return CR_OK;
 }
 

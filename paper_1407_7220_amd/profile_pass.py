@@ -1,10 +1,15 @@
-"""Profiling driver: repeated gradient pair passes on a named workload, then one
-theta export (k_theta_export: reads the N x N pass-precision theta once and
-writes it as N x N doubles), a plain copy of known size that serves as the
-reference for scaling hardware byte counters.  Run it under rocprofv3, e.g.
+"""Profiling driver: repeated pair passes on a named workload, then one theta
+export (k_theta_export: reads the N x N pass-precision theta once and writes
+it as N x N doubles), a plain copy of known size that serves as the reference
+for scaling hardware byte counters.  Run it under rocprofv3, e.g.
 
-    rocprofv3 --kernel-trace --stats -d OUT -- python -m paper_1407_7220_amd.profile_pass
-    rocprofv3 --pmc FETCH_SIZE -d OUT -- python -m paper_1407_7220_amd.profile_pass
+    rocprofv3 --kernel-trace --stats -d OUT -- python -u paper_1407_7220_amd/profile_pass.py
+    rocprofv3 --pmc FETCH_SIZE -d OUT -- python -u paper_1407_7220_amd/profile_pass.py --reps 5
+
+--kernel pass     gradient pair passes (k_pair_pass) with the tile height the
+                  autotuner cached for the workload (the benchmark's launch);
+--kernel adjoint  adjoint pair passes of a MAPG step (k_adj_pass) after one
+                  forward and reverse run of 2 x 2 unrolled iterations.
 """
 import argparse
 import os
@@ -17,22 +22,37 @@ if ROOT not in sys.path:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="logsumexp_5000")
-    ap.add_argument("--precision", choices=("f32", "f64"), default="f32")
+    ap.add_argument("--kernel", choices=("pass", "adjoint"), default="pass")
+    ap.add_argument("--workload", default=None)
+    ap.add_argument("--precision", choices=("f32", "f64", "mixed_bf16"), default="f32")
     ap.add_argument("--reps", type=int, default=20)
     args = ap.parse_args()
     import torch
     import paper_1407_7220_amd as cr
+    from paper_1407_7220_amd import autotune
     import synth
-    p = synth.workload(args.workload)
-    prec = cr.F32 if args.precision == "f32" else cr.F64
-    ctx = cr.Context(torch.from_numpy(p.X).cuda(), torch.from_numpy(p.ybar).cuda(), cr.Params(precision=prec))
-    ms = ctx.time_pass(args.reps)
-    ctx.get_theta()
+    workload = args.workload or ("logsumexp_5000" if args.kernel == "pass" else "quadratic_10000")
+    p = synth.workload(workload)
+    prec = {"f32": cr.F32, "f64": cr.F64, "mixed_bf16": cr.MIXED_BF16}[args.precision]
+    X = torch.from_numpy(p.X).cuda()
+    yb = torch.from_numpy(p.ybar).cuda()
+    tile = autotune.tile_rows_for(X, yb, prec, tune_if_missing=False)
+    esz = 8 if prec == cr.F64 else 4
+    if args.kernel == "pass":
+        ctx = cr.Context(X, yb, cr.Params(precision=prec, tile_rows=tile))
+        ms = ctx.time_pass(args.reps)
+        ctx.get_theta()
+        what = "pair passes"
+    else:
+        d = cr.Diff(X, yb, cr.Params(precision=prec, inner_iters=2, max_outer=2, tile_rows=tile), checkpoint_every=2)
+        d.forward(yb, None)
+        d.backward(torch.from_numpy(synth.weights(p.N)).cuda())
+        ms = d.time_adjoint_pass(args.reps)
+        what = "adjoint pair passes"
     torch.cuda.synchronize()
-    esz = 4 if prec == cr.F32 else 8
-    print("workload %s N=%d n=%d precision %s: %d pair passes, avg %.3f us; theta export reads %d B, writes %d B" % (
-        args.workload, p.N, p.n, args.precision, args.reps, ms * 1e3, p.N * p.N * esz, p.N * p.N * 8), flush=True)
+    print("workload %s N=%d n=%d precision %s tile_rows %d: %d %s, avg %.3f us; theta export reads %d B, writes %d B"
+          % (workload, p.N, p.n, args.precision, tile, args.reps, what, ms * 1e3, p.N * p.N * esz, p.N * p.N * 8),
+          flush=True)
 
 
 if __name__ == "__main__":
