@@ -75,6 +75,7 @@ Layout make_layout(int64_t N, int n, int precision, int64_t max_iters, int tile_
         rpc = (L.Nrow + chunks - 1) / chunks;
         rpc = ((rpc + 63) / 64) * 64;
     }
+    rpc = std::min<int64_t>(rpc, cr::kMaxRowsPerChunk);
     L.rpc = (int)rpc;
     L.chunks = (int)((L.Nrow + rpc - 1) / rpc);
     L.nb = (int)((L.ld * 32 + cr::kBlock - 1) / cr::kBlock);  // blocks of the O(N n) kernels (32 lanes per point)

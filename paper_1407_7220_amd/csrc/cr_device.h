@@ -9,6 +9,7 @@ constexpr int kBlock = 256;          // threads per workgroup of every kernel
 constexpr int kTileRows = 16;        // rows (i) of one MFMA tile
 constexpr int kWaves = 4;            // waves per pair-pass workgroup, split over rows
 constexpr int kMaxDim = 31;          // n + 1 <= 32 output columns of W^T [X 1]
+constexpr int kMaxRowsPerChunk = 4096;  // rows of one pass workgroup (row sums staged in LDS)
 
 // Scalars the host sets once per ALCC iteration (Fig. 3 steps 1-2, 5-6).
 struct OuterArgs {

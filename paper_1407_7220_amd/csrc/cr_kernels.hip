@@ -54,6 +54,9 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
     const T* __restrict__ ycol = (const T*)a.ycol;
     T* __restrict__ theta = (T*)a.theta;
     constexpr bool theta_mode = THETA_MODE != 0;
+    // row sums of the chunk, staged in the column-sum area (free until the epilogue)
+    T* srow = reinterpret_cast<T*>(lds);
+    static_assert(kMaxRowsPerChunk * 8 <= 32768, "row staging");
 
     typename Ops::Breg breg;
     Ops::load_breg(breg, a, jl, g);
@@ -146,8 +149,10 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
             rs[v] = row16_sum(s);
         }
         if (c == 0) {
-            // rowpart[strip][i]: the 16 row sums of a tile are contiguous
-            T* dst = (T*)a.rowpart + (int64_t)strip * a.Nrow + i0;
+            // staged in LDS (no global store inside the tile loop, so that the
+            // prefetched loads stay in flight across iterations); written once
+            // per workgroup after the loop
+            T* dst = srow + (i0 - I0);
             if (Ops::RM4 && sizeof(T) == 4) {
                 V16<T> o;
 #pragma unroll
@@ -172,14 +177,32 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
     T ys[NSET][4];
     V16<T> ts[NSET][4];
 #pragma unroll
-    for (int b = 0; b < NSET; ++b) load_tile(row_of(b), xs[b], ys[b], ts[b]);
+    // The scheduling barriers keep each staging set's loads together and in
+    // program order, so the prologue leaves the same pending-load sequence as
+    // the loop's back edge; otherwise the wait-count merge at the loop head
+    // drains nearly every prefetched load once per NSET tiles.
+    for (int b = 0; b < NSET; ++b) {
+        load_tile(row_of(b), xs[b], ys[b], ts[b]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma nounroll
     for (int m = 0; m < ntile; m += NSET) {
 #pragma unroll
         for (int b = 0; b < NSET; ++b) {
             if (m + b < ntile) process(row_of(m + b), xs[b], ys[b], ts[b]);
+            __builtin_amdgcn_sched_barrier(0);
             load_tile(row_of(m + b + NSET), xs[b], ys[b], ts[b]);
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
+
+    // rowpart[strip][i] of this chunk's rows, from the LDS staging area
+    __syncthreads();
+    {
+        T* dst = (T*)a.rowpart + (int64_t)strip * a.Nrow + I0;
+        for (int r = threadIdx.x; r < (int)(I1 - I0); r += kBlock) dst[r] = srow[r];
+    }
+    __syncthreads();
 
     // Combine the 4 waves' column sums (fixed order) and write this chunk's partial.
     static_assert(sizeof(T) * kWaves * TW * NKB * 4 * 64 <= 32768, "pass LDS");
@@ -271,26 +294,10 @@ __device__ double block_gather(const double* part, int count, int q, int op) {
 template <typename T, int G>
 __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk) {
     DevState* st = a.st;
+    int64_t l = 0;
     if (a.mode == 0) {
         if (st->active == 0) return;
-        // Fig. 4 steps 6-9 for the previous iteration l - 1, from the block
-        // pieces that k_update left: every block takes the same decision.
-        const int64_t l = st->base + a.q + 1;
-        if (l > 1) {
-            const double dy = sqrt(block_gather(a.blockpart, nblk, 2, 0));
-            const double dxi = sqrt(block_gather(a.blockpart, nblk, 3, 0));
-            const bool alpha_stop = a.oa->adaptive && dy <= a.oa->alpha_y && dxi <= a.oa->alpha_xi;
-            if (alpha_stop || l - 1 >= a.oa->lmax) {
-                if (blk == 0 && threadIdx.x == 0) {
-                    st->active = 0;
-                    st->it = l - 1;
-                    st->stopped_by_alpha = alpha_stop ? 1 : 0;
-                    st->dy = dy;
-                    st->dxi = dxi;
-                }
-                return;
-            }
-        }
+        l = st->base + a.q + 1;
     }
     constexpr int PER = kBlock / G;
     const int k = threadIdx.x % G;
@@ -305,7 +312,8 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
     } else {
         mu = a.mu; gamma = a.gamma;
     }
-    double rs = 0.0, ck = 0.0;
+    // every load of this point first, so that they overlap the stop test's gather
+    double rs = 0.0, ck = 0.0, yj = 0.0, ybj = 0.0, xjk = 0.0, xik = 0.0;
     if (valid) {
 #pragma unroll 4
         for (int q = k; q < a.strips; q += G) rs += (double)rowpart[(int64_t)q * a.Nrow + j];
@@ -314,6 +322,26 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
 #pragma unroll 4
             for (int h = 0; h < a.chunks; ++h) ck += (double)cp[(int64_t)h * a.ld * nc];
         }
+        if (k == n) { yj = a.y[j]; ybj = a.ybar[j]; }
+        else if (k < n) { xjk = a.X[j * n + k]; xik = a.xi[j * n + k]; }
+    }
+    if (a.mode == 0 && l > 1) {
+        // Fig. 4 steps 6-9 for the previous iteration l - 1, from the block
+        // pieces that k_update left: every block takes the same decision.
+        double dy2, dx2;
+        gather_sum2(a.blockpart, nblk, 2, 3, dy2, dx2);
+        const double dy = sqrt(dy2), dxi = sqrt(dx2);
+        const bool alpha_stop = a.oa->adaptive && dy <= a.oa->alpha_y && dxi <= a.oa->alpha_xi;
+        if (alpha_stop || l - 1 >= a.oa->lmax) {
+            if (blk == 0 && threadIdx.x == 0) {
+                st->active = 0;
+                st->it = l - 1;
+                st->stopped_by_alpha = alpha_stop ? 1 : 0;
+                st->dy = dy;
+                st->dxi = dxi;
+            }
+            return;
+        }
     }
     rs = group_sum<G>(rs);
     const int base = (threadIdx.x & 63) & ~(G - 1);
@@ -321,7 +349,6 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
     bool bad = false;
     if (valid && k == n) {
-        const double yj = a.y[j], ybj = a.ybar[j];
         if (a.mode == 0) {
             const double gy = (yj - ybj) / mu - rs + cs;
             const double vy = yj - sy * gy;
@@ -337,7 +364,6 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
             bad = !isfinite(yj);
         }
     } else if (valid && k < n) {
-        const double xjk = a.X[j * n + k], xik = a.xi[j * n + k];
         const double aw = ck - cs * xjk;          // -(A2^T w)_jk
         if (a.mode == 0) {
             const double gx = (gamma / mu) * xik + aw;
@@ -357,8 +383,8 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
     if (a.mode == 1) return;
     if (a.mode == 0) {
         // per-block pieces of ||v_y - ybar||^2 and ||v_xi||^2; k_update combines them
-        const double b0 = block_reduce(acc0, 0), b1 = block_reduce(acc1, 0);
-        if (threadIdx.x == 0) { a.blockpart[blk * 4 + 0] = b0; a.blockpart[blk * 4 + 1] = b1; }
+        block_sum2(acc0, acc1);
+        if (threadIdx.x == 0) { a.blockpart[blk * 4 + 0] = acc0; a.blockpart[blk * 4 + 1] = acc1; }
         return;
     }
     // mode 2: KKT residuals of the multiplier step
@@ -417,30 +443,35 @@ __device__ void update_block(const UpdateArgs& a, const int blk, const int nblk)
     const bool valid = j < a.N;
     const int n = a.n;
     const double beta = a.beta[st->base + a.q + 1];   // (t_l - 1) / t_{l+1}
+    // this point's state first, so that the loads overlap the norm gather
+    double v = 0.0, c2 = 0.0, c1p = 0.0, cb = 0.0, xe = 0.0;
+    const int64_t e = j * n + k;
+    if (valid && k == n) {
+        v = a.vy[j]; c2 = a.y2[j]; c1p = a.y1p[j]; cb = a.ybar[j];
+    } else if (valid && k < n) {
+        v = a.vxi[e]; c2 = a.xi2[e]; c1p = a.xi1p[e]; xe = a.X[e];
+    }
     // ball projections (Fig. 4 steps 1-2): every block forms the same norms
-    const double ny = sqrt(block_gather(a.blockpart, nblk, 0, 0));
-    const double nx = sqrt(block_gather(a.blockpart, nblk, 1, 0));
+    double ny2, nx2;
+    gather_sum2(a.blockpart, nblk, 0, 1, ny2, nx2);
+    const double ny = sqrt(ny2), nx = sqrt(nx2);
     const double sc_y = ny > a.oa->By ? a.oa->By / ny : 1.0;
     const double sc_xi = nx > a.oa->Bxi ? a.oa->Bxi / nx : 1.0;
     double dy2 = 0.0, dx2 = 0.0, prod = 0.0, y2n = 0.0;
     T* xa = (T*)a.xiaug + j * a.kp;
     if (a.sv_nrm && blk == 0 && threadIdx.x == 0) { a.sv_nrm[0] = ny; a.sv_nrm[1] = nx; }
     if (valid && k == n) {
-        const double yb = a.ybar[j];
-        const double y1 = yb + sc_y * (a.vy[j] - yb);       // projection onto Q_y
-        const double y2o = a.y2[j];
-        if (a.sv_y2) { a.sv_y2[j] = y2o; a.sv_vy[j] = a.vy[j]; }
-        dy2 = (y1 - y2o) * (y1 - y2o);
-        y2n = y1 + beta * (y1 - a.y1p[j]);                  // extrapolation
+        const double y1 = cb + sc_y * (v - cb);             // projection onto Q_y
+        if (a.sv_y2) { a.sv_y2[j] = c2; a.sv_vy[j] = v; }
+        dy2 = (y1 - c2) * (y1 - c2);
+        y2n = y1 + beta * (y1 - c1p);                       // extrapolation
         a.y1p[j] = y1;
         a.y2[j] = y2n;
     } else if (valid && k < n) {
-        const int64_t e = j * n + k;
-        const double x1 = sc_xi * a.vxi[e];                 // projection onto Q_xi
-        const double x2o = a.xi2[e];
-        if (a.sv_y2) { a.sv_xi2[e] = x2o; a.sv_vxi[e] = a.vxi[e]; }
-        dx2 = (x1 - x2o) * (x1 - x2o);
-        const double x2n = x1 + beta * (x1 - a.xi1p[e]);
+        const double x1 = sc_xi * v;                        // projection onto Q_xi
+        if (a.sv_y2) { a.sv_xi2[e] = c2; a.sv_vxi[e] = v; }
+        dx2 = (x1 - c2) * (x1 - c2);
+        const double x2n = x1 + beta * (x1 - c1p);
         a.xi1p[e] = x1;
         a.xi2[e] = x2n;
         if (MIX) {
@@ -453,7 +484,7 @@ __device__ void update_block(const UpdateArgs& a, const int blk, const int nblk)
         } else {
             xa[k] = (T)(-x2n);
         }
-        prod = a.X[e] * x2n;
+        prod = xe * x2n;
     }
     const double d = group_sum<G>(prod);                    // x_j^T xi_j
     if (valid && k == n) {
@@ -461,8 +492,8 @@ __device__ void update_block(const UpdateArgs& a, const int blk, const int nblk)
         else xa[n] = (T)(d - y2n);
         ((T*)a.ycol)[j] = (T)y2n;
     }
-    const double b0 = block_reduce(dy2, 0), b1 = block_reduce(dx2, 0);
-    if (threadIdx.x == 0) { a.blockpart[blk * 4 + 2] = b0; a.blockpart[blk * 4 + 3] = b1; }
+    block_sum2(dy2, dx2);
+    if (threadIdx.x == 0) { a.blockpart[blk * 4 + 2] = dy2; a.blockpart[blk * 4 + 3] = dx2; }
 }
 
 template <typename T, int G>
@@ -522,8 +553,9 @@ __global__ void k_replay_end(DevState* st, int iters) {
 __global__ __launch_bounds__(kBlock) void k_mapg_end(const double* blockpart, int nblk, int64_t launched,
                                                      DevState* st) {
     if (st->active == 0) return;
-    const double dy = sqrt(block_gather(blockpart, nblk, 2, 0));
-    const double dxi = sqrt(block_gather(blockpart, nblk, 3, 0));
+    double dy2, dx2;
+    gather_sum2(blockpart, nblk, 2, 3, dy2, dx2);
+    const double dy = sqrt(dy2), dxi = sqrt(dx2);
     if (threadIdx.x == 0) {
         st->active = 0;
         st->it = launched;

@@ -89,6 +89,33 @@ static __device__ double block_reduce(double v, int op) {
     return r;
 }
 
+// Sums of two doubles per thread over the block, one barrier pair for both;
+// results valid in every thread.
+static __device__ void block_sum2(double& a, double& b) {
+    __shared__ double red2[kBlock / 64][2];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) { red2[threadIdx.x >> 6][0] = a; red2[threadIdx.x >> 6][1] = b; }
+    __syncthreads();
+    a = red2[0][0];
+    b = red2[0][1];
+    for (int w = 1; w < kBlock / 64; ++w) { a += red2[w][0]; b += red2[w][1]; }
+}
+
+// Sums of fields q0 and q1 of the first `count` 4-double records that an
+// earlier kernel wrote (plain loads: the kernel boundary orders them), by all
+// threads of the block in a fixed order.
+static __device__ void gather_sum2(const double* part, int count, int q0, int q1, double& s0, double& s1) {
+    s0 = 0.0;
+    s1 = 0.0;
+    for (int b = threadIdx.x; b < count; b += kBlock) {
+        s0 += part[(int64_t)b * 4 + q0];
+        s1 += part[(int64_t)b * 4 + q1];
+    }
+    block_sum2(s0, s1);
+}
+
 // Each block calls this once after writing its partial results; it returns
 // true in every thread of the one block that arrives last (that block then
 // sees every other block's partials) and re-arms the counter.
