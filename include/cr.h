@@ -134,7 +134,7 @@ const char* cr_last_error(const cr_ctx* ctx);
  * (dominated by the N x N multiplier array theta of Fig. 3, stored once, in
  * FP64 for CR_F64 and FP32 otherwise).  Pure host arithmetic.
  * Errors: CR_ERR_ARG for N < 2, n < 1, bad params or bytes == NULL;
- * CR_ERR_UNSUPPORTED for n > CR_MAX_DIM.
+ * CR_ERR_UNSUPPORTED for n > CR_MAX_DIM or N > 2^20.
  */
 cr_status cr_workspace_bytes(int64_t N, int32_t n, const cr_params* params, size_t* bytes);
 
@@ -149,7 +149,7 @@ cr_status cr_workspace_bytes(int64_t N, int32_t n, const cr_params* params, size
  * (y_0, xi_0) = that fit, theta_1 = 0.  Host-synchronous.
  * Errors: CR_ERR_ARG (null pointers, N < 2, n < 1, gamma <= 0, c <= 1,
  * kappa <= 0, tau1 <= 0, step_scale not in (0, 1], max_outer < 1,
- * unknown precision), CR_ERR_UNSUPPORTED (n > CR_MAX_DIM), CR_ERR_NOMEM
+ * unknown precision), CR_ERR_UNSUPPORTED (n > CR_MAX_DIM or N > 2^20), CR_ERR_NOMEM
  * (ws_bytes too small), CR_ERR_NONFINITE (NaN/Inf in X or ybar),
  * CR_ERR_HIP.  On error *out is NULL.
  */

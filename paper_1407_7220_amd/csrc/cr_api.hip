@@ -76,6 +76,11 @@ Layout make_layout(int64_t N, int n, int precision, int64_t max_iters, int tile_
         rpc = ((rpc + 63) / 64) * 64;
     }
     rpc = std::min<int64_t>(rpc, cr::kMaxRowsPerChunk);
+    // the pass addresses a workgroup's rows (plus the prefetch overrun of
+    // three 64-row steps) through 32-bit buffer offsets
+    const int64_t row_bytes = L.ld * L.esz;
+    const int64_t rpc_cap = ((((int64_t)1 << 32) - 1) / row_bytes - 256) / 64 * 64;
+    rpc = std::max<int64_t>(64, std::min(rpc, rpc_cap));
     L.rpc = (int)rpc;
     L.chunks = (int)((L.Nrow + rpc - 1) / rpc);
     L.nb = (int)((L.ld * 32 + cr::kBlock - 1) / cr::kBlock);  // blocks of the O(N n) kernels (32 lanes per point)
@@ -135,7 +140,9 @@ cr_status check_dims(int64_t N, int32_t n, std::string& msg) {
     if (N < 2) { msg = "N must be >= 2"; return CR_ERR_ARG; }
     if (n < 1) { msg = "n must be >= 1"; return CR_ERR_ARG; }
     if (n > CR_MAX_DIM) { msg = "n above CR_MAX_DIM is not supported"; return CR_ERR_UNSUPPORTED; }
-    if (N > (int64_t)1 << 22) { msg = "N too large"; return CR_ERR_ARG; }
+    // beyond 2^20 points a theta row no longer fits the pass's 32-bit buffer
+    // offsets (and the N^2 theta would need terabytes)
+    if (N > (int64_t)1 << 20) { msg = "N above 2^20 is not supported"; return CR_ERR_UNSUPPORTED; }
     return CR_OK;
 }
 

@@ -69,24 +69,55 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
 
     double k_rneg_max = 0.0, k_rneg_sq = 0.0, k_wr_max = 0.0, k_wr_sum = 0.0;
 
+    constexpr int64_t step = 16 * kWaves;
+    constexpr int NSET = Ops::NSET;   // staging sets (tiles in flight per wave)
+    // Tiles of this wave: rows I0 + 16 wave + step m < I1 (at least one, since
+    // I1 - I0 >= 64).  Prefetches are unconditional (past the last tile they
+    // read zeros from the buffer views), so the compiler can count
+    // outstanding loads exactly.
+    const int64_t first = I0 + 16 * wave;
+    const int ntile = (int)((I1 - first + step - 1) / step);
+    auto row_of = [&](int m) { return first + step * (int64_t)m; };
+
     // Operands of one 16-row tile: packed X (L2-resident), y_i, and the
     // wave's 16 x 16TW block of theta (HBM stream).  NSET register sets rotate
     // so that each tile's loads are issued NSET - 1 tiles ahead of its use.
-    auto load_tile = [&](int64_t i0, typename Ops::Xop& xop, T* yv, V16<T>* th) {
-        Ops::load_xop(xop, a, i0, lane);
+    // Buffer views of this workgroup's rows: the per-lane offsets are fixed,
+    // tile m of the wave adds m times a per-view scalar step, and the loads
+    // past the last tile return zeros.
+    const uint32_t rows = (uint32_t)(I1 - I0);
+    const uint32_t row_bytes = (uint32_t)a.ld * (uint32_t)sizeof(T);
+    const rsrc_t th_r = make_rsrc(theta + I0 * a.ld + J0, rows * row_bytes);
+    const rsrc_t xp_r = make_rsrc((const char*)a.xp + (I0 >> 4) * 64 * Ops::XPB, (rows >> 4) * 64u * Ops::XPB);
+    const rsrc_t y_r = make_rsrc(ycol + I0, rows * (uint32_t)sizeof(T));
+    uint32_t th_vo[4], y_vo[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        th_vo[v] = (uint32_t)(16 * wave + orow<Ops>(g, v)) * row_bytes + (uint32_t)(TW * c) * (uint32_t)sizeof(T);
+        y_vo[v] = (uint32_t)(16 * wave + orow<Ops>(g, v)) * (uint32_t)sizeof(T);
+    }
+    const uint32_t xp_vo = (uint32_t)(wave * 64 + lane) * (uint32_t)Ops::XPB;
+    const uint32_t th_step = 16u * kWaves * row_bytes;
+    const uint32_t xp_step = (uint32_t)kWaves * 64u * (uint32_t)Ops::XPB;
+    const uint32_t y_step = 16u * kWaves * (uint32_t)sizeof(T);
+    auto load_tile = [&](int m, typename Ops::Xop& xop, T* yv, V16<T>* th) {
+        const uint32_t mm = (uint32_t)m;
+        Ops::load_xop_b(xop, xp_r, xp_vo, mm * xp_step);
         if (sizeof(T) == 4) {
-            V16<T> tv = ld16(ycol + i0 + 4 * g);
+            // rows 4g .. 4g + 3 of the tile
+            V16<T> tv = bld16<T>(y_r, y_vo[0], mm * y_step);
 #pragma unroll
             for (int e = 0; e < 4; ++e) yv[e] = tv.v[e];
         } else {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) yv[v] = ycol[i0 + orow<Ops>(g, v)];
+            for (int v = 0; v < 4; ++v) yv[v] = (T)bld8(y_r, y_vo[v], mm * y_step);
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) th[v] = ld16(theta + (i0 + orow<Ops>(g, v)) * a.ld + jl);
+        for (int v = 0; v < 4; ++v) th[v] = bld16<T>(th_r, th_vo[v], mm * th_step);
     };
 
-    auto process = [&](const int64_t i0, const typename Ops::Xop& xop, const T* yv, const V16<T>* th) {
+    auto process = [&](const int m, const typename Ops::Xop& xop, const T* yv, const V16<T>* th) {
+        const int64_t i0 = row_of(m);
         // residual tiles R_t
         acc_t R[TW];
         Ops::residual(R, xop, breg, yv);
@@ -101,13 +132,18 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
                 W[t][v] = d > (T)0 ? d : (T)0;
             }
         const bool edge = (i0 < J0 + 16 * TW && i0 + 16 > J0) || (J0 + 16 * TW > a.N) || (i0 + 16 > a.N);
+        // tile-relative 32-bit indices: pair (i0 + r, J0 + q) is a constraint
+        // iff r < rlim, q < qlim and r + dij != q
+        const int rlim = (int)min((int64_t)16, a.N - i0);
+        const int qlim = (int)min((int64_t)(16 * TW), a.N - J0);
+        const int dij = (int)max((int64_t)-64, min((int64_t)64, i0 - J0));   // |i0 - J0| >= 64: no diagonal
         if (edge) {
 #pragma unroll
             for (int t = 0; t < TW; ++t)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int64_t i = i0 + orow<Ops>(g, v), j = jl + t;
-                    if (!(i < a.N && j < a.N && i != j)) W[t][v] = (T)0;
+                    const int r = orow<Ops>(g, v), q = TW * c + t;
+                    if (!(r < rlim && q < qlim && r + dij != q)) W[t][v] = (T)0;
                 }
         }
 
@@ -124,8 +160,8 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
             for (int t = 0; t < TW; ++t)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int64_t i = i0 + orow<Ops>(g, v), j = jl + t;
-                    if (i < a.N && j < a.N && i != j) {
+                    const int r = orow<Ops>(g, v), q = TW * c + t;
+                    if (r < rlim && q < qlim && r + dij != q) {
                         const double r = (double)R[t][v];
                         const double rn = r < 0.0 ? -r : 0.0;
                         const double wr = (double)W[t][v] * r;
@@ -165,14 +201,6 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
         }
     };
 
-    constexpr int64_t step = 16 * kWaves;
-    constexpr int NSET = Ops::NSET;   // staging sets (tiles in flight per wave)
-    // Tiles of this wave: rows I0 + 16 wave + step m < I1 (at least one, since
-    // I1 - I0 >= 64).  Prefetches are unconditional, clamped to the last tile,
-    // so the compiler can count outstanding loads exactly.
-    const int64_t first = I0 + 16 * wave;
-    const int ntile = (int)((I1 - first + step - 1) / step);
-    auto row_of = [&](int m) { return first + step * (int64_t)(m < ntile ? m : ntile - 1); };
     typename Ops::Xop xs[NSET];
     T ys[NSET][4];
     V16<T> ts[NSET][4];
@@ -182,16 +210,16 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
     // the loop's back edge; otherwise the wait-count merge at the loop head
     // drains nearly every prefetched load once per NSET tiles.
     for (int b = 0; b < NSET; ++b) {
-        load_tile(row_of(b), xs[b], ys[b], ts[b]);
+        load_tile(b, xs[b], ys[b], ts[b]);
         __builtin_amdgcn_sched_barrier(0);
     }
 #pragma nounroll
     for (int m = 0; m < ntile; m += NSET) {
 #pragma unroll
         for (int b = 0; b < NSET; ++b) {
-            if (m + b < ntile) process(row_of(m + b), xs[b], ys[b], ts[b]);
+            if (m + b < ntile) process(m + b, xs[b], ys[b], ts[b]);
             __builtin_amdgcn_sched_barrier(0);
-            load_tile(row_of(m + b + NSET), xs[b], ys[b], ts[b]);
+            load_tile(m + b + NSET, xs[b], ys[b], ts[b]);
             __builtin_amdgcn_sched_barrier(0);
         }
     }

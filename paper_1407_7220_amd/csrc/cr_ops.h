@@ -65,6 +65,23 @@ __device__ __forceinline__ V16<T> ld16(const T* p) { return *reinterpret_cast<co
 template <typename T>
 __device__ __forceinline__ void st16(T* p, const V16<T>& x) { *reinterpret_cast<V16<T>*>(p) = x; }
 
+// Buffer views (gfx9 raw buffer resources, third descriptor word 0x00020000):
+// a load at byte offset voffset + soffset at or past `bytes` returns zeros and
+// touches no memory, so a prefetch that runs past a workgroup's rows needs no
+// clamp; the per-tile step goes into the scalar soffset.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ V16<T> bld16(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(V16<T>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ double bld8(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+
 // ---------------------------------------------------------------------------
 // Block reductions (256 threads) and the last-arriving-block handshake.
 // ---------------------------------------------------------------------------
@@ -180,6 +197,16 @@ template <typename T, int KS, int NSET_ = 0> struct PlainOps {
             for (int e = 0; e < EV; ++e) X.q[q * EV + e] = tv.v[e];
         }
     }
+    // bytes of one (16-row tile, lane) entry of the packed operands
+    static constexpr int XPB = QP * (int)sizeof(T);
+    static __device__ void load_xop_b(Xop& X, rsrc_t r, uint32_t voff, uint32_t soff) {
+#pragma unroll
+        for (int q = 0; q < QP / EV; ++q) {
+            V16<T> tv = bld16<T>(r, voff + 16 * q, soff);
+#pragma unroll
+            for (int e = 0; e < EV; ++e) X.q[q * EV + e] = tv.v[e];
+        }
+    }
     static __device__ void residual(acc_t R[TW], const Xop& X, const Breg& B, const T yv[4]) {
 #pragma unroll
         for (int t = 0; t < TW; ++t) {
@@ -229,6 +256,16 @@ template <int KB, int NKB_> struct MixedOps {
         for (int kb = 0; kb < KB; ++kb) X.r[kb] = xp[kb];
 #pragma unroll
         for (int kb = 0; kb < NKB; ++kb) { X.c1[kb] = xp[KB + 2 * kb]; X.c2[kb] = xp[KB + 2 * kb + 1]; }
+    }
+    static constexpr int XPB = (KB + 2 * NKB) * 16;
+    static __device__ void load_xop_b(Xop& X, rsrc_t r, uint32_t voff, uint32_t soff) {
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) X.r[kb] = __builtin_bit_cast(bf16x8, bld16<float>(r, voff + 16 * kb, soff));
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb) {
+            X.c1[kb] = __builtin_bit_cast(bf16x8, bld16<float>(r, voff + 16 * (KB + 2 * kb), soff));
+            X.c2[kb] = __builtin_bit_cast(bf16x8, bld16<float>(r, voff + 16 * (KB + 2 * kb + 1), soff));
+        }
     }
     static __device__ void residual(acc_t R[TW], const Xop& X, const Breg& B, const float yv[4]) {
 #pragma unroll

@@ -124,6 +124,26 @@ def test_theta_pass(cr, prec, N, n):
     assert abs(info.gap_norm - m["gap_norm"]) <= t * max(1e-3, abs(m["gap_norm"]))
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+@pytest.mark.parametrize("tile_rows", [64, 128, 512])
+def test_passes_across_tile_heights(cr, prec, tile_rows):
+    """Gradient and multiplier passes against the oracle when a workgroup's
+    wave owns one tile (64 rows per workgroup), two tiles, or eight, with the
+    ragged last chunk of N = 1000."""
+    say("tile heights %s tile_rows=%d" % (PREC_NAME[prec], tile_rows))
+    N, n = 1000, 5
+    X, ybar, y, xi, theta = _random_state(N, n, seed=11)
+    gamma, mu, mu_next = 1e-2, 0.25, 1.0
+    ctx = cr.Context(dev(X), dev(ybar), cr.Params(gamma=gamma, precision=prec, tile_rows=tile_rows))
+    ctx.set_theta(dev(theta))
+    gy, gxi = ctx.pairwise_step(cr.GRAD, dev(y), dev(xi), mu)
+    ry, rxi = oracle.grad_P(X, ybar, gamma, mu, theta, y, xi)
+    assert rel(host(gy), ry) < TOL_PASS[prec] and rel(host(gxi), rxi) < TOL_PASS[prec]
+    ctx.pairwise_step(cr.THETA_UPDATE, dev(y), dev(xi), mu, mu_next)
+    W = oracle.penalty_weights(X, y, xi, theta)
+    assert rel(host(ctx.get_theta()), (mu / mu_next) * W) < TOL_PASS[prec]
+
+
 def test_pass_is_deterministic(cr):
     say("deterministic N=700 n=10")
     X, ybar, y, xi, theta = _random_state(700, 10, seed=3)
