@@ -39,7 +39,7 @@ WORKLOAD = "logsumexp_5000"
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("cr_kernels.hip", "cr_device.h", "cr_api.hip"):
+    for f in ("cr_kernels.hip", "cr_ops.h", "cr_device.h", "cr_api.hip"):
         with open(os.path.join(ROOT, "paper_1407_7220_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

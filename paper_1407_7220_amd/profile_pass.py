@@ -48,6 +48,9 @@ def main():
         d.forward(yb, None)
         d.backward(torch.from_numpy(synth.weights(p.N)).cuda())
         ms = d.time_adjoint_pass(args.reps)
+        d.close()
+        # the calibration copy on a context of the same size
+        cr.Context(X, yb, cr.Params(precision=prec, tile_rows=tile)).get_theta()
         what = "adjoint pair passes"
     torch.cuda.synchronize()
     print("workload %s N=%d n=%d precision %s tile_rows %d: %d %s, avg %.3f us; theta export reads %d B, writes %d B"
