@@ -273,13 +273,32 @@ __global__ __launch_bounds__(kBlock) void k_adj_reduce(AdjReduceArgs a) {
     const T* cwpart = (const T*)a.cwpart;
     double rs = 0.0, rv = 0.0, ck = 0.0, cw = 0.0;
     if (valid) {
+#pragma unroll 4
         for (int q = k; q < a.strips; q += G) rs += (double)rowpart[(int64_t)q * a.Nrow + m];
-        if (k < n)
-            for (int q = 0; q < a.strips; ++q) rv += (double)rowvpart[((int64_t)q * a.Nrow + m) * n + k];
-        if (k < nc)
+        if (k < n) {
+            // every strip's partial of component k: four independent sums (fixed
+            // order) so that the loads overlap
+            const T* rp = rowvpart + (int64_t)m * n + k;
+            const int64_t stride = a.Nrow * n;
+            double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+            int q = 0;
+            for (; q + 4 <= a.strips; q += 4) {
+                r0 += (double)rp[(int64_t)q * stride];
+                r1 += (double)rp[(int64_t)(q + 1) * stride];
+                r2 += (double)rp[(int64_t)(q + 2) * stride];
+                r3 += (double)rp[(int64_t)(q + 3) * stride];
+            }
+            for (; q < a.strips; ++q) r0 += (double)rp[(int64_t)q * stride];
+            rv = (r0 + r1) + (r2 + r3);
+        }
+        if (k < nc) {
+#pragma unroll 4
             for (int h = 0; h < a.chunks; ++h) ck += (double)cpart[((int64_t)h * a.ld + m) * nc + k];
-        if (a.mode == 0 && k == n)
+        }
+        if (a.mode == 0 && k == n) {
+#pragma unroll 4
             for (int h = 0; h < a.chunks; ++h) cw += (double)cwpart[(int64_t)h * a.ld + m];
+        }
     }
     rs = adj_group_sum<G>(rs);
     const int base = (threadIdx.x & 63) & ~(G - 1);

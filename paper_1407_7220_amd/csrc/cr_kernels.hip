@@ -271,8 +271,9 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
     }
 }
 
-// WAVES: minimum waves per SIMD the register allocation must allow (3 for the
-// plain gradient passes with KS <= 4, which then need no spills; 2 otherwise).
+// WAVES: minimum waves per SIMD the register allocation must allow (the
+// largest count at which the gradient pass of the class needs no spills:
+// 4 for FP32 with KS <= 3, 3 for FP32 KS = 4 and FP64 KS <= 4, 2 otherwise).
 template <typename Ops, int THETA_MODE, int WAVES>
 __global__ __launch_bounds__(kBlock, WAVES) void k_pair_pass(PassArgs a) {
     if (*a.active == 0) return;
@@ -941,11 +942,13 @@ static hipError_t launch_pass_ops(const PassArgs& a, dim3 grid, hipStream_t s) {
 
 template <typename T>
 static hipError_t launch_pass_t(int ks, const PassArgs& a, dim3 grid, hipStream_t s) {
+    // waves per SIMD the small classes' gradient passes allow without spills
+    constexpr int W_SMALL = sizeof(T) == 4 ? 4 : 3;
     switch (ks) {
-        case 1: return launch_pass_ops<PlainOps<T, 1>, 3>(a, grid, s);
-        case 2: return launch_pass_ops<PlainOps<T, 2>, 3>(a, grid, s);
-        case 3: return launch_pass_ops<PlainOps<T, 3>, 3>(a, grid, s);
-        case 4: return launch_pass_ops<PlainOps<T, 4>>(a, grid, s);
+        case 1: return launch_pass_ops<PlainOps<T, 1>, W_SMALL>(a, grid, s);
+        case 2: return launch_pass_ops<PlainOps<T, 2>, W_SMALL>(a, grid, s);
+        case 3: return launch_pass_ops<PlainOps<T, 3>, W_SMALL>(a, grid, s);
+        case 4: return launch_pass_ops<PlainOps<T, 4>, 3>(a, grid, s);
         case 5: return launch_pass_ops<PlainOps<T, 5>>(a, grid, s);
         case 6: return launch_pass_ops<PlainOps<T, 6>>(a, grid, s);
         case 7: return launch_pass_ops<PlainOps<T, 7>>(a, grid, s);

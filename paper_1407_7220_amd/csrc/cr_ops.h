@@ -174,7 +174,9 @@ template <typename T, int KS, int NSET_ = 0> struct PlainOps {
     static constexpr int NKB = nkb_of_ks(KS);
     static constexpr int QP = qp_of_ks(KS, (int)sizeof(T));
     static constexpr int EV = 16 / (int)sizeof(T);
-    static constexpr int NSET = NSET_ > 0 ? NSET_ : (sizeof(T) == 4 ? 3 : 2);
+    // two staging sets: with them the FP32 pass fits 4 waves per SIMD, which hides
+    // the per-tile chain better than a third set at 3 waves (measured)
+    static constexpr int NSET = NSET_ > 0 ? NSET_ : 2;
     static constexpr int RM4 = sizeof(T) == 4;   // accumulator row map 4 g + v (else g + 4 v)
     struct Breg { T b[KS][TW]; };
     struct Xop { T q[QP]; };
