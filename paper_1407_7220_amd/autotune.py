@@ -113,11 +113,11 @@ def _main(argv=None) -> int:
     ap.add_argument("--force", action="store_true", help="re-tune keys that the cache already holds")
     args = ap.parse_args(argv)
     names = {v: k for k, v in _PREC.items()}
+    done = set()       # keys tuned in this run: the first target to reach a key keeps it
     for t in args.targets:
         wl, pn = t.split(":")
         prec = names[pn]
         probs = synth.batched_workload() if wl == "batched" else [synth.workload(wl)]
-        done = set()
         for p in probs:
             k = key(p.N, p.n, prec)
             if k in done or (not args.force and k in load_cache()):

@@ -39,8 +39,10 @@ template <typename T> struct AdjTile {
     static constexpr int kLds = kCsum + kCw + kStage;
 };
 
+// NST staging sets of tile operands (2 while the registers allow, else 1).
 template <typename T, int KS, int MODE>
 __global__ __launch_bounds__(kBlock, 2) void k_adj_pass(AdjPassArgs a) {
+    constexpr int NST = (KS <= 3 || (KS == 4 && sizeof(T) == 4)) ? 2 : 1;
     typedef PlainOps<T, KS, 1> Ops;
     typedef typename Ops::acc_t acc_t;
     constexpr int TW = Ops::TW;
@@ -96,59 +98,99 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_pass(AdjPassArgs a) {
 #pragma unroll
     for (int t = 0; t < TW; ++t) cw[t] = (T)0;
 
-    const T* __restrict__ ycol = (const T*)a.ycol;
-    const T* __restrict__ acol = (const T*)a.acol;
-    const T* __restrict__ theta = (const T*)a.theta;
     T* __restrict__ thetabar = (T*)a.thetabar;
     const bool tb_read = (MODE == 1) || a.tb_mode == 1;
     const bool tb_write = a.tb_mode != 0;
     const T scale = (T)a.scale;
-    __syncthreads();
 
-    for (int64_t i0 = I0 + 16 * wave; i0 < I1; i0 += 16 * kWaves) {
+    // Buffer views of this workgroup's rows (as in the forward pass): fixed
+    // per-lane offsets, the tile step in the scalar offset, zeros past the rows.
+    const uint32_t rows = (uint32_t)(I1 - I0);
+    const uint32_t row_bytes = (uint32_t)a.ld * (uint32_t)sizeof(T);
+    const rsrc_t th_r = make_rsrc((const T*)a.theta + I0 * a.ld + J0, rows * row_bytes);
+    const rsrc_t tb_r = make_rsrc(tb_read ? thetabar + I0 * a.ld + J0 : (const T*)a.theta + I0 * a.ld + J0,
+                                  rows * row_bytes);
+    const rsrc_t xp_r = make_rsrc((const char*)a.xp + (I0 >> 4) * 64 * Ops::XPB, (rows >> 4) * 64u * Ops::XPB);
+    const rsrc_t y_r = make_rsrc((const T*)a.ycol + I0, rows * (uint32_t)sizeof(T));
+    const rsrc_t a_r = make_rsrc((const T*)a.acol + I0, rows * (uint32_t)sizeof(T));
+    uint32_t th_vo[4], y_vo[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        th_vo[v] = (uint32_t)(16 * wave + orow<Ops>(g, v)) * row_bytes + (uint32_t)(TW * c) * (uint32_t)sizeof(T);
+        y_vo[v] = (uint32_t)(16 * wave + orow<Ops>(g, v)) * (uint32_t)sizeof(T);
+    }
+    const uint32_t xp_vo = (uint32_t)(wave * 64 + lane) * (uint32_t)Ops::XPB;
+    const uint32_t th_step = 16u * kWaves * row_bytes;
+    const uint32_t xp_step = (uint32_t)kWaves * 64u * (uint32_t)Ops::XPB;
+    const uint32_t y_step = 16u * kWaves * (uint32_t)sizeof(T);
+    const int64_t first = I0 + 16 * wave;
+    const int ntile = (int)((I1 - first + 16 * kWaves - 1) / (16 * kWaves));
+
+    struct Stage {
         typename Ops::Xop xop;
-        Ops::load_xop(xop, pa, i0, lane);
         T yv[4], av[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            yv[v] = ycol[i0 + orow<Ops>(g, v)];
-            av[v] = MODE == 0 ? acol[i0 + orow<Ops>(g, v)] : (T)0;
-        }
         V16<T> th[4], tb[4];
+    };
+    auto load_tile = [&](int m, Stage& S) {
+        const uint32_t mm = (uint32_t)m;
+        Ops::load_xop_b(S.xop, xp_r, xp_vo, mm * xp_step);
+        if constexpr (sizeof(T) == 4) {
+            // rows 4g .. 4g + 3 of the tile: one 16-byte load each
+            const V16<T> ty = bld16<T>(y_r, y_vo[0], mm * y_step);
+            V16<T> ta;
+            if (MODE == 0) ta = bld16<T>(a_r, y_vo[0], mm * y_step);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t off = (i0 + orow<Ops>(g, v)) * a.ld + jl;
-            th[v] = ld16(theta + off);
-            if (tb_read) tb[v] = ld16(thetabar + off);
-            else {
+            for (int e = 0; e < 4; ++e) {
+                S.yv[e] = ty.v[e];
+                S.av[e] = MODE == 0 ? ta.v[e] : (T)0;
+            }
+        } else {
 #pragma unroll
-                for (int t = 0; t < TW; ++t) tb[v].v[t] = (T)0;
+            for (int v = 0; v < 4; ++v) {
+                S.yv[v] = (T)bld8(y_r, y_vo[v], mm * y_step);
+                S.av[v] = MODE == 0 ? (T)bld8(a_r, y_vo[v], mm * y_step) : (T)0;
             }
         }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            S.th[v] = bld16<T>(th_r, th_vo[v], mm * th_step);
+            if (tb_read) S.tb[v] = bld16<T>(tb_r, th_vo[v], mm * th_step);
+            else {
+#pragma unroll
+                for (int t = 0; t < TW; ++t) S.tb[v].v[t] = (T)0;
+            }
+        }
+    };
 
+    auto process = [&](int m, const Stage& S) {
+        const int64_t i0 = first + 16 * kWaves * (int64_t)m;
         acc_t R[TW];
-        Ops::residual(R, xop, breg, yv);
+        Ops::residual(R, S.xop, breg, S.yv);
         acc_t P[TW];
-        if (MODE == 0) Ops::residual(P, xop, dreg, av);
+        if (MODE == 0) Ops::residual(P, S.xop, dreg, S.av);
 
         const bool edge = (i0 < J0 + NW && i0 + 16 > J0) || (J0 + NW > a.N) || (i0 + 16 > a.N);
+        // tile-relative indices: pair (i0 + r, J0 + q) is a constraint iff r < rlim, q < qlim, r + dij != q
+        const int rlim = (int)min((int64_t)16, a.N - i0);
+        const int qlim = (int)min((int64_t)NW, a.N - J0);
+        const int dij = (int)max((int64_t)-64, min((int64_t)64, i0 - J0));
         T W[TW][4], Z[TW][4];
 #pragma unroll
         for (int t = 0; t < TW; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const T d = th[v].v[t] - R[t][v];
-                bool m = d > (T)0;
+                const T d = S.th[v].v[t] - R[t][v];
+                bool mk = d > (T)0;
                 if (edge) {
-                    const int64_t i = i0 + orow<Ops>(g, v), j = jl + t;
-                    m = m && i < a.N && j < a.N && i != j;
+                    const int r = orow<Ops>(g, v), q = TW * c + t;
+                    mk = mk && r < rlim && q < qlim && r + dij != q;
                 }
                 if (MODE == 0) {
-                    W[t][v] = m ? d : (T)0;
-                    Z[t][v] = m ? P[t][v] : (T)0;
+                    W[t][v] = mk ? d : (T)0;
+                    Z[t][v] = mk ? P[t][v] : (T)0;
                 } else {
                     W[t][v] = (T)0;
-                    Z[t][v] = m ? scale * tb[v].v[t] : (T)0;
+                    Z[t][v] = mk ? scale * S.tb[v].v[t] : (T)0;
                 }
             }
         if (tb_write) {
@@ -156,12 +198,12 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_pass(AdjPassArgs a) {
             for (int v = 0; v < 4; ++v) {
                 V16<T> o;
 #pragma unroll
-                for (int t = 0; t < TW; ++t) o.v[t] = MODE == 0 ? tb[v].v[t] + Z[t][v] : Z[t][v];
+                for (int t = 0; t < TW; ++t) o.v[t] = MODE == 0 ? S.tb[v].v[t] + Z[t][v] : Z[t][v];
                 st16(thetabar + (i0 + orow<Ops>(g, v)) * a.ld + jl, o);
             }
         }
 
-        Ops::colsums(cacc, Z, xop);
+        Ops::colsums(cacc, Z, S.xop);
         if (MODE == 0) {
 #pragma unroll
             for (int t = 0; t < TW; ++t) cw[t] += (W[t][0] + W[t][1]) + (W[t][2] + W[t][3]);
@@ -171,10 +213,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_pass(AdjPassArgs a) {
         T rs[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            T s = Z[0][v];
+            T sm = Z[0][v];
 #pragma unroll
-            for (int t = 1; t < TW; ++t) s += Z[t][v];
-            rs[v] = row16_sum(s);
+            for (int t = 1; t < TW; ++t) sm += Z[t][v];
+            rs[v] = row16_sum(sm);
         }
         if (c == 0) {
             T* dst = (T*)a.rowpart + (int64_t)strip * a.Nrow + i0;
@@ -196,14 +238,14 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_pass(AdjPassArgs a) {
             if (MODE == 0) bv = *reinterpret_cast<const V16<T>*>(sb + k * NW + TW * c);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                T s = (T)0;
+                T sm = (T)0;
 #pragma unroll
                 for (int t = 0; t < TW; ++t) {
-                    if (MODE == 0) s += W[t][v] * bv.v[t];
-                    s -= Z[t][v] * xv.v[t];
+                    if (MODE == 0) sm += W[t][v] * bv.v[t];
+                    sm -= Z[t][v] * xv.v[t];
                 }
-                s = row16_sum(s);
-                if (c == (k & 15)) keep[k >> 4][v] = s;
+                sm = row16_sum(sm);
+                if (c == (k & 15)) keep[k >> 4][v] = sm;
             }
         }
         T* rv = (T*)a.rowvpart;
@@ -215,6 +257,26 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_pass(AdjPassArgs a) {
                 for (int v = 0; v < 4; ++v)
                     rv[((int64_t)strip * a.Nrow + i0 + orow<Ops>(g, v)) * n + k] = keep[h][v];
             }
+        }
+    };
+
+    __syncthreads();
+    // staging sets; the scheduling barriers keep each set's loads together so
+    // that one set stays in flight while another is processed
+    Stage st[NST];
+#pragma unroll
+    for (int b = 0; b < NST; ++b) {
+        load_tile(b, st[b]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma nounroll
+    for (int m = 0; m < ntile; m += NST) {
+#pragma unroll
+        for (int b = 0; b < NST; ++b) {
+            if (m + b < ntile) process(m + b, st[b]);
+            __builtin_amdgcn_sched_barrier(0);
+            load_tile(m + b + NST, st[b]);
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 
