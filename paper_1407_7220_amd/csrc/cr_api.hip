@@ -32,6 +32,8 @@ struct Layout {
     size_t off_theta, off_xp, off_xiaug, off_ycol, off_rowpart, off_cpart, off_kkt;
     size_t off_y1p, off_y2, off_vy, off_y0, off_xi1p, off_xi2, off_vxi, off_xi0;
     size_t off_blockpart, off_supart, off_su, off_oa, off_st, off_beta, off_cvec;
+    size_t off_y1p1, off_xi1p1, off_spart;   // second iterate buffers and stopping-test pieces (lazy passes)
+    bool lazy = false;                       // MAPG runs use lazy passes (their LDS fits this chunk height)
     int prec = 0;
     int64_t nbeta = 0;
     size_t total;
@@ -103,6 +105,10 @@ Layout make_layout(int64_t N, int n, int precision, int64_t max_iters, int tile_
     L.off_xi2 = take((size_t)L.Nrow * n * 8);
     L.off_vxi = take((size_t)L.Nrow * n * 8);
     L.off_xi0 = take((size_t)L.Nrow * n * 8);
+    L.off_y1p1 = take((size_t)L.Nrow * 8);
+    L.off_xi1p1 = take((size_t)L.Nrow * n * 8);
+    L.off_spart = take((size_t)(L.chunks + L.strips) * 8);
+    L.lazy = cr::lazy_fits(precision, L.rpc);
     L.off_blockpart = take((size_t)std::max<int64_t>(L.nb, 1) * 4 * 8);
     L.off_supart = take((size_t)(std::max<int64_t>((int64_t)L.nsu * (n * n + n + 3), L.nb) + 64) * 8);
     L.off_su = take((size_t)(3 * n + 2 + n * n + 8) * 8);
@@ -171,6 +177,7 @@ struct cr_ctx {
     cr::DevState last{};
     bool have_kkt = false;
     bool verbose = false;
+    bool lazy = false;   // MAPG iterations use lazy passes (single-problem runs whose chunk height allows them)
     char* P(size_t off) const { return ws + off; }
     double* D(size_t off) const { return reinterpret_cast<double*>(ws + off); }
 };
@@ -196,6 +203,22 @@ static cr::PassArgs pass_args(cr_ctx* c, int mode, double theta_scale, const int
     a.rowpart = c->P(L.off_rowpart); a.cpart = c->P(L.off_cpart); a.kktpart = c->D(L.off_kkt);
     a.theta_scale = theta_scale; a.active = active;
     a.cvec = (const float*)c->P(L.off_cvec);
+    return a;
+}
+
+// Gradient pass of a captured MAPG iteration at replay position q (see LazyStep).
+static cr::PassArgs lazy_pass_args(cr_ctx* c, int q, int lfix) {
+    const Layout& L = c->L;
+    cr::PassArgs a = pass_args(c, 0, 0.0, lfix > 0 ? &c->st->one : &c->st->active);
+    cr::LazyStep& z = a.lz;
+    z.on = 1; z.q = q; z.lfix = lfix; z.n = L.n;
+    z.nblk = cr::reduce_blocks(L.N, L.n); z.chunks = L.chunks;
+    z.vy = c->D(L.off_vy); z.vxi = c->D(L.off_vxi); z.X = c->X; z.ybar = c->ybar;
+    z.y1p[0] = c->D(L.off_y1p); z.y1p[1] = c->D(L.off_y1p1);
+    z.xi1p[0] = c->D(L.off_xi1p); z.xi1p[1] = c->D(L.off_xi1p1);
+    z.y2 = c->D(L.off_y2); z.xi2 = c->D(L.off_xi2);
+    z.beta = c->D(L.off_beta); z.npart = c->D(L.off_blockpart); z.spart = c->D(L.off_spart);
+    z.oa = c->oa; z.st = c->st;
     return a;
 }
 
@@ -240,15 +263,19 @@ static cr::UpdateArgs update_args(cr_ctx* c) {
 // One MAPG iteration (position q of a replay): pair pass at (y2, xi2), the
 // stopping test of the previous iteration plus the gradient step, then
 // projection and momentum.
+//
+// With lazy passes the update kernel is not needed: the next iteration's pass
+// completes the step (projection, momentum) for the points it touches.
 static hipError_t enqueue_mapg_iteration(cr_ctx* c, int q, hipStream_t s) {
     const Layout& L = c->L;
-    cr::PassArgs pa = pass_args(c, 0, 0.0, &c->st->active);
+    cr::PassArgs pa = c->lazy ? lazy_pass_args(c, q, 0) : pass_args(c, 0, 0.0, &c->st->active);
     hipError_t e = cr::launch_pair_pass(c->prec, c->n, pa, pass_grid(L), s);
     if (e != hipSuccess) return e;
     cr::ReduceArgs ra = reduce_args(c, 0, c->D(L.off_y2), c->D(L.off_xi2), c->D(L.off_vy), c->D(L.off_vxi), 0.0);
     ra.q = q;
+    if (c->lazy) ra.spart = c->D(L.off_spart);
     e = cr::launch_reduce(c->f64, ra, s);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || c->lazy) return e;
     cr::UpdateArgs ua = update_args(c);
     ua.q = q;
     return cr::launch_update(c->prec, ua, s);
@@ -325,7 +352,14 @@ struct Schedule {
 static hipError_t enqueue_multiplier_step(cr_ctx* c, double mu, double mu_next, int64_t launched, int nblk,
                                           hipStream_t cs) {
     const Layout& L = c->L;
-    hipError_t e = cr::launch_mapg_end(c->D(L.off_blockpart), nblk, launched, c->st, cs);
+    hipError_t e = hipSuccess;
+    if (c->lazy) {
+        // the run's last iterate into y1p / xi1p; no update-kernel norms to gather
+        e = cr::launch_mapg_finish(lazy_pass_args(c, 0, 0).lz, L.N, cs);
+        if (e != hipSuccess) return e;
+        nblk = 0;
+    }
+    e = cr::launch_mapg_end(c->D(L.off_blockpart), nblk, launched, c->st, cs);
     if (e != hipSuccess) return e;
     cr::PointArgs pt = point_args(c, c->D(L.off_y1p), c->D(L.off_xi1p), 1);
     if ((e = cr::launch_set_point(c->prec, pt, cs)) != hipSuccess) return e;
@@ -403,6 +437,7 @@ cr_status cr_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params, c
     c->n = n;
     c->f64 = params->precision == CR_F64;
     c->prec = params->precision;
+    c->lazy = L.lazy;
     c->user_stream = (hipStream_t)stream;
     {
         const char* v = std::getenv("CR_VERBOSE");
@@ -653,7 +688,29 @@ cr_status cr_time_pass(cr_ctx* c, int32_t mode, int32_t reps, double* avg_ms) {
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
     cr::PassArgs pa = pass_args(c, 0, 0.0, &c->st->one);
-    hipError_t e = hipEventRecord(e0, c->cs);
+    hipError_t e = hipSuccess;
+    if (c->lazy) {
+        // The kernel a MAPG run launches: a lazy pass at iteration 2.  Its inputs
+        // come from one step at the start point (pass, reduce); the timed passes
+        // rewrite the same state (y1_1, y2_2) each time.
+        Schedule sch;
+        sch.start(c);
+        const cr::OuterArgs oa = sch.next(c);
+        e = cr::launch_begin_outer(oa, c->oa, c->st, c->cs);
+        cr::PointArgs pt = point_args(c, c->D(L.off_y0), c->D(L.off_xi0), 1);
+        if (e == hipSuccess) e = cr::launch_set_point(c->prec, pt, c->cs);
+        if (e == hipSuccess) e = cr::launch_pair_pass(c->prec, c->n, pa, pass_grid(L), c->cs);
+        cr::ReduceArgs ra = reduce_args(c, 0, c->D(L.off_y2), c->D(L.off_xi2), c->D(L.off_vy), c->D(L.off_vxi), 0.0);
+        ra.spart = c->D(L.off_spart);
+        if (e == hipSuccess) e = cr::launch_reduce(c->f64, ra, c->cs);
+        pa = lazy_pass_args(c, 0, 2);
+        if (e != hipSuccess) {
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            return fail(c, CR_ERR_HIP, std::string("time pass set-up: ") + hipGetErrorString(e));
+        }
+    }
+    e = hipEventRecord(e0, c->cs);
     for (int r = 0; r < reps && e == hipSuccess; ++r) e = cr::launch_pair_pass(c->prec, c->n, pa, pass_grid(L), c->cs);
     if (e == hipSuccess) e = hipEventRecord(e1, c->cs);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -891,6 +948,7 @@ cr_status cr_batch_init(cr_batch** out, const cr_problem* probs, int32_t P, cons
         cr_status st = cr_init(&c, probs[p].N, probs[p].n, &pp, probs[p].X_dev, probs[p].ybar_dev,
                                b->ws + B.off[p], B.L[p].total, stream);
         if (st != CR_OK) { g_last_error = "problem " + std::to_string(p) + ": " + g_last_error; return bad(st); }
+        c->lazy = false;   // the batched graph completes each step with the batched update kernel
         b->sub.push_back(c);
     }
     // device argument tables
@@ -1235,6 +1293,9 @@ cr_status cr_diff_init(cr_diff** out, int64_t N, int32_t n, const cr_params* par
     if (!d) return fail(nullptr, CR_ERR_NOMEM, "host allocation failed");
     s = cr_init(&d->c, N, n, params, X_dev, ybar_dev, workspace_dev, L.total, stream);
     if (s != CR_OK) { delete d; return s; }
+    // checkpoints hold (y1_{l-1}, y2_l) before each segment, which needs the
+    // update kernel to complete every step
+    d->c->lazy = false;
     d->D = D;
     d->base_bytes = L.total;
     d->ws = (char*)align256((size_t)workspace_dev + L.total);

@@ -57,6 +57,36 @@ __host__ __device__ constexpr int qp_of_ks(int ks, int elem) {
 // Mixed precision: K = 3n BF16 slots of the residual contraction in blocks of 32.
 __host__ __device__ constexpr int mixed_kb(int n) { return (3 * n + 31) / 32; }
 
+// Lazy MAPG step.  In a captured MAPG run the gradient pass of iteration l >= 2
+// first completes step l - 1 (Fig. 4 steps 1-2 and 4) for the points it touches:
+// from the unprojected steps v = (vy, vxi) that the reduce kernel wrote and the
+// two norms ||vy - ybar||, ||vxi|| (summed from that kernel's block records),
+//   y1 = Proj_{Q_y}(vy),  y2 = y1 + beta_{l-1} (y1 - y1_{l-2})   (xi alike),
+// and takes its operands from (y2, xi2) directly.  Iterate y1_m lives in
+// y1p[m & 1] (y1_0, the start, in y1p[0]).  Workgroups of strip 0 write the
+// state (y1, y2) of their rows, workgroups of chunk 0 that of their columns'
+// xi, together with the pieces of the stopping test ||y1 - y2_{l-1}||^2
+// (spart[chunk]) and ||xi1 - xi2_{l-1}||^2 (spart[chunks + strip]).  At l = 1
+// the operands come from xiaug / ycol (set by k_set_point).
+struct LazyStep {
+    int32_t on, q;            // q: position of the iteration in the captured replay
+    int32_t lfix, n;          // lfix > 0: iteration number to use instead of base + q + 1
+    int32_t nblk, chunks;     // records in npart; chunk count of the pass grid
+    const double* vy;         // N
+    const double* vxi;        // N x n
+    const double* X;          // N x n
+    const double* ybar;       // N
+    double* y1p[2];           // N each
+    double* xi1p[2];          // N x n each
+    double* y2;               // y^(2)_l (N), read by the reduce kernel
+    double* xi2;              // xi^(2)_l (N x n)
+    const double* beta;       // beta[l] = (t_l - 1) / t_{l+1}
+    const double* npart;      // reduce block records: fields 0, 1 = pieces of ||vy - ybar||^2, ||vxi||^2
+    double* spart;            // chunks + strips stopping-test pieces
+    const OuterArgs* oa;
+    DevState* st;
+};
+
 struct PassArgs {
     int64_t N, Nrow, ld;      // points, padded rows (x16), theta row stride (x64)
     int32_t nc;               // n + 1
@@ -73,6 +103,7 @@ struct PassArgs {
     double theta_scale;       // mu_k / mu_{k+1} (multiplier pass)
     const int32_t* active;
     const float* cvec;        // mixed precision: c_j = x_j^T xi_j - y_j in FP32 (ld)
+    LazyStep lz;              // gradient passes of a captured MAPG run (lz.on = 1)
 };
 
 // Sum of the pass partials for point j, then the gradient (mode 1), the MAPG
@@ -94,6 +125,10 @@ struct ReduceArgs {
     const OuterArgs* oa;
     DevState* st;
     double mu, gamma;         // modes 1 and 2
+    // mode 0 after lazy passes: the stopping-test pieces of the pass
+    // (spart[0 .. chunks) for y, spart[chunks .. chunks + strips) for xi);
+    // null: fields 2 and 3 of the update kernel's block records
+    const double* spart;
 };
 
 // Completion of a MAPG step (Fig. 4): projections, momentum, stopping test.
@@ -150,6 +185,12 @@ hipError_t launch_begin_outer(const OuterArgs& args, OuterArgs* dst, DevState* s
                               int64_t base = 0);
 hipError_t launch_replay_end(DevState* st, int iters, hipStream_t s);
 hipError_t launch_mapg_end(const double* blockpart, int nblk, int64_t launched, DevState* st, hipStream_t s);
+// After a run of lazy passes: y1_it (xi1_it) into y1p[0] (xi1p[0]); if the run
+// ended at l^max with no pass after the last step, that step's projection.
+hipError_t launch_mapg_finish(const LazyStep& lz, int64_t N, hipStream_t s);
+// Largest rows per chunk for which a lazy pass's LDS (row sums, y operands and
+// staged column operands) fits the pass workgroup's 32 KiB area.
+bool lazy_fits(int prec, int64_t rows_per_chunk);
 int reduce_blocks(int64_t N, int n);
 int reduce_blocks_g(int64_t N, int G);
 // Batched form (plain precisions): see cr_batch.hip.

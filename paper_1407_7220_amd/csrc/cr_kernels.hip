@@ -36,7 +36,166 @@ namespace cr {
 // 4 x TW x NKB x 4 x 64 elements = 32 KiB in every precision) and 4 x 4 KKT doubles.
 constexpr int kPassLds = 32768 + 256;
 
-template <typename Ops, int THETA_MODE>
+// Lazy passes place, inside the 32 KiB area, the row sums at [0, R), the y
+// operands of the chunk's rows at [R, 2R) (R = rows x element size, 16-byte
+// aligned) and the staged column operands at [2R, 2R + kBsBytes): 16 TW
+// columns of 33 slots each (k < n: -xi2_jk, k = n: c_j, then zeros).
+constexpr int kBsBytes = 64 * kBsStride * 4;   // 16 TW x 33 x element size, either precision
+__host__ __device__ constexpr int64_t lazy_rbytes(int64_t rows, int esz) { return (rows * esz + 15) / 16 * 16; }
+
+// Threads per staged column, and k entries per thread (slots 0 .. KCAP - 1).
+template <typename Ops> struct LazyShape {
+    static constexpr int COLS = 16 * Ops::TW;
+    static constexpr int PT = kBlock / COLS;
+    static constexpr int KMAX = (Ops::KCAP + PT - 1) / PT;
+};
+
+// Operands of a lazy gradient pass (see LazyStep): the y operands of rows
+// [I0, I1) into ylds, the column operands of [J0, J0 + 16 TW) into breg, and
+// the state and stopping-test pieces that this workgroup owns.  The pieces
+// (per-wave sums) go to `stop` (2 x kWaves doubles) for the epilogue.
+template <typename Ops>
+__device__ void lazy_operands(const PassArgs& a, const int strip, const int chunk, const int64_t I0, const int64_t I1,
+                              const int64_t J0, char* __restrict__ lds, typename Ops::elem* __restrict__ ylds,
+                              typename Ops::Breg& breg, const int g, const int c, double* stop) {
+    typedef typename Ops::elem T;
+    typedef LazyShape<Ops> S;
+    const LazyStep& z = a.lz;
+    const int64_t l = z.lfix > 0 ? (int64_t)z.lfix : z.st->base + z.q + 1;
+    const int rows = (int)(I1 - I0);
+    if (l <= 1) {
+        // first iteration of the run: the operands k_set_point wrote
+        const T* yc = (const T*)a.ycol + I0;
+        for (int r = threadIdx.x; r < rows; r += kBlock) ylds[r] = yc[r];
+        Ops::load_breg(breg, a, J0 + Ops::TW * c, g);
+        __syncthreads();
+        return;
+    }
+    const int64_t N = a.N;
+    const int n = z.n;
+    const bool wrows = strip == 0, wcols = chunk == 0;
+    const int par = (int)(l & 1);                        // y1_{l-2} in y1p[l & 1]
+    const double* __restrict__ vy = z.vy;
+    const double* __restrict__ vxi = z.vxi;
+    const double* __restrict__ X = z.X;
+    const double* __restrict__ ybar = z.ybar;
+    const double* __restrict__ y1in = z.y1p[par];
+    const double* __restrict__ xi1in = z.xi1p[par];
+    double* __restrict__ y1out = z.y1p[par ^ 1];
+    double* __restrict__ xi1out = z.xi1p[par ^ 1];
+    double* __restrict__ y2 = z.y2;
+    double* __restrict__ xi2 = z.xi2;
+
+    // Every load first (column j = J0 + jj, k = r0 + PT e; then the first rows),
+    // so that they are in flight together with the norm gather.
+    const int jj = threadIdx.x / S::PT, r0 = threadIdx.x % S::PT;
+    const int64_t j = J0 + jj;
+    const bool vj = j < N;
+    double cv[S::KMAX], cp[S::KMAX], cx[S::KMAX], co[S::KMAX];
+#pragma unroll
+    for (int e = 0; e < S::KMAX; ++e) {
+        const int k = r0 + S::PT * e;
+        cv[e] = cp[e] = cx[e] = co[e] = 0.0;
+        if (vj && k < n) {
+            const int64_t q = j * n + k;
+            cv[e] = vxi[q]; cp[e] = xi1in[q]; cx[e] = X[q];
+            if (wcols) co[e] = xi2[q];
+        }
+    }
+    double jv = 0.0, jb = 0.0, jp = 0.0;
+    if (vj) { jv = vy[j]; jb = ybar[j]; jp = y1in[j]; }
+    constexpr int RB = 2;
+    double rv[RB], rb[RB], rp[RB], ro[RB];
+#pragma unroll
+    for (int e = 0; e < RB; ++e) {
+        const int r = threadIdx.x + kBlock * e;
+        const int64_t i = I0 + r;
+        rv[e] = rb[e] = rp[e] = ro[e] = 0.0;
+        if (r < rows && i < N) {
+            rv[e] = vy[i]; rb[e] = ybar[i]; rp[e] = y1in[i];
+            if (wrows) ro[e] = y2[i];
+        }
+    }
+
+    // Fig. 4 steps 1-2 of iteration l - 1: the ball projections' scales
+    double ny2, nx2;
+    gather_sum2(z.npart, z.nblk, 0, 1, ny2, nx2);
+    const double ny = sqrt(ny2), nx = sqrt(nx2);
+    const OuterArgs* oa = z.oa;
+    const bool py = ny > oa->By, px = nx > oa->Bxi;
+    const double sy = py ? oa->By / ny : 1.0, sx = px ? oa->Bxi / nx : 1.0;
+    const double beta = z.beta[l - 1];               // (t_{l-1} - 1) / t_l
+    double dy = 0.0, dx = 0.0;
+
+    // columns: -xi2_jk, and c_j = x_j^T xi2_j - y2_j from the PT threads' products
+    T* Bs = reinterpret_cast<T*>(lds + 2 * lazy_rbytes(rows, (int)sizeof(T)));
+    T* brow = Bs + jj * kBsStride;
+    double prod = 0.0;
+#pragma unroll
+    for (int e = 0; e < S::KMAX; ++e) {
+        const int k = r0 + S::PT * e;
+        if (k < n) {
+            const double x1 = px ? sx * cv[e] : cv[e];          // projection onto Q_xi
+            const double x2n = x1 + beta * (x1 - cp[e]);        // extrapolation
+            prod += cx[e] * x2n;
+            brow[k] = vj ? (T)(-x2n) : (T)0;
+            if (wcols && vj) {
+                const int64_t q = j * n + k;
+                dx += (x1 - co[e]) * (x1 - co[e]);
+                xi1out[q] = x1;
+                xi2[q] = x2n;
+            }
+        }
+    }
+    for (int k = n + 1 + r0; k < kBsStride; k += S::PT) brow[k] = (T)0;
+#pragma unroll
+    for (int o = S::PT / 2; o > 0; o >>= 1) prod += __shfl_xor(prod, o);
+    {
+        const double y1 = py ? jb + sy * (jv - jb) : jv;
+        const double y2j = y1 + beta * (y1 - jp);
+        if (r0 == 0) brow[n] = vj ? (T)(prod - y2j) : (T)0;
+    }
+
+    // rows: y2_i, and the state of this workgroup's rows when it owns them
+    auto row = [&](int r, double v, double b, double p, double o) {
+        const int64_t i = I0 + r;
+        T yv = (T)0;
+        if (i < N) {
+            const double y1 = py ? b + sy * (v - b) : v;       // projection onto Q_y
+            const double y2n = y1 + beta * (y1 - p);
+            yv = (T)y2n;
+            if (wrows) {
+                dy += (y1 - o) * (y1 - o);
+                y1out[i] = y1;
+                y2[i] = y2n;
+            }
+        }
+        ylds[r] = yv;
+    };
+#pragma unroll
+    for (int e = 0; e < RB; ++e) {
+        const int r = threadIdx.x + kBlock * e;
+        if (r < rows) row(r, rv[e], rb[e], rp[e], ro[e]);
+    }
+    for (int r = threadIdx.x + kBlock * RB; r < rows; r += kBlock) {
+        const int64_t i = I0 + r;
+        double v = 0.0, b = 0.0, p = 0.0, o = 0.0;
+        if (i < N) {
+            v = vy[i]; b = ybar[i]; p = y1in[i];
+            if (wrows) o = y2[i];
+        }
+        row(r, v, b, p, o);
+    }
+    if (wrows || wcols) {
+        dy = wave_sum(dy);
+        dx = wave_sum(dx);
+        if ((threadIdx.x & 63) == 0) { stop[threadIdx.x >> 6] = dy; stop[kWaves + (threadIdx.x >> 6)] = dx; }
+    }
+    __syncthreads();
+    Ops::load_breg_lds(breg, Bs, Ops::TW * c, g, n);
+}
+
+template <typename Ops, int THETA_MODE, int LAZY = 0>
 __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chunk, const int nstrips,
                                char* __restrict__ lds) {
     typedef typename Ops::elem T;
@@ -58,8 +217,11 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
     T* srow = reinterpret_cast<T*>(lds);
     static_assert(kMaxRowsPerChunk * 8 <= 32768, "row staging");
 
+    // lazy passes: y operands of the chunk's rows in LDS, after the row sums
+    T* ylds = reinterpret_cast<T*>(lds + lazy_rbytes(I1 - I0, (int)sizeof(T)));
+    double* stop = reinterpret_cast<double*>(lds + 32768);
     typename Ops::Breg breg;
-    Ops::load_breg(breg, a, jl, g);
+    if constexpr (!LAZY) Ops::load_breg(breg, a, jl, g);
 
     acc_t cacc[TW][NKB];
 #pragma unroll
@@ -103,7 +265,9 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
     auto load_tile = [&](int m, typename Ops::Xop& xop, T* yv, V16<T>* th) {
         const uint32_t mm = (uint32_t)m;
         Ops::load_xop_b(xop, xp_r, xp_vo, mm * xp_step);
-        if (sizeof(T) == 4) {
+        if constexpr (LAZY) {
+            (void)yv;
+        } else if (sizeof(T) == 4) {
             // rows 4g .. 4g + 3 of the tile
             V16<T> tv = bld16<T>(y_r, y_vo[0], mm * y_step);
 #pragma unroll
@@ -120,7 +284,21 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
         const int64_t i0 = row_of(m);
         // residual tiles R_t
         acc_t R[TW];
-        Ops::residual(R, xop, breg, yv);
+        if constexpr (LAZY) {
+            T yl[4];
+            const T* yr = ylds + (i0 - I0);
+            if (sizeof(T) == 4) {
+                const V16<T> tv = *reinterpret_cast<const V16<T>*>(yr + 4 * g);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) yl[e] = tv.v[e];
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) yl[v] = yr[orow<Ops>(g, v)];
+            }
+            Ops::residual(R, xop, breg, yl);
+        } else {
+            Ops::residual(R, xop, breg, yv);
+        }
 
         // w = max(theta - r, 0); explicit zero off the constraint set
         T W[TW][4];
@@ -204,14 +382,26 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
     typename Ops::Xop xs[NSET];
     T ys[NSET][4];
     V16<T> ts[NSET][4];
-#pragma unroll
     // The scheduling barriers keep each staging set's loads together and in
     // program order, so the prologue leaves the same pending-load sequence as
     // the loop's back edge; otherwise the wait-count merge at the loop head
     // drains nearly every prefetched load once per NSET tiles.
-    for (int b = 0; b < NSET; ++b) {
-        load_tile(b, xs[b], ys[b], ts[b]);
+    if constexpr (LAZY) {
+        // one tile in flight during the operand set-up (more would spill)
+        load_tile(0, xs[0], ys[0], ts[0]);
         __builtin_amdgcn_sched_barrier(0);
+        lazy_operands<Ops>(a, strip, chunk, I0, I1, J0, lds, ylds, breg, g, c, stop);
+#pragma unroll
+        for (int b = 1; b < NSET; ++b) {
+            load_tile(b, xs[b], ys[b], ts[b]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
+#pragma unroll
+        for (int b = 0; b < NSET; ++b) {
+            load_tile(b, xs[b], ys[b], ts[b]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
 #pragma nounroll
     for (int m = 0; m < ntile; m += NSET) {
@@ -226,6 +416,15 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
 
     // rowpart[strip][i] of this chunk's rows, from the LDS staging area
     __syncthreads();
+    if constexpr (LAZY) {
+        const int64_t l = a.lz.lfix > 0 ? (int64_t)a.lz.lfix : a.lz.st->base + a.lz.q + 1;
+        if (threadIdx.x == 0 && l > 1 && (strip == 0 || chunk == 0)) {
+            double sy2 = stop[0], sx2 = stop[kWaves];
+            for (int w = 1; w < kWaves; ++w) { sy2 += stop[w]; sx2 += stop[kWaves + w]; }
+            if (strip == 0) a.lz.spart[chunk] = sy2;
+            if (chunk == 0) a.lz.spart[a.lz.chunks + strip] = sx2;
+        }
+    }
     {
         T* dst = (T*)a.rowpart + (int64_t)strip * a.Nrow + I0;
         for (int r = threadIdx.x; r < (int)(I1 - I0); r += kBlock) dst[r] = srow[r];
@@ -274,11 +473,11 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
 // WAVES: minimum waves per SIMD the register allocation must allow (the
 // largest count at which the gradient pass of the class needs no spills:
 // 4 for FP32 with KS <= 3, 3 for FP32 KS = 4 and FP64 KS <= 4, 2 otherwise).
-template <typename Ops, int THETA_MODE, int WAVES>
+template <typename Ops, int THETA_MODE, int WAVES, int LAZY = 0>
 __global__ __launch_bounds__(kBlock, WAVES) void k_pair_pass(PassArgs a) {
     if (*a.active == 0) return;
     __shared__ __align__(16) char lds[kPassLds];
-    pair_pass_item<Ops, THETA_MODE>(a, blockIdx.x, blockIdx.y, gridDim.x, lds);
+    pair_pass_item<Ops, THETA_MODE, LAZY>(a, blockIdx.x, blockIdx.y, gridDim.x, lds);
 }
 
 // Batched pass: a persistent grid walks the (problem, strip, chunk) items of
@@ -355,10 +554,12 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
         else if (k < n) { xjk = a.X[j * n + k]; xik = a.xi[j * n + k]; }
     }
     if (a.mode == 0 && l > 1) {
-        // Fig. 4 steps 6-9 for the previous iteration l - 1, from the block
-        // pieces that k_update left: every block takes the same decision.
+        // Fig. 4 steps 6-9 for the previous iteration l - 1, from the pieces
+        // that this iteration's lazy pass (or k_update) left: every block
+        // takes the same decision.
         double dy2, dx2;
-        gather_sum2(a.blockpart, nblk, 2, 3, dy2, dx2);
+        if (a.spart) gather_ranges2(a.spart, a.chunks, a.strips, dy2, dx2);
+        else gather_sum2(a.blockpart, nblk, 2, 3, dy2, dx2);
         const double dy = sqrt(dy2), dxi = sqrt(dx2);
         const bool alpha_stop = a.oa->adaptive && dy <= a.oa->alpha_y && dxi <= a.oa->alpha_xi;
         if (alpha_stop || l - 1 >= a.oa->lmax) {
@@ -490,7 +691,7 @@ __device__ void update_block(const UpdateArgs& a, const int blk, const int nblk)
     T* xa = (T*)a.xiaug + j * a.kp;
     if (a.sv_nrm && blk == 0 && threadIdx.x == 0) { a.sv_nrm[0] = ny; a.sv_nrm[1] = nx; }
     if (valid && k == n) {
-        const double y1 = cb + sc_y * (v - cb);             // projection onto Q_y
+        const double y1 = ny > a.oa->By ? cb + sc_y * (v - cb) : v;   // projection onto Q_y
         if (a.sv_y2) { a.sv_y2[j] = c2; a.sv_vy[j] = v; }
         dy2 = (y1 - c2) * (y1 - c2);
         y2n = y1 + beta * (y1 - c1p);                       // extrapolation
@@ -591,6 +792,39 @@ __global__ __launch_bounds__(kBlock) void k_mapg_end(const double* blockpart, in
         st->stopped_by_alpha = 0;
         st->dy = dy;
         st->dxi = dxi;
+    }
+}
+
+// End of a run of lazy passes (see LazyStep).  If no reduce kernel stopped the
+// run, it ended at l^max = the launched count after the reduce of step l^max,
+// and that step's projections (Fig. 4 steps 1-2) give (y1, xi1); otherwise the
+// stopping iteration `it` left y1_it in y1p[it & 1].  Either way the result
+// goes to y1p[0] / xi1p[0].  `active` is read here and cleared afterwards by
+// k_mapg_end.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_mapg_finish(LazyStep z, int64_t N) {
+    constexpr int PER = kBlock / G;
+    const int k = threadIdx.x % G;
+    const int64_t j = (int64_t)blockIdx.x * PER + threadIdx.x / G;
+    const int n = z.n;
+    const bool valid = j < N;
+    const DevState* st = z.st;
+    if (st->active) {
+        double ny2, nx2;
+        gather_sum2(z.npart, z.nblk, 0, 1, ny2, nx2);
+        const double ny = sqrt(ny2), nx = sqrt(nx2);
+        const bool py = ny > z.oa->By, px = nx > z.oa->Bxi;
+        const double sy = py ? z.oa->By / ny : 1.0, sx = px ? z.oa->Bxi / nx : 1.0;
+        if (valid && k == n) {
+            const double v = z.vy[j], b = z.ybar[j];
+            z.y1p[0][j] = py ? b + sy * (v - b) : v;
+        } else if (valid && k < n) {
+            const double v = z.vxi[j * n + k];
+            z.xi1p[0][j * n + k] = px ? sx * v : v;
+        }
+    } else if (st->it & 1) {
+        if (valid && k == n) z.y1p[0][j] = z.y1p[1][j];
+        else if (valid && k < n) z.xi1p[0][j * n + k] = z.xi1p[1][j * n + k];
     }
 }
 
@@ -936,8 +1170,14 @@ __global__ void k_su_start_final(const double* part, int nblk, int64_t N, int n,
 template <typename Ops, int GRAD_WAVES = 2>
 static hipError_t launch_pass_ops(const PassArgs& a, dim3 grid, hipStream_t s) {
     if (a.mode == 1) hipLaunchKernelGGL((k_pair_pass<Ops, 1, 2>), grid, dim3(kBlock), 0, s, a);
+    else if (a.lz.on) hipLaunchKernelGGL((k_pair_pass<Ops, 0, GRAD_WAVES, 1>), grid, dim3(kBlock), 0, s, a);
     else hipLaunchKernelGGL((k_pair_pass<Ops, 0, GRAD_WAVES>), grid, dim3(kBlock), 0, s, a);
     return hipGetLastError();
+}
+
+bool lazy_fits(int prec, int64_t rows_per_chunk) {
+    const int esz = prec == 0 ? 8 : 4;
+    return 2 * lazy_rbytes(rows_per_chunk, esz) + kBsBytes <= 32768;
 }
 
 template <typename T>
@@ -1006,6 +1246,12 @@ hipError_t launch_update(int prec, const UpdateArgs& a, hipStream_t s) {
 }
 
 int reduce_blocks(int64_t N, int n) { return (int)points_grid(N, group_of(n)).x; }
+
+hipError_t launch_mapg_finish(const LazyStep& z, int64_t N, hipStream_t s) {
+    if (group_of(z.n) == 16) hipLaunchKernelGGL((k_mapg_finish<16>), points_grid(N, 16), dim3(kBlock), 0, s, z, N);
+    else hipLaunchKernelGGL((k_mapg_finish<32>), points_grid(N, 32), dim3(kBlock), 0, s, z, N);
+    return hipGetLastError();
+}
 int reduce_blocks_g(int64_t N, int G) { return (int)points_grid(N, G).x; }
 
 template <typename T, int KS>

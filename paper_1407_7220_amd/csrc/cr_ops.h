@@ -126,10 +126,28 @@ static __device__ void block_sum2(double& a, double& b) {
 static __device__ void gather_sum2(const double* part, int count, int q0, int q1, double& s0, double& s1) {
     s0 = 0.0;
     s1 = 0.0;
-    for (int b = threadIdx.x; b < count; b += kBlock) {
-        s0 += part[(int64_t)b * 4 + q0];
-        s1 += part[(int64_t)b * 4 + q1];
+    // four records per thread in flight, summed in index order
+    for (int b = threadIdx.x; b < count; b += 4 * kBlock) {
+        double u0[4], u1[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = b + e * kBlock;
+            u0[e] = r < count ? part[(int64_t)r * 4 + q0] : 0.0;
+            u1[e] = r < count ? part[(int64_t)r * 4 + q1] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) { s0 += u0[e]; s1 += u1[e]; }
     }
+    block_sum2(s0, s1);
+}
+
+// Sums of part[0 .. n0) and of part[n0 .. n0 + n1) (written by an earlier
+// kernel), by all threads of the block in a fixed order.
+static __device__ void gather_ranges2(const double* part, int n0, int n1, double& s0, double& s1) {
+    s0 = 0.0;
+    s1 = 0.0;
+    for (int b = threadIdx.x; b < n0; b += kBlock) s0 += part[b];
+    for (int b = threadIdx.x; b < n1; b += kBlock) s1 += part[n0 + b];
     block_sum2(s0, s1);
 }
 
@@ -167,6 +185,9 @@ static __device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 acc)
 }
 
 // FP64 / FP32: 16x16x4 MFMA in the pass precision; c_j and y_i enter R exactly.
+// Row stride (elements) of the column operands a lazy pass stages in LDS.
+constexpr int kBsStride = 33;
+
 template <typename T, int KS, int NSET_ = 0> struct PlainOps {
     typedef T elem;
     typedef typename Tr<T>::acc acc_t;
@@ -189,6 +210,15 @@ template <typename T, int KS, int NSET_ = 0> struct PlainOps {
 #pragma unroll
             for (int s = 0; s < KS; ++s) B.b[s][t] = row[4 * s + g];
         }
+    }
+    // slots of one column's operand row: [-xi_j (n), c_j, 0 ...]
+    static constexpr int KCAP = 4 * KS;
+    // the same from a staged LDS copy (column c0 + t at row c0 + t, stride kBsStride)
+    static __device__ void load_breg_lds(Breg& B, const T* Bs, int c0, int g, int) {
+#pragma unroll
+        for (int t = 0; t < TW; ++t)
+#pragma unroll
+            for (int s = 0; s < KS; ++s) B.b[s][t] = Bs[(c0 + t) * kBsStride + 4 * s + g];
     }
     static __device__ void load_xop(Xop& X, const PassArgs& a, int64_t i0, int lane) {
         const T* xp = (const T*)a.xp;
@@ -250,6 +280,32 @@ template <int KB, int NKB_> struct MixedOps {
             for (int kb = 0; kb < KB; ++kb)
                 B.b[kb][t] = *reinterpret_cast<const bf16x8*>(xb + ((jl + t) * KB + kb) * 32 + 8 * g);
             B.cc[t] = a.cvec[jl + t];
+        }
+    }
+    // -xi_j entries of one column (3n <= 32 KB)
+    static constexpr int KCAP = (32 * KB) / 3 + 1 < 32 ? (32 * KB) / 3 + 1 : 32;
+    // from a staged LDS copy of [-xi_j (n), c_j] in FP32: the hi/lo slots as k_set_point lays them out
+    static __device__ void load_breg_lds(Breg& B, const float* Bs, int c0, int g, int n) {
+#pragma unroll
+        for (int t = 0; t < TW; ++t) {
+            const float* row = Bs + (c0 + t) * kBsStride;
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+                bf16x8 v;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int q = 32 * kb + 8 * g + e;
+                    __bf16 val = (__bf16)0.0f;
+                    if (q < 3 * n) {
+                        const float x = row[q % n];
+                        const __bf16 hi = (__bf16)x;
+                        val = q < 2 * n ? hi : (__bf16)(x - (float)hi);
+                    }
+                    v[e] = val;
+                }
+                B.b[kb][t] = v;
+            }
+            B.cc[t] = row[n];
         }
     }
     static __device__ void load_xop(Xop& X, const PassArgs& a, int64_t i0, int lane) {

@@ -170,6 +170,61 @@ def test_fixed_schedule_small_quadratic(cr, prec):
     assert exi < TOL_SOLVE[prec] * 10
 
 
+# MAPG run lengths around the 32-iteration replay: a run that a reduce kernel
+# stops (last iterate odd or even) and one that ends with the last replay
+# (l^max a multiple of 32, finished after the replays), plus the shortest runs.
+@pytest.mark.parametrize("prec,inner", [(0, 1), (0, 2), (0, 31), (0, 32), (0, 33), (0, 64), (1, 32), (1, 33),
+                                        (2, 32), (2, 31)])
+def test_fixed_schedule_run_lengths(cr, prec, inner):
+    say("fixed schedule run length %s inner=%d N=130 n=5" % (PREC_NAME[prec], inner))
+    p = synth.quad_l1_gaussian(130, 5, seed=7)
+    sched = dict(inner_iters=inner, max_outer=3)
+    ref = oracle.alcc(p.X, p.ybar, oracle.Params(**sched), record_kkt=False)
+    y, xi, info = cr.solve(dev(p.X), dev(p.ybar), cr.Params(precision=prec, **sched))
+    assert info.inner_iters == 3 * inner and info.outer_iters == 3
+    ey, exi = rel(host(y), ref.y), rel(host(xi), ref.xi)
+    say("  y %.2e xi %.2e" % (ey, exi))
+    assert ey < TOL_SOLVE[prec]
+    assert exi < TOL_SOLVE[prec] * 10
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+def test_tall_chunks_match_short_chunks(cr, prec):
+    # 4096-row chunks leave no LDS room for the staged operands of a lazy
+    # pass, so that solve completes each step with the update kernel; 256-row
+    # chunks use lazy passes.  Both follow the same iteration.
+    N = 1700 if prec == 0 else 3100
+    say("tall vs short chunks %s N=%d n=3" % (PREC_NAME[prec], N))
+    p = synth.quad_l1_gaussian(N, 3, seed=8)
+    sched = dict(inner_iters=20, max_outer=2)
+    out = {}
+    for tr in (256, 4096):
+        y, xi, info = cr.solve(dev(p.X), dev(p.ybar), cr.Params(precision=prec, tile_rows=tr, **sched))
+        out[tr] = (host(y), host(xi))
+    ref = oracle.alcc(p.X, p.ybar, oracle.Params(**sched), record_kkt=False)
+    for tr, (y, xi) in out.items():
+        say("  tile_rows %d: y %.2e xi %.2e" % (tr, rel(y, ref.y), rel(xi, ref.xi)))
+        assert rel(y, ref.y) < TOL_SOLVE[prec]
+        assert rel(xi, ref.xi) < TOL_SOLVE[prec] * 10
+    tol = 1e-12 if prec == 0 else 1e-5
+    assert rel(out[256][0], out[4096][0]) < tol
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "mixed"])
+def test_time_pass_then_solve(cr, prec):
+    # the timing hook runs the solve's pass kernel on scratch state; a solve
+    # on the same context afterwards is unaffected
+    say("time_pass then solve %s N=200 n=2" % PREC_NAME[prec])
+    p = synth.workload("small_quadratic")
+    sched = dict(inner_iters=20, max_outer=2)
+    ctx = cr.Context(dev(p.X), dev(p.ybar), cr.Params(precision=prec, **sched))
+    ms = ctx.time_pass(3)
+    assert ms > 0
+    y, xi, info = ctx.run()
+    ref = oracle.alcc(p.X, p.ybar, oracle.Params(**sched), record_kkt=False)
+    assert rel(host(y), ref.y) < TOL_SOLVE[prec]
+
+
 @pytest.mark.parametrize("N,n,seed", [(37, 3, 1), (130, 5, 2), (96, 20, 3)])
 def test_fixed_schedule_ragged(cr, N, n, seed):
     say("fixed schedule ragged N=%d n=%d seed=%d" % (N, n, seed))
