@@ -540,37 +540,92 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
     } else {
         mu = a.mu; gamma = a.gamma;
     }
-    // every load of this point first, so that they overlap the stop test's gather
-    double rs = 0.0, ck = 0.0, yj = 0.0, ybj = 0.0, xjk = 0.0, xik = 0.0;
-    if (valid) {
-#pragma unroll 4
-        for (int q = k; q < a.strips; q += G) rs += (double)rowpart[(int64_t)q * a.Nrow + j];
-        if (k < nc) {
-            const T* cp = cpart + j * nc + k;
-#pragma unroll 4
-            for (int h = 0; h < a.chunks; ++h) ck += (double)cp[(int64_t)h * a.ld * nc];
-        }
-        if (k == n) { yj = a.y[j]; ybj = a.ybar[j]; }
-        else if (k < n) { xjk = a.X[j * n + k]; xik = a.xi[j * n + k]; }
+    // Every load of this point first, so that they are in flight together.
+    // Lane k sums the strips k, k + G, ... and (k < n + 1) column k over the
+    // chunks, each in index order.  Buffer views of 8 strips x G (16 chunks)
+    // per batch, based at the wave's first point: entries past the last strip
+    // (chunk) read as zeros, so there is no per-entry branch.
+    constexpr int URS = 8, UCK = 16;
+    const int p = (threadIdx.x & 63) / G;
+    const int64_t j0 = __builtin_amdgcn_readfirstlane((int)(j - p));   // the same in every lane of the wave
+    const uint32_t rvo = ((uint32_t)k * (uint32_t)a.Nrow + (uint32_t)p) * (uint32_t)sizeof(T);
+    const uint32_t rso = (uint32_t)G * (uint32_t)a.Nrow * (uint32_t)sizeof(T);
+    const uint32_t cvo = ((uint32_t)p * (uint32_t)nc + (uint32_t)k) * (uint32_t)sizeof(T);
+    const uint32_t cso = (uint32_t)(a.ld * nc) * (uint32_t)sizeof(T);
+    auto rs_view = [&](int s0) {
+        const uint64_t rem = (uint64_t)(a.strips - s0) * (uint64_t)a.Nrow * sizeof(T);
+        return make_rsrc(rowpart + (int64_t)s0 * a.Nrow + j0, (uint32_t)min(rem, (uint64_t)0xffffffffu));
+    };
+    auto ck_view = [&](int h0) {
+        const uint64_t rem = (uint64_t)(a.chunks - h0) * (uint64_t)(a.ld * nc) * sizeof(T);
+        return make_rsrc(cpart + ((int64_t)h0 * a.ld + j0) * nc, (uint32_t)min(rem, (uint64_t)0xffffffffu));
+    };
+    // Block 0 takes the stopping decision of iteration l - 1 (below); the
+    // first record of each of its two sums is loaded here with the rest.
+    const bool decide = a.mode == 0 && l > 1 && blk == 0;
+    const int tid = threadIdx.x;
+    const int d0 = a.spart ? a.chunks : nblk, d1 = a.spart ? a.strips : nblk;
+    double x0 = 0.0, x1 = 0.0;
+    if (decide) {
+        x0 = a.spart ? a.spart[min(tid, d0 - 1)] : a.blockpart[(int64_t)min(tid, d0 - 1) * 4 + 2];
+        x1 = a.spart ? a.spart[d0 + min(tid, d1 - 1)] : a.blockpart[(int64_t)min(tid, d1 - 1) * 4 + 3];
     }
-    if (a.mode == 0 && l > 1) {
+    // first batches and the point's own values, all issued before any sum
+    T ur[URS], uc[UCK];
+    {
+        const rsrc_t r = rs_view(0), c = ck_view(0);
+#pragma unroll
+        for (int e = 0; e < URS; ++e) ur[e] = bld_t<T>(r, rvo, (uint32_t)e * rso);
+#pragma unroll
+        for (int e = 0; e < UCK; ++e) uc[e] = bld_t<T>(c, cvo, (uint32_t)e * cso);
+    }
+    const int64_t jc = valid ? j : a.N - 1;
+    const int kk = min(k, n - 1);
+    const double y_l = a.y[jc], yb_l = a.ybar[jc], x_l = a.X[jc * n + kk], xi_l = a.xi[jc * n + kk];
+    double rs = 0.0, ck = 0.0;
+#pragma unroll
+    for (int e = 0; e < URS; ++e) rs += (double)ur[e];
+    for (int s0 = G * URS; s0 < a.strips; s0 += G * URS) {
+        const rsrc_t r = rs_view(s0);
+#pragma unroll
+        for (int e = 0; e < URS; ++e) ur[e] = bld_t<T>(r, rvo, (uint32_t)e * rso);
+#pragma unroll
+        for (int e = 0; e < URS; ++e) rs += (double)ur[e];
+    }
+#pragma unroll
+    for (int e = 0; e < UCK; ++e) ck += (double)uc[e];
+    for (int h0 = UCK; h0 < a.chunks; h0 += UCK) {
+        const rsrc_t c = ck_view(h0);
+#pragma unroll
+        for (int e = 0; e < UCK; ++e) uc[e] = bld_t<T>(c, cvo, (uint32_t)e * cso);
+#pragma unroll
+        for (int e = 0; e < UCK; ++e) ck += (double)uc[e];
+    }
+    if (k >= nc) ck = 0.0;
+    const bool own_y = valid && k == n, own_x = valid && k < n;
+    const double yj = own_y ? y_l : 0.0, ybj = own_y ? yb_l : 0.0;
+    const double xjk = own_x ? x_l : 0.0, xik = own_x ? xi_l : 0.0;
+    if (decide) {
         // Fig. 4 steps 6-9 for the previous iteration l - 1, from the pieces
-        // that this iteration's lazy pass (or k_update) left: every block
-        // takes the same decision.
-        double dy2, dx2;
-        if (a.spart) gather_ranges2(a.spart, a.chunks, a.strips, dy2, dx2);
-        else gather_sum2(a.blockpart, nblk, 2, 3, dy2, dx2);
+        // that this iteration's lazy pass (spart: chunks y pieces, then strips
+        // xi pieces) or k_update (fields 2, 3 of its block records) left.
+        // Block 0 decides; the other blocks go on, since nothing reads this
+        // step's output once MAPG has stopped.
+        double g0 = tid < d0 ? x0 : 0.0, g1 = tid < d1 ? x1 : 0.0;
+        for (int b = tid + kBlock; b < max(d0, d1); b += kBlock) {
+            if (b < d0) g0 += a.spart ? a.spart[b] : a.blockpart[(int64_t)b * 4 + 2];
+            if (b < d1) g1 += a.spart ? a.spart[d0 + b] : a.blockpart[(int64_t)b * 4 + 3];
+        }
+        double dy2 = g0, dx2 = g1;
+        block_sum2(dy2, dx2);
         const double dy = sqrt(dy2), dxi = sqrt(dx2);
         const bool alpha_stop = a.oa->adaptive && dy <= a.oa->alpha_y && dxi <= a.oa->alpha_xi;
-        if (alpha_stop || l - 1 >= a.oa->lmax) {
-            if (blk == 0 && threadIdx.x == 0) {
-                st->active = 0;
-                st->it = l - 1;
-                st->stopped_by_alpha = alpha_stop ? 1 : 0;
-                st->dy = dy;
-                st->dxi = dxi;
-            }
-            return;
+        if ((alpha_stop || l - 1 >= a.oa->lmax) && threadIdx.x == 0) {
+            st->active = 0;
+            st->it = l - 1;
+            st->stopped_by_alpha = alpha_stop ? 1 : 0;
+            st->dy = dy;
+            st->dxi = dxi;
         }
     }
     rs = group_sum<G>(rs);

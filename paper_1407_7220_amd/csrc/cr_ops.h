@@ -81,6 +81,13 @@ __device__ __forceinline__ V16<T> bld16(rsrc_t r, uint32_t voff, uint32_t soff) 
 __device__ __forceinline__ double bld8(rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
+template <typename T> __device__ __forceinline__ T bld_t(rsrc_t r, uint32_t voff, uint32_t soff);
+template <> __device__ __forceinline__ float bld_t<float>(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <> __device__ __forceinline__ double bld_t<double>(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return bld8(r, voff, soff);
+}
 
 // ---------------------------------------------------------------------------
 // Block reductions (256 threads) and the last-arriving-block handshake.
@@ -131,23 +138,16 @@ static __device__ void gather_sum2(const double* part, int count, int q0, int q1
         double u0[4], u1[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
+            // clamped address and a select (no branch, so the loads stay in flight together)
             const int r = b + e * kBlock;
-            u0[e] = r < count ? part[(int64_t)r * 4 + q0] : 0.0;
-            u1[e] = r < count ? part[(int64_t)r * 4 + q1] : 0.0;
+            const int64_t rc = min(r, count - 1);
+            const double x0 = part[rc * 4 + q0], x1 = part[rc * 4 + q1];
+            u0[e] = r < count ? x0 : 0.0;
+            u1[e] = r < count ? x1 : 0.0;
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) { s0 += u0[e]; s1 += u1[e]; }
     }
-    block_sum2(s0, s1);
-}
-
-// Sums of part[0 .. n0) and of part[n0 .. n0 + n1) (written by an earlier
-// kernel), by all threads of the block in a fixed order.
-static __device__ void gather_ranges2(const double* part, int n0, int n1, double& s0, double& s1) {
-    s0 = 0.0;
-    s1 = 0.0;
-    for (int b = threadIdx.x; b < n0; b += kBlock) s0 += part[b];
-    for (int b = threadIdx.x; b < n1; b += kBlock) s1 += part[n0 + b];
     block_sum2(s0, s1);
 }
 
