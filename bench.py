@@ -130,7 +130,7 @@ def batched_rate(cr, autotune, inner=100, outer=2):
     import synth
     probs = synth.batched_workload()
     pairs = [(torch.from_numpy(q.X).cuda(), torch.from_numpy(q.ybar).cuda()) for q in probs]
-    tiles = [autotune.tile_rows_for(X, yb, cr.F32) for X, yb in pairs]
+    tiles = [autotune.tile_rows_for(X, yb, cr.F32, form="batched") for X, yb in pairs]
     b = cr.Batch(pairs, cr.Params(precision=cr.F32, inner_iters=inner, max_outer=outer), tile_rows=tiles)
     b.run()
     _, infos, secs = b.run()

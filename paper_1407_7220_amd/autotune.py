@@ -2,13 +2,18 @@
 
 The one free tile dimension of the pass is the number of theta rows a
 workgroup sweeps (``tile_rows``): taller tiles amortise the per-workgroup
-prologue and the column-partial writes, shorter ones give the scheduler more
-workgroups.  The tuner times the gradient pass (HIP events inside the library,
-``Context.time_pass``) for a set of candidates on the caller's own data and
-keeps the fastest.  Choices are cached in a JSON file keyed on
-(n, precision, N bucket), the bucket being N rounded to the nearest quarter
-octave.  The cache path is ``tile_cache.json`` next to this file unless
-``CR_TILE_CACHE`` names another.
+prologue (in a MAPG run, the completion of the previous step for the
+workgroup's rows and columns) and the column-partial writes, shorter ones give
+the scheduler more workgroups.  For single-problem solves the tuner times whole
+MAPG iterations (a short fixed-schedule run: pair pass plus reductions, since
+the tile height also sets the reduction's work and whether the pass can
+complete the previous step itself); for the batched form, whose graph runs the
+plain pass and its own update, it times the gradient pass alone (HIP events
+inside the library, ``Context.time_pass``).  Candidates run on the caller's
+own data and the fastest is kept.  Choices are cached in a JSON file keyed on
+(form, n, precision, N bucket), the bucket being N rounded to the nearest
+quarter octave.  The cache path is ``tile_cache.json`` next to this file
+unless ``CR_TILE_CACHE`` names another.
 """
 from __future__ import annotations
 
@@ -38,8 +43,12 @@ def bucket(N: int) -> int:
     return int(round(2.0 ** (round(4.0 * math.log2(max(2, int(N)))) / 4.0)))
 
 
-def key(N: int, n: int, precision: int) -> str:
-    return "n%d-%s-N%d" % (int(n), _PREC[int(precision)], bucket(N))
+FORMS = ("solve", "batched")
+
+
+def key(N: int, n: int, precision: int, form: str = "solve") -> str:
+    k = "n%d-%s-N%d" % (int(n), _PREC[int(precision)], bucket(N))
+    return k if form == "solve" else form + "-" + k
 
 
 def load_cache() -> Dict[str, dict]:
@@ -58,42 +67,55 @@ def save_cache(cache: Dict[str, dict]) -> None:
     os.replace(tmp, path)
 
 
-def lookup(N: int, n: int, precision: int) -> Optional[int]:
-    entry = load_cache().get(key(N, n, precision))
+def lookup(N: int, n: int, precision: int, form: str = "solve") -> Optional[int]:
+    entry = load_cache().get(key(N, n, precision, form))
     return int(entry["tile_rows"]) if entry else None
 
 
-def tune(X, ybar, precision: int, reps: int = 20, candidates=CANDIDATES, save: bool = True) -> int:
-    """Time the gradient pass for each candidate tile height on (X, ybar); return
-    and cache the fastest."""
+def _time(X, ybar, precision: int, r: int, form: str, reps: int) -> float:
+    """Milliseconds per MAPG iteration (form 'solve') or per gradient pass ('batched')."""
+    if form == "batched":
+        ctx = Context(X, ybar, Params(precision=precision, tile_rows=int(r)))
+        ctx.time_pass(3)
+        ms = ctx.time_pass(reps)
+    else:
+        iters = max(32, 2 * reps)
+        ctx = Context(X, ybar, Params(precision=precision, tile_rows=int(r), inner_iters=iters, max_outer=1))
+        ctx.run()                                  # captures the iteration graph
+        ms = min(1e3 * ctx.run()[2].seconds / iters for _ in range(2))
+    ctx.close()
+    return ms
+
+
+def tune(X, ybar, precision: int, reps: int = 20, candidates=CANDIDATES, save: bool = True,
+         form: str = "solve") -> int:
+    """Time each candidate tile height on (X, ybar); return and cache the fastest."""
     N, n = int(X.shape[0]), int(X.shape[1])
     rows = ((N + 63) // 64) * 64
     timings = {}
     for r in candidates:
         if r > rows and timings:
             continue
-        ctx = Context(X, ybar, Params(precision=precision, tile_rows=int(r)))
-        ctx.time_pass(3)
-        timings[int(r)] = ctx.time_pass(reps)
-        ctx.close()
-        del ctx
+        timings[int(r)] = _time(X, ybar, precision, r, form, reps)
     best = min(timings, key=timings.get)
     if save:
         cache = load_cache()
-        cache[key(N, n, precision)] = {"tile_rows": best, "pass_ms": timings[best], "N": N,
-                                       "timings_ms": {str(k): v for k, v in sorted(timings.items())}}
+        cache[key(N, n, precision, form)] = {
+            "tile_rows": best, "ms": timings[best], "N": N,
+            "metric": "ms per MAPG iteration" if form == "solve" else "ms per gradient pass",
+            "timings_ms": {str(k): v for k, v in sorted(timings.items())}}
         save_cache(cache)
     return best
 
 
-def tile_rows_for(X, ybar, precision: int, tune_if_missing: bool = True) -> int:
-    """Cached tile height for this (n, precision, N bucket), tuning on (X, ybar) if absent
-    (0, the library's heuristic, when tuning is not allowed)."""
+def tile_rows_for(X, ybar, precision: int, tune_if_missing: bool = True, form: str = "solve") -> int:
+    """Cached tile height for this (form, n, precision, N bucket), tuning on (X, ybar) if
+    absent (0, the library's heuristic, when tuning is not allowed)."""
     N, n = int(X.shape[0]), int(X.shape[1])
-    found = lookup(N, n, precision)
+    found = lookup(N, n, precision, form)
     if found is not None:
         return found
-    return tune(X, ybar, precision) if tune_if_missing else 0
+    return tune(X, ybar, precision, form=form) if tune_if_missing else 0
 
 
 def _main(argv=None) -> int:
@@ -117,18 +139,19 @@ def _main(argv=None) -> int:
     for t in args.targets:
         wl, pn = t.split(":")
         prec = names[pn]
+        form = "batched" if wl == "batched" else "solve"
         probs = synth.batched_workload() if wl == "batched" else [synth.workload(wl)]
         for p in probs:
-            k = key(p.N, p.n, prec)
+            k = key(p.N, p.n, prec, form)
             if k in done or (not args.force and k in load_cache()):
                 continue
             done.add(k)
             X = torch.from_numpy(p.X).cuda()
             yb = torch.from_numpy(p.ybar).cuda()
-            best = tune(X, yb, prec, reps=args.reps)
+            best = tune(X, yb, prec, reps=args.reps, form=form)
             e = load_cache()[k]
-            print("%-28s N=%-6d tile_rows=%-5d pass %.4f ms  (%s)" % (
-                k, p.N, best, e["pass_ms"], " ".join("%s:%.4f" % kv for kv in e["timings_ms"].items())),
+            print("%-36s N=%-6d tile_rows=%-5d %.4f %s  (%s)" % (
+                k, p.N, best, e["ms"], e["metric"], " ".join("%s:%.4f" % kv for kv in e["timings_ms"].items())),
                 flush=True)
             del X, yb
     return 0
