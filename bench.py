@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "constraint-pair updates/s (N(N-1)·iters/s) at KKT<=1e-4, plain vs mixed/batched"
 HBM_PEAK_GBS = 8000.0
+MFMA_F64_PEAK_TFS = 78.6       # MI355X dense FP64 matrix peak
 WORKLOAD = "logsumexp_5000"
 
 
@@ -175,6 +176,32 @@ def diff_rate(cr, K=10, L=20, C=20):
                              "frac": adj_bytes / (adj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
 
+def eval_rate(cr, reps=10):
+    """Estimator evaluation (cr_eval, FP64): the 20000 tangent planes
+    (f0(x_l), grad f0(x_l)) of the maxaffine_20000 workload at 20000 query
+    points q ~ U[-1,1]^20.  Device time from HIP events on the stream the
+    kernels run on; algorithmic work 2(n+1) flops per (query, plane)."""
+    import torch
+    import synth
+    p = synth.workload("maxaffine_20000")
+    Q = torch.from_numpy(synth.query_points(p.N, p.n)).cuda()
+    est = cr.Estimator(torch.from_numpy(p.X).cuda(), torch.from_numpy(p.f0).cuda(), torch.from_numpy(p.grad_f0).cuda())
+    for _ in range(2):
+        est(Q)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        est(Q)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    pairs = float(Q.shape[0]) * p.N
+    tflops = 2.0 * (p.n + 1) * pairs / (ms * 1e-3) / 1e12
+    return {"value": pairs / (ms * 1e-3), "unit": "query-plane evaluations/s", "M": int(Q.shape[0]), "N": p.N,
+            "n": p.n, "ms": ms, "roofline": {"bound": "mfma", "achieved": tflops, "peak": MFMA_F64_PEAK_TFS,
+                                             "unit": "TFLOP/s", "frac": tflops / MFMA_F64_PEAK_TFS}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +278,8 @@ def main():
         v["batched_f32_64_problems"] = batched_rate(cr, autotune)
         torch.cuda.empty_cache()
         v["differentiable_f32_quadratic_10000"] = diff_rate(cr)
+        torch.cuda.empty_cache()
+        v["estimator_eval_f64_20000x20000"] = eval_rate(cr)
         line["variants"] = v
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_budget)

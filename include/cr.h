@@ -319,6 +319,33 @@ cr_status cr_diff_destroy(cr_diff* d);
  * backward clears.  CR_ERR_STATE before a backward; CR_ERR_ARG, CR_ERR_HIP. */
 cr_status cr_diff_time_adjoint_pass(cr_diff* d, int32_t reps, double* avg_ms);
 
+/* Estimator evaluation ---------------------------------------------------- */
+
+/* Sec. I: the least-squares estimator is the piecewise-linear convex function
+ * that takes the value y_l at x_l with subgradient xi_l there; it is evaluated
+ * at a point q as its largest supporting hyperplane,
+ *   fhat(q) = max_l ( y_l + xi_l^T (q - x_l) ),
+ * and the maximising l (the smallest one on exact ties) names a subgradient
+ * xi_l of the estimator at q.  (y, xi) is typically the output of cr_solve;
+ * any values are accepted.
+ *
+ * X (N x n), y (N), xi (N x n) and Q (M x n, the query points): FP64,
+ * row-major, on the device of `stream`; borrowed for the call.  Outputs:
+ * fhat (M doubles) and, unless arg is NULL, arg (M int64, plane indices).
+ * workspace: at least cr_eval_workspace_bytes(N, n) bytes of device memory
+ * (packed plane operands), caller-owned, rewritten by each call.
+ * Asynchronous on `stream` (a hipStream_t; NULL is the default stream).
+ * M = 0 is a no-op.  A query whose plane values are all NaN gets
+ * fhat = -Inf and arg = INT64_MAX.
+ * Errors (checked on the host, before any HIP call): CR_ERR_ARG (NULL
+ * pointers, N < 1, n < 1, M < 0), CR_ERR_UNSUPPORTED (n > CR_MAX_DIM),
+ * CR_ERR_NOMEM (workspace too small); CR_ERR_HIP on a failed launch.
+ * Messages in cr_last_error(NULL). */
+cr_status cr_eval_workspace_bytes(int64_t N, int32_t n, size_t* bytes);
+cr_status cr_eval(const void* X_dev, const void* y_dev, const void* xi_dev, int64_t N, int32_t n,
+                  const void* Q_dev, int64_t M, void* fhat_dev, int64_t* arg_dev, void* workspace_dev,
+                  size_t ws_bytes, void* stream);
+
 /* Inspection and test hooks --------------------------------------------- */
 
 /* Copy the context's theta to / from an N x N FP64 device array (diagonal

@@ -95,6 +95,8 @@ def _load():
         "cr_diff_backward": (i32, [vp, vp, vp, vp, vp, vp, vp]),
         "cr_diff_destroy": (i32, [vp]),
         "cr_diff_time_adjoint_pass": (i32, [vp, i32, ctypes.POINTER(dbl)]),
+        "cr_eval_workspace_bytes": (i32, [i64, i32, ctypes.POINTER(ctypes.c_size_t)]),
+        "cr_eval": (i32, [vp, vp, vp, i64, i32, vp, i64, vp, vp, vp, ctypes.c_size_t, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -109,7 +111,8 @@ EXPORTED = ("cr_params_default", "cr_status_string", "cr_last_error", "cr_worksp
             "cr_destroy", "cr_pairwise_step", "cr_run", "cr_solve", "cr_get_theta", "cr_set_theta",
             "cr_get_start", "cr_get_info", "cr_time_pass", "cr_batch_workspace_bytes", "cr_batch_init",
             "cr_batch_run", "cr_batch_destroy", "cr_solve_batched", "cr_diff_workspace_bytes", "cr_diff_init",
-            "cr_diff_forward", "cr_diff_backward", "cr_diff_destroy", "cr_diff_time_adjoint_pass")
+            "cr_diff_forward", "cr_diff_backward", "cr_diff_destroy", "cr_diff_time_adjoint_pass",
+            "cr_eval_workspace_bytes", "cr_eval")
 
 
 class CRError(RuntimeError):
@@ -480,3 +483,42 @@ def solve_unrolled(X, ybar, params: Params, y0=None, xi0=None, checkpoint_every:
     if xi0 is None:
         xi0 = torch.zeros(X.shape[0], X.shape[1], dtype=torch.float64, device=X.device)
     return _UNROLLED.apply(X, ybar, y0, xi0, params, int(checkpoint_every))
+
+
+def eval_workspace_bytes(N: int, n: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(_lib.cr_eval_workspace_bytes(int(N), int(n), ctypes.byref(out)))
+    return int(out.value)
+
+
+class Estimator:
+    """The fitted estimator (X, y, xi) of Sec. I, evaluated at query points on the
+    device: fhat(q) = max_l (y_l + xi_l^T (q - x_l)) and the maximising plane
+    (``cr_eval``).  Keeps references to its inputs and a workspace tensor."""
+
+    def __init__(self, X, y, xi):
+        torch = _torch()
+        self.N, self.n = int(X.shape[0]), int(X.shape[1])
+        self._X = _dev_f64(X, (self.N, self.n), "X")
+        self._y = _dev_f64(y, (self.N,), "y")
+        self._xi = _dev_f64(xi, (self.N, self.n), "xi")
+        self._keep = (X, y, xi)
+        self._ws = torch.empty(eval_workspace_bytes(self.N, self.n), dtype=torch.uint8, device=X.device)
+
+    def __call__(self, Q, with_arg: bool = True):
+        """(fhat (M,) float64, arg (M,) int64 or None) at the rows of Q (M x n)."""
+        torch = _torch()
+        M = int(Q.shape[0])
+        q = _dev_f64(Q, (M, self.n), "Q")
+        f = torch.empty(M, dtype=torch.float64, device=Q.device)
+        arg = torch.empty(M, dtype=torch.int64, device=Q.device) if with_arg else None
+        _check(_lib.cr_eval(self._X, self._y, self._xi, self.N, self.n, q, M, ctypes.c_void_p(f.data_ptr()),
+                            ctypes.c_void_p(arg.data_ptr()) if arg is not None else None,
+                            ctypes.c_void_p(self._ws.data_ptr()), self._ws.numel(), _stream()))
+        return f, arg
+
+
+def evaluate(X, y, xi, Q, with_arg: bool = True):
+    """One-shot ``Estimator(X, y, xi)(Q)``."""
+    return Estimator(X, y, xi)(Q, with_arg)
+

@@ -1510,3 +1510,8 @@ cr_status cr_diff_time_adjoint_pass(cr_diff* d, int32_t reps, double* avg_ms) {
 }
 
 }  // extern "C"
+
+namespace cr {
+// Message of a failed context-free call in another source file (cr_last_error(NULL)).
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace cr

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string>
 
 namespace cr {
 
@@ -175,6 +176,9 @@ struct PointArgs {
     void* ycol;
     float* cvec;     // mixed precision only
 };
+
+// Message for cr_last_error(NULL) (context-free calls outside cr_api.hip).
+void set_last_error(const std::string& msg);
 
 // prec: 0 FP64, 1 FP32, 2 mixed BF16 (the pass precision of cr.h)
 hipError_t launch_pair_pass(int prec, int n, const PassArgs& a, dim3 grid, hipStream_t s);

@@ -1,0 +1,235 @@
+// Evaluation of the fitted estimator at new points (gfx950).
+//
+// The least-squares estimator of Sec. I (Aybat & Wang) is the piecewise-linear
+// convex function with value y_l at x_l and subgradient xi_l there; at a query
+// point q it is the largest supporting hyperplane,
+//   f(q) = max_l ( y_l + xi_l^T (q - x_l) ) = max_l ( [q 1] . [xi_l  d_l] ),
+//   d_l = y_l - x_l^T xi_l,
+// and the maximising l names a subgradient xi_l of f at q.  For M queries and N
+// planes the values form the M x N product [Q 1] [Xi d]^T, a dense contraction
+// with K = n + 1: FP64 MFMA (16x16x4) tiles, with a running maximum and argmax
+// per query instead of a stored product.
+//
+// Launch: one workgroup per 32 queries (two 16-row blocks); its 4 waves take
+// interleaved 32-plane tiles (two 16-column MFMA tiles) of all N planes, each
+// wave keeping (max, argmax) per query, and the 4 waves' results are combined
+// in LDS.  Ties go to the smaller plane index, so the result does not depend
+// on the traversal order.
+#include "cr_device.h"
+#include "cr_ops.h"
+#include "../../include/cr.h"
+
+#include <cmath>
+#include <string>
+
+namespace cr {
+
+constexpr int kEvalRows = 32;     // queries per workgroup
+constexpr int kEvalCols = 32;     // planes per wave step
+
+// Packed plane operands: row l holds [xi_l (n), d_l, 0 ...] (4 KS doubles);
+// rows l >= N are zero (and masked out by index).
+__global__ __launch_bounds__(kBlock) void k_eval_prep(const double* __restrict__ X, const double* __restrict__ y,
+                                                      const double* __restrict__ xi, int64_t N, int n, int kp,
+                                                      int64_t Npad, double* __restrict__ B) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= Npad * kp) return;
+    const int64_t l = e / kp;
+    const int k = (int)(e % kp);
+    double v = 0.0;
+    if (l < N) {
+        if (k < n) {
+            v = xi[l * n + k];
+        } else if (k == n) {
+            double s = 0.0;
+            for (int q = 0; q < n; ++q) s += X[l * n + q] * xi[l * n + q];
+            v = y[l] - s;
+        }
+    }
+    B[e] = v;
+}
+
+struct EvalArgs {
+    int64_t N, M;
+    int32_t n, kp;
+    int64_t ntiles;           // 32-plane tiles
+    const double* Q;          // M x n
+    const double* B;          // packed planes, ntiles * 32 rows of kp
+    double* f;                // M
+    int64_t* arg;             // M or null
+};
+
+__device__ __forceinline__ void better(double& bv, int64_t& bl, double v, int64_t l) {
+    if (v > bv || (v == bv && l < bl)) { bv = v; bl = l; }
+}
+
+template <int KS>
+__global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int64_t m0 = (int64_t)blockIdx.x * kEvalRows;
+    const int n = a.n, kp = a.kp;
+
+    // A operands of the two query blocks: lane (g, c) holds [q_m 1][4 s + g], m = block + c
+    double A[2][KS];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+        const int64_t m = m0 + 16 * rb + c;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int k = 4 * s + g;
+            double v = 0.0;
+            if (m < a.M) v = k < n ? a.Q[m * n + k] : (k == n ? 1.0 : 0.0);
+            A[rb][s] = v;
+        }
+    }
+
+    // Running (max, argmax) of this lane's 4 accumulator rows (g + 4 v) per block.
+    double bv[2][4];
+    int64_t bl[2][4];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) { bv[rb][v] = -INFINITY; bl[rb][v] = INT64_MAX; }
+
+    // B operands of one 32-plane tile: lane (g, c) holds plane (tile + 16 h + c), slot 4 s + g
+    auto load_b = [&](int64_t t, double (&b)[2][KS]) {
+        const int64_t tt = t < a.ntiles ? t : a.ntiles - 1;     // past the end: any valid tile, masked below
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const double* row = a.B + (tt * kEvalCols + 16 * h + c) * kp + g;
+#pragma unroll
+            for (int s = 0; s < KS; ++s) b[h][s] = row[4 * s];
+        }
+    };
+    double bcur[2][KS], bnext[2][KS];
+    int64_t t = wave;
+    load_b(t, bcur);
+    for (; t < a.ntiles; t += kWaves) {
+        load_b(t + kWaves, bnext);                              // next tile in flight during this one
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t l = t * kEvalCols + 16 * h + c;       // this lane's plane
+            const bool lv = l < a.N;
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) {
+                f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s = 0; s < KS; ++s) acc = mfma4(A[rb][s], bcur[h][s], acc);
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (lv && acc[v] > bv[rb][v]) { bv[rb][v] = acc[v]; bl[rb][v] = l; }   // l increases: ties keep the first
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int s = 0; s < KS; ++s) bcur[h][s] = bnext[h][s];
+    }
+
+    // Combine over the 16 lanes of each row group (different planes), then over the waves.
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) {
+                const double ov = __shfl_xor(bv[rb][v], o);
+                const int64_t ol = __shfl_xor(bl[rb][v], o);
+                better(bv[rb][v], bl[rb][v], ov, ol);
+            }
+    __shared__ double sv[kWaves][kEvalRows];
+    __shared__ int64_t sl[kWaves][kEvalRows];
+    if (c == 0) {
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * rb + g + 4 * v;              // FP64 accumulator row map
+                sv[wave][r] = bv[rb][v];
+                sl[wave][r] = bl[rb][v];
+            }
+    }
+    __syncthreads();
+    if (threadIdx.x < kEvalRows) {
+        const int r = threadIdx.x;
+        double best = sv[0][r];
+        int64_t bi = sl[0][r];
+        for (int w = 1; w < kWaves; ++w) better(best, bi, sv[w][r], sl[w][r]);
+        const int64_t m = m0 + r;
+        if (m < a.M) {
+            a.f[m] = best;
+            if (a.arg) a.arg[m] = bi;
+        }
+    }
+}
+
+static int eval_ks(int n) { return (n + 1 + 3) / 4; }
+static int64_t eval_tiles(int64_t N) { return (N + kEvalCols - 1) / kEvalCols; }
+
+static hipError_t launch_eval(const EvalArgs& a, hipStream_t s) {
+    const dim3 grid((unsigned)((a.M + kEvalRows - 1) / kEvalRows));
+    switch (eval_ks(a.n)) {
+        case 1: hipLaunchKernelGGL(k_eval<1>, grid, dim3(kBlock), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_eval<2>, grid, dim3(kBlock), 0, s, a); break;
+        case 3: hipLaunchKernelGGL(k_eval<3>, grid, dim3(kBlock), 0, s, a); break;
+        case 4: hipLaunchKernelGGL(k_eval<4>, grid, dim3(kBlock), 0, s, a); break;
+        case 5: hipLaunchKernelGGL(k_eval<5>, grid, dim3(kBlock), 0, s, a); break;
+        case 6: hipLaunchKernelGGL(k_eval<6>, grid, dim3(kBlock), 0, s, a); break;
+        case 7: hipLaunchKernelGGL(k_eval<7>, grid, dim3(kBlock), 0, s, a); break;
+        case 8: hipLaunchKernelGGL(k_eval<8>, grid, dim3(kBlock), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace cr
+
+namespace {
+size_t eval_ws_bytes(int64_t N, int n) {
+    return (size_t)(cr::eval_tiles(N) * cr::kEvalCols) * (size_t)(4 * cr::eval_ks(n)) * 8 + 256;
+}
+
+cr_status eval_fail(cr_status s, const std::string& msg) {
+    cr::set_last_error(msg);
+    return s;
+}
+}  // namespace
+
+extern "C" {
+
+cr_status cr_eval_workspace_bytes(int64_t N, int32_t n, size_t* bytes) {
+    if (!bytes) return eval_fail(CR_ERR_ARG, "bytes is NULL");
+    if (N < 1 || n < 1) return eval_fail(CR_ERR_ARG, "N and n must be >= 1");
+    if (n > CR_MAX_DIM) return eval_fail(CR_ERR_UNSUPPORTED, "n above CR_MAX_DIM is not supported");
+    *bytes = eval_ws_bytes(N, n);
+    return CR_OK;
+}
+
+cr_status cr_eval(const void* X_dev, const void* y_dev, const void* xi_dev, int64_t N, int32_t n, const void* Q_dev,
+                  int64_t M, void* fhat_dev, int64_t* arg_dev, void* workspace_dev, size_t ws_bytes, void* stream) {
+    if (N < 1 || n < 1 || M < 0) return eval_fail(CR_ERR_ARG, "N and n must be >= 1 and M >= 0");
+    if (n > CR_MAX_DIM) return eval_fail(CR_ERR_UNSUPPORTED, "n above CR_MAX_DIM is not supported");
+    if (!X_dev || !y_dev || !xi_dev || !workspace_dev || (M > 0 && (!Q_dev || !fhat_dev)))
+        return eval_fail(CR_ERR_ARG, "X, y, xi, Q, fhat and the workspace must be non-NULL");
+    if (ws_bytes < eval_ws_bytes(N, n)) return eval_fail(CR_ERR_NOMEM, "workspace smaller than cr_eval_workspace_bytes()");
+    if (M == 0) return CR_OK;
+    hipStream_t s = (hipStream_t)stream;
+    double* B = reinterpret_cast<double*>(((uintptr_t)workspace_dev + 255) & ~(uintptr_t)255);
+    const int kp = 4 * cr::eval_ks(n);
+    const int64_t ntiles = cr::eval_tiles(N);
+    const int64_t Npad = ntiles * cr::kEvalCols;
+    const int64_t elems = Npad * kp;
+    hipLaunchKernelGGL(cr::k_eval_prep, dim3((unsigned)((elems + cr::kBlock - 1) / cr::kBlock)), dim3(cr::kBlock), 0, s,
+                       (const double*)X_dev, (const double*)y_dev, (const double*)xi_dev, N, (int)n, kp, Npad, B);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return eval_fail(CR_ERR_HIP, std::string("eval prep: ") + hipGetErrorString(e));
+    cr::EvalArgs a{};
+    a.N = N; a.M = M; a.n = n; a.kp = kp; a.ntiles = ntiles;
+    a.Q = (const double*)Q_dev; a.B = B; a.f = (double*)fhat_dev; a.arg = arg_dev;
+    e = cr::launch_eval(a, s);
+    if (e != hipSuccess) return eval_fail(CR_ERR_HIP, std::string("eval: ") + hipGetErrorString(e));
+    return CR_OK;
+}
+
+}  // extern "C"

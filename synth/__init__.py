@@ -149,3 +149,9 @@ def batched_workload(P: int = 64, n_min: int = 500, n_max: int = 8000,
 def weights(N: int, seed: int = 1) -> np.ndarray:
     """Random output weights w ~ N(0,1)^N for the scalar sum_l w_l y_l."""
     return np.random.default_rng(seed).normal(0.0, 1.0, size=N)
+
+
+def query_points(M: int, n: int, seed: int = 2, low: float = -1.0, high: float = 1.0) -> np.ndarray:
+    """Points at which a fitted estimator is evaluated: q ~ U[low, high]^n (the
+    distribution of the uniform workloads' x)."""
+    return np.random.default_rng(seed).uniform(low, high, size=(M, n))

@@ -158,3 +158,27 @@ def test_diff_workspace_and_argument_checks():
     with pytest.raises(cr.CRError) as e:
         cr.diff_workspace_bytes(2000, 10, cr.Params(precision=cr.MIXED_BF16, inner_iters=5), 20)
     assert e.value.status == 7
+
+
+def test_eval_workspace_and_argument_checks():
+    """cr_eval_workspace_bytes / cr_eval: host-side checks (no device pointer is
+    touched when an argument is rejected)."""
+    import ctypes
+    import paper_1407_7220_amd as cr
+    b = cr.eval_workspace_bytes(1000, 20)
+    assert b >= 1024 * 24 * 8                      # 32-plane tiles of [xi d 0..] rows, 4 ceil((n+1)/4) slots
+    assert b < 1024 * 24 * 8 + 4096
+    for N, n, status in ((0, 3, 1), (10, 0, 1), (10, 32, 7)):
+        with pytest.raises(cr.CRError) as e:
+            cr.eval_workspace_bytes(N, n)
+        assert e.value.status == status
+    fake = ctypes.c_void_p(0x1000)
+    lib = cr._lib
+    # NULL operands, negative M, too small a workspace: rejected before any launch
+    assert lib.cr_eval(None, fake, fake, 10, 3, fake, 5, fake, None, fake, 1 << 20, None) == 1
+    assert lib.cr_eval(fake, fake, fake, 10, 3, fake, -1, fake, None, fake, 1 << 20, None) == 1
+    assert lib.cr_eval(fake, fake, fake, 10, 3, fake, 5, fake, None, fake, 16, None) == 2
+    assert b"workspace" in lib.cr_last_error(None)
+    assert lib.cr_eval(fake, fake, fake, 10, 40, fake, 5, fake, None, fake, 1 << 20, None) == 7
+    # M = 0 is a no-op (nothing launched)
+    assert lib.cr_eval(fake, fake, fake, 10, 3, None, 0, None, None, fake, 1 << 20, None) == 0
