@@ -283,6 +283,38 @@ def test_full_size_pass_sampled(cr, prec):
         assert np.max(np.abs((hxi[m] - gamma / mu * xi[m]) - (-v))) <= tol * scale * (1 + np.abs(p.X).max())
 
 
+_FULL_REF = {}
+
+
+def _full_size_reference():
+    # the oracle's 2 x 33 run on the 5000-point workload, shared by both precisions
+    if "ref" not in _FULL_REF:
+        p = synth.workload("logsumexp_5000")
+        _FULL_REF["ref"] = oracle.alcc(p.X, p.ybar, oracle.Params(inner_iters=33, max_outer=2), record_kkt=False)
+    return _FULL_REF["ref"]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+def test_full_size_fixed_schedule_benchmark_launch(cr, prec):
+    """The 5000-point workload through whole MAPG runs in the benchmark's launch
+    configuration (the tuned chunk height: lazy passes, two kernels per
+    iteration), 2 ALCC iterations of 33 MAPG steps (an odd run length, so the
+    last iterate sits in the second parity buffer), against the oracle."""
+    from paper_1407_7220_amd import autotune
+    p = synth.workload("logsumexp_5000")
+    X, yb = dev(p.X), dev(p.ybar)
+    tile = autotune.tile_rows_for(X, yb, prec, tune_if_missing=False)
+    say("full-size fixed schedule logsumexp_5000 %s tile_rows %d, 2 x 33" % (PREC_NAME[prec], tile))
+    sched = dict(inner_iters=33, max_outer=2)
+    y, xi, info = cr.solve(X, yb, cr.Params(precision=prec, tile_rows=tile, **sched))
+    assert info.inner_iters == 66 and info.outer_iters == 2
+    ref = _full_size_reference()
+    ey, exi = rel(host(y), ref.y), rel(host(xi), ref.xi)
+    say("  relative error vs FP64 oracle: y %.3e  xi %.3e" % (ey, exi))
+    assert ey < {0: 1e-9, 1: 2e-5}[prec]
+    assert exi < {0: 1e-8, 1: 2e-4}[prec]
+
+
 # --------------------------------------------------------------------------
 # Batched form
 # --------------------------------------------------------------------------
