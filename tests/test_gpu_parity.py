@@ -283,6 +283,37 @@ def test_full_size_pass_sampled(cr, prec):
         assert np.max(np.abs((hxi[m] - gamma / mu * xi[m]) - (-v))) <= tol * scale * (1 + np.abs(p.X).max())
 
 
+@pytest.mark.parametrize("prec,N", [(1, 131072), (0, 65536)], ids=["f32-131072", "f64-65536"])
+def test_large_n_pass_sampled(cr, prec, N):
+    """One gradient pass far beyond the benchmark sizes (theta of 64 GiB in FP32,
+    32 GiB in FP64, as the context allocates it): the 32-bit buffer offsets of
+    the pass and the partial sums at their largest here.  theta = 0 after set-up,
+    so w = (r)_-; sampled rows and columns recomputed by the oracle."""
+    n = 3
+    say("large-N pass %s N=%d n=%d" % (PREC_NAME[prec], N, n))
+    rng = np.random.default_rng(21)
+    X = rng.uniform(-1, 1, size=(N, n))
+    ybar = np.sum(X * X, axis=1)
+    y = ybar + 0.05 * rng.normal(size=N)
+    xi = 2.0 * X + 0.1 * rng.normal(size=(N, n))
+    gamma, mu = 1e-3, 1e-4
+    ctx = cr.Context(dev(X), dev(ybar), cr.Params(gamma=gamma, precision=prec))
+    gy, gxi = ctx.pairwise_step(cr.GRAD, dev(y), dev(xi), mu)
+    hy, hxi = host(gy), host(gxi)
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    tol = {0: 1e-11, 1: 3e-4}[prec]
+    for m in [0, 1, 4095, 4096, N // 2 + 7, N - 65, N - 1]:
+        row, col = oracle.residual_row_col(X, y, xi, m)
+        wrow = np.maximum(-row, 0.0); wrow[m] = 0.0
+        wcol = np.maximum(-col, 0.0); wcol[m] = 0.0
+        u, v = oracle.adjoint_one(X, m, wrow, wcol)
+        scale = wrow.sum() + wcol.sum() + 1.0
+        assert abs((hy[m] - (y[m] - ybar[m]) / mu) - (-u)) <= tol * scale, m
+        assert np.max(np.abs((hxi[m] - gamma / mu * xi[m]) - (-v))) <= tol * scale * 2, m
+
+
 _FULL_REF = {}
 
 
