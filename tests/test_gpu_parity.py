@@ -236,6 +236,35 @@ def test_fixed_schedule_ragged(cr, N, n, seed):
     assert rel(host(xi), ref.xi) < 1e-8
 
 
+def test_nonfinite_inputs_rejected(cr):
+    say("non-finite X / ybar at set-up: CR_ERR_NONFINITE")
+    p = synth.quad_l1_gaussian(50, 3, seed=30)
+    yb = p.ybar.copy(); yb[17] = np.nan
+    with pytest.raises(cr.CRError) as e:
+        cr.Context(dev(p.X), dev(yb), cr.Params(precision=1))
+    assert e.value.status == 4
+    X = p.X.copy(); X[3, 1] = np.inf
+    with pytest.raises(cr.CRError) as e:
+        cr.solve(dev(X), dev(p.ybar), cr.Params(precision=0, inner_iters=5, max_outer=1))
+    assert e.value.status == 4
+
+
+@pytest.mark.parametrize("N,n,prec", [(2, 1, 0), (2, 3, 1), (5, 10, 0), (40, 31, 0), (40, 31, 1)],
+                         ids=["N2n1-f64", "N2n3-f32", "N5n10-f64", "N40n31-f64", "N40n31-f32"])
+def test_degenerate_and_widest_shapes(cr, N, n, prec):
+    # two points (two constraints), fewer points than dimensions (the
+    # minimum-norm affine start of R16), and the widest supported n
+    say("fixed schedule N=%d n=%d %s" % (N, n, PREC_NAME[prec]))
+    p = synth.quad_l1_gaussian(N, n, seed=31 + N + n)
+    sched = dict(inner_iters=30, max_outer=3)
+    ref = oracle.alcc(p.X, p.ybar, oracle.Params(**sched), record_kkt=False)
+    y, xi, info = cr.solve(dev(p.X), dev(p.ybar), cr.Params(precision=prec, **sched))
+    ey, exi = rel(host(y), ref.y), rel(host(xi), ref.xi)
+    say("  y %.2e xi %.2e" % (ey, exi))
+    assert ey < TOL_SOLVE[prec]
+    assert exi < TOL_SOLVE[prec] * 10
+
+
 def test_constant_data_fixed_point(cr):
     say("constant data N=50 n=3")
     p = synth.constant_data(50, 3, value=1.5)
