@@ -360,12 +360,17 @@ cr_status cr_get_start(cr_ctx* ctx, void* y_dev, void* xi_dev);
  * pass or a run, the KKT scalars of the last multiplier step. */
 cr_status cr_get_info(cr_ctx* ctx, cr_info* info);
 
-/* Host-synchronous: average device time in milliseconds of one pair pass
- * (mode as in cr_pairwise_step) at the context's current MAPG point, launched
- * reps times back to back on the context's internal stream with the launch
- * configuration that cr_run uses, bracketed by HIP events.  Only CR_GRAD is
- * accepted (it leaves theta unchanged).  Errors: CR_ERR_ARG (NULL, reps < 1,
- * mode other than CR_GRAD), CR_ERR_HIP. */
+/* Host-synchronous: average device time in milliseconds of the gradient pair
+ * pass that cr_run launches, run reps times back to back on the context's
+ * internal stream with cr_run's launch configuration, bracketed by HIP events.
+ * When cr_run completes each MAPG step inside the next pass (chunk heights
+ * whose LDS allows it), the timed kernel is that form at MAPG iteration 2: the
+ * call first restarts MAPG at the ALCC starting point and takes one step
+ * there (pass and reduction) to give it inputs, so the context's MAPG state
+ * is overwritten; otherwise the plain pass at the current operands is timed.
+ * theta is unchanged either way; a later cr_run starts afresh.  Only CR_GRAD
+ * is accepted.  Errors: CR_ERR_ARG (NULL, reps < 1, mode other than CR_GRAD),
+ * CR_ERR_HIP. */
 cr_status cr_time_pass(cr_ctx* ctx, int32_t mode, int32_t reps, double* avg_ms);
 
 #ifdef __cplusplus
