@@ -333,34 +333,83 @@ __global__ __launch_bounds__(kBlock) void k_adj_reduce(AdjReduceArgs a) {
     const T* rowvpart = (const T*)a.rowvpart;
     const T* cpart = (const T*)a.cpart;
     const T* cwpart = (const T*)a.cwpart;
+    // Partial sums through buffer views based at the wave's first point, in
+    // batches whose loads are all issued before any sum (entries past the
+    // last strip or chunk read as zeros):
+    //   rowpart [strip][i]      lane k: strips k, k + G, ...       (in order)
+    //   rowvpart[strip][i][k]   lane k < n: every strip, four sums (strip q into sum q % 4)
+    //   cpart   [chunk][j][k]   lane k < n + 1: every chunk        (in order)
+    //   cwpart  [chunk][j]      lane n: every chunk                (in order)
+    constexpr int URS = 8, URV = 32, UCK = 16;
+    const int p = (threadIdx.x & 63) / G;
+    const int64_t m0 = __builtin_amdgcn_readfirstlane((int)(m - p));   // the same in every lane of the wave
+    const uint32_t esz = (uint32_t)sizeof(T);
+    auto view = [&](const T* base, uint64_t bytes) {
+        return make_rsrc(base, (uint32_t)min(bytes, (uint64_t)0xffffffffu));
+    };
+    // this lane's own values (clamped addresses; used only by lanes that own them)
+    const int64_t mc = valid ? m : a.N - 1;
+    const int64_t ec = mc * n + min(k, n - 1);
+    const bool own_y = k == n;
+    const double o_vb = a.mode == 0 ? (own_y ? a.vb_y[mc] : a.vb_xi[ec]) : 0.0;
+    const double o_acc = own_y ? (a.mode == 0 ? a.dybar[mc] : a.out_y[mc]) : a.dX[ec];
+    const double o_out = a.mode == 0 ? 0.0 : (own_y ? 0.0 : a.out_xi[ec]);
+    const double o_x = a.X[ec], o_xi = a.xi[ec];
     double rs = 0.0, rv = 0.0, ck = 0.0, cw = 0.0;
-    if (valid) {
-#pragma unroll 4
-        for (int q = k; q < a.strips; q += G) rs += (double)rowpart[(int64_t)q * a.Nrow + m];
-        if (k < n) {
-            // every strip's partial of component k: four independent sums (fixed
-            // order) so that the loads overlap
-            const T* rp = rowvpart + (int64_t)m * n + k;
-            const int64_t stride = a.Nrow * n;
-            double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
-            int q = 0;
-            for (; q + 4 <= a.strips; q += 4) {
-                r0 += (double)rp[(int64_t)q * stride];
-                r1 += (double)rp[(int64_t)(q + 1) * stride];
-                r2 += (double)rp[(int64_t)(q + 2) * stride];
-                r3 += (double)rp[(int64_t)(q + 3) * stride];
+    {
+        const uint32_t vo = ((uint32_t)k * (uint32_t)a.Nrow + (uint32_t)p) * esz;
+        const uint32_t so = (uint32_t)G * (uint32_t)a.Nrow * esz;
+        for (int s0 = 0; s0 < a.strips; s0 += G * URS) {
+            const rsrc_t r = view(rowpart + (int64_t)s0 * a.Nrow + m0, (uint64_t)(a.strips - s0) * a.Nrow * esz);
+            T u[URS];
+#pragma unroll
+            for (int e = 0; e < URS; ++e) u[e] = bld_t<T>(r, vo, (uint32_t)e * so);
+#pragma unroll
+            for (int e = 0; e < URS; ++e) rs += (double)u[e];
+        }
+    }
+    {
+        const uint32_t vo = ((uint32_t)p * (uint32_t)n + (uint32_t)k) * esz;
+        const uint32_t so = (uint32_t)a.Nrow * (uint32_t)n * esz;
+        double r4[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int q0 = 0; q0 < a.strips; q0 += URV) {
+            // four views of 8 strips each keep the scalar offsets below 2^31
+            T u[URV];
+#pragma unroll
+            for (int sv = 0; sv < URV / 8; ++sv) {
+                const int qs = q0 + 8 * sv;
+                const rsrc_t r = view(rowvpart + ((int64_t)qs * a.Nrow + m0) * n,
+                                      qs < a.strips ? (uint64_t)(a.strips - qs) * a.Nrow * n * esz : 0);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) u[8 * sv + e] = bld_t<T>(r, vo, (uint32_t)e * so);
             }
-            for (; q < a.strips; ++q) r0 += (double)rp[(int64_t)q * stride];
-            rv = (r0 + r1) + (r2 + r3);
+#pragma unroll
+            for (int e = 0; e < URV; ++e) r4[e & 3] += (double)u[e];
         }
-        if (k < nc) {
-#pragma unroll 4
-            for (int h = 0; h < a.chunks; ++h) ck += (double)cpart[((int64_t)h * a.ld + m) * nc + k];
+        rv = k < n ? (r4[0] + r4[1]) + (r4[2] + r4[3]) : 0.0;
+    }
+    {
+        const uint32_t vo = ((uint32_t)p * (uint32_t)nc + (uint32_t)k) * esz;
+        const uint32_t so = (uint32_t)(a.ld * nc) * esz;
+        const uint32_t wvo = (uint32_t)p * esz, wso = (uint32_t)a.ld * esz;
+        for (int h0 = 0; h0 < a.chunks; h0 += UCK) {
+            const rsrc_t r = view(cpart + ((int64_t)h0 * a.ld + m0) * nc, (uint64_t)(a.chunks - h0) * a.ld * nc * esz);
+            T u[UCK], w[UCK];
+#pragma unroll
+            for (int e = 0; e < UCK; ++e) u[e] = bld_t<T>(r, vo, (uint32_t)e * so);
+            if (a.mode == 0) {
+                const rsrc_t rw = view(cwpart + (int64_t)h0 * a.ld + m0, (uint64_t)(a.chunks - h0) * a.ld * esz);
+#pragma unroll
+                for (int e = 0; e < UCK; ++e) w[e] = bld_t<T>(rw, wvo, (uint32_t)e * wso);
+            } else {
+#pragma unroll
+                for (int e = 0; e < UCK; ++e) w[e] = (T)0;
+            }
+#pragma unroll
+            for (int e = 0; e < UCK; ++e) { ck += (double)u[e]; cw += (double)w[e]; }
         }
-        if (a.mode == 0 && k == n) {
-#pragma unroll 4
-            for (int h = 0; h < a.chunks; ++h) cw += (double)cwpart[(int64_t)h * a.ld + m];
-        }
+        if (k >= nc) ck = 0.0;
+        if (k != n) cw = 0.0;
     }
     rs = adj_group_sum<G>(rs);
     const int base = (threadIdx.x & 63) & ~(G - 1);
@@ -369,24 +418,24 @@ __global__ __launch_bounds__(kBlock) void k_adj_reduce(AdjReduceArgs a) {
     if (!valid) return;
     if (k == n) {
         if (a.mode == 0) {
-            const double vb = a.vb_y[m];
+            const double vb = o_vb;
             const double at = a.sy * vb;
             a.out_y[m] = vb - at / a.mu - (rs - czn);
-            a.dybar[m] += at / a.mu;
+            a.dybar[m] = o_acc + at / a.mu;
         } else {
-            a.out_y[m] += -(rs - czn);
+            a.out_y[m] = o_acc + -(rs - czn);
         }
     } else if (k < n) {
         const int64_t e = m * n + k;
-        const double xmk = a.X[e];
+        const double xmk = o_x;
         if (a.mode == 0) {
-            const double vb = a.vb_xi[e];
+            const double vb = o_vb;
             const double bt = a.sxi * vb;
             a.out_xi[e] = vb - a.gamma * bt / a.mu + ck - czn * xmk;
-            a.dX[e] += rv - czn * a.xi[e] + cwn * bt;
+            a.dX[e] = o_acc + (rv - czn * o_xi + cwn * bt);
         } else {
-            a.out_xi[e] += ck - czn * xmk;
-            a.dX[e] += rv - czn * a.xi[e];
+            a.out_xi[e] = o_out + (ck - czn * xmk);
+            a.dX[e] = o_acc + (rv - czn * o_xi);
         }
     }
 }
