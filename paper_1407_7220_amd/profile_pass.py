@@ -9,7 +9,9 @@ for scaling hardware byte counters.  Run it under rocprofv3, e.g.
 --kernel pass     gradient pair passes (k_pair_pass) with the tile height the
                   autotuner cached for the workload (the benchmark's launch);
 --kernel adjoint  adjoint pair passes of a MAPG step (k_adj_pass) after one
-                  forward and reverse run of 2 x 2 unrolled iterations.
+                  forward and reverse run of 2 x 2 unrolled iterations;
+--kernel eval     estimator evaluations (k_eval) of the workload's tangent planes
+                  (f0(x_l), grad f0(x_l)) at N query points q ~ U[-1,1]^n.
 """
 import argparse
 import os
@@ -22,7 +24,7 @@ if ROOT not in sys.path:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--kernel", choices=("pass", "adjoint"), default="pass")
+    ap.add_argument("--kernel", choices=("pass", "adjoint", "eval"), default="pass")
     ap.add_argument("--workload", default=None)
     ap.add_argument("--precision", choices=("f32", "f64", "mixed_bf16"), default="f32")
     ap.add_argument("--reps", type=int, default=20)
@@ -31,8 +33,23 @@ def main():
     import paper_1407_7220_amd as cr
     from paper_1407_7220_amd import autotune
     import synth
-    workload = args.workload or ("logsumexp_5000" if args.kernel == "pass" else "quadratic_10000")
+    workload = args.workload or {"pass": "logsumexp_5000", "adjoint": "quadratic_10000",
+                                 "eval": "maxaffine_20000"}[args.kernel]
     p = synth.workload(workload)
+    if args.kernel == "eval":
+        Q = torch.from_numpy(synth.query_points(p.N, p.n)).cuda()
+        est = cr.Estimator(torch.from_numpy(p.X).cuda(), torch.from_numpy(p.f0).cuda(),
+                           torch.from_numpy(p.grad_f0).cuda())
+        est(Q)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.reps):
+            est(Q)
+        e1.record()
+        torch.cuda.synchronize()
+        print("workload %s N=%d n=%d queries %d: %d evaluations, avg %.3f us"
+              % (workload, p.N, p.n, Q.shape[0], args.reps, e0.elapsed_time(e1) / args.reps * 1e3), flush=True)
+        return
     prec = {"f32": cr.F32, "f64": cr.F64, "mixed_bf16": cr.MIXED_BF16}[args.precision]
     X = torch.from_numpy(p.X).cuda()
     yb = torch.from_numpy(p.ybar).cuda()
