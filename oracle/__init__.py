@@ -182,25 +182,32 @@ def affine_fit(X, ybar, gamma: float):
 # ALCC subproblem P_k (eq. "subproblem") and its gradient
 # ---------------------------------------------------------------------------
 
-def penalty_weights(X, y, xi, theta):
-    """w = (A1 y + A2 xi - theta)_- for every pair, diagonal 0."""
-    R = forward(X, y, xi)
+def _shifted(xi, shift):
+    """The slopes that enter the constraints: xi itself, or xi + shift when the
+    problem is posed in shifted coordinates (see `alcc`)."""
+    return xi if shift is None else xi + shift
+
+
+def penalty_weights(X, y, xi, theta, shift=None):
+    """w = (A1 y + A2 (xi + shift) - theta)_- for every pair, diagonal 0."""
+    R = forward(X, y, _shifted(xi, shift))
     W = neg_part(R - theta)
     np.fill_diagonal(W, 0.0)
     return W
 
 
-def grad_P(X, ybar, gamma, mu, theta, y, xi):
+def grad_P(X, ybar, gamma, mu, theta, y, xi, shift=None):
     """(grad_y P_k, grad_xi P_k) at (y, xi):
     grad_y  = (y - ybar)/mu      - A1^T (A1 y + A2 xi - theta)_-
-    grad_xi = (gamma/mu) xi      - A2^T (A1 y + A2 xi - theta)_-"""
-    W = penalty_weights(X, y, xi, theta)
+    grad_xi = (gamma/mu) xi      - A2^T (A1 y + A2 xi - theta)_-
+    (with xi + shift in the constraints when a shift is given)."""
+    W = penalty_weights(X, y, xi, theta, shift)
     u, v = adjoint(X, W)
     return (y - ybar) / mu - u, (gamma / mu) * xi - v
 
 
-def P_value(X, ybar, gamma, mu, theta, y, xi) -> float:
-    W = penalty_weights(X, y, xi, theta)
+def P_value(X, ybar, gamma, mu, theta, y, xi, shift=None) -> float:
+    W = penalty_weights(X, y, xi, theta, shift)
     return (0.5 / mu) * float(np.sum((y - ybar) ** 2)) + (0.5 * gamma / mu) * float(np.sum(xi ** 2)) \
         + 0.5 * float(np.sum(W * W))
 
@@ -252,7 +259,7 @@ def resolve(params: Params, N: int, Bbar: float, gamma: float):
 # ---------------------------------------------------------------------------
 
 def mapg(X, ybar, gamma, mu, theta, Ly, Lxi, y0, xi0, By, Bxi, alpha_y, alpha_xi,
-         lmax, step_scale=0.5, adaptive=True, trace=None):
+         lmax, step_scale=0.5, adaptive=True, trace=None, shift=None):
     """Modified accelerated projected gradient on P_k over Q_y x Q_xi.
 
     Iteration 0: y1_0 = y2_1 = y0, same for xi, t_1 = 1.  Iteration l:
@@ -267,7 +274,7 @@ def mapg(X, ybar, gamma, mu, theta, Ly, Lxi, y0, xi0, By, Bxi, alpha_y, alpha_xi
     t = 1.0
     zero = np.zeros_like(xi0)
     for l in range(1, lmax + 1):
-        gy, gxi = grad_P(X, ybar, gamma, mu, theta, y2, xi2)
+        gy, gxi = grad_P(X, ybar, gamma, mu, theta, y2, xi2, shift)
         y1 = project_ball(y2 - (step_scale / Ly) * gy, ybar, By)
         xi1 = project_ball(xi2 - (step_scale / Lxi) * gxi, zero, Bxi)
         t_next = (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0
@@ -285,7 +292,7 @@ def mapg(X, ybar, gamma, mu, theta, Ly, Lxi, y0, xi0, By, Bxi, alpha_y, alpha_xi
     return y1_prev, xi1_prev, lmax
 
 
-def kkt_measures(X, ybar, gamma, y, xi, lam):
+def kkt_measures(X, ybar, gamma, y, xi, lam, shift=None):
     """First-order optimality residuals of eq. "regularize" at (y, xi) with a
     multiplier estimate lam >= 0 (one entry per pair):
       stationarity  y - ybar - A1^T lam,  gamma xi - A2^T lam   (inf-norms)
@@ -295,7 +302,7 @@ def kkt_measures(X, ybar, gamma, y, xi, lam):
     Also the paper's normalized infeasibility ||(r)_-||_2 / sqrt(N^2-N) and
     normalized gap lam^T r / (N^2-N) (Sec. III)."""
     N = X.shape[0]
-    R = forward(X, y, xi)
+    R = forward(X, y, _shifted(xi, shift))
     u, v = adjoint(X, lam)
     st_y = float(np.max(np.abs(y - ybar - u)))
     st_xi = float(np.max(np.abs(gamma * xi - v)))
@@ -326,7 +333,7 @@ class Result:
 
 
 def alcc(X, ybar, params: Optional[Params] = None, y0=None, xi0=None,
-         record_kkt: bool = True) -> Result:
+         record_kkt: bool = True, xi_shift=None) -> Result:
     """ALCC (Fig. 3) on eq. "regularize", MAPG (Fig. 4) as the inner solver.
 
     Outer iteration k:
@@ -339,12 +346,27 @@ def alcc(X, ybar, params: Optional[Params] = None, y0=None, xi0=None,
       6. alpha_{k+1} = alpha_k/(c k^{1+kappa})^2 (both blocks)
     theta_1 = 0.  The multiplier estimate after step 4 is mu_{k+1} theta_{k+1};
     the run stops after the first outer iteration whose KKT measure is within
-    params.kkt_tol (adaptive schedule only) or after params.max_outer."""
+    params.kkt_tol (adaptive schedule only) or after params.max_outer.
+
+    xi_shift (N x n, optional) poses the problem in shifted slopes: with
+    xi = xi' + shift the run solves
+      min 1/2||y - ybar||^2 + gamma/2||xi'||^2  s.t.  A1 y + A2 (xi' + shift) >= 0,
+    i.e. eq. "regularize" with the slope term gamma/2||xi - shift||^2, the form
+    of each block subproblem of P-APG step 1 (Fig. 2, eq. "g_gamma").  The run
+    returns xi'.  The affine fit stays the start; in shifted slopes it is
+    (yhat, a - shift), feasible for the shifted constraints, and Bbar is the
+    objective there: Bbar^2 = ||yhat - ybar||^2 + gamma ||a - shift||^2."""
     p = params or Params()
     X, ybar = _f64(X), _f64(ybar)
     N, n = X.shape
     gamma = p.gamma
     yhat, xihat, Bbar, By, Bxi = affine_fit(X, ybar, gamma)
+    shift = None
+    if xi_shift is not None:
+        shift = _f64(xi_shift).reshape(N, n)
+        xihat = xihat - shift
+        Bbar = math.sqrt(float(np.sum((yhat - ybar) ** 2)) + gamma * float(np.sum(xihat ** 2)))
+        By, Bxi = Bbar, Bbar / math.sqrt(gamma)
     if p.By_override > 0:
         By = p.By_override
     if p.Bxi_override > 0:
@@ -369,15 +391,15 @@ def alcc(X, ybar, params: Optional[Params] = None, y0=None, xi0=None,
             lmax = int(math.ceil(4.0 * math.sqrt((Ly * By ** 2 + Lxi * Bxi ** 2) / tau)))
             lmax = max(1, min(lmax, p.max_inner))
         y, xi, used = mapg(X, ybar, gamma, mu, theta, Ly, Lxi, y, xi, By, Bxi, ay, axi,
-                           lmax, p.step_scale, adaptive=not fixed)
+                           lmax, p.step_scale, adaptive=not fixed, shift=shift)
         inner_list.append(used)
         mu_next = p.c * mu
-        R = forward(X, y, xi)
+        R = forward(X, y, _shifted(xi, shift))
         Wk = neg_part(R - theta)
         np.fill_diagonal(Wk, 0.0)
         theta = (mu / mu_next) * Wk
         if record_kkt:
-            m = kkt_measures(X, ybar, gamma, y, xi, mu_next * theta)
+            m = kkt_measures(X, ybar, gamma, y, xi, mu_next * theta, shift)
             m.update(k=k, inner=used, mu=mu)
             hist.append(m)
             if not fixed and m["kkt"] <= p.kkt_tol:
