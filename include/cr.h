@@ -319,6 +319,67 @@ cr_status cr_diff_destroy(cr_diff* d);
  * backward clears.  CR_ERR_STATE before a backward; CR_ERR_ARG, CR_ERR_HIP. */
 cr_status cr_diff_time_adjoint_pass(cr_diff* d, int32_t reps, double* avg_ms);
 
+/* P-APG on the partial dual ------------------------------------------------ */
+
+/*
+ * P-APG (Sec. II-B to II-D, Fig. 2).  The N points split into K index sets
+ * C_i of Nbar = N / K consecutive points (Sec. II-B); the constraints of
+ * pairs in different sets, and y >= 0, are dualised (C = [A3 A4; I 0],
+ * eq. "C"), and the dual eq. "lambda_dual" is maximised over
+ * Q2 = {theta >= 0, ||theta||_2 <= B_theta} with accelerated projected
+ * gradient steps.  Iteration l (theta^(1)_0 = theta^(2)_1 = 0, t_1 = 1):
+ *   1. eta_l = (y, xi) minimising the Lagrangian of eq. "g_gamma" at
+ *      theta^(2)_l over the within-block constraints: K independent problems,
+ *      block i being eq. "regularize" on its points with data
+ *      ybar_i + y_shift + (A3^T theta + theta_y)_i and the slope term
+ *      gamma/2 ||xi_i - (A4^T theta)_i / gamma||^2, solved together by the
+ *      batched ALCC (cr_solve_batched's machinery) with `alcc`'s schedule,
+ *      each from its affine fit with zero within-block multipliers;
+ *   2. theta^(1)_l = Pi_Q2(theta^(2)_l - C eta_l / L);
+ *   3-4. t_{l+1} = (1 + sqrt(1 + 4 t_l^2))/2 and
+ *      theta^(2)_{l+1} = theta^(1)_l + (t_l - 1)/t_{l+1} (theta^(1)_l - theta^(1)_{l-1}).
+ * Outputs: eta of the last step 1 (y shifted back by y_shift) and, when the
+ * pointers are not NULL, theta^(1) of the last iteration: theta_dev N x N
+ * row-major FP64 (entry (i, j) for the pair (i, j); zero inside the diagonal
+ * blocks), theta_y_dev N.
+ */
+typedef struct {
+    int32_t K;          /* number of index sets; N % K == 0 and N / K >= 2 */
+    int32_t iters;      /* P-APG iterations, >= 1 */
+    double L;           /* step constant (L_g of eq. "lischitz" or above); <= 0:
+                           (2N + sigma_max(A2)^2 + 1) / gamma, a bound of L_g */
+    double B_theta;     /* radius of Q2; <= 0 or +Inf: the nonnegative orthant */
+    double y_shift;     /* added to ybar so that y >= 0 holds at the solution
+                           (Sec. II-D) and subtracted from y on output;
+                           < 0: max(0, max(ybar) - 2 min(ybar)) */
+} cr_papg_params;
+
+typedef struct {
+    double L, y_shift;          /* the constants used */
+    double theta_norm;          /* ||theta^(1)|| of the last iteration */
+    double infeas_cross;        /* ||(A3 y + A4 xi)_-||_2 of the last eta */
+    int64_t inner_iters;        /* MAPG iterations, summed over blocks and P-APG iterations */
+    double seconds;
+} cr_papg_info;
+
+/* Bytes of device workspace for cr_papg: two N x N FP64 multiplier arrays, the
+ * block data and outputs, and the batched ALCC's workspace for K problems of
+ * Nbar points.  Errors: CR_ERR_ARG (NULL, bad params, N % K != 0,
+ * N / K < 2, iters < 1), CR_ERR_UNSUPPORTED (as cr_batch_workspace_bytes). */
+cr_status cr_papg_workspace_bytes(int64_t N, int32_t n, const cr_params* alcc, const cr_papg_params* pp,
+                                  size_t* bytes);
+
+/* Host-synchronous P-APG run (above).  X (N x n), ybar (N) FP64 device inputs;
+ * y (N), xi (N x n) FP64 device outputs; theta_dev, theta_y_dev optional.
+ * All buffers are the caller's.  `alcc` is the block solves' schedule (its
+ * precision CR_F64 or CR_F32).  Errors: as cr_papg_workspace_bytes,
+ * CR_ERR_NOMEM (ws_bytes too small), CR_ERR_NONFINITE (NaN/Inf in the inputs
+ * or an iterate), CR_ERR_HIP.  A block solve that ends CR_NOT_CONVERGED
+ * (adaptive schedule) is not an error; info->inner_iters counts its steps. */
+cr_status cr_papg(const void* X_dev, const void* ybar_dev, int64_t N, int32_t n, const cr_params* alcc,
+                  const cr_papg_params* pp, void* y_dev, void* xi_dev, void* theta_dev, void* theta_y_dev,
+                  void* workspace_dev, size_t ws_bytes, cr_papg_info* info, void* stream);
+
 /* Estimator evaluation ---------------------------------------------------- */
 
 /* Sec. I: the least-squares estimator is the piecewise-linear convex function

@@ -14,13 +14,15 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import math
 import os
 from typing import Optional
 
 __all__ = [
     "Params", "Info", "CRError", "Context", "solve", "workspace_bytes", "lib_path",
     "F64", "F32", "MIXED_BF16", "GRAD", "THETA_UPDATE", "MAX_DIM", "Batch", "solve_batched",
-    "Diff", "diff_workspace_bytes", "solve_unrolled",
+    "Diff", "diff_workspace_bytes", "solve_unrolled", "Estimator", "evaluate", "eval_workspace_bytes",
+    "PapgParams", "papg_workspace_bytes", "papg",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -45,6 +47,16 @@ class _CProblem(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("n", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("X_dev", ctypes.c_void_p), ("ybar_dev", ctypes.c_void_p),
                 ("y_dev", ctypes.c_void_p), ("xi_dev", ctypes.c_void_p)]
+
+
+class _CPapgParams(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("iters", ctypes.c_int32), ("L", ctypes.c_double),
+                ("B_theta", ctypes.c_double), ("y_shift", ctypes.c_double)]
+
+
+class _CPapgInfo(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_double), ("y_shift", ctypes.c_double), ("theta_norm", ctypes.c_double),
+                ("infeas_cross", ctypes.c_double), ("inner_iters", ctypes.c_int64), ("seconds", ctypes.c_double)]
 
 
 class _CInfo(ctypes.Structure):
@@ -97,6 +109,9 @@ def _load():
         "cr_diff_time_adjoint_pass": (i32, [vp, i32, ctypes.POINTER(dbl)]),
         "cr_eval_workspace_bytes": (i32, [i64, i32, ctypes.POINTER(ctypes.c_size_t)]),
         "cr_eval": (i32, [vp, vp, vp, i64, i32, vp, i64, vp, vp, vp, ctypes.c_size_t, vp]),
+        "cr_papg_workspace_bytes": (i32, [i64, i32, pp, ctypes.POINTER(_CPapgParams), ctypes.POINTER(ctypes.c_size_t)]),
+        "cr_papg": (i32, [vp, vp, i64, i32, pp, ctypes.POINTER(_CPapgParams), vp, vp, vp, vp, vp, ctypes.c_size_t,
+                          ctypes.POINTER(_CPapgInfo), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -112,7 +127,7 @@ EXPORTED = ("cr_params_default", "cr_status_string", "cr_last_error", "cr_worksp
             "cr_get_start", "cr_get_info", "cr_time_pass", "cr_batch_workspace_bytes", "cr_batch_init",
             "cr_batch_run", "cr_batch_destroy", "cr_solve_batched", "cr_diff_workspace_bytes", "cr_diff_init",
             "cr_diff_forward", "cr_diff_backward", "cr_diff_destroy", "cr_diff_time_adjoint_pass",
-            "cr_eval_workspace_bytes", "cr_eval")
+            "cr_eval_workspace_bytes", "cr_eval", "cr_papg_workspace_bytes", "cr_papg")
 
 
 class CRError(RuntimeError):
@@ -522,3 +537,54 @@ def evaluate(X, y, xi, Q, with_arg: bool = True):
     """One-shot ``Estimator(X, y, xi)(Q)``."""
     return Estimator(X, y, xi)(Q, with_arg)
 
+
+
+# ---------------------------------------------------------------------------
+# P-APG on the partial dual (cr_papg)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class PapgParams:
+    """cr_papg_params: K index sets, iterations, step constant L (<= 0: the
+    bound (2N + sigma_max(A2)^2 + 1)/gamma), radius of Q2 (inf: none) and the
+    data shift (< 0: the library's default)."""
+    K: int = 2
+    iters: int = 10
+    L: float = 0.0
+    B_theta: float = math.inf
+    y_shift: float = -1.0
+
+    def to_c(self):
+        return _CPapgParams(int(self.K), int(self.iters), float(self.L),
+                            float(self.B_theta) if math.isfinite(self.B_theta) else 0.0, float(self.y_shift))
+
+
+def papg_workspace_bytes(N: int, n: int, params: Params, pp: PapgParams) -> int:
+    out = ctypes.c_size_t(0)
+    cp, cpp = params.to_c(), pp.to_c()
+    _check(_lib.cr_papg_workspace_bytes(int(N), int(n), ctypes.byref(cp), ctypes.byref(cpp), ctypes.byref(out)))
+    return int(out.value)
+
+
+def papg(X, ybar, pp: PapgParams, params: Optional[Params] = None, with_theta: bool = False):
+    """cr_papg: returns (y, xi, info dict[, theta (N x N), theta_y (N)])."""
+    torch = _torch()
+    params = params or Params()
+    N, n = int(X.shape[0]), int(X.shape[1])
+    px = _dev_f64(X, (N, n), "X")
+    py = _dev_f64(ybar, (N,), "ybar")
+    nbytes = papg_workspace_bytes(N, n, params, pp)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
+    y = torch.empty(N, dtype=torch.float64, device=X.device)
+    xi = torch.empty(N, n, dtype=torch.float64, device=X.device)
+    th = torch.empty(N, N, dtype=torch.float64, device=X.device) if with_theta else None
+    thy = torch.empty(N, dtype=torch.float64, device=X.device) if with_theta else None
+    cp, cpp, ci = params.to_c(), pp.to_c(), _CPapgInfo()
+    _check(_lib.cr_papg(px, py, N, n, ctypes.byref(cp), ctypes.byref(cpp), ctypes.c_void_p(y.data_ptr()),
+                        ctypes.c_void_p(xi.data_ptr()), ctypes.c_void_p(th.data_ptr()) if th is not None else None,
+                        ctypes.c_void_p(thy.data_ptr()) if thy is not None else None, ctypes.c_void_p(ws.data_ptr()),
+                        nbytes, ctypes.byref(ci), _stream()))
+    info = {k: getattr(ci, k) for k, _ in _CPapgInfo._fields_}
+    if with_theta:
+        return y, xi, info, th, thy
+    return y, xi, info

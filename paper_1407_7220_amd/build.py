@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcr.so")
-SOURCES = ["cr_kernels.hip", "cr_adjoint.hip", "cr_eval.hip", "cr_api.hip"]
+SOURCES = ["cr_kernels.hip", "cr_adjoint.hip", "cr_eval.hip", "cr_papg.hip", "cr_api.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed-FP32 instructions are kept out of every kernel

@@ -178,6 +178,7 @@ struct cr_ctx {
     bool have_kkt = false;
     bool verbose = false;
     bool lazy = false;   // MAPG iterations use lazy passes (single-problem runs whose chunk height allows them)
+    const double* shift = nullptr;   // slope shift c (problems in shifted slopes xi = xi' + c; never lazy)
     char* P(size_t off) const { return ws + off; }
     double* D(size_t off) const { return reinterpret_cast<double*>(ws + off); }
 };
@@ -245,6 +246,7 @@ static cr::PointArgs point_args(cr_ctx* c, const double* y, const double* xi, in
     a.y1p = c->D(L.off_y1p); a.y2 = c->D(L.off_y2); a.xi1p = c->D(L.off_xi1p); a.xi2 = c->D(L.off_xi2);
     a.xiaug = c->P(L.off_xiaug); a.ycol = c->P(L.off_ycol);
     a.cvec = (float*)c->P(L.off_cvec);
+    a.shift = c->shift;
     return a;
 }
 
@@ -257,6 +259,7 @@ static cr::UpdateArgs update_args(cr_ctx* c) {
     a.xiaug = c->P(L.off_xiaug); a.ycol = c->P(L.off_ycol);
     a.cvec = (float*)c->P(L.off_cvec);
     a.blockpart = c->D(L.off_blockpart); a.oa = c->oa; a.st = c->st;
+    a.shift = c->shift;
     return a;
 }
 
@@ -908,8 +911,11 @@ cr_status cr_batch_destroy(cr_batch* b) {
     return CR_OK;
 }
 
-cr_status cr_batch_init(cr_batch** out, const cr_problem* probs, int32_t P, const cr_params* params,
-                        void* workspace_dev, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+// shifts: per-problem slope shifts (null: none), fixed for the batch's lifetime.
+static cr_status batch_init_impl(cr_batch** out, const cr_problem* probs, int32_t P, const cr_params* params,
+                                 void* workspace_dev, size_t ws_bytes, void* stream, const double* const* shifts) {
     std::string msg;
     if (!out) return fail(nullptr, CR_ERR_ARG, "out is NULL");
     *out = nullptr;
@@ -949,6 +955,7 @@ cr_status cr_batch_init(cr_batch** out, const cr_problem* probs, int32_t P, cons
                                b->ws + B.off[p], B.L[p].total, stream);
         if (st != CR_OK) { g_last_error = "problem " + std::to_string(p) + ": " + g_last_error; return bad(st); }
         c->lazy = false;   // the batched graph completes each step with the batched update kernel
+        c->shift = shifts ? shifts[p] : nullptr;
         b->sub.push_back(c);
     }
     // device argument tables
@@ -981,6 +988,13 @@ cr_status cr_batch_init(cr_batch** out, const cr_problem* probs, int32_t P, cons
     if (e != hipSuccess) { fail(nullptr, CR_ERR_HIP, std::string("batch tables: ") + hipGetErrorString(e)); return bad(CR_ERR_HIP); }
     *out = b;
     return CR_OK;
+}
+
+extern "C" {
+
+cr_status cr_batch_init(cr_batch** out, const cr_problem* probs, int32_t P, const cr_params* params,
+                        void* workspace_dev, size_t ws_bytes, void* stream) {
+    return batch_init_impl(out, probs, P, params, workspace_dev, ws_bytes, stream, nullptr);
 }
 
 cr_status cr_batch_run(cr_batch* b, cr_info* infos, double* seconds) {
@@ -1515,3 +1529,238 @@ namespace cr {
 // Message of a failed context-free call in another source file (cr_last_error(NULL)).
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 }  // namespace cr
+
+// ---------------------------------------------------------------------------
+// P-APG (Fig. 2): the K block problems of step 1 are one batch of shifted-slope
+// problems whose data (ybar_i + u_i) and slope centres (v_i / gamma) are
+// rewritten in place before every iteration; each problem's set-up (affine
+// fit, Bbar) is redone for its new data.  Step 2 and the data of the next
+// step 1 are the O(N^2) kernels of cr_papg.hip.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct PapgLayout {
+    int64_t N = 0, Nbar = 0;
+    int n = 0, K = 0;
+    size_t th[2], ty[2], ybs, shift, y, xis, part, scal, su, supart, y0, xi0, st, batch;
+    size_t batch_bytes = 0, total = 0;
+};
+
+cr_status check_papg(int64_t N, int32_t n, const cr_params* alcc, const cr_papg_params* pp, std::string& msg) {
+    if (!alcc || !pp) { msg = "alcc and pp must be non-NULL"; return CR_ERR_ARG; }
+    cr_status s = check_dims(N, n, msg);
+    if (s != CR_OK) return s;
+    if (!check_params(alcc, msg)) return CR_ERR_ARG;
+    if (pp->K < 1 || N % pp->K != 0 || N / pp->K < 2) { msg = "K must divide N with N / K >= 2"; return CR_ERR_ARG; }
+    if (pp->iters < 1) { msg = "iters must be >= 1"; return CR_ERR_ARG; }
+    if (alcc->precision == CR_MIXED_BF16) { msg = "P-APG block solves run CR_F64 or CR_F32"; return CR_ERR_UNSUPPORTED; }
+    return CR_OK;
+}
+
+std::vector<cr_problem> papg_problems(int64_t N, int n, int K, const double* X, double* ybs, double* y, double* xis) {
+    const int64_t nb = N / K;
+    std::vector<cr_problem> pr(K);
+    for (int i = 0; i < K; ++i) {
+        pr[i].N = nb;
+        pr[i].n = n;
+        pr[i].tile_rows = 0;
+        pr[i].X_dev = X ? X + i * nb * n : nullptr;
+        pr[i].ybar_dev = ybs ? ybs + i * nb : nullptr;
+        pr[i].y_dev = y ? y + i * nb : nullptr;
+        pr[i].xi_dev = xis ? xis + i * nb * n : nullptr;
+    }
+    return pr;
+}
+
+PapgLayout papg_layout(int64_t N, int n, const cr_params* alcc, const cr_papg_params* pp) {
+    PapgLayout P;
+    P.N = N; P.n = n; P.K = pp->K; P.Nbar = N / pp->K;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    for (int q = 0; q < 2; ++q) P.th[q] = take((size_t)N * N * 8);
+    for (int q = 0; q < 2; ++q) P.ty[q] = take((size_t)N * 8);
+    P.ybs = take((size_t)N * 8);
+    P.shift = take((size_t)N * n * 8);
+    P.y = take((size_t)N * 8);
+    P.xis = take((size_t)N * n * 8);
+    P.part = take((size_t)N * 2 * 8);
+    P.scal = take(64);
+    // set-up of the whole point set, for sigma_max(A2)^2 of the default L
+    const int64_t ld = (N + 63) / 64 * 64;
+    const int64_t nsu = (N + 1023) / 1024, nbk = (ld * 32 + cr::kBlock - 1) / cr::kBlock;
+    P.supart = take((size_t)(std::max<int64_t>(nsu * (n * n + n + 3), nbk) + 64) * 8);
+    P.su = take((size_t)(3 * n + 2 + n * n + 8) * 8);
+    P.y0 = take((size_t)N * 8);
+    P.xi0 = take((size_t)N * n * 8);
+    P.st = take(sizeof(cr::DevState));
+    std::vector<cr_problem> pr = papg_problems(N, n, pp->K, nullptr, nullptr, nullptr, nullptr);
+    P.batch_bytes = plan_batch(pr.data(), pp->K, alcc).total;
+    P.batch = take(P.batch_bytes);
+    P.total = o + 256;
+    return P;
+}
+
+}  // namespace
+
+// Redo a problem's set-up for new data in its ybar buffer (affine fit, sigma,
+// Bbar, then the shifted start); the host constants follow after a sync.
+static hipError_t ctx_resetup(cr_ctx* c, hipStream_t cs) {
+    const Layout& L = c->L;
+    hipError_t e = cr::launch_setup(c->X, c->ybar, c->N, c->n, c->p.gamma, c->D(L.off_su), c->D(L.off_supart),
+                                    c->D(L.off_y0), c->D(L.off_xi0), c->st, cs);
+    if (e == hipSuccess && c->shift)
+        e = cr::launch_setup_shift(c->D(L.off_y0), c->ybar, c->D(L.off_xi0), c->shift, c->N, c->n, c->p.gamma, c->st,
+                                   cs);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->pinned_state, c->st, sizeof(cr::DevState), hipMemcpyDeviceToHost, cs);
+    return e;
+}
+
+static bool ctx_take_setup(cr_ctx* c) {
+    const cr::DevState& h = *c->pinned_state;
+    if (h.nonfinite || !std::isfinite(h.Bbar) || !std::isfinite(h.sigma2_A2)) return false;
+    c->sigma2_A2 = h.sigma2_A2;
+    c->Bbar = h.Bbar;
+    c->By = c->p.By_override > 0 ? c->p.By_override : h.Bbar;
+    c->Bxi = c->p.Bxi_override > 0 ? c->p.Bxi_override : h.Bbar / std::sqrt(c->p.gamma);
+    c->ybar_inf = h.ybar_inf;
+    return true;
+}
+
+extern "C" {
+
+cr_status cr_papg_workspace_bytes(int64_t N, int32_t n, const cr_params* alcc, const cr_papg_params* pp,
+                                  size_t* bytes) {
+    std::string msg;
+    if (!bytes) return fail(nullptr, CR_ERR_ARG, "bytes is NULL");
+    cr_status s = check_papg(N, n, alcc, pp, msg);
+    if (s != CR_OK) return fail(nullptr, s, msg);
+    *bytes = papg_layout(N, n, alcc, pp).total;
+    return CR_OK;
+}
+
+cr_status cr_papg(const void* X_dev, const void* ybar_dev, int64_t N, int32_t n, const cr_params* alcc,
+                  const cr_papg_params* pp, void* y_dev, void* xi_dev, void* theta_dev, void* theta_y_dev,
+                  void* workspace_dev, size_t ws_bytes, cr_papg_info* info, void* stream) {
+    std::string msg;
+    cr_status s = check_papg(N, n, alcc, pp, msg);
+    if (s != CR_OK) return fail(nullptr, s, msg);
+    if (!X_dev || !ybar_dev || !y_dev || !xi_dev || !workspace_dev)
+        return fail(nullptr, CR_ERR_ARG, "X, ybar, y, xi and the workspace must be non-NULL");
+    const PapgLayout P = papg_layout(N, n, alcc, pp);
+    if (ws_bytes < P.total) return fail(nullptr, CR_ERR_NOMEM, "workspace smaller than cr_papg_workspace_bytes()");
+    const auto t0 = std::chrono::steady_clock::now();
+    char* ws = (char*)align256((size_t)workspace_dev);
+    auto D = [&](size_t off) { return reinterpret_cast<double*>(ws + off); };
+    hipStream_t us = (hipStream_t)stream;
+    const double* X = (const double*)X_dev;
+    const double gamma = alcc->gamma;
+
+#define PCHK(call)                                                                                   \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess) return fail(nullptr, CR_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+    // constants: y_shift from ybar's range, L from sigma_max(A2)^2 of all points
+    std::vector<double> hy((size_t)N);
+    PCHK(hipMemcpyAsync(hy.data(), ybar_dev, (size_t)N * 8, hipMemcpyDeviceToHost, us));
+    PCHK(hipStreamSynchronize(us));
+    double ymin = hy[0], ymax = hy[0];
+    for (double v : hy) {
+        if (!std::isfinite(v)) return fail(nullptr, CR_ERR_NONFINITE, "ybar holds NaN or Inf");
+        ymin = std::min(ymin, v);
+        ymax = std::max(ymax, v);
+    }
+    const double yshift = pp->y_shift >= 0 ? pp->y_shift : std::max(0.0, ymax - 2.0 * ymin);
+    double L = pp->L;
+    if (!(L > 0)) {
+        cr::DevState hs{};
+        PCHK(cr::launch_zero(ws + P.st, (sizeof(cr::DevState) + 15) / 16 * 16, us));
+        PCHK(cr::launch_setup(X, (const double*)ybar_dev, N, n, gamma, D(P.su), D(P.supart), D(P.y0), D(P.xi0),
+                              reinterpret_cast<cr::DevState*>(ws + P.st), us));
+        PCHK(hipMemcpyAsync(&hs, ws + P.st, sizeof(cr::DevState), hipMemcpyDeviceToHost, us));
+        PCHK(hipStreamSynchronize(us));
+        if (hs.nonfinite || !std::isfinite(hs.sigma2_A2)) return fail(nullptr, CR_ERR_NONFINITE, "X holds NaN or Inf");
+        L = (2.0 * (double)N + hs.sigma2_A2 + 1.0) / gamma;
+    }
+
+    cr::PapgArgs a{};
+    a.N = N; a.Nbar = P.Nbar; a.n = n;
+    a.L = L; a.gamma = gamma; a.yshift = yshift;
+    a.B = pp->B_theta > 0 ? pp->B_theta : INFINITY;
+    a.X = X; a.ybar = (const double*)ybar_dev;
+    double* th[2] = {D(P.th[0]), D(P.th[1])};
+    double* ty[2] = {D(P.ty[0]), D(P.ty[1])};
+    a.ybs = D(P.ybs); a.shift = D(P.shift); a.y = D(P.y); a.xis = D(P.xis);
+    a.part = D(P.part); a.scal = D(P.scal);
+    for (int q = 0; q < 2; ++q) {
+        PCHK(cr::launch_zero(th[q], (size_t)N * N * 8, us));
+        PCHK(cr::launch_zero(ty[q], (size_t)N * 8, us));
+    }
+    int cur = 0;                 // th[cur] = theta^(1)_{l-1}, th[cur ^ 1] = theta^(1)_{l-2}
+    auto set_theta = [&]() { a.tc = th[cur]; a.tp = th[cur ^ 1]; a.tyc = ty[cur]; a.typ = ty[cur ^ 1]; };
+    set_theta();
+    a.beta = 0.0;
+    PCHK(cr::launch_papg_lin(a, us));      // theta^(2)_1 = 0: the blocks' own data, zero centres
+
+    std::vector<cr_problem> pr = papg_problems(N, n, pp->K, X, D(P.ybs), D(P.y), D(P.xis));
+    std::vector<const double*> shifts(pp->K);
+    for (int i = 0; i < pp->K; ++i) shifts[i] = D(P.shift) + (int64_t)i * P.Nbar * n;
+    cr_batch* b = nullptr;
+    s = batch_init_impl(&b, pr.data(), pp->K, alcc, ws + P.batch, P.batch_bytes, stream, shifts.data());
+    if (s != CR_OK) return s;
+    struct Guard { cr_batch* b; ~Guard() { cr_batch_destroy(b); } } guard{b};
+    hipStream_t cs = b->cs;
+    hipEvent_t ev = b->ev[0];
+#define PBCHK(call)                                                                                  \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess) return bfail(b, CR_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+    // everything above ran on the caller's stream: order the batch's stream after it
+    PBCHK(hipEventRecord(ev, us));
+    PBCHK(hipStreamWaitEvent(cs, ev, 0));
+
+    double t = 1.0;
+    int64_t inner = 0;
+    std::vector<cr_info> infos(pp->K);
+    cr_status result = CR_OK;
+    for (int l = 1; l <= pp->iters; ++l) {
+        if (l > 1) PBCHK(cr::launch_papg_lin(a, cs));
+        for (cr_ctx* c : b->sub) PBCHK(ctx_resetup(c, cs));
+        PBCHK(hipStreamSynchronize(cs));
+        for (cr_ctx* c : b->sub)
+            if (!ctx_take_setup(c)) return bfail(b, CR_ERR_NONFINITE, "non-finite block data");
+        s = cr_batch_run(b, infos.data(), nullptr);
+        if (s != CR_OK && s != CR_NOT_CONVERGED) return s;
+        for (const cr_info& f : infos) inner += f.inner_iters;
+        PBCHK(cr::launch_papg_step2(a, cs));
+        cur ^= 1;
+        set_theta();
+        const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+        a.beta = (t - 1.0) / tn;
+        t = tn;
+    }
+    PBCHK(cr::launch_papg_out(a, (double*)y_dev, (double*)xi_dev, cs));
+    if (theta_dev) PBCHK(hipMemcpyAsync(theta_dev, a.tc, (size_t)N * N * 8, hipMemcpyDeviceToDevice, cs));
+    if (theta_y_dev) PBCHK(hipMemcpyAsync(theta_y_dev, a.tyc, (size_t)N * 8, hipMemcpyDeviceToDevice, cs));
+    double sc[3] = {0, 0, 0};
+    PBCHK(hipMemcpyAsync(sc, a.scal, sizeof(sc), hipMemcpyDeviceToHost, cs));
+    PBCHK(hipStreamSynchronize(cs));
+    // the caller's stream waits for nothing more: the run is host-synchronous
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->L = L;
+        info->y_shift = yshift;
+        info->theta_norm = sc[1];
+        info->infeas_cross = sc[2];
+        info->inner_iters = inner;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (!std::isfinite(sc[1])) return fail(nullptr, CR_ERR_NONFINITE, "non-finite multipliers");
+    return result;
+#undef PCHK
+#undef PBCHK
+}
+
+}  // extern "C"

@@ -159,6 +159,9 @@ struct UpdateArgs {
     double* sv_vy;
     double* sv_vxi;
     double* sv_nrm;
+    // slope shift c (N x n, null: none): the operands of the next pass are
+    // built from xi + c (problems posed in shifted slopes, see k_su_shift)
+    const double* shift;
 };
 
 // Operands of the next pass at (y, xi), optionally restarting MAPG there.
@@ -175,6 +178,7 @@ struct PointArgs {
     void* xiaug;
     void* ycol;
     float* cvec;     // mixed precision only
+    const double* shift;   // slope shift c (null: none); operands from xi + c
 };
 
 // Message for cr_last_error(NULL) (context-free calls outside cr_api.hip).
@@ -195,6 +199,33 @@ hipError_t launch_mapg_finish(const LazyStep& lz, int64_t N, hipStream_t s);
 // Largest rows per chunk for which a lazy pass's LDS (row sums, y operands and
 // staged column operands) fits the pass workgroup's 32 KiB area.
 bool lazy_fits(int prec, int64_t rows_per_chunk);
+// Start of a problem posed in shifted slopes xi = xi' + c: xi0 <- xi0 - c and
+// st->Bbar = sqrt(||y0 - ybar||^2 + gamma ||xi0 - c||^2) (one workgroup).
+hipError_t launch_setup_shift(const double* y0, const double* ybar, double* xi0, const double* shift, int64_t N,
+                              int n, double gamma, DevState* st, hipStream_t s);
+
+// P-APG (Fig. 2) kernels, see cr_papg.hip.
+struct PapgArgs {
+    int64_t N, Nbar;
+    int32_t n, pad;
+    double beta;              // (t_{l-1} - 1) / t_l: theta2 = tc + beta (tc - tp)
+    double L, gamma, yshift, B;   // step constant of Fig. 2 step 2, Tikhonov weight, data shift, ball radius
+    const double* X;
+    const double* ybar;
+    double* tc;               // theta^(1)_{l-1}, N x N (cross entries; diagonal blocks 0)
+    double* tp;               // theta^(1)_{l-2} in, theta^(1)_l out
+    double* tyc;              // the same for the y >= 0 multipliers (N)
+    double* typ;
+    double* ybs;              // block data ybar + yshift + u (N)
+    double* shift;            // block slope centres v / gamma (N x n)
+    const double* y;          // step-1 output y (N)
+    const double* xis;        // step-1 output in shifted slopes xi' (N x n)
+    double* part;             // per-row partial sums (2 per row)
+    double* scal;             // [scale, ||theta||, ||(r_cross)_-||]
+};
+hipError_t launch_papg_lin(const PapgArgs& a, hipStream_t s);
+hipError_t launch_papg_step2(const PapgArgs& a, hipStream_t s);
+hipError_t launch_papg_out(const PapgArgs& a, double* y_out, double* xi_out, hipStream_t s);
 int reduce_blocks(int64_t N, int n);
 int reduce_blocks_g(int64_t N, int G);
 // Batched form (plain precisions): see cr_batch.hip.

@@ -759,17 +759,18 @@ __device__ void update_block(const UpdateArgs& a, const int blk, const int nblk)
         const double x2n = x1 + beta * (x1 - c1p);
         a.xi1p[e] = x1;
         a.xi2[e] = x2n;
+        const double xo = a.shift ? x2n + a.shift[e] : x2n;   // slope of the next pass's operands
         if (MIX) {
             __bf16* xb = (__bf16*)a.xiaug + j * a.kp;
             __bf16 hi, lo;
-            bf16_split((float)(-x2n), hi, lo);
+            bf16_split((float)(-xo), hi, lo);
             xb[k] = hi;
             xb[n + k] = hi;
             xb[2 * n + k] = lo;
         } else {
-            xa[k] = (T)(-x2n);
+            xa[k] = (T)(-xo);
         }
-        prod = xe * x2n;
+        prod = xe * xo;
     }
     const double d = group_sum<G>(prod);                    // x_j^T xi_j
     if (valid && k == n) {
@@ -896,9 +897,10 @@ __global__ __launch_bounds__(kBlock) void k_set_point(PointArgs a) {
     double prod = 0.0, x = 0.0;
     const bool valid = j < a.N;
     if (valid && k < n) {
-        x = a.xi[j * n + k];
+        const double xs = a.xi[j * n + k];
+        if (a.write_state) { a.xi1p[j * n + k] = xs; a.xi2[j * n + k] = xs; }
+        x = a.shift ? xs + a.shift[j * n + k] : xs;     // operands from the constraint slope
         prod = a.X[j * n + k] * x;
-        if (a.write_state) { a.xi1p[j * n + k] = x; a.xi2[j * n + k] = x; }
     }
     const double d = group_sum<G>(prod);
     if (j >= a.ld) return;
@@ -917,7 +919,7 @@ __global__ __launch_bounds__(kBlock) void k_set_point(PointArgs a) {
             if (valid && q < 3 * n) {
                 const int kk = q % n;
                 __bf16 hi, lo;
-                bf16_split((float)(-a.xi[j * n + kk]), hi, lo);
+                bf16_split((float)(-(a.shift ? a.xi[j * n + kk] + a.shift[j * n + kk] : a.xi[j * n + kk])), hi, lo);
                 val = q < 2 * n ? hi : lo;
             }
             xb[q] = val;
@@ -1219,6 +1221,26 @@ __global__ void k_su_start_final(const double* part, int nblk, int64_t N, int n,
     st->Bbar = sqrt(s + gamma * (double)N * aa);
 }
 
+// Start of a problem in shifted slopes xi = xi' + c: the affine fit (yhat, a)
+// is (yhat, a - c) there, still feasible; Bbar is the objective at it.  One
+// workgroup; fixed summation order.
+__global__ __launch_bounds__(kBlock) void k_su_shift(const double* y0, const double* ybar, double* xi0,
+                                                     const double* shift, int64_t N, int n, double gamma,
+                                                     DevState* st) {
+    double r2 = 0.0, x2 = 0.0;
+    for (int64_t j = threadIdx.x; j < N; j += kBlock) {
+        const double d = y0[j] - ybar[j];
+        r2 += d * d;
+        for (int k = 0; k < n; ++k) {
+            const double x = xi0[j * n + k] - shift[j * n + k];
+            xi0[j * n + k] = x;
+            x2 += x * x;
+        }
+    }
+    const double R2 = block_reduce(r2, 0), X2 = block_reduce(x2, 0);
+    if (threadIdx.x == 0) st->Bbar = sqrt(R2 + gamma * X2);
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launch helpers (called by the driver in cr_api.hip).
 // ---------------------------------------------------------------------------
@@ -1423,6 +1445,12 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_zero16, dim3((unsigned)blocks), dim3(kBlock), 0, s, (uint4*)p, n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup_shift(const double* y0, const double* ybar, double* xi0, const double* shift, int64_t N,
+                              int n, double gamma, DevState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_su_shift, dim3(1), dim3(kBlock), 0, s, y0, ybar, xi0, shift, N, n, gamma, st);
     return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@ __all__ = [
     "max_affine_uniform",
     "quad_l1_gaussian",
     "constant_data",
+    "gaussian_quadratic",
     "workload",
     "batched_workload",
     "WORKLOADS",
@@ -62,6 +63,18 @@ def quadratic_uniform(N: int, n: int, sigma: float = 0.1, seed: int = 0,
     f0 = np.sum(X * X, axis=1)
     eps = rng.normal(0.0, 1.0, size=N) * sigma
     return _finish(name, X, f0, 2.0 * X, eps, seed)
+
+
+def gaussian_quadratic(N: int = 100, n: int = 5, seed: int = 0, name: str = "gaussian_quadratic") -> Problem:
+    """The small study of Sec. III: x ~ N(0, I_n), f0(x) = 1/2 x^T Q x with
+    Q = Lambda^T Lambda, Lambda_ij ~ N(0, 1), eps ~ N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(N, n))
+    Lam = rng.normal(size=(n, n))
+    Q = Lam.T @ Lam
+    f0 = 0.5 * np.einsum("li,ij,lj->l", X, Q, X)
+    eps = rng.normal(size=N)
+    return _finish(name, X, f0, X @ Q, eps, seed)
 
 
 def logsumexp_gaussian(N: int, n: int, pieces: int = 20, sigma: float = 0.05,

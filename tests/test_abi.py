@@ -182,3 +182,28 @@ def test_eval_workspace_and_argument_checks():
     assert lib.cr_eval(fake, fake, fake, 10, 40, fake, 5, fake, None, fake, 1 << 20, None) == 7
     # M = 0 is a no-op (nothing launched)
     assert lib.cr_eval(fake, fake, fake, 10, 3, None, 0, None, None, fake, 1 << 20, None) == 0
+
+
+def test_papg_workspace_and_argument_checks():
+    """cr_papg_workspace_bytes / cr_papg: host-side checks before any launch."""
+    import ctypes
+    import paper_1407_7220_amd as cr
+    p = cr.Params(precision=cr.F64, inner_iters=20, max_outer=3)
+    b = cr.papg_workspace_bytes(100, 5, p, cr.PapgParams(K=2, iters=3))
+    assert b >= 2 * 100 * 100 * 8                  # two N x N multiplier arrays
+    for N, n, K, it, status in ((100, 5, 3, 3, 1), (100, 5, 0, 3, 1), (100, 5, 100, 3, 1), (100, 5, 2, 0, 1),
+                                (100, 40, 2, 3, 7)):
+        with pytest.raises(cr.CRError) as e:
+            cr.papg_workspace_bytes(N, n, p, cr.PapgParams(K=K, iters=it))
+        assert e.value.status == status
+    with pytest.raises(cr.CRError) as e:
+        cr.papg_workspace_bytes(100, 5, cr.Params(precision=cr.MIXED_BF16), cr.PapgParams(K=2))
+    assert e.value.status == 7
+    fake = ctypes.c_void_p(0x1000)
+    cp, cpp = p.to_c(), cr.PapgParams(K=2, iters=3).to_c()
+    lib = cr._lib
+    assert lib.cr_papg(None, fake, 100, 5, ctypes.byref(cp), ctypes.byref(cpp), fake, fake, None, None, fake,
+                       1 << 30, None, None) == 1
+    assert lib.cr_papg(fake, fake, 100, 5, ctypes.byref(cp), ctypes.byref(cpp), fake, fake, None, None, fake,
+                       16, None, None) == 2
+    assert b"workspace" in lib.cr_last_error(None)

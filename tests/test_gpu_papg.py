@@ -1,0 +1,139 @@
+"""GPU parity of P-APG (cr_papg, Fig. 2) against the FP64 oracle (oracle/papg.py).
+
+Both sides run the same fixed schedules: `iters` P-APG iterations, each
+solving the K block problems with ALCC for max_outer x inner_iters MAPG steps,
+and the same constants (L and y_shift are passed where a case pins them).
+Every case prints its name, sizes and schedule before touching the GPU."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import papg as opapg
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1407_7220_amd as cr
+    return cr
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+# FP64 block solves against the FP64 oracle: the two differ by summation order
+# in every reduction (the same bound as the fixed-schedule ALCC parity, 1e-9),
+# and P-APG's multiplier step adds O(N) sums of such values per iteration.
+TOL = 1e-9
+
+
+def _run(cr, p, K, iters, inner, outer, gamma, L=0.0, B=math.inf, y_shift=None, prec=0):
+    sched = dict(gamma=gamma, inner_iters=inner, max_outer=outer)
+    ref = opapg.papg(p.X, p.ybar, K, gamma, iters, oracle.Params(**sched), L=L, B_theta=B, y_shift=y_shift)
+    pp = cr.PapgParams(K=K, iters=iters, L=L, B_theta=B, y_shift=-1.0 if y_shift is None else y_shift)
+    y, xi, info, th, thy = cr.papg(dev(p.X), dev(p.ybar), pp, cr.Params(precision=prec, **sched), with_theta=True)
+    return ref, host(y), host(xi), info, host(th), host(thy)
+
+
+CASES = [
+    # (name, problem, K, iters, inner, outer, gamma)
+    ("gaussian_quadratic N=12 n=2 K=2", lambda: synth.gaussian_quadratic(12, 2, seed=3), 2, 4, 40, 4, 0.1),
+    ("gaussian_quadratic N=100 n=5 K=2 (Sec. III study)", lambda: synth.gaussian_quadratic(100, 5, seed=0), 2, 3,
+     40, 4, 0.05),
+    ("quadratic_uniform N=90 n=3 K=3", lambda: synth.quadratic_uniform(90, 3, seed=4), 3, 3, 33, 3, 0.1),
+    ("quad_l1_gaussian N=96 n=7 K=4", lambda: synth.quad_l1_gaussian(96, 7, seed=5), 4, 2, 31, 3, 0.2),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_papg_matches_oracle(cr, case):
+    name, mk, K, iters, inner, outer, gamma = case
+    p = mk()
+    say("papg %s: %d iterations of %d x %d MAPG steps per block, gamma %g" % (name, iters, outer, inner, gamma))
+    ref, y, xi, info, th, thy = _run(cr, p, K, iters, inner, outer, gamma)
+    assert abs(info["L"] - ref.L) <= 1e-10 * ref.L
+    assert info["y_shift"] == ref.y_shift
+    ey, exi, eth = rel(y, ref.y), rel(xi, ref.xi), rel(th, ref.Th)
+    say("  relative error vs FP64 oracle: y %.3e  xi %.3e  theta %.3e  (||theta|| %.3e)"
+        % (ey, exi, eth, info["theta_norm"]))
+    assert ey < TOL and exi < TOL * 10 and eth < TOL * 10
+    np.testing.assert_allclose(thy, ref.th_y, rtol=0, atol=TOL * (1 + np.abs(ref.Th).max()))
+    # structure: zero inside the diagonal blocks, nonnegative everywhere
+    assert np.all(th[~opapg.cross_mask(p.N, K)] == 0.0) and np.all(th >= 0.0) and np.all(thy >= 0.0)
+    assert info["inner_iters"] == iters * K * inner * outer
+    nrm = math.sqrt(float(np.sum(th * th) + np.sum(thy * thy)))
+    assert abs(info["theta_norm"] - nrm) <= 1e-12 * max(nrm, 1.0)
+
+
+def test_papg_ball_active_and_given_constants(cr):
+    # data moved down by 5 and no shift: the rows y >= 0 bind (theta_y > 0), and
+    # the radius 0.02 is below the unprojected ||theta|| (0.0236 with the oracle)
+    p = synth.gaussian_quadratic(60, 3, seed=6)
+    p.ybar = p.ybar - 5.0
+    L = 0.5 * opapg.lipschitz_bound(p.X, 0.1)
+    B = 0.02
+    say("papg ball radius %g, L %.3e, y_shift 0: N=60 n=3 K=3, 3 iterations of 3 x 30" % (B, L))
+    ref, y, xi, info, th, thy = _run(cr, p, 3, 3, 30, 3, 0.1, L=L, B=B, y_shift=0.0)
+    assert info["L"] == L and info["y_shift"] == 0.0
+    assert abs(info["theta_norm"] - B) <= 1e-12      # the ball is active
+    assert np.count_nonzero(ref.th_y) > 0
+    ey, eth = rel(y, ref.y), rel(th, ref.Th)
+    say("  relative error vs FP64 oracle: y %.3e  theta %.3e  theta_y %.3e" % (ey, eth, rel(thy, ref.th_y)))
+    assert ey < TOL and eth < TOL * 10 and rel(thy, ref.th_y) < TOL * 10
+
+
+def test_papg_single_block_is_a_batched_solve(cr):
+    # K = 1: no cross pairs; theta_y stays 0 once y > 0, so eta is one ALCC solve
+    p = synth.quadratic_uniform(80, 4, seed=8)
+    sched = dict(gamma=0.1, inner_iters=32, max_outer=3)
+    say("papg K=1 N=80 n=4, 2 iterations of 3 x 32, against cr.solve")
+    y, xi, info = cr.papg(dev(p.X), dev(p.ybar), cr.PapgParams(K=1, iters=2), cr.Params(precision=0, **sched))
+    ys, xis, _ = cr.solve(dev(p.X), dev(p.ybar), cr.Params(precision=0, **sched))
+    assert rel(host(y), host(ys)) < TOL and rel(host(xi), host(xis)) < TOL * 10
+    assert info["theta_norm"] == 0.0
+
+
+def test_papg_f32_blocks(cr):
+    p = synth.gaussian_quadratic(100, 5, seed=0)
+    say("papg f32 block solves N=100 n=5 K=2, 2 iterations of 4 x 40")
+    ref, y, xi, info, th, thy = _run(cr, p, 2, 2, 40, 4, 0.05, prec=1)
+    ey, eth = rel(y, ref.y), rel(th, ref.Th)
+    say("  relative error vs FP64 oracle: y %.3e  theta %.3e" % (ey, eth))
+    assert ey < 1e-5 and eth < 1e-4
+
+
+def test_papg_rejects_bad_arguments(cr):
+    p = synth.gaussian_quadratic(12, 2, seed=3)
+    say("papg argument errors (host-side)")
+    with pytest.raises(cr.CRError) as e:
+        cr.papg(dev(p.X), dev(p.ybar), cr.PapgParams(K=5, iters=1), cr.Params(precision=0, inner_iters=5))
+    assert e.value.status == 1
+    bad = p.ybar.copy()
+    bad[3] = np.nan
+    with pytest.raises(cr.CRError) as e:
+        cr.papg(dev(p.X), dev(bad), cr.PapgParams(K=2, iters=1), cr.Params(precision=0, inner_iters=5))
+    assert e.value.status == 4
