@@ -16,8 +16,9 @@ Also reported on the same JSON line:
   variants      the same metric for the FP64 solve of the same workload, and the
                 steady-state MAPG throughput (fixed iteration count, stated) of
                 the mixed BF16 form on the 20000-point workload and of the
-                64-problem batched form, and the differentiable form (10000
-                points, 10 x 20 unrolled iterations, forward + reverse pass).
+                64-problem batched form, the differentiable form (10000
+                points, 10 x 20 unrolled iterations, forward + reverse pass),
+                the estimator evaluation and P-APG (4096 points, K = 4).
 The pass tile height comes from the autotuner (paper_1407_7220_amd.autotune).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision f32|f64]
@@ -202,6 +203,33 @@ def eval_rate(cr, reps=10):
                                              "unit": "TFLOP/s", "frac": tflops / MFMA_F64_PEAK_TFS}}
 
 
+def papg_rate(cr, N=4096, n=5, K=4, iters=5, inner=40, outer=4):
+    """P-APG (Fig. 2) on the problem of the Sec. III study scaled up: x ~ N(0, I_5),
+    f0 = 1/2 x^T Q x with Q = Lambda^T Lambda, Lambda ~ N(0, 1), noise N(0, 1),
+    N = 4096 points in K = 4 index sets; FP32 block solves of outer x inner MAPG
+    steps, `iters` P-APG iterations after one untimed run."""
+    import torch
+    import synth
+    p = synth.gaussian_quadratic(N, n, seed=0)
+    X, yb = torch.from_numpy(p.X).cuda(), torch.from_numpy(p.ybar).cuda()
+    params = cr.Params(precision=cr.F32, gamma=0.05, inner_iters=inner, max_outer=outer)
+    pp = cr.PapgParams(K=K, iters=iters)
+    cr.papg(X, yb, pp, params)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, info = cr.papg(X, yb, pp, params)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    nb = N // K
+    block_pairs = float(K * nb * (nb - 1)) * inner * outer
+    cross_pairs = float(N * N - K * nb * nb)
+    return {"value": iters / secs, "unit": "P-APG iterations/s", "N": N, "n": n, "K": K,
+            "schedule": "%d P-APG iterations, blocks %d x %d MAPG" % (iters, outer, inner),
+            "ms_per_iteration": secs / iters * 1e3,
+            "pair_updates_per_s": (block_pairs + cross_pairs) * iters / secs,
+            "final_infeas_cross": info["infeas_cross"], "theta_norm": info["theta_norm"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,6 +308,8 @@ def main():
         v["differentiable_f32_quadratic_10000"] = diff_rate(cr)
         torch.cuda.empty_cache()
         v["estimator_eval_f64_20000x20000"] = eval_rate(cr)
+        torch.cuda.empty_cache()
+        v["papg_f32_gaussian_quadratic_4096_K4"] = papg_rate(cr)
         line["variants"] = v
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_budget)

@@ -352,7 +352,13 @@ typedef struct {
     double y_shift;     /* added to ybar so that y >= 0 holds at the solution
                            (Sec. II-D) and subtracted from y on output;
                            < 0: max(0, max(ybar) - 2 min(ybar)) */
+    int32_t method;     /* CR_PAPG_ACCELERATED: Fig. 2; CR_PAPG_GRADIENT: steps
+                           3-4 dropped (theta^(2)_{l+1} = theta^(1)_l), the
+                           projected gradient ascent P-APG is compared with in Sec. III */
+    int32_t reserved;   /* 0 */
 } cr_papg_params;
+
+enum { CR_PAPG_ACCELERATED = 0, CR_PAPG_GRADIENT = 1 };
 
 typedef struct {
     double L, y_shift;          /* the constants used */
@@ -365,12 +371,17 @@ typedef struct {
 /* Bytes of device workspace for cr_papg: two N x N FP64 multiplier arrays, the
  * block data and outputs, and the batched ALCC's workspace for K problems of
  * Nbar points.  Errors: CR_ERR_ARG (NULL, bad params, N % K != 0,
- * N / K < 2, iters < 1), CR_ERR_UNSUPPORTED (as cr_batch_workspace_bytes). */
+ * N / K < 2, iters < 1, unknown method), CR_ERR_UNSUPPORTED (as
+ * cr_batch_workspace_bytes). */
 cr_status cr_papg_workspace_bytes(int64_t N, int32_t n, const cr_params* alcc, const cr_papg_params* pp,
                                   size_t* bytes);
 
 /* Host-synchronous P-APG run (above).  X (N x n), ybar (N) FP64 device inputs;
  * y (N), xi (N x n) FP64 device outputs; theta_dev, theta_y_dev optional.
+ * trace_host (optional, host memory of iters x 3 doubles) receives per
+ * iteration l: ||theta^(1)_l||, ||(A3 y + A4 xi)_-||_2 at eta_l and
+ * theta^(2)_l^T C eta_l (the objective of eq. "omega_primal" at eta_l minus
+ * the Lagrangian of eq. "g_gamma" there).
  * All buffers are the caller's.  `alcc` is the block solves' schedule (its
  * precision CR_F64 or CR_F32).  Errors: as cr_papg_workspace_bytes,
  * CR_ERR_NOMEM (ws_bytes too small), CR_ERR_NONFINITE (NaN/Inf in the inputs
@@ -378,7 +389,7 @@ cr_status cr_papg_workspace_bytes(int64_t N, int32_t n, const cr_params* alcc, c
  * (adaptive schedule) is not an error; info->inner_iters counts its steps. */
 cr_status cr_papg(const void* X_dev, const void* ybar_dev, int64_t N, int32_t n, const cr_params* alcc,
                   const cr_papg_params* pp, void* y_dev, void* xi_dev, void* theta_dev, void* theta_y_dev,
-                  void* workspace_dev, size_t ws_bytes, cr_papg_info* info, void* stream);
+                  double* trace_host, void* workspace_dev, size_t ws_bytes, cr_papg_info* info, void* stream);
 
 /* Estimator evaluation ---------------------------------------------------- */
 

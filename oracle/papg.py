@@ -149,7 +149,7 @@ class PapgResult:
 
 def papg(X, ybar, K: int, gamma: float, iters: int, params: Optional[_o.Params] = None,
          L: float = 0.0, B_theta: float = math.inf, y_shift: Optional[float] = None,
-         record: bool = False) -> PapgResult:
+         record: bool = False, accelerate: bool = True) -> PapgResult:
     """P-APG (Fig. 2) for `iters` iterations.
 
     Iteration 0: theta^(1)_0 = theta^(2)_1 = 0, t_1 = 1.  Iteration l:
@@ -157,7 +157,16 @@ def papg(X, ybar, K: int, gamma: float, iters: int, params: Optional[_o.Params] 
       2. theta^(1)_l = Pi_Q2(theta^(2)_l - C eta_l / L)
       3. t_{l+1} = (1 + sqrt(1 + 4 t_l^2)) / 2
       4. theta^(2)_{l+1} = theta^(1)_l + (t_l - 1)/t_{l+1} (theta^(1)_l - theta^(1)_{l-1})
-    `params` is the block ALCC's schedule (its gamma is replaced by `gamma`)."""
+    `params` is the block ALCC's schedule (its gamma is replaced by `gamma`).
+    With accelerate=False steps 3-4 are dropped (theta^(2)_{l+1} = theta^(1)_l):
+    projected gradient ascent on the same dual, the method P-APG is compared
+    with in Sec. III.
+
+    With record=True every iteration appends theta_norm = ||theta^(1)_l||,
+    infeas_cross = ||(A3 y + A4 xi)_-||_2 at eta_l, gap = theta^(2)_l^T C eta_l
+    (the objective of eq. "omega_primal" at eta_l minus the Lagrangian there,
+    i.e. minus g_gamma(theta^(2)_l) when eta_l is exact), the Lagrangian g,
+    the all-pairs infeasibility and the primal objective."""
     X, ybar = _o._f64(X), _o._f64(ybar)
     N, n = X.shape
     block_of(N, K)
@@ -180,11 +189,13 @@ def papg(X, ybar, K: int, gamma: float, iters: int, params: Optional[_o.Params] 
             neg = _o.neg_part(Rall)
             np.fill_diagonal(neg, 0.0)
             trace.append(dict(l=l, g=lagrangian(X, ybs, gamma, K, T2, t2, y, xi),
+                              theta_norm=math.sqrt(float(np.sum(T1 * T1)) + float(np.sum(t1 * t1))),
+                              gap=float(np.sum(np.where(mask, T2, 0.0) * R)) + float(np.dot(t2, yy)),
                               infeas=float(np.sqrt(np.sum(neg * neg))),
                               infeas_cross=float(np.sqrt(np.sum(np.where(mask, neg, 0.0) ** 2))),
                               primal=0.5 * float(np.sum((y - ybs) ** 2)) + 0.5 * gamma * float(np.sum(xi * xi))))
         t_next = (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0
-        beta = (t - 1.0) / t_next
+        beta = (t - 1.0) / t_next if accelerate else 0.0
         T2 = T1 + beta * (T1 - T1p)
         t2 = t1 + beta * (t1 - t1p)
         T1p, t1p = T1, t1

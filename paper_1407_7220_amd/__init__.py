@@ -29,6 +29,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libcr.so")
 
 F64, F32, MIXED_BF16 = 0, 1, 2
+PAPG_ACCELERATED, PAPG_GRADIENT = 0, 1
 GRAD, THETA_UPDATE = 0, 1
 MAX_DIM = 31
 
@@ -51,7 +52,8 @@ class _CProblem(ctypes.Structure):
 
 class _CPapgParams(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("iters", ctypes.c_int32), ("L", ctypes.c_double),
-                ("B_theta", ctypes.c_double), ("y_shift", ctypes.c_double)]
+                ("B_theta", ctypes.c_double), ("y_shift", ctypes.c_double), ("method", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class _CPapgInfo(ctypes.Structure):
@@ -110,8 +112,8 @@ def _load():
         "cr_eval_workspace_bytes": (i32, [i64, i32, ctypes.POINTER(ctypes.c_size_t)]),
         "cr_eval": (i32, [vp, vp, vp, i64, i32, vp, i64, vp, vp, vp, ctypes.c_size_t, vp]),
         "cr_papg_workspace_bytes": (i32, [i64, i32, pp, ctypes.POINTER(_CPapgParams), ctypes.POINTER(ctypes.c_size_t)]),
-        "cr_papg": (i32, [vp, vp, i64, i32, pp, ctypes.POINTER(_CPapgParams), vp, vp, vp, vp, vp, ctypes.c_size_t,
-                          ctypes.POINTER(_CPapgInfo), vp]),
+        "cr_papg": (i32, [vp, vp, i64, i32, pp, ctypes.POINTER(_CPapgParams), vp, vp, vp, vp,
+                          ctypes.POINTER(dbl), vp, ctypes.c_size_t, ctypes.POINTER(_CPapgInfo), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -546,17 +548,20 @@ def evaluate(X, y, xi, Q, with_arg: bool = True):
 @dataclasses.dataclass
 class PapgParams:
     """cr_papg_params: K index sets, iterations, step constant L (<= 0: the
-    bound (2N + sigma_max(A2)^2 + 1)/gamma), radius of Q2 (inf: none) and the
-    data shift (< 0: the library's default)."""
+    bound (2N + sigma_max(A2)^2 + 1)/gamma), radius of Q2 (inf: none), the
+    data shift (< 0: the library's default) and the method (PAPG_ACCELERATED,
+    Fig. 2, or PAPG_GRADIENT, projected gradient ascent)."""
     K: int = 2
     iters: int = 10
     L: float = 0.0
     B_theta: float = math.inf
     y_shift: float = -1.0
+    method: int = 0
 
     def to_c(self):
         return _CPapgParams(int(self.K), int(self.iters), float(self.L),
-                            float(self.B_theta) if math.isfinite(self.B_theta) else 0.0, float(self.y_shift))
+                            float(self.B_theta) if math.isfinite(self.B_theta) else 0.0, float(self.y_shift),
+                            int(self.method), 0)
 
 
 def papg_workspace_bytes(N: int, n: int, params: Params, pp: PapgParams) -> int:
@@ -567,7 +572,10 @@ def papg_workspace_bytes(N: int, n: int, params: Params, pp: PapgParams) -> int:
 
 
 def papg(X, ybar, pp: PapgParams, params: Optional[Params] = None, with_theta: bool = False):
-    """cr_papg: returns (y, xi, info dict[, theta (N x N), theta_y (N)])."""
+    """cr_papg: returns (y, xi, info dict[, theta (N x N), theta_y (N)]).
+    info["trace"] is an iters x 3 numpy array: ||theta^(1)_l||, the cross-block
+    infeasibility at eta_l and theta^(2)_l^T C eta_l."""
+    import numpy as np
     torch = _torch()
     params = params or Params()
     N, n = int(X.shape[0]), int(X.shape[1])
@@ -580,11 +588,14 @@ def papg(X, ybar, pp: PapgParams, params: Optional[Params] = None, with_theta: b
     th = torch.empty(N, N, dtype=torch.float64, device=X.device) if with_theta else None
     thy = torch.empty(N, dtype=torch.float64, device=X.device) if with_theta else None
     cp, cpp, ci = params.to_c(), pp.to_c(), _CPapgInfo()
+    trace = np.zeros((int(pp.iters), 3), dtype=np.float64)
     _check(_lib.cr_papg(px, py, N, n, ctypes.byref(cp), ctypes.byref(cpp), ctypes.c_void_p(y.data_ptr()),
                         ctypes.c_void_p(xi.data_ptr()), ctypes.c_void_p(th.data_ptr()) if th is not None else None,
-                        ctypes.c_void_p(thy.data_ptr()) if thy is not None else None, ctypes.c_void_p(ws.data_ptr()),
+                        ctypes.c_void_p(thy.data_ptr()) if thy is not None else None,
+                        trace.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.c_void_p(ws.data_ptr()),
                         nbytes, ctypes.byref(ci), _stream()))
     info = {k: getattr(ci, k) for k, _ in _CPapgInfo._fields_}
+    info["trace"] = trace
     if with_theta:
         return y, xi, info, th, thy
     return y, xi, info

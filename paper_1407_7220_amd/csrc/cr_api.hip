@@ -86,7 +86,7 @@ Layout make_layout(int64_t N, int n, int precision, int64_t max_iters, int tile_
     L.rpc = (int)rpc;
     L.chunks = (int)((L.Nrow + rpc - 1) / rpc);
     L.nb = (int)((L.ld * 32 + cr::kBlock - 1) / cr::kBlock);  // blocks of the O(N n) kernels (32 lanes per point)
-    L.nsu = (int)((N + 1023) / 1024);
+    L.nsu = (int)((N + cr::kSuRows - 1) / cr::kSuRows);
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
     L.off_theta = take((size_t)L.Nrow * L.ld * L.esz);
@@ -1542,7 +1542,7 @@ namespace {
 struct PapgLayout {
     int64_t N = 0, Nbar = 0;
     int n = 0, K = 0;
-    size_t th[2], ty[2], ybs, shift, y, xis, part, scal, su, supart, y0, xi0, st, batch;
+    size_t th[2], ty[2], ybs, shift, y, xis, part, scal, trace, su, supart, y0, xi0, st, batch;
     size_t batch_bytes = 0, total = 0;
 };
 
@@ -1553,6 +1553,7 @@ cr_status check_papg(int64_t N, int32_t n, const cr_params* alcc, const cr_papg_
     if (!check_params(alcc, msg)) return CR_ERR_ARG;
     if (pp->K < 1 || N % pp->K != 0 || N / pp->K < 2) { msg = "K must divide N with N / K >= 2"; return CR_ERR_ARG; }
     if (pp->iters < 1) { msg = "iters must be >= 1"; return CR_ERR_ARG; }
+    if (pp->method != CR_PAPG_ACCELERATED && pp->method != CR_PAPG_GRADIENT) { msg = "unknown method"; return CR_ERR_ARG; }
     if (alcc->precision == CR_MIXED_BF16) { msg = "P-APG block solves run CR_F64 or CR_F32"; return CR_ERR_UNSUPPORTED; }
     return CR_OK;
 }
@@ -1583,11 +1584,12 @@ PapgLayout papg_layout(int64_t N, int n, const cr_params* alcc, const cr_papg_pa
     P.shift = take((size_t)N * n * 8);
     P.y = take((size_t)N * 8);
     P.xis = take((size_t)N * n * 8);
-    P.part = take((size_t)N * 2 * 8);
+    P.part = take((size_t)N * 3 * 8);
     P.scal = take(64);
+    P.trace = take((size_t)pp->iters * 3 * 8);
     // set-up of the whole point set, for sigma_max(A2)^2 of the default L
     const int64_t ld = (N + 63) / 64 * 64;
-    const int64_t nsu = (N + 1023) / 1024, nbk = (ld * 32 + cr::kBlock - 1) / cr::kBlock;
+    const int64_t nsu = (N + cr::kSuRows - 1) / cr::kSuRows, nbk = (ld * 32 + cr::kBlock - 1) / cr::kBlock;
     P.supart = take((size_t)(std::max<int64_t>(nsu * (n * n + n + 3), nbk) + 64) * 8);
     P.su = take((size_t)(3 * n + 2 + n * n + 8) * 8);
     P.y0 = take((size_t)N * 8);
@@ -1602,11 +1604,12 @@ PapgLayout papg_layout(int64_t N, int n, const cr_params* alcc, const cr_papg_pa
 
 }  // namespace
 
-// Redo a problem's set-up for new data in its ybar buffer (affine fit, sigma,
-// Bbar, then the shifted start); the host constants follow after a sync.
+// Redo a problem's set-up for new data in its ybar buffer on the same points
+// (affine fit from the stored eigen-decomposition, Bbar, then the shifted
+// start); the host constants follow after a sync.
 static hipError_t ctx_resetup(cr_ctx* c, hipStream_t cs) {
     const Layout& L = c->L;
-    hipError_t e = cr::launch_setup(c->X, c->ybar, c->N, c->n, c->p.gamma, c->D(L.off_su), c->D(L.off_supart),
+    hipError_t e = cr::launch_refit(c->X, c->ybar, c->N, c->n, c->p.gamma, c->D(L.off_su), c->D(L.off_supart),
                                     c->D(L.off_y0), c->D(L.off_xi0), c->st, cs);
     if (e == hipSuccess && c->shift)
         e = cr::launch_setup_shift(c->D(L.off_y0), c->ybar, c->D(L.off_xi0), c->shift, c->N, c->n, c->p.gamma, c->st,
@@ -1640,7 +1643,7 @@ cr_status cr_papg_workspace_bytes(int64_t N, int32_t n, const cr_params* alcc, c
 
 cr_status cr_papg(const void* X_dev, const void* ybar_dev, int64_t N, int32_t n, const cr_params* alcc,
                   const cr_papg_params* pp, void* y_dev, void* xi_dev, void* theta_dev, void* theta_y_dev,
-                  void* workspace_dev, size_t ws_bytes, cr_papg_info* info, void* stream) {
+                  double* trace_host, void* workspace_dev, size_t ws_bytes, cr_papg_info* info, void* stream) {
     std::string msg;
     cr_status s = check_papg(N, n, alcc, pp, msg);
     if (s != CR_OK) return fail(nullptr, s, msg);
@@ -1692,7 +1695,7 @@ cr_status cr_papg(const void* X_dev, const void* ybar_dev, int64_t N, int32_t n,
     double* th[2] = {D(P.th[0]), D(P.th[1])};
     double* ty[2] = {D(P.ty[0]), D(P.ty[1])};
     a.ybs = D(P.ybs); a.shift = D(P.shift); a.y = D(P.y); a.xis = D(P.xis);
-    a.part = D(P.part); a.scal = D(P.scal);
+    a.part = D(P.part); a.scal = D(P.scal); a.trace = D(P.trace);
     for (int q = 0; q < 2; ++q) {
         PCHK(cr::launch_zero(th[q], (size_t)N * N * 8, us));
         PCHK(cr::launch_zero(ty[q], (size_t)N * 8, us));
@@ -1734,16 +1737,19 @@ cr_status cr_papg(const void* X_dev, const void* ybar_dev, int64_t N, int32_t n,
         s = cr_batch_run(b, infos.data(), nullptr);
         if (s != CR_OK && s != CR_NOT_CONVERGED) return s;
         for (const cr_info& f : infos) inner += f.inner_iters;
+        a.it = l - 1;
         PBCHK(cr::launch_papg_step2(a, cs));
         cur ^= 1;
         set_theta();
         const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
-        a.beta = (t - 1.0) / tn;
+        a.beta = pp->method == CR_PAPG_ACCELERATED ? (t - 1.0) / tn : 0.0;
         t = tn;
     }
     PBCHK(cr::launch_papg_out(a, (double*)y_dev, (double*)xi_dev, cs));
     if (theta_dev) PBCHK(hipMemcpyAsync(theta_dev, a.tc, (size_t)N * N * 8, hipMemcpyDeviceToDevice, cs));
     if (theta_y_dev) PBCHK(hipMemcpyAsync(theta_y_dev, a.tyc, (size_t)N * 8, hipMemcpyDeviceToDevice, cs));
+    if (trace_host)
+        PBCHK(hipMemcpyAsync(trace_host, a.trace, (size_t)pp->iters * 3 * 8, hipMemcpyDeviceToHost, cs));
     double sc[3] = {0, 0, 0};
     PBCHK(hipMemcpyAsync(sc, a.scal, sizeof(sc), hipMemcpyDeviceToHost, cs));
     PBCHK(hipStreamSynchronize(cs));

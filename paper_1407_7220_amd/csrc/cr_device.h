@@ -204,10 +204,18 @@ bool lazy_fits(int prec, int64_t rows_per_chunk);
 hipError_t launch_setup_shift(const double* y0, const double* ybar, double* xi0, const double* shift, int64_t N,
                               int n, double gamma, DevState* st, hipStream_t s);
 
+// Rows per workgroup of the set-up sums (means, centred scatter, X_c^T ybar_c).
+constexpr int64_t kSuRows = 64;
+// The set-up again for new data ybar on the same points: means, the affine fit
+// from the eigen-decomposition the full set-up left in su, the start point and
+// Bbar; sigma_max(A2)^2 (a function of X alone) is kept.
+hipError_t launch_refit(const double* X, const double* ybar, int64_t N, int n, double gamma, double* su,
+                        double* part, double* y0, double* xi0, DevState* st, hipStream_t s);
+
 // P-APG (Fig. 2) kernels, see cr_papg.hip.
 struct PapgArgs {
     int64_t N, Nbar;
-    int32_t n, pad;
+    int32_t n, it;            // it: 0-based iteration (row of the trace)
     double beta;              // (t_{l-1} - 1) / t_l: theta2 = tc + beta (tc - tp)
     double L, gamma, yshift, B;   // step constant of Fig. 2 step 2, Tikhonov weight, data shift, ball radius
     const double* X;
@@ -220,8 +228,9 @@ struct PapgArgs {
     double* shift;            // block slope centres v / gamma (N x n)
     const double* y;          // step-1 output y (N)
     const double* xis;        // step-1 output in shifted slopes xi' (N x n)
-    double* part;             // per-row partial sums (2 per row)
-    double* scal;             // [scale, ||theta||, ||(r_cross)_-||]
+    double* part;             // per-row partial sums (3 per row)
+    double* scal;             // [scale, ||theta||, ||(r_cross)_-||, theta2^T C eta]
+    double* trace;            // per iteration: ||theta||, ||(r_cross)_-||, theta2^T C eta
 };
 hipError_t launch_papg_lin(const PapgArgs& a, hipStream_t s);
 hipError_t launch_papg_step2(const PapgArgs& a, hipStream_t s);

@@ -1041,47 +1041,94 @@ __global__ void k_su_sums(const double* X, const double* ybar, int64_t N, int n,
                           const double* su, int phase, double* part) {
     // phase 0: e < n: sum x_ik; e = n: sum ybar; e = n+1: max |ybar|; e = n+2: # non-finite
     // phase 1: e < n*n: sum u_ik u_il; n*n <= e < n*n+n: sum u_ik (ybar_i - ybar_mean)
+    // phase 2: e < n: sum u_ik (ybar_i - ybar_mean) (the entries n*n + e of phase 1)
+    // Each thread owns output entries e and walks the workgroup's rows with
+    // four interleaved accumulators (rows i, i+1, i+2, i+3 of every step), so
+    // that four loads are in flight; the four are combined in a fixed order.
     const int64_t r0 = (int64_t)blockIdx.x * rows, r1 = min(r0 + rows, N);
-    const int ne = phase == 0 ? n + 3 : n * n + n;
+    const int ne = phase == 0 ? n + 3 : (phase == 1 ? n * n + n : n);
+    const int eq = phase == 2 ? n * n : 0;        // phase 2 computes phase 1's entries n*n + e
+    const double ym = phase != 0 ? su[n] : 0.0;
     for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-        double acc = 0.0;
-        if (phase == 0) {
-            for (int64_t i = r0; i < r1; ++i) {
-                if (e < n) acc += X[i * n + e];
-                else if (e == n) acc += ybar[i];
-                else if (e == n + 1) acc = fmax(acc, fabs(ybar[i]));
-                else {
-                    bool bad = !isfinite(ybar[i]);
-                    for (int k = 0; k < n; ++k) bad = bad || !isfinite(X[i * n + k]);
-                    acc += bad ? 1.0 : 0.0;
-                }
+        const bool is_max = phase == 0 && e == n + 1;
+        auto term = [&](int64_t i) -> double {
+            if (phase == 0) {
+                if (e < n) return X[i * n + e];
+                if (e == n) return ybar[i];
+                if (e == n + 1) return fabs(ybar[i]);
+                bool bad = !isfinite(ybar[i]);
+                for (int k = 0; k < n; ++k) bad = bad || !isfinite(X[i * n + k]);
+                return bad ? 1.0 : 0.0;
             }
+            const int ee = e + eq;
+            if (ee < n * n) {
+                const int k = ee / n, l = ee % n;
+                return (X[i * n + k] - su[k]) * (X[i * n + l] - su[l]);
+            }
+            const int k = ee - n * n;
+            return (X[i * n + k] - su[k]) * (ybar[i] - ym);
+        };
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int64_t i = r0;
+        if (is_max) {
+            for (; i + 4 <= r1; i += 4) {
+                a0 = fmax(a0, term(i)); a1 = fmax(a1, term(i + 1));
+                a2 = fmax(a2, term(i + 2)); a3 = fmax(a3, term(i + 3));
+            }
+            for (; i < r1; ++i) a0 = fmax(a0, term(i));
+            part[(int64_t)blockIdx.x * ne + e] = fmax(fmax(a0, a1), fmax(a2, a3));
         } else {
-            const double ym = su[n];
-            if (e < n * n) {
-                const int k = e / n, l = e % n;
-                for (int64_t i = r0; i < r1; ++i) acc += (X[i * n + k] - su[k]) * (X[i * n + l] - su[l]);
-            } else {
-                const int k = e - n * n;
-                for (int64_t i = r0; i < r1; ++i) acc += (X[i * n + k] - su[k]) * (ybar[i] - ym);
+            for (; i + 4 <= r1; i += 4) {
+                a0 += term(i); a1 += term(i + 1);
+                a2 += term(i + 2); a3 += term(i + 3);
             }
+            for (; i < r1; ++i) a0 += term(i);
+            part[(int64_t)blockIdx.x * ne + e] = (a0 + a1) + (a2 + a3);
         }
-        part[(int64_t)blockIdx.x * ne + e] = acc;
     }
 }
 
 __global__ void k_su_means_final(const double* part, int nblk, int64_t N, int n, double* su, DevState* st) {
-    if (threadIdx.x != 0) return;
-    st->one = 1;
+    // one thread per entry, blocks summed in index order
     const int ne = n + 3;
-    for (int e = 0; e < ne; ++e) {
+    const int e = threadIdx.x;
+    if (e == 0) st->one = 1;
+    if (e >= ne) return;
+    double acc = 0.0;
+    for (int b = 0; b < nblk; ++b) acc = (e == n + 1) ? fmax(acc, part[b * ne + e]) : acc + part[b * ne + e];
+    if (e < n) su[e] = acc / (double)N;
+    else if (e == n) { su[n] = acc / (double)N; st->ybar_mean = su[n]; }
+    else if (e == n + 1) st->ybar_inf = acc;
+    else st->nonfinite = acc > 0.0 ? 1 : 0;
+}
+
+// The affine fit for new data on the same points: q = X_c^T ybar_c from the
+// phase-2 partials, then a and b from the eigen-decomposition already in su
+// (the same formula and order as k_su_eig_final).
+__global__ void k_su_fit_final(const double* part, int nblk, int n, double* su) {
+    if (threadIdx.x != 0) return;
+    double q[kMaxDim];
+    for (int e = 0; e < n; ++e) {
         double acc = 0.0;
-        for (int b = 0; b < nblk; ++b) acc = (e == n + 1) ? fmax(acc, part[b * ne + e]) : acc + part[b * ne + e];
-        if (e < n) su[e] = acc / (double)N;
-        else if (e == n) { su[n] = acc / (double)N; st->ybar_mean = su[n]; }
-        else if (e == n + 1) st->ybar_inf = acc;
-        else st->nonfinite = acc > 0.0 ? 1 : 0;
+        for (int b = 0; b < nblk; ++b) acc += part[b * n + e];
+        q[e] = acc;
     }
+    const double* lam = su + 2 * n + 2;
+    const double* V = su + 3 * n + 2;
+    double lmax = 0.0;
+    for (int k = 0; k < n; ++k) lmax = fmax(lmax, lam[k]);
+    double* acoef = su + n + 1;
+    for (int l = 0; l < n; ++l) acoef[l] = 0.0;
+    for (int k = 0; k < n; ++k) {
+        if (!(lam[k] > 1e-12 * lmax)) continue;
+        double proj = 0.0;
+        for (int l = 0; l < n; ++l) proj += V[l * n + k] * q[l];
+        proj /= lam[k];
+        for (int l = 0; l < n; ++l) acoef[l] += proj * V[l * n + k];
+    }
+    double b = su[n];
+    for (int l = 0; l < n; ++l) b -= su[l] * acoef[l];
+    su[2 * n + 1] = b;
 }
 
 // Cyclic Jacobi eigen-decomposition of the centred scatter matrix M0 and the
@@ -1454,9 +1501,24 @@ hipError_t launch_setup_shift(const double* y0, const double* ybar, double* xi0,
     return hipGetLastError();
 }
 
+hipError_t launch_refit(const double* X, const double* ybar, int64_t N, int n, double gamma, double* su,
+                        double* part, double* y0, double* xi0, DevState* st, hipStream_t s) {
+    const int64_t rows = kSuRows;
+    const int nblk = (int)((N + rows - 1) / rows);
+    hipLaunchKernelGGL(k_su_sums, dim3(nblk), dim3(kBlock), 0, s, X, ybar, N, n, rows, (const double*)su, 0, part);
+    hipLaunchKernelGGL(k_su_means_final, dim3(1), dim3(64), 0, s, (const double*)part, nblk, N, n, su, st);
+    hipLaunchKernelGGL(k_su_sums, dim3(nblk), dim3(kBlock), 0, s, X, ybar, N, n, rows, (const double*)su, 2, part);
+    hipLaunchKernelGGL(k_su_fit_final, dim3(1), dim3(64), 0, s, (const double*)part, nblk, n, su);
+    const int nb = (int)((N + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_su_start, dim3(nb), dim3(kBlock), 0, s, X, ybar, N, n, (const double*)su, y0, xi0, part);
+    hipLaunchKernelGGL(k_su_start_final, dim3(1), dim3(64), 0, s, (const double*)part, nb, N, n, gamma,
+                       (const double*)su, st);
+    return hipGetLastError();
+}
+
 hipError_t launch_setup(const double* X, const double* ybar, int64_t N, int n, double gamma, double* su,
                         double* part, double* y0, double* xi0, DevState* st, hipStream_t s) {
-    const int64_t rows = 1024;
+    const int64_t rows = kSuRows;
     const int nblk = (int)((N + rows - 1) / rows);
     hipLaunchKernelGGL(k_su_sums, dim3(nblk), dim3(kBlock), 0, s, X, ybar, N, n, rows, (const double*)su, 0, part);
     hipLaunchKernelGGL(k_su_means_final, dim3(1), dim3(64), 0, s, (const double*)part, nblk, N, n, su, st);

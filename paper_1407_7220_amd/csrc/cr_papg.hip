@@ -14,8 +14,9 @@
 //               u = A3^T theta2 + theta2_y, v = A4^T theta2.  One workgroup
 //               per point l, reading row l and column l of theta2.
 //  k_papg_step2 step 2 before the ball: theta^(1)_l = max(theta2 - C eta / L, 0)
-//               written over tp, with per-row sums of theta^2 and of the
-//               negative parts of the cross residuals.  One workgroup per row.
+//               written over tp, with per-row sums of theta^2, of the squared
+//               negative parts of the cross residuals and of theta2 * (C eta).
+//               One workgroup per row.
 //  k_papg_ball  ||theta||, the scale of the projection onto the ball of Q2.
 //  k_papg_scale the scale applied (only when the ball is active).
 //
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_papg_step2(PapgArgs a) {
     for (int k = 0; k < kPapgMaxN; ++k) xi_[k] = k < n ? a.X[i * n + k] : 0.0;
     const double yi = a.y[i];
     const double L = a.L;
-    double s2 = 0.0, neg2 = 0.0;
+    double s2 = 0.0, neg2 = 0.0, gap = 0.0;
     for (int64_t j = threadIdx.x; j < N; j += kBlock) {
         const int64_t idx = i * N + j;
         double tn = 0.0;
@@ -101,8 +102,10 @@ __global__ __launch_bounds__(kBlock) void k_papg_step2(PapgArgs a) {
             for (int k = 0; k < kPapgMaxN; ++k)
                 if (k < n) h += (a.xis[j * n + k] + a.shift[j * n + k]) * (xi_[k] - a.X[j * n + k]);
             const double r = (yi - a.y[j]) - h;
-            tn = fmax(theta2_at(a, idx) - r / L, 0.0);
+            const double t2 = theta2_at(a, idx);
+            tn = fmax(t2 - r / L, 0.0);
             if (r < 0.0) neg2 += r * r;
+            gap += t2 * r;
         }
         a.tp[idx] = tn;
         s2 += tn * tn;
@@ -112,27 +115,36 @@ __global__ __launch_bounds__(kBlock) void k_papg_step2(PapgArgs a) {
         const double tn = fmax(ty - yi / L, 0.0);
         a.typ[i] = tn;
         s2 += tn * tn;
+        gap += ty * yi;
     }
     block_sum2(s2, neg2);
+    gap = block_reduce(gap, 0);
     if (threadIdx.x == 0) {
-        a.part[2 * i] = s2;
-        a.part[2 * i + 1] = neg2;
+        a.part[3 * i] = s2;
+        a.part[3 * i + 1] = neg2;
+        a.part[3 * i + 2] = gap;
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_papg_ball(PapgArgs a) {
-    double s = 0.0, g = 0.0;
+    double s = 0.0, g = 0.0, d = 0.0;
     for (int64_t i = threadIdx.x; i < a.N; i += kBlock) {
-        s += a.part[2 * i];
-        g += a.part[2 * i + 1];
+        s += a.part[3 * i];
+        g += a.part[3 * i + 1];
+        d += a.part[3 * i + 2];
     }
     block_sum2(s, g);
+    d = block_reduce(d, 0);
     if (threadIdx.x == 0) {
         const double nrm = sqrt(s);
         const double sc = (a.B > 0.0 && isfinite(a.B) && nrm > a.B) ? a.B / nrm : 1.0;
         a.scal[0] = sc;
         a.scal[1] = nrm * sc;
         a.scal[2] = sqrt(g);
+        a.scal[3] = d;
+        a.trace[3 * a.it] = nrm * sc;
+        a.trace[3 * a.it + 1] = sqrt(g);
+        a.trace[3 * a.it + 2] = d;
     }
 }
 

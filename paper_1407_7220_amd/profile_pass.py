@@ -11,10 +11,15 @@ for scaling hardware byte counters.  Run it under rocprofv3, e.g.
 --kernel adjoint  adjoint pair passes of a MAPG step (k_adj_pass) after one
                   forward and reverse run of 2 x 2 unrolled iterations;
 --kernel eval     estimator evaluations (k_eval) of the workload's tangent planes
-                  (f0(x_l), grad f0(x_l)) at N query points q ~ U[-1,1]^n.
+                  (f0(x_l), grad f0(x_l)) at N query points q ~ U[-1,1]^n;
+--kernel papg     P-APG runs (cr_papg: k_papg_lin, k_papg_step2 and the batched
+                  block solves) on the Sec. III study problem at N = 4096,
+                  n = 5, K = 4, FP32 blocks of 4 x 40 MAPG steps, --reps
+                  iterations after one untimed run of the same length.
 """
 import argparse
 import os
+import time
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -24,7 +29,7 @@ if ROOT not in sys.path:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--kernel", choices=("pass", "adjoint", "eval"), default="pass")
+    ap.add_argument("--kernel", choices=("pass", "adjoint", "eval", "papg"), default="pass")
     ap.add_argument("--workload", default=None)
     ap.add_argument("--precision", choices=("f32", "f64", "mixed_bf16"), default="f32")
     ap.add_argument("--reps", type=int, default=20)
@@ -33,6 +38,19 @@ def main():
     import paper_1407_7220_amd as cr
     from paper_1407_7220_amd import autotune
     import synth
+    if args.kernel == "papg":
+        q = synth.gaussian_quadratic(4096, 5, seed=0)
+        X, yb = torch.from_numpy(q.X).cuda(), torch.from_numpy(q.ybar).cuda()
+        params = cr.Params(precision=cr.F32, gamma=0.05, inner_iters=40, max_outer=4)
+        pp = cr.PapgParams(K=4, iters=args.reps)
+        cr.papg(X, yb, pp, params)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, info = cr.papg(X, yb, pp, params)
+        torch.cuda.synchronize()
+        print("workload gaussian_quadratic N=4096 n=5 K=4: %d P-APG iterations, %.3f ms each"
+              % (args.reps, (time.perf_counter() - t0) / args.reps * 1e3), flush=True)
+        return
     workload = args.workload or {"pass": "logsumexp_5000", "adjoint": "quadratic_10000",
                                  "eval": "maxaffine_20000"}[args.kernel]
     p = synth.workload(workload)

@@ -199,11 +199,14 @@ def test_papg_workspace_and_argument_checks():
     with pytest.raises(cr.CRError) as e:
         cr.papg_workspace_bytes(100, 5, cr.Params(precision=cr.MIXED_BF16), cr.PapgParams(K=2))
     assert e.value.status == 7
+    with pytest.raises(cr.CRError) as e:
+        cr.papg_workspace_bytes(100, 5, p, cr.PapgParams(K=2, method=2))
+    assert e.value.status == 1
     fake = ctypes.c_void_p(0x1000)
     cp, cpp = p.to_c(), cr.PapgParams(K=2, iters=3).to_c()
     lib = cr._lib
-    assert lib.cr_papg(None, fake, 100, 5, ctypes.byref(cp), ctypes.byref(cpp), fake, fake, None, None, fake,
+    assert lib.cr_papg(None, fake, 100, 5, ctypes.byref(cp), ctypes.byref(cpp), fake, fake, None, None, None, fake,
                        1 << 30, None, None) == 1
-    assert lib.cr_papg(fake, fake, 100, 5, ctypes.byref(cp), ctypes.byref(cpp), fake, fake, None, None, fake,
+    assert lib.cr_papg(fake, fake, 100, 5, ctypes.byref(cp), ctypes.byref(cpp), fake, fake, None, None, None, fake,
                        16, None, None) == 2
     assert b"workspace" in lib.cr_last_error(None)

@@ -51,10 +51,12 @@ def rel(a, b):
 TOL = 1e-9
 
 
-def _run(cr, p, K, iters, inner, outer, gamma, L=0.0, B=math.inf, y_shift=None, prec=0):
+def _run(cr, p, K, iters, inner, outer, gamma, L=0.0, B=math.inf, y_shift=None, prec=0, accelerate=True):
     sched = dict(gamma=gamma, inner_iters=inner, max_outer=outer)
-    ref = opapg.papg(p.X, p.ybar, K, gamma, iters, oracle.Params(**sched), L=L, B_theta=B, y_shift=y_shift)
-    pp = cr.PapgParams(K=K, iters=iters, L=L, B_theta=B, y_shift=-1.0 if y_shift is None else y_shift)
+    ref = opapg.papg(p.X, p.ybar, K, gamma, iters, oracle.Params(**sched), L=L, B_theta=B, y_shift=y_shift,
+                     record=True, accelerate=accelerate)
+    pp = cr.PapgParams(K=K, iters=iters, L=L, B_theta=B, y_shift=-1.0 if y_shift is None else y_shift,
+                       method=cr.PAPG_ACCELERATED if accelerate else cr.PAPG_GRADIENT)
     y, xi, info, th, thy = cr.papg(dev(p.X), dev(p.ybar), pp, cr.Params(precision=prec, **sched), with_theta=True)
     return ref, host(y), host(xi), info, host(th), host(thy)
 
@@ -137,3 +139,39 @@ def test_papg_rejects_bad_arguments(cr):
     with pytest.raises(cr.CRError) as e:
         cr.papg(dev(p.X), dev(bad), cr.PapgParams(K=2, iters=1), cr.Params(precision=0, inner_iters=5))
     assert e.value.status == 4
+
+
+def _check_trace(trace, ref):
+    # per iteration: ||theta^(1)_l||, cross-block infeasibility at eta_l, theta^(2)_l^T C eta_l
+    for col, key in enumerate(("theta_norm", "infeas_cross", "gap")):
+        r = np.array([t[key] for t in ref.trace])
+        scale = max(np.abs(r).max(), 1e-300)
+        assert np.abs(trace[:, col] - r).max() <= 1e-9 * scale, key
+
+
+def test_gradient_ascent_matches_oracle(cr):
+    p = synth.quadratic_uniform(64, 3, seed=11)
+    say("projected gradient ascent (no momentum) N=64 n=3 K=4, 4 iterations of 3 x 32")
+    ref, y, xi, info, th, thy = _run(cr, p, 4, 4, 32, 3, 0.1, accelerate=False)
+    ey, eth = rel(y, ref.y), rel(th, ref.Th)
+    say("  relative error vs FP64 oracle: y %.3e  theta %.3e" % (ey, eth))
+    assert ey < TOL and eth < TOL * 10
+    _check_trace(info["trace"], ref)
+
+
+def test_small_study_accelerated_against_gradient_ascent(cr):
+    # the comparison of Sec. III on its problem: n = 5, N = 100, K = 2,
+    # f0 = 1/2 x^T Q x with Q = Lambda^T Lambda, Lambda, x, eps ~ N(0, 1)
+    p = synth.gaussian_quadratic(100, 5, seed=0)
+    say("Sec. III study N=100 n=5 K=2: P-APG and gradient ascent, 40 iterations of 4 x 40")
+    out = {}
+    for acc in (True, False):
+        ref, y, xi, info, th, thy = _run(cr, p, 2, 40, 40, 4, 0.05, accelerate=acc)
+        _check_trace(info["trace"], ref)
+        assert rel(y, ref.y) < TOL and rel(th, ref.Th) < TOL * 10
+        out[acc] = info["trace"]
+        say("  %s: infeasibility %.4e -> %.4e, ||theta|| %.4e"
+            % ("P-APG" if acc else "ascent", info["trace"][0, 1], info["trace"][-1, 1], info["trace"][-1, 0]))
+    # the accelerated dual iterates move further: lower cross-block infeasibility
+    assert out[True][-1, 1] < out[False][-1, 1]
+    assert out[True][-1, 0] > out[False][-1, 0]

@@ -198,3 +198,18 @@ def test_step1_minimises_the_lagrangian_slsqp():
     np.testing.assert_allclose(y, res.x[:N], rtol=0, atol=2e-3)
     np.testing.assert_allclose(xi[:, 0], res.x[N:], rtol=0, atol=2e-2)
     assert f(np.concatenate([y, xi[:, 0]])) <= res.fun + 1e-4
+
+
+def test_trace_identity_and_gradient_variant():
+    # gap = theta2^T C eta is the primal objective minus the Lagrangian
+    # (eq. "g_gamma"); without momentum the first two iterations coincide with
+    # P-APG (beta_1 = (t_1 - 1)/t_2 = 0) and the third differs
+    X, yb = _data(12, 2, 11)
+    p = oracle.Params(gamma=0.1, inner_iters=30, max_outer=3)
+    a = pp.papg(X, yb, 2, 0.1, 3, p, record=True)
+    b = pp.papg(X, yb, 2, 0.1, 3, p, record=True, accelerate=False)
+    for t in a.trace + b.trace:
+        assert abs((t["primal"] - t["g"]) - t["gap"]) <= 1e-10 * (1 + abs(t["primal"]))
+    for k in ("theta_norm", "infeas_cross", "gap"):
+        assert a.trace[0][k] == b.trace[0][k] and a.trace[1][k] == b.trace[1][k]
+    assert a.trace[2]["theta_norm"] != b.trace[2]["theta_norm"]
