@@ -1055,6 +1055,16 @@ cr_status cr_batch_run(cr_batch* b, cr_info* infos, double* seconds) {
         for (int q = 0; q < P; ++q)
             if (!sch[q].done)
                 BHIPCHK(b, enqueue_multiplier_step(b->sub[q], mus[q], mun[q], launched, b->plan.nblk[q], cs));
+        if (fixed) {
+            // nothing of the schedule depends on the device: enqueue the next
+            // ALCC iteration at once; the state is read back after the last
+            // (a non-finite iterate stays non-finite until then)
+            for (int q = 0; q < P; ++q) {
+                sch[q].total_inner += lmax_all;
+                sch[q].advance(b->sub[q]);
+            }
+            continue;
+        }
         BHIPCHK(b, hipStreamSynchronize(cs));
         bool all_done = true;
         for (int q = 0; q < P; ++q) {
@@ -1071,6 +1081,13 @@ cr_status cr_batch_run(cr_batch* b, cr_info* infos, double* seconds) {
             all_done = false;
         }
         if (all_done) break;
+    }
+    if (fixed) {
+        BHIPCHK(b, hipStreamSynchronize(cs));
+        for (int q = 0; q < P; ++q) {
+            sch[q].last = *b->sub[q]->pinned_state;
+            if (sch[q].last.iterate_nonfinite) result = CR_ERR_NONFINITE;
+        }
     }
     for (int q = 0; q < P; ++q) {
         cr_ctx* c = b->sub[q];

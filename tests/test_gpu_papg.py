@@ -175,3 +175,24 @@ def test_small_study_accelerated_against_gradient_ascent(cr):
     # the accelerated dual iterates move further: lower cross-block infeasibility
     assert out[True][-1, 1] < out[False][-1, 1]
     assert out[True][-1, 0] > out[False][-1, 0]
+
+
+def test_papg_approaches_the_direct_solution(cr):
+    # A property at any size: as the dual iterates improve, eta(theta) approaches
+    # the solution y(gamma) of eq. "regularize" (which eq. "omega_primal" equals
+    # once y >= 0 is inactive), and the cross-block constraints are met better.
+    p = synth.quadratic_uniform(40, 2, seed=21)
+    X, yb = dev(p.X), dev(p.ybar)
+    say("papg convergence N=40 n=2 K=2: 25, 100, 400 iterations of 8 x 100 against a direct solve to KKT 1e-5")
+    yd, _, info = cr.solve(X, yb, cr.Params(precision=0, gamma=0.1, kkt_tol=1e-5, max_outer=30))
+    assert info.status == 0 and info.kkt <= 1e-5
+    yd = host(yd)
+    err, inf = [], []
+    for it in (25, 100, 400):
+        y, xi, pinfo = cr.papg(X, yb, cr.PapgParams(K=2, iters=it),
+                               cr.Params(precision=0, gamma=0.1, inner_iters=100, max_outer=8))
+        err.append(float(np.linalg.norm(host(y) - yd)))
+        inf.append(pinfo["infeas_cross"])
+        say("  %3d iterations: |y - y(gamma)| %.3e  cross infeasibility %.3e" % (it, err[-1], inf[-1]))
+    assert err[0] > err[1] > err[2] and inf[0] > inf[1] > inf[2]
+    assert inf[2] < inf[0] / 10 and err[2] < err[0] / 4
