@@ -410,7 +410,8 @@ cr_status cr_papg(const void* X_dev, const void* ybar_dev, int64_t N, int32_t n,
  * M = 0 is a no-op.  A query whose plane values are all NaN gets
  * fhat = -Inf and arg = INT64_MAX.
  * Errors (checked on the host, before any HIP call): CR_ERR_ARG (NULL
- * pointers, N < 1, n < 1, M < 0), CR_ERR_UNSUPPORTED (n > CR_MAX_DIM),
+ * pointers, N < 1, n < 1, M < 0), CR_ERR_UNSUPPORTED (n > CR_MAX_DIM or
+ * N >= 2^31 - 64),
  * CR_ERR_NOMEM (workspace too small); CR_ERR_HIP on a failed launch.
  * Messages in cr_last_error(NULL). */
 cr_status cr_eval_workspace_bytes(int64_t N, int32_t n, size_t* bytes);

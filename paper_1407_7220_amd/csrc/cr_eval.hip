@@ -27,8 +27,9 @@ namespace cr {
 constexpr int kEvalRows = 32;     // queries per workgroup
 constexpr int kEvalCols = 32;     // planes per wave step
 
-// Packed plane operands: row l holds [xi_l (n), d_l, 0 ...] (4 KS doubles);
-// rows l >= N are zero (and masked out by index).
+// Packed plane operands: row l holds [xi_l (n), d_l, 0 ...] (4 KS doubles).
+// Padding rows l >= N hold d = -Inf and zeros: their value -Inf at every valid
+// query never exceeds a running maximum, so the loop needs no index mask.
 __global__ __launch_bounds__(kBlock) void k_eval_prep(const double* __restrict__ X, const double* __restrict__ y,
                                                       const double* __restrict__ xi, int64_t N, int n, int kp,
                                                       int64_t Npad, double* __restrict__ B) {
@@ -45,6 +46,8 @@ __global__ __launch_bounds__(kBlock) void k_eval_prep(const double* __restrict__
             for (int q = 0; q < n; ++q) s += X[l * n + q] * xi[l * n + q];
             v = y[l] - s;
         }
+    } else if (k == n) {
+        v = -INFINITY;
     }
     B[e] = v;
 }
@@ -59,7 +62,7 @@ struct EvalArgs {
     int64_t* arg;             // M or null
 };
 
-__device__ __forceinline__ void better(double& bv, int64_t& bl, double v, int64_t l) {
+__device__ __forceinline__ void better(double& bv, int32_t& bl, double v, int32_t l) {
     if (v > bv || (v == bv && l < bl)) { bv = v; bl = l; }
 }
 
@@ -84,13 +87,14 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a) {
         }
     }
 
-    // Running (max, argmax) of this lane's 4 accumulator rows (g + 4 v) per block.
+    // Running (max, argmax) of this lane's 4 accumulator rows (g + 4 v) per
+    // block; plane indices fit 32 bits (N < 2^31 is checked by the host).
     double bv[2][4];
-    int64_t bl[2][4];
+    int32_t bl[2][4];
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) { bv[rb][v] = -INFINITY; bl[rb][v] = INT64_MAX; }
+        for (int v = 0; v < 4; ++v) { bv[rb][v] = -INFINITY; bl[rb][v] = INT32_MAX; }
 
     // B operands of one 32-plane tile: lane (g, c) holds plane (tile + 16 h + c), slot 4 s + g
     auto load_b = [&](int64_t t, double (&b)[2][KS]) {
@@ -109,16 +113,19 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a) {
         load_b(t + kWaves, bnext);                              // next tile in flight during this one
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int64_t l = t * kEvalCols + 16 * h + c;       // this lane's plane
-            const bool lv = l < a.N;
+            const int32_t l = (int32_t)t * kEvalCols + 16 * h + c;   // this lane's plane
 #pragma unroll
             for (int rb = 0; rb < 2; ++rb) {
                 f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int s = 0; s < KS; ++s) acc = mfma4(A[rb][s], bcur[h][s], acc);
+                // l increases along a lane: a strict test keeps the first of equal
+                // values; fmax keeps the running value when acc is NaN
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    if (lv && acc[v] > bv[rb][v]) { bv[rb][v] = acc[v]; bl[rb][v] = l; }   // l increases: ties keep the first
+                for (int v = 0; v < 4; ++v) {
+                    bl[rb][v] = acc[v] > bv[rb][v] ? l : bl[rb][v];
+                    bv[rb][v] = fmax(bv[rb][v], acc[v]);
+                }
             }
         }
 #pragma unroll
@@ -135,11 +142,11 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a) {
 #pragma unroll
             for (int o = 1; o < 16; o <<= 1) {
                 const double ov = __shfl_xor(bv[rb][v], o);
-                const int64_t ol = __shfl_xor(bl[rb][v], o);
+                const int32_t ol = __shfl_xor(bl[rb][v], o);
                 better(bv[rb][v], bl[rb][v], ov, ol);
             }
     __shared__ double sv[kWaves][kEvalRows];
-    __shared__ int64_t sl[kWaves][kEvalRows];
+    __shared__ int32_t sl[kWaves][kEvalRows];
     if (c == 0) {
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
@@ -154,12 +161,12 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a) {
     if (threadIdx.x < kEvalRows) {
         const int r = threadIdx.x;
         double best = sv[0][r];
-        int64_t bi = sl[0][r];
+        int32_t bi = sl[0][r];
         for (int w = 1; w < kWaves; ++w) better(best, bi, sv[w][r], sl[w][r]);
         const int64_t m = m0 + r;
         if (m < a.M) {
             a.f[m] = best;
-            if (a.arg) a.arg[m] = bi;
+            if (a.arg) a.arg[m] = bi == INT32_MAX ? INT64_MAX : (int64_t)bi;
         }
     }
 }
@@ -202,6 +209,7 @@ cr_status cr_eval_workspace_bytes(int64_t N, int32_t n, size_t* bytes) {
     if (!bytes) return eval_fail(CR_ERR_ARG, "bytes is NULL");
     if (N < 1 || n < 1) return eval_fail(CR_ERR_ARG, "N and n must be >= 1");
     if (n > CR_MAX_DIM) return eval_fail(CR_ERR_UNSUPPORTED, "n above CR_MAX_DIM is not supported");
+    if (N >= ((int64_t)1 << 31) - 64) return eval_fail(CR_ERR_UNSUPPORTED, "N must be below 2^31 - 64");
     *bytes = eval_ws_bytes(N, n);
     return CR_OK;
 }
@@ -209,6 +217,7 @@ cr_status cr_eval_workspace_bytes(int64_t N, int32_t n, size_t* bytes) {
 cr_status cr_eval(const void* X_dev, const void* y_dev, const void* xi_dev, int64_t N, int32_t n, const void* Q_dev,
                   int64_t M, void* fhat_dev, int64_t* arg_dev, void* workspace_dev, size_t ws_bytes, void* stream) {
     if (N < 1 || n < 1 || M < 0) return eval_fail(CR_ERR_ARG, "N and n must be >= 1 and M >= 0");
+    if (N >= ((int64_t)1 << 31) - 64) return eval_fail(CR_ERR_UNSUPPORTED, "N must be below 2^31 - 64");
     if (n > CR_MAX_DIM) return eval_fail(CR_ERR_UNSUPPORTED, "n above CR_MAX_DIM is not supported");
     if (!X_dev || !y_dev || !xi_dev || !workspace_dev || (M > 0 && (!Q_dev || !fhat_dev)))
         return eval_fail(CR_ERR_ARG, "X, y, xi, Q, fhat and the workspace must be non-NULL");

@@ -68,6 +68,10 @@ CASES = [
      40, 4, 0.05),
     ("quadratic_uniform N=90 n=3 K=3", lambda: synth.quadratic_uniform(90, 3, seed=4), 3, 3, 33, 3, 0.1),
     ("quad_l1_gaussian N=96 n=7 K=4", lambda: synth.quad_l1_gaussian(96, 7, seed=5), 4, 2, 31, 3, 0.2),
+    # the widest points (n = CR_MAX_DIM), two-point blocks, and a ragged size spanning several tiles
+    ("quadratic_uniform N=64 n=31 K=2", lambda: synth.quadratic_uniform(64, 31, seed=95), 2, 2, 20, 2, 0.1),
+    ("quadratic_uniform N=24 n=2 K=12", lambda: synth.quadratic_uniform(24, 2, seed=26), 12, 3, 20, 3, 0.1),
+    ("quadratic_uniform N=1000 n=10 K=4", lambda: synth.quadratic_uniform(1000, 10, seed=1010), 4, 2, 32, 2, 0.1),
 ]
 
 
@@ -196,3 +200,25 @@ def test_papg_approaches_the_direct_solution(cr):
         say("  %3d iterations: |y - y(gamma)| %.3e  cross infeasibility %.3e" % (it, err[-1], inf[-1]))
     assert err[0] > err[1] > err[2] and inf[0] > inf[1] > inf[2]
     assert inf[2] < inf[0] / 10 and err[2] < err[0] / 4
+
+
+def test_papg_with_adaptive_block_solves(cr):
+    # block solves to KKT <= 1e-4 instead of a fixed schedule: no parity (the
+    # stopping tests are discontinuous), but the run must improve on the
+    # block-diagonal start as with fixed schedules
+    p = synth.quadratic_uniform(40, 2, seed=21)
+    X, yb = dev(p.X), dev(p.ybar)
+    say("papg with adaptive block solves (KKT 1e-4, at most 1000 MAPG steps per ALCC iteration) N=40 n=2 K=2, "
+        "1 and 20 iterations")
+    adaptive = cr.Params(precision=0, gamma=0.1, kkt_tol=1e-4, max_outer=30, max_inner=1000)
+    yd, _, info = cr.solve(X, yb, cr.Params(precision=0, gamma=0.1, kkt_tol=1e-5, max_outer=30))
+    assert info.status == 0
+    yd = host(yd)
+    y1, _, i1 = cr.papg(X, yb, cr.PapgParams(K=2, iters=1), adaptive)
+    y20, _, i20 = cr.papg(X, yb, cr.PapgParams(K=2, iters=20), adaptive)
+    e1, e20 = np.linalg.norm(host(y1) - yd), np.linalg.norm(host(y20) - yd)
+    say("  |y - y(gamma)|: %.3e after 1, %.3e after 20; cross infeasibility %.3e -> %.3e; MAPG steps %d, %d"
+        % (e1, e20, i1["infeas_cross"], i20["infeas_cross"], i1["inner_iters"], i20["inner_iters"]))
+    assert np.all(np.isfinite(host(y20)))
+    assert e20 < e1 and i20["infeas_cross"] < i1["infeas_cross"] / 1.2
+    assert i1["inner_iters"] > 0 and i20["inner_iters"] > 10 * i1["inner_iters"]
