@@ -222,3 +222,65 @@ def test_papg_with_adaptive_block_solves(cr):
     assert np.all(np.isfinite(host(y20)))
     assert e20 < e1 and i20["infeas_cross"] < i1["infeas_cross"] / 1.2
     assert i1["inner_iters"] > 0 and i20["inner_iters"] > 10 * i1["inner_iters"]
+
+
+def _dense_C(X, K):
+    # C = [A3 A4; I 0] (eq. "C") row by row, for sigma_max(C) of a small case
+    N, n = X.shape
+    mask = opapg.cross_mask(N, K)
+    rows = []
+    for i in range(N):
+        for j in range(N):
+            if mask[i, j]:
+                r = np.zeros(N + N * n)
+                r[i] += 1.0
+                r[j] -= 1.0
+                r[N + j * n:N + (j + 1) * n] = -(X[i] - X[j])
+                rows.append(r)
+    for i in range(N):
+        r = np.zeros(N + N * n)
+        r[i] = 1.0
+        rows.append(r)
+    return np.array(rows)
+
+
+def test_theorem1_bounds_on_the_dual_iterates(cr):
+    # Theorem 1 through its intermediate bound eq. "mixed_bound": for a
+    # delta-optimal theta_delta in Q2 and eta_delta minimising the Lagrangian
+    # there, ||y_delta - y(gamma)|| and ||(A3 y_delta + A4 xi_delta)_-|| are at most
+    # sqrt(2 delta / gamma) sigma_max(C).  Gradient ascent keeps theta^(2) in Q2;
+    # g* = the optimal value of eq. "regularize" (strong duality, y >= 0
+    # inactive after the shift) from a direct solve, g(theta^(2)_l) = the
+    # objective at eta_l minus the reported theta^(2)_l^T C eta_l.  Ascent with
+    # step 1/L >= 1/L_g also increases g monotonically, and P-APG's delta falls
+    # faster (the accelerated rate).
+    N, n, K, gamma = 40, 2, 2, 0.1
+    p = synth.quadratic_uniform(N, n, seed=21)
+    X, yb = dev(p.X), dev(p.ybar)
+    say("Theorem 1 bounds: N=40 n=2 K=2, gradient ascent 20 / 100 / 300 iterations and P-APG 300, blocks 8 x 100")
+    yd, xid, info = cr.solve(X, yb, cr.Params(precision=0, gamma=gamma, kkt_tol=1e-6, max_outer=30))
+    assert info.status == 0
+    yd, xid = host(yd), host(xid)
+    gstar = 0.5 * np.sum((yd - p.ybar) ** 2) + 0.5 * gamma * np.sum(xid ** 2)
+    smax = np.linalg.norm(_dense_C(p.X, K), 2)
+    blocks = cr.Params(precision=0, gamma=gamma, inner_iters=100, max_outer=8)
+
+    def run(it, method):
+        y, xi, pinfo = cr.papg(X, yb, cr.PapgParams(K=K, iters=it, method=method), blocks)
+        y, xi = host(y), host(xi)
+        gval = 0.5 * np.sum((y - p.ybar) ** 2) + 0.5 * gamma * np.sum(xi ** 2) - pinfo["trace"][-1, 2]
+        return gstar - gval, float(np.linalg.norm(y - yd)), pinfo["infeas_cross"]
+
+    deltas = []
+    for it in (20, 100, 300):
+        delta, dy, infx = run(it, cr.PAPG_GRADIENT)
+        rhs = math.sqrt(max(2.0 * delta / gamma, 0.0)) * smax
+        say("  ascent %3d iterations: delta %.3e  |y - y(gamma)| %.3e  cross infeasibility %.3e  bound %.3e"
+            % (it, delta, dy, infx, rhs))
+        assert delta > 0.0
+        assert dy <= rhs and infx <= rhs
+        deltas.append(delta)
+    assert deltas[0] > deltas[1] > deltas[2]
+    delta, dy, infx = run(300, cr.PAPG_ACCELERATED)
+    say("  P-APG  300 iterations: delta %.3e  |y - y(gamma)| %.3e  cross infeasibility %.3e" % (delta, dy, infx))
+    assert 0.0 < delta < deltas[2] / 5
