@@ -1559,7 +1559,7 @@ namespace {
 struct PapgLayout {
     int64_t N = 0, Nbar = 0;
     int n = 0, K = 0;
-    size_t th[2], ty[2], ybs, shift, y, xis, part, scal, trace, su, supart, y0, xi0, st, batch;
+    size_t th[2], ty[2], ybs, shift, y, xis, part, cpart, scal, trace, su, supart, y0, xi0, st, batch;
     size_t batch_bytes = 0, total = 0;
 };
 
@@ -1601,7 +1601,8 @@ PapgLayout papg_layout(int64_t N, int n, const cr_params* alcc, const cr_papg_pa
     P.shift = take((size_t)N * n * 8);
     P.y = take((size_t)N * 8);
     P.xis = take((size_t)N * n * 8);
-    P.part = take((size_t)N * 3 * 8);
+    P.part = take((size_t)cr::papg_step_parts(N) * 3 * 8);
+    P.cpart = take((size_t)cr::papg_col_chunks(N) * N * (n + 1) * 8);
     P.scal = take(64);
     P.trace = take((size_t)pp->iters * 3 * 8);
     // set-up of the whole point set, for sigma_max(A2)^2 of the default L
@@ -1712,7 +1713,7 @@ cr_status cr_papg(const void* X_dev, const void* ybar_dev, int64_t N, int32_t n,
     double* th[2] = {D(P.th[0]), D(P.th[1])};
     double* ty[2] = {D(P.ty[0]), D(P.ty[1])};
     a.ybs = D(P.ybs); a.shift = D(P.shift); a.y = D(P.y); a.xis = D(P.xis);
-    a.part = D(P.part); a.scal = D(P.scal); a.trace = D(P.trace);
+    a.part = D(P.part); a.cpart = D(P.cpart); a.scal = D(P.scal); a.trace = D(P.trace);
     for (int q = 0; q < 2; ++q) {
         PCHK(cr::launch_zero(th[q], (size_t)N * N * 8, us));
         PCHK(cr::launch_zero(ty[q], (size_t)N * 8, us));

@@ -228,10 +228,17 @@ struct PapgArgs {
     double* shift;            // block slope centres v / gamma (N x n)
     const double* y;          // step-1 output y (N)
     const double* xis;        // step-1 output in shifted slopes xi' (N x n)
-    double* part;             // per-row partial sums (3 per row)
+    double* part;             // per-workgroup partial sums of k_papg_step2 (3 each)
+    double* cpart;            // column partials of k_papg_colsum: [row chunk][N][n + 1]
     double* scal;             // [scale, ||theta||, ||(r_cross)_-||, theta2^T C eta]
     double* trace;            // per iteration: ||theta||, ||(r_cross)_-||, theta2^T C eta
 };
+constexpr int kPapgStepRows = 32;     // rows per workgroup of k_papg_step2
+__host__ __device__ inline int64_t papg_step_parts(int64_t N) { return ((N + kBlock - 1) / kBlock) * ((N + kPapgStepRows - 1) / kPapgStepRows); }
+// Rows per workgroup of k_papg_colsum: 64, or more once that would give more
+// than 64 row chunks (the partials hold chunks x N x (n + 1) doubles).
+__host__ __device__ inline int64_t papg_col_rows(int64_t N) { return N <= 64 * 64 ? 64 : ((N + 63) / 64 + 7) / 8 * 8; }
+__host__ __device__ inline int64_t papg_col_chunks(int64_t N) { return (N + papg_col_rows(N) - 1) / papg_col_rows(N); }
 hipError_t launch_papg_lin(const PapgArgs& a, hipStream_t s);
 hipError_t launch_papg_step2(const PapgArgs& a, hipStream_t s);
 hipError_t launch_papg_out(const PapgArgs& a, double* y_out, double* xi_out, hipStream_t s);

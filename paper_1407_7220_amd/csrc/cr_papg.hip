@@ -9,14 +9,16 @@
 // (tc) and theta^(1)_{l-2} (tp); the extrapolated point of Fig. 2 step 4,
 // theta^(2)_l = tc + beta (tc - tp), is formed on the fly wherever it is read.
 //
-//  k_papg_lin   data of the block problems of step 1 (eq. "g_gamma" after
+//  k_papg_colsum, k_papg_lin
+//               data of the block problems of step 1 (eq. "g_gamma" after
 //               completing the square): ybar + yshift + u and centres v/gamma,
-//               u = A3^T theta2 + theta2_y, v = A4^T theta2.  One workgroup
-//               per point l, reading row l and column l of theta2.
+//               u = A3^T theta2 + theta2_y, v = A4^T theta2: column partials
+//               over row chunks (thread <-> column), then one workgroup per
+//               point for its row sum and the combination.
 //  k_papg_step2 step 2 before the ball: theta^(1)_l = max(theta2 - C eta / L, 0)
-//               written over tp, with per-row sums of theta^2, of the squared
-//               negative parts of the cross residuals and of theta2 * (C eta).
-//               One workgroup per row.
+//               written over tp, with per-workgroup sums of theta^2, of the
+//               squared negative parts of the cross residuals and of
+//               theta2 * (C eta).  Tiles of 32 rows x 256 columns.
 //  k_papg_ball  ||theta||, the scale of the projection onto the ball of Q2.
 //  k_papg_scale the scale applied (only when the ball is active).
 //
@@ -29,88 +31,166 @@
 namespace cr {
 
 constexpr int kPapgMaxN = 32;
+constexpr int kPapgBatch = 8;     // rows whose loads are issued together
 
 __device__ __forceinline__ double theta2_at(const PapgArgs& a, int64_t idx) {
     const double c = a.tc[idx];
     return c + a.beta * (c - a.tp[idx]);
 }
 
+// Column sums of theta2 over one chunk of papg_col_rows(N) rows, for every column
+// l: c_l = sum_i theta2_il and w_lk = sum_i theta2_il x_ik over the rows i
+// outside l's index set.  Thread <-> column, so every row is one coalesced
+// read per array; x_i is the same for the whole workgroup.
+template <int NM>
+__global__ __launch_bounds__(kBlock) void k_papg_colsum(PapgArgs a) {
+    const int64_t N = a.N;
+    const int n = a.n;
+    const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t rows = papg_col_rows(N);
+    const int64_t i0 = (int64_t)blockIdx.y * rows, i1 = min(i0 + rows, N);
+    const bool vl = l < N;
+    const int64_t lb0 = vl ? l / a.Nbar * a.Nbar : -1, lb1 = lb0 + a.Nbar;   // l's index set [lb0, lb1)
+    double c = 0.0, w[NM];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) w[k] = 0.0;
+    // rows in batches of kPapgBatch: every load of a batch is issued first
+    for (int64_t ib = i0; ib < i1; ib += kPapgBatch) {
+        double tc[kPapgBatch], tp[kPapgBatch];
+#pragma unroll
+        for (int u = 0; u < kPapgBatch; ++u) {
+            const int64_t i = ib + u;
+            const bool ok = vl && i < i1;
+            tc[u] = ok ? a.tc[i * N + l] : 0.0;
+            tp[u] = ok ? a.tp[i * N + l] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kPapgBatch; ++u) {
+            const int64_t i = ib + u;
+            if (!(vl && i < i1) || (i >= lb0 && i < lb1)) continue;
+            const double t = tc[u] + a.beta * (tc[u] - tp[u]);
+            c += t;
+#pragma unroll
+            for (int k = 0; k < NM; ++k)
+                if (k < n) w[k] += t * a.X[i * n + k];
+        }
+    }
+    if (vl) {
+        double* out = a.cpart + ((int64_t)blockIdx.y * N + l) * (n + 1);
+        out[0] = c;
+#pragma unroll
+        for (int k = 0; k < NM; ++k)
+            if (k < n) out[1 + k] = w[k];
+    }
+}
+
+// Block data of step 1 for point l (one workgroup): the row sum of theta2 over
+// the columns outside l's set (coalesced), the column sums from the chunk
+// partials of k_papg_colsum (chunks in order), then
+//   u_l = rowsum_l - colsum_l + theta2_y,l,   v_lk = -(w_lk - x_lk colsum_l).
 __global__ __launch_bounds__(kBlock) void k_papg_lin(PapgArgs a) {
     const int64_t l = blockIdx.x;
     const int64_t N = a.N;
     const int n = a.n;
-    const int64_t bl = l / a.Nbar;
-    double su = 0.0, sv[kPapgMaxN], xl[kPapgMaxN];
+    const int64_t lb0 = l / a.Nbar * a.Nbar, lb1 = lb0 + a.Nbar;    // l's index set
+    double su = 0.0;
+    for (int64_t m = threadIdx.x; m < N; m += kBlock)
+        if (m < lb0 || m >= lb1) su += theta2_at(a, l * N + m);    // pair (l, m): +y_l
+    su = block_reduce(su, 0);
+    __shared__ double cs[kPapgMaxN + 1];
+    const int64_t chunks = papg_col_chunks(N);
+    if (threadIdx.x <= n) {
+        // chunks in order, kPapgBatch loads in flight
+        double t = 0.0;
+        for (int64_t q0 = 0; q0 < chunks; q0 += kPapgBatch) {
+            double v[kPapgBatch];
 #pragma unroll
-    for (int k = 0; k < kPapgMaxN; ++k) {
-        sv[k] = 0.0;
-        xl[k] = k < n ? a.X[l * n + k] : 0.0;
-    }
-    for (int64_t m = threadIdx.x; m < N; m += kBlock) {
-        if (m / a.Nbar == bl) continue;
-        const double r = theta2_at(a, l * N + m);    // pair (l, m): +y_l
-        const double c = theta2_at(a, m * N + l);    // pair (m, l): -y_l and -xi_l^T (x_m - x_l)
-        su += r - c;
+            for (int u = 0; u < kPapgBatch; ++u)
+                v[u] = q0 + u < chunks ? a.cpart[((q0 + u) * N + l) * (n + 1) + threadIdx.x] : 0.0;
 #pragma unroll
-        for (int k = 0; k < kPapgMaxN; ++k)
-            if (k < n) sv[k] -= c * (a.X[m * n + k] - xl[k]);
-    }
-    __shared__ double red[kBlock / 64][kPapgMaxN + 1];
-    su = wave_sum(su);
-#pragma unroll
-    for (int k = 0; k < kPapgMaxN; ++k)
-        if (k < n) sv[k] = wave_sum(sv[k]);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        red[w][kPapgMaxN] = su;
-#pragma unroll
-        for (int k = 0; k < kPapgMaxN; ++k)
-            if (k < n) red[w][k] = sv[k];
+            for (int u = 0; u < kPapgBatch; ++u) t += v[u];
+        }
+        cs[threadIdx.x] = t;                                     // [colsum, w_l0 .. w_l(n-1)]
     }
     __syncthreads();
     if (threadIdx.x <= n) {
-        const int k = threadIdx.x == n ? kPapgMaxN : (int)threadIdx.x;
-        double t = red[0][k];
-        for (int q = 1; q < kBlock / 64; ++q) t += red[q][k];
+        const double colsum = cs[0];
         if (threadIdx.x == n) {
             const double ty = a.tyc[l] + a.beta * (a.tyc[l] - a.typ[l]);
-            a.ybs[l] = (a.ybar[l] + a.yshift) + (t + ty);
+            a.ybs[l] = (a.ybar[l] + a.yshift) + ((su - colsum) + ty);
         } else {
-            a.shift[l * n + k] = t / a.gamma;
+            const int k = threadIdx.x;
+            a.shift[l * n + k] = -(cs[1 + k] - a.X[l * n + k] * colsum) / a.gamma;
         }
     }
 }
 
+// Step 2 over a tile of kPapgStepRows rows and kBlock columns: thread <-> column
+// j keeps x_j, y_j and the slope xi'_j + c_j in registers and walks the rows
+// (x_i, y_i the same for the whole workgroup), so every theta row segment is
+// one coalesced read of each array and one coalesced write.  The workgroups of
+// column block 0 also take the rows y >= 0 of their row range.
+template <int NM>
 __global__ __launch_bounds__(kBlock) void k_papg_step2(PapgArgs a) {
-    const int64_t i = blockIdx.x;
     const int64_t N = a.N;
     const int n = a.n;
-    const int64_t bi = i / a.Nbar;
-    double xi_[kPapgMaxN];
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.y * kPapgStepRows, i1 = min(i0 + kPapgStepRows, N);
+    const bool vj = j < N;
+    const int64_t jb0 = vj ? j / a.Nbar * a.Nbar : -1, jb1 = jb0 + a.Nbar;   // j's index set [jb0, jb1)
+    // the tile's rows: x_i (n values) and y_i, staged once
+    __shared__ double xs[kPapgStepRows][kPapgMaxN + 1];
+    for (int e = threadIdx.x; e < kPapgStepRows * (n + 1); e += kBlock) {
+        const int r = e / (n + 1), k = e % (n + 1);
+        const int64_t i = i0 + r;
+        xs[r][k] = i < i1 ? (k < n ? a.X[i * n + k] : a.y[i]) : 0.0;
+    }
+    __syncthreads();
+    double xj[NM], sj[NM];
 #pragma unroll
-    for (int k = 0; k < kPapgMaxN; ++k) xi_[k] = k < n ? a.X[i * n + k] : 0.0;
-    const double yi = a.y[i];
+    for (int k = 0; k < NM; ++k) {
+        xj[k] = (vj && k < n) ? a.X[j * n + k] : 0.0;
+        sj[k] = (vj && k < n) ? a.xis[j * n + k] + a.shift[j * n + k] : 0.0;
+    }
+    const double yj = vj ? a.y[j] : 0.0;
     const double L = a.L;
     double s2 = 0.0, neg2 = 0.0, gap = 0.0;
-    for (int64_t j = threadIdx.x; j < N; j += kBlock) {
-        const int64_t idx = i * N + j;
-        double tn = 0.0;
-        if (j / a.Nbar != bi) {
-            // r_ij = y_i - y_j - xi_j^T (x_i - x_j), xi_j = xi'_j + c_j
-            double h = 0.0;
+    // rows in batches of kPapgBatch: the batch's loads are issued before its
+    // stores (which overwrite tp in place, element by element)
+    for (int64_t ib = i0; ib < i1; ib += kPapgBatch) {
+        double tc[kPapgBatch], tq[kPapgBatch];
 #pragma unroll
-            for (int k = 0; k < kPapgMaxN; ++k)
-                if (k < n) h += (a.xis[j * n + k] + a.shift[j * n + k]) * (xi_[k] - a.X[j * n + k]);
-            const double r = (yi - a.y[j]) - h;
-            const double t2 = theta2_at(a, idx);
-            tn = fmax(t2 - r / L, 0.0);
-            if (r < 0.0) neg2 += r * r;
-            gap += t2 * r;
+        for (int u = 0; u < kPapgBatch; ++u) {
+            const int64_t i = ib + u;
+            const bool ok = vj && i < i1;
+            tc[u] = ok ? a.tc[i * N + j] : 0.0;
+            tq[u] = ok ? a.tp[i * N + j] : 0.0;
         }
-        a.tp[idx] = tn;
-        s2 += tn * tn;
+#pragma unroll
+        for (int u = 0; u < kPapgBatch; ++u) {
+            const int64_t i = ib + u;
+            if (!(vj && i < i1)) continue;
+            double tn = 0.0;
+            if (i < jb0 || i >= jb1) {
+                // r_ij = y_i - y_j - xi_j^T (x_i - x_j), xi_j = xi'_j + c_j
+                const double* xr = xs[ib + u - i0];
+                double h = 0.0;
+#pragma unroll
+                for (int k = 0; k < NM; ++k)
+                    if (k < n) h += sj[k] * (xr[k] - xj[k]);
+                const double r = (xr[n] - yj) - h;
+                const double t2 = tc[u] + a.beta * (tc[u] - tq[u]);
+                tn = fmax(t2 - r / L, 0.0);
+                if (r < 0.0) neg2 += r * r;
+                gap += t2 * r;
+            }
+            a.tp[i * N + j] = tn;
+            s2 += tn * tn;
+        }
     }
-    if (threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x < i1 - i0) {
+        const int64_t i = i0 + threadIdx.x;
+        const double yi = a.y[i];
         const double ty = a.tyc[i] + a.beta * (a.tyc[i] - a.typ[i]);
         const double tn = fmax(ty - yi / L, 0.0);
         a.typ[i] = tn;
@@ -120,15 +200,17 @@ __global__ __launch_bounds__(kBlock) void k_papg_step2(PapgArgs a) {
     block_sum2(s2, neg2);
     gap = block_reduce(gap, 0);
     if (threadIdx.x == 0) {
-        a.part[3 * i] = s2;
-        a.part[3 * i + 1] = neg2;
-        a.part[3 * i + 2] = gap;
+        const int64_t wg = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+        a.part[3 * wg] = s2;
+        a.part[3 * wg + 1] = neg2;
+        a.part[3 * wg + 2] = gap;
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_papg_ball(PapgArgs a) {
     double s = 0.0, g = 0.0, d = 0.0;
-    for (int64_t i = threadIdx.x; i < a.N; i += kBlock) {
+    const int64_t parts = papg_step_parts(a.N);
+    for (int64_t i = threadIdx.x; i < parts; i += kBlock) {
         s += a.part[3 * i];
         g += a.part[3 * i + 1];
         d += a.part[3 * i + 2];
@@ -166,13 +248,23 @@ __global__ __launch_bounds__(kBlock) void k_papg_out(PapgArgs a, double* y_out, 
     if (e < a.N) y_out[e] = a.y[e] - a.yshift;
 }
 
+// The per-thread arrays of the tiled kernels hold NM >= n slots.
 hipError_t launch_papg_lin(const PapgArgs& a, hipStream_t s) {
+    const unsigned cb = (unsigned)((a.N + kBlock - 1) / kBlock);
+    const dim3 g(cb, (unsigned)papg_col_chunks(a.N));
+    if (a.n <= 8) hipLaunchKernelGGL(k_papg_colsum<8>, g, dim3(kBlock), 0, s, a);
+    else if (a.n <= 16) hipLaunchKernelGGL(k_papg_colsum<16>, g, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL(k_papg_colsum<kPapgMaxN>, g, dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_papg_lin, dim3((unsigned)a.N), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_papg_step2(const PapgArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_papg_step2, dim3((unsigned)a.N), dim3(kBlock), 0, s, a);
+    const unsigned cb = (unsigned)((a.N + kBlock - 1) / kBlock);
+    const unsigned rb = (unsigned)((a.N + kPapgStepRows - 1) / kPapgStepRows);
+    if (a.n <= 8) hipLaunchKernelGGL(k_papg_step2<8>, dim3(cb, rb), dim3(kBlock), 0, s, a);
+    else if (a.n <= 16) hipLaunchKernelGGL(k_papg_step2<16>, dim3(cb, rb), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL(k_papg_step2<kPapgMaxN>, dim3(cb, rb), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_papg_ball, dim3(1), dim3(kBlock), 0, s, a);
     const int64_t tot = a.N * a.N + a.N;
     const unsigned grid = (unsigned)std::min<int64_t>((tot + kBlock - 1) / kBlock, 4096);
