@@ -23,6 +23,7 @@
 namespace {
 
 constexpr int kGraphIters = 32;
+constexpr int kTailIters = 8;     // the batched form's short replay (fixed schedules)
 thread_local std::string g_last_error;
 
 struct Layout {
@@ -831,7 +832,8 @@ struct cr_batch {
     std::vector<cr_problem> probs;
     std::vector<cr_ctx*> sub;
     hipStream_t user_stream = nullptr, cs = nullptr;
-    hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph = nullptr;        // kGraphIters MAPG iterations
+    hipGraphExec_t tail = nullptr;         // kTailIters, to finish a fixed schedule
     hipEvent_t ev[2] = {nullptr, nullptr};
     int32_t* pinned_flag = nullptr;
     char* ws = nullptr;
@@ -853,14 +855,16 @@ static cr_status bfail(cr_batch* b, cr_status s, const std::string& msg) {
             return bfail(b, CR_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));      \
     } while (0)
 
-static cr_status build_batch_graph(cr_batch* b) {
-    if (b->graph) return CR_OK;
+// One graph of `iters` MAPG iterations of every problem (positions q = 0 ..
+// iters - 1 of the replay), closed by the replay-end kernel that advances each
+// problem's iteration base by `iters`.
+static cr_status capture_batch_graph(cr_batch* b, int iters, hipGraphExec_t* out) {
     const BatchPlan& B = b->plan;
     char* h = b->ws;
     hipGraph_t g = nullptr;
     BHIPCHK(b, hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int q = 0; q < kGraphIters && e == hipSuccess; ++q) {
+    for (int q = 0; q < iters && e == hipSuccess; ++q) {
         for (size_t ci = 0; ci < B.ks_classes.size() && e == hipSuccess; ++ci) {
             const int grid = std::max(1, std::min(b->grid, B.class_cnt[ci]));
             e = cr::launch_pass_batched(b->f64, B.ks_classes[ci], (const cr::PassArgs*)(h + B.off_pass),
@@ -876,14 +880,24 @@ static cr_status build_batch_graph(cr_batch* b) {
                                           (const int32_t*)(h + B.off_nblk), B.nblocks, q, b->cs);
     }
     if (e == hipSuccess)
-        e = cr::launch_replay_end_batched((cr::DevState* const*)(h + B.off_sts), b->P, kGraphIters,
+        e = cr::launch_replay_end_batched((cr::DevState* const*)(h + B.off_sts), b->P, iters,
                                           (int32_t*)(h + B.off_any), b->cs);
     hipError_t e2 = hipStreamEndCapture(b->cs, &g);
     if (e != hipSuccess) return bfail(b, CR_ERR_HIP, std::string("batch capture: ") + hipGetErrorString(e));
     if (e2 != hipSuccess) return bfail(b, CR_ERR_HIP, std::string("batch end capture: ") + hipGetErrorString(e2));
-    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     hipGraphDestroy(g);
-    if (e != hipSuccess) { b->graph = nullptr; return bfail(b, CR_ERR_HIP, std::string("batch instantiate: ") + hipGetErrorString(e)); }
+    if (e != hipSuccess) { *out = nullptr; return bfail(b, CR_ERR_HIP, std::string("batch instantiate: ") + hipGetErrorString(e)); }
+    return CR_OK;
+}
+
+static cr_status build_batch_graph(cr_batch* b) {
+    if (!b->graph) {
+        cr_status s = capture_batch_graph(b, kGraphIters, &b->graph);
+        if (s != CR_OK) return s;
+    }
+    if (!b->tail && b->p.inner_iters > 0 && b->p.inner_iters % kGraphIters != 0)
+        return capture_batch_graph(b, kTailIters, &b->tail);
     return CR_OK;
 }
 
@@ -902,6 +916,7 @@ cr_status cr_batch_destroy(cr_batch* b) {
     if (!b) return CR_OK;
     if (b->cs) hipStreamSynchronize(b->cs);
     if (b->graph) hipGraphExecDestroy(b->graph);
+    if (b->tail) hipGraphExecDestroy(b->tail);
     for (cr_ctx* c : b->sub) cr_destroy(c);
     for (int q = 0; q < 2; ++q)
         if (b->ev[q]) hipEventDestroy(b->ev[q]);
@@ -1040,6 +1055,13 @@ cr_status cr_batch_run(cr_batch* b, cr_info* infos, double* seconds) {
         int slot = 0, pending = -1;
         int32_t* any = (int32_t*)(b->ws + b->plan.off_any);
         while (launched < lmax_all) {
+            // a fixed schedule ends with short replays: at most kTailIters - 1
+            // iterations past l_max are launched (and skip their work)
+            if (fixed && b->tail && lmax_all - launched < kGraphIters) {
+                BHIPCHK(b, hipGraphLaunch(b->tail, cs));
+                launched += kTailIters;
+                continue;
+            }
             BHIPCHK(b, hipGraphLaunch(b->graph, cs));
             launched += kGraphIters;
             if (fixed) continue;
