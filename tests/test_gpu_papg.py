@@ -72,6 +72,8 @@ CASES = [
     ("quadratic_uniform N=64 n=31 K=2", lambda: synth.quadratic_uniform(64, 31, seed=95), 2, 2, 20, 2, 0.1),
     ("quadratic_uniform N=24 n=2 K=12", lambda: synth.quadratic_uniform(24, 2, seed=26), 12, 3, 20, 3, 0.1),
     ("quadratic_uniform N=1000 n=10 K=4", lambda: synth.quadratic_uniform(1000, 10, seed=1010), 4, 2, 32, 2, 0.1),
+    # above 4096 points the column sums take longer row chunks (72 rows here, 58 chunks); ragged tiles
+    ("quadratic_uniform N=4160 n=6 K=4", lambda: synth.quadratic_uniform(4160, 6, seed=4166), 4, 2, 5, 2, 0.1),
 ]
 
 
