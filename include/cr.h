@@ -355,7 +355,10 @@ typedef struct {
     int32_t method;     /* CR_PAPG_ACCELERATED: Fig. 2; CR_PAPG_GRADIENT: steps
                            3-4 dropped (theta^(2)_{l+1} = theta^(1)_l), the
                            projected gradient ascent P-APG is compared with in Sec. III */
-    int32_t reserved;   /* 0 */
+    int32_t power_iters; /* with L <= 0: 0 takes the bound above; > 0 runs that many
+                           power iterations on C^T C (from a fixed start) and takes
+                           L = min(bound, 1.05 ||C v||^2 / gamma), v the last unit
+                           iterate (a lower estimate of sigma_max(C)^2, 5% added) */
 } cr_papg_params;
 
 enum { CR_PAPG_ACCELERATED = 0, CR_PAPG_GRADIENT = 1 };

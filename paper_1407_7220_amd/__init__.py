@@ -53,7 +53,7 @@ class _CProblem(ctypes.Structure):
 class _CPapgParams(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("iters", ctypes.c_int32), ("L", ctypes.c_double),
                 ("B_theta", ctypes.c_double), ("y_shift", ctypes.c_double), ("method", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("power_iters", ctypes.c_int32)]
 
 
 class _CPapgInfo(ctypes.Structure):
@@ -549,19 +549,21 @@ def evaluate(X, y, xi, Q, with_arg: bool = True):
 class PapgParams:
     """cr_papg_params: K index sets, iterations, step constant L (<= 0: the
     bound (2N + sigma_max(A2)^2 + 1)/gamma), radius of Q2 (inf: none), the
-    data shift (< 0: the library's default) and the method (PAPG_ACCELERATED,
-    Fig. 2, or PAPG_GRADIENT, projected gradient ascent)."""
+    data shift (< 0: the library's default), the method (PAPG_ACCELERATED,
+    Fig. 2, or PAPG_GRADIENT, projected gradient ascent) and, with L <= 0,
+    the number of power iterations that estimate sigma_max(C) (0: the bound)."""
     K: int = 2
     iters: int = 10
     L: float = 0.0
     B_theta: float = math.inf
     y_shift: float = -1.0
     method: int = 0
+    power_iters: int = 0
 
     def to_c(self):
         return _CPapgParams(int(self.K), int(self.iters), float(self.L),
                             float(self.B_theta) if math.isfinite(self.B_theta) else 0.0, float(self.y_shift),
-                            int(self.method), 0)
+                            int(self.method), int(self.power_iters))
 
 
 def papg_workspace_bytes(N: int, n: int, params: Params, pp: PapgParams) -> int:

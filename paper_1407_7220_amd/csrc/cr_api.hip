@@ -1581,7 +1581,8 @@ namespace {
 struct PapgLayout {
     int64_t N = 0, Nbar = 0;
     int n = 0, K = 0;
-    size_t th[2], ty[2], ybs, shift, y, xis, part, cpart, scal, trace, su, supart, y0, xi0, st, batch;
+    size_t th[2], ty[2], ybs, shift, y, xis, part, cpart, scal, trace, pvy, pvxi, pzero, su, supart, y0, xi0, st,
+        batch;
     size_t batch_bytes = 0, total = 0;
 };
 
@@ -1593,6 +1594,7 @@ cr_status check_papg(int64_t N, int32_t n, const cr_params* alcc, const cr_papg_
     if (pp->K < 1 || N % pp->K != 0 || N / pp->K < 2) { msg = "K must divide N with N / K >= 2"; return CR_ERR_ARG; }
     if (pp->iters < 1) { msg = "iters must be >= 1"; return CR_ERR_ARG; }
     if (pp->method != CR_PAPG_ACCELERATED && pp->method != CR_PAPG_GRADIENT) { msg = "unknown method"; return CR_ERR_ARG; }
+    if (pp->power_iters < 0) { msg = "power_iters must be >= 0"; return CR_ERR_ARG; }
     if (alcc->precision == CR_MIXED_BF16) { msg = "P-APG block solves run CR_F64 or CR_F32"; return CR_ERR_UNSUPPORTED; }
     return CR_OK;
 }
@@ -1627,6 +1629,9 @@ PapgLayout papg_layout(int64_t N, int n, const cr_params* alcc, const cr_papg_pa
     P.cpart = take((size_t)cr::papg_col_chunks(N) * N * (n + 1) * 8);
     P.scal = take(64);
     P.trace = take((size_t)pp->iters * 3 * 8);
+    P.pvy = take((size_t)N * 8);
+    P.pvxi = take((size_t)N * n * 8);
+    P.pzero = take((size_t)N * 8);
     // set-up of the whole point set, for sigma_max(A2)^2 of the default L
     const int64_t ld = (N + 63) / 64 * 64;
     const int64_t nsu = (N + cr::kSuRows - 1) / cr::kSuRows, nbk = (ld * 32 + cr::kBlock - 1) / cr::kBlock;
@@ -1736,6 +1741,19 @@ cr_status cr_papg(const void* X_dev, const void* ybar_dev, int64_t N, int32_t n,
     double* ty[2] = {D(P.ty[0]), D(P.ty[1])};
     a.ybs = D(P.ybs); a.shift = D(P.shift); a.y = D(P.y); a.xis = D(P.xis);
     a.part = D(P.part); a.cpart = D(P.cpart); a.scal = D(P.scal); a.trace = D(P.trace);
+    if (!(pp->L > 0) && pp->power_iters > 0) {
+        // sigma_max(C)^2 estimated by power iteration (th[0] and the block-data
+        // buffers serve as scratch before they are initialised below)
+        a.tc = th[0];
+        PCHK(cr::launch_zero(ws + P.pzero, (size_t)N * 8, us));
+        PCHK(cr::launch_papg_power(a, D(P.pvy), D(P.pvxi), D(P.pzero), pp->power_iters, us));
+        double sc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        PCHK(hipMemcpyAsync(sc, a.scal, sizeof(sc), hipMemcpyDeviceToHost, us));
+        PCHK(hipStreamSynchronize(us));
+        if (!std::isfinite(sc[4]) || !(sc[4] > 0)) return fail(nullptr, CR_ERR_NONFINITE, "power iteration failed");
+        L = std::min(L, 1.05 * sc[4] / gamma);
+        a.L = L;
+    }
     for (int q = 0; q < 2; ++q) {
         PCHK(cr::launch_zero(th[q], (size_t)N * N * 8, us));
         PCHK(cr::launch_zero(ty[q], (size_t)N * 8, us));

@@ -230,7 +230,7 @@ struct PapgArgs {
     const double* xis;        // step-1 output in shifted slopes xi' (N x n)
     double* part;             // per-workgroup partial sums of k_papg_step2 (3 each)
     double* cpart;            // column partials of k_papg_colsum: [row chunk][N][n + 1]
-    double* scal;             // [scale, ||theta||, ||(r_cross)_-||, theta2^T C eta]
+    double* scal;             // [scale, ||theta||, ||(r_cross)_-||, theta2^T C eta, power: ||C v||^2, ||w||]
     double* trace;            // per iteration: ||theta||, ||(r_cross)_-||, theta2^T C eta
 };
 constexpr int kPapgStepRows = 32;     // rows per workgroup of k_papg_step2
@@ -242,6 +242,11 @@ __host__ __device__ inline int64_t papg_col_chunks(int64_t N) { return (N + papg
 hipError_t launch_papg_lin(const PapgArgs& a, hipStream_t s);
 hipError_t launch_papg_step2(const PapgArgs& a, hipStream_t s);
 hipError_t launch_papg_out(const PapgArgs& a, double* y_out, double* xi_out, hipStream_t s);
+// `iters` power iterations on C^T C from a fixed start; afterwards scal[4] is
+// ||C v||^2 for the last unit vector v (a lower estimate of sigma_max(C)^2).
+// Uses tc as the scratch pair array, ybs/shift as scratch vectors and part.
+hipError_t launch_papg_power(const PapgArgs& a, double* vy, double* vxi, const double* zero, int iters,
+                             hipStream_t s);
 int reduce_blocks(int64_t N, int n);
 int reduce_blocks_g(int64_t N, int G);
 // Batched form (plain precisions): see cr_batch.hip.

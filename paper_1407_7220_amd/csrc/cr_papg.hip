@@ -207,6 +207,100 @@ __global__ __launch_bounds__(kBlock) void k_papg_step2(PapgArgs a) {
     }
 }
 
+// sigma_max(C)^2 by power iteration on C^T C (an option of cr_papg).  One
+// step: R = C v for v = (y, xi) (this kernel: the cross residuals r_ij into
+// the tc array, zero inside the diagonal blocks, with the per-workgroup sums of
+// r^2 and, in column block 0, of y^2), then C^T (R, y) by k_papg_colsum and
+// k_papg_lin (theta2 = R, theta2_y = y, zero data, gamma = 1), then
+// k_papg_pnorm.  Tiles as in k_papg_step2.
+template <int NM>
+__global__ __launch_bounds__(kBlock) void k_papg_capply(PapgArgs a) {
+    const int64_t N = a.N;
+    const int n = a.n;
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.y * kPapgStepRows, i1 = min(i0 + kPapgStepRows, N);
+    const bool vj = j < N;
+    const int64_t jb0 = vj ? j / a.Nbar * a.Nbar : -1, jb1 = jb0 + a.Nbar;
+    __shared__ double xs[kPapgStepRows][kPapgMaxN + 1];
+    for (int e = threadIdx.x; e < kPapgStepRows * (n + 1); e += kBlock) {
+        const int r = e / (n + 1), k = e % (n + 1);
+        const int64_t i = i0 + r;
+        xs[r][k] = i < i1 ? (k < n ? a.X[i * n + k] : a.y[i]) : 0.0;
+    }
+    __syncthreads();
+    double xj[NM], sj[NM];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+        xj[k] = (vj && k < n) ? a.X[j * n + k] : 0.0;
+        sj[k] = (vj && k < n) ? a.xis[j * n + k] : 0.0;
+    }
+    const double yj = vj ? a.y[j] : 0.0;
+    double s2 = 0.0;
+    for (int64_t i = i0; i < i1; ++i) {
+        if (!vj) continue;
+        double r = 0.0;
+        if (i < jb0 || i >= jb1) {
+            const double* xr = xs[i - i0];
+            double h = 0.0;
+#pragma unroll
+            for (int k = 0; k < NM; ++k)
+                if (k < n) h += sj[k] * (xr[k] - xj[k]);
+            r = (xr[n] - yj) - h;
+        }
+        a.tc[i * N + j] = r;
+        s2 += r * r;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < i1 - i0) {
+        const double yi = a.y[i0 + threadIdx.x];
+        s2 += yi * yi;
+    }
+    s2 = block_reduce(s2, 0);
+    if (threadIdx.x == 0) {
+        const int64_t wg = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+        a.part[3 * wg] = s2;
+        a.part[3 * wg + 1] = 0.0;
+        a.part[3 * wg + 2] = 0.0;
+    }
+}
+
+// One workgroup: w = (ybs, shift) holds C^T C v (or, at the start, any vector);
+// scal[4] <- ||C v||^2 from the capply partials (the Rayleigh quotient, v having
+// unit norm), scal[5] <- ||w||, and v <- w / ||w|| into (y, xis).
+__global__ __launch_bounds__(kBlock) void k_papg_pnorm(PapgArgs a, double* vy, double* vxi, int with_rayleigh) {
+    const int64_t N = a.N, Nn = a.N * a.n;
+    double q = 0.0, w2 = 0.0;
+    if (with_rayleigh) {
+        const int64_t parts = papg_step_parts(N);
+        for (int64_t e = threadIdx.x; e < parts; e += kBlock) q += a.part[3 * e];
+    }
+    for (int64_t e = threadIdx.x; e < N; e += kBlock) w2 += a.ybs[e] * a.ybs[e];
+    for (int64_t e = threadIdx.x; e < Nn; e += kBlock) w2 += a.shift[e] * a.shift[e];
+    block_sum2(q, w2);
+    const double nw = sqrt(w2);
+    const double inv = nw > 0.0 ? 1.0 / nw : 0.0;
+    for (int64_t e = threadIdx.x; e < N; e += kBlock) vy[e] = a.ybs[e] * inv;
+    for (int64_t e = threadIdx.x; e < Nn; e += kBlock) vxi[e] = a.shift[e] * inv;
+    if (threadIdx.x == 0) {
+        if (with_rayleigh) a.scal[4] = q;
+        a.scal[5] = nw;
+    }
+}
+
+// A fixed start for the power iteration: entries in [0.5, 1.5) from a
+// counter-based integer hash of the index (no state, same on every call).
+__global__ __launch_bounds__(kBlock) void k_papg_pstart(PapgArgs a) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t Nn = a.N * a.n;
+    if (e >= a.N + Nn) return;
+    uint64_t z = (uint64_t)e + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const double u = 0.5 + (double)(z >> 11) * (1.0 / 9007199254740992.0);
+    if (e < a.N) a.ybs[e] = u;
+    else a.shift[e - a.N] = u;
+}
+
 __global__ __launch_bounds__(kBlock) void k_papg_ball(PapgArgs a) {
     double s = 0.0, g = 0.0, d = 0.0;
     const int64_t parts = papg_step_parts(a.N);
@@ -269,6 +363,32 @@ hipError_t launch_papg_step2(const PapgArgs& a, hipStream_t s) {
     const int64_t tot = a.N * a.N + a.N;
     const unsigned grid = (unsigned)std::min<int64_t>((tot + kBlock - 1) / kBlock, 4096);
     hipLaunchKernelGGL(k_papg_scale, dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_papg_power(const PapgArgs& a0, double* vy, double* vxi, const double* zero, int iters,
+                             hipStream_t s) {
+    // v0 from the hash start, normalised
+    PapgArgs a = a0;
+    const int64_t tot = a.N + a.N * a.n;
+    hipLaunchKernelGGL(k_papg_pstart, dim3((unsigned)((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_papg_pnorm, dim3(1), dim3(kBlock), 0, s, a, vy, vxi, 0);
+    const unsigned cb = (unsigned)((a.N + kBlock - 1) / kBlock);
+    const unsigned rb = (unsigned)((a.N + kPapgStepRows - 1) / kPapgStepRows);
+    // C^T through the step-1 kernels: theta2 = R (beta 0), theta2_y = y, zero data, gamma 1
+    PapgArgs b = a;
+    b.y = vy; b.xis = vxi;
+    b.tp = b.tc; b.beta = 0.0;
+    b.tyc = vy; b.typ = vy;
+    b.ybar = zero; b.yshift = 0.0; b.gamma = 1.0;
+    for (int it = 0; it < iters; ++it) {
+        if (a.n <= 8) hipLaunchKernelGGL(k_papg_capply<8>, dim3(cb, rb), dim3(kBlock), 0, s, b);
+        else if (a.n <= 16) hipLaunchKernelGGL(k_papg_capply<16>, dim3(cb, rb), dim3(kBlock), 0, s, b);
+        else hipLaunchKernelGGL(k_papg_capply<kPapgMaxN>, dim3(cb, rb), dim3(kBlock), 0, s, b);
+        hipError_t e = launch_papg_lin(b, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_papg_pnorm, dim3(1), dim3(kBlock), 0, s, b, vy, vxi, 1);
+    }
     return hipGetLastError();
 }
 

@@ -286,3 +286,24 @@ def test_theorem1_bounds_on_the_dual_iterates(cr):
     delta, dy, infx = run(300, cr.PAPG_ACCELERATED)
     say("  P-APG  300 iterations: delta %.3e  |y - y(gamma)| %.3e  cross infeasibility %.3e" % (delta, dy, infx))
     assert 0.0 < delta < deltas[2] / 5
+
+
+def test_power_iteration_step_constant(cr):
+    # sigma_max(C)^2 by power iteration on C^T C: the step constant must not fall
+    # below L_g = sigma_max(C)^2 / gamma (eq. "lischitz", dense SVD here) and is
+    # at most 5% above it once converged; ascent with it gains more per
+    # iteration than with the bound (2N + sigma_max(A2)^2 + 1) / gamma
+    N, n, K, gamma = 40, 2, 2, 0.1
+    p = synth.quadratic_uniform(N, n, seed=21)
+    X, yb = dev(p.X), dev(p.ybar)
+    say("power iteration for L_g: N=40 n=2 K=2, 200 iterations; ascent 60 iterations with each constant")
+    s2 = np.linalg.norm(_dense_C(p.X, K), 2) ** 2
+    Lg = s2 / gamma
+    blocks = cr.Params(precision=0, gamma=gamma, inner_iters=100, max_outer=8)
+    _, _, ib = cr.papg(X, yb, cr.PapgParams(K=K, iters=60, method=cr.PAPG_GRADIENT), blocks)
+    _, _, ip = cr.papg(X, yb, cr.PapgParams(K=K, iters=60, method=cr.PAPG_GRADIENT, power_iters=200), blocks)
+    say("  L_g %.4f  bound %.4f  power %.4f; cross infeasibility after 60: %.3e (bound) %.3e (power)"
+        % (Lg, ib["L"], ip["L"], ib["infeas_cross"], ip["infeas_cross"]))
+    assert Lg <= ip["L"] <= 1.05 * Lg * (1 + 1e-9)
+    assert ip["L"] < ib["L"]
+    assert ip["infeas_cross"] < ib["infeas_cross"]
