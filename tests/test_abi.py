@@ -202,6 +202,9 @@ def test_papg_workspace_and_argument_checks():
     with pytest.raises(cr.CRError) as e:
         cr.papg_workspace_bytes(100, 5, p, cr.PapgParams(K=2, method=2))
     assert e.value.status == 1
+    with pytest.raises(cr.CRError) as e:
+        cr.papg_workspace_bytes(100, 5, p, cr.PapgParams(K=2, power_iters=-1))
+    assert e.value.status == 1
     fake = ctypes.c_void_p(0x1000)
     cp, cpp = p.to_c(), cr.PapgParams(K=2, iters=3).to_c()
     lib = cr._lib
