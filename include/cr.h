@@ -333,7 +333,9 @@ cr_status cr_diff_time_adjoint_pass(cr_diff* d, int32_t reps, double* avg_ms);
  *      block i being eq. "regularize" on its points with data
  *      ybar_i + y_shift + (A3^T theta + theta_y)_i and the slope term
  *      gamma/2 ||xi_i - (A4^T theta)_i / gamma||^2, solved together by the
- *      batched ALCC (cr_solve_batched's machinery) with `alcc`'s schedule,
+ *      batched ALCC (cr_solve_batched's machinery) with `alcc`'s schedule
+ *      (alcc->tile_rows = 0: row chunks sized for about 512 work items over
+ *      all blocks, the batched pass's persistent grid),
  *      each from its affine fit with zero within-block multipliers;
  *   2. theta^(1)_l = Pi_Q2(theta^(2)_l - C eta_l / L);
  *   3-4. t_{l+1} = (1 + sqrt(1 + 4 t_l^2))/2 and

@@ -1599,13 +1599,31 @@ cr_status check_papg(int64_t N, int32_t n, const cr_params* alcc, const cr_papg_
     return CR_OK;
 }
 
-std::vector<cr_problem> papg_problems(int64_t N, int n, int K, const double* X, double* ybs, double* y, double* xis) {
+// Rows per chunk of the block solves when the caller leaves tile_rows at 0: the
+// batched pass runs a persistent grid of about 2 workgroups per CU (512 on
+// MI355X) over (problem, strip, chunk) items, so the chunks are sized for about
+// that many items in total instead of the single-problem default.
+int papg_block_tile_rows(int64_t nb, int K, const cr_params* alcc) {
+    if (alcc->tile_rows > 0) return alcc->tile_rows;
+    const int tw = alcc->precision == CR_F64 ? 2 : 4;
+    const int64_t ld = (nb + 63) / 64 * 64;
+    const int64_t strips = ld / (16 * tw);
+    const int64_t target = 512;
+    int64_t chunks = (target + (int64_t)K * strips / 2) / ((int64_t)K * strips);
+    chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, ld / 64));
+    const int64_t rpc = ((ld + chunks - 1) / chunks + 63) / 64 * 64;
+    return (int)rpc;
+}
+
+std::vector<cr_problem> papg_problems(int64_t N, int n, int K, const double* X, double* ybs, double* y, double* xis,
+                                      const cr_params* alcc) {
     const int64_t nb = N / K;
     std::vector<cr_problem> pr(K);
+    const int tr = papg_block_tile_rows(nb, K, alcc);
     for (int i = 0; i < K; ++i) {
         pr[i].N = nb;
         pr[i].n = n;
-        pr[i].tile_rows = 0;
+        pr[i].tile_rows = tr;
         pr[i].X_dev = X ? X + i * nb * n : nullptr;
         pr[i].ybar_dev = ybs ? ybs + i * nb : nullptr;
         pr[i].y_dev = y ? y + i * nb : nullptr;
@@ -1640,7 +1658,7 @@ PapgLayout papg_layout(int64_t N, int n, const cr_params* alcc, const cr_papg_pa
     P.y0 = take((size_t)N * 8);
     P.xi0 = take((size_t)N * n * 8);
     P.st = take(sizeof(cr::DevState));
-    std::vector<cr_problem> pr = papg_problems(N, n, pp->K, nullptr, nullptr, nullptr, nullptr);
+    std::vector<cr_problem> pr = papg_problems(N, n, pp->K, nullptr, nullptr, nullptr, nullptr, alcc);
     P.batch_bytes = plan_batch(pr.data(), pp->K, alcc).total;
     P.batch = take(P.batch_bytes);
     P.total = o + 256;
@@ -1764,7 +1782,7 @@ cr_status cr_papg(const void* X_dev, const void* ybar_dev, int64_t N, int32_t n,
     a.beta = 0.0;
     PCHK(cr::launch_papg_lin(a, us));      // theta^(2)_1 = 0: the blocks' own data, zero centres
 
-    std::vector<cr_problem> pr = papg_problems(N, n, pp->K, X, D(P.ybs), D(P.y), D(P.xis));
+    std::vector<cr_problem> pr = papg_problems(N, n, pp->K, X, D(P.ybs), D(P.y), D(P.xis), alcc);
     std::vector<const double*> shifts(pp->K);
     for (int i = 0; i < pp->K; ++i) shifts[i] = D(P.shift) + (int64_t)i * P.Nbar * n;
     cr_batch* b = nullptr;
