@@ -10,9 +10,9 @@
 // with K = n + 1: FP64 MFMA (16x16x4) tiles, with a running maximum and argmax
 // per query instead of a stored product.
 //
-// Launch: one workgroup per 32 queries (two 16-row blocks); its 4 waves take
+// Launch: one workgroup per 32 queries (two 16-row blocks); its 8 waves take
 // interleaved 32-plane tiles (two 16-column MFMA tiles) of all N planes, each
-// wave keeping (max, argmax) per query, and the 4 waves' results are combined
+// wave keeping (max, argmax) per query, and the 8 waves' results are combined
 // in LDS.  Ties go to the smaller plane index, so the result does not depend
 // on the traversal order.
 #include "cr_device.h"
@@ -26,6 +26,7 @@ namespace cr {
 
 constexpr int kEvalRows = 32;     // queries per workgroup
 constexpr int kEvalCols = 32;     // planes per wave step
+constexpr int kEvalWaves = 8;     // waves per workgroup (interleaved plane tiles)
 
 // Packed plane operands: row l holds [xi_l (n), d_l, 0 ...] (4 KS doubles).
 // Padding rows l >= N hold d = -Inf and zeros: their value -Inf at every valid
@@ -67,7 +68,7 @@ __device__ __forceinline__ void better(double& bv, int32_t& bl, double v, int32_
 }
 
 template <int KS>
-__global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a) {
+__global__ __launch_bounds__(64 * kEvalWaves) void k_eval(EvalArgs a) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, c = lane & 15;
     const int64_t m0 = (int64_t)blockIdx.x * kEvalRows;
@@ -109,8 +110,8 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a) {
     double bcur[2][KS], bnext[2][KS];
     int64_t t = wave;
     load_b(t, bcur);
-    for (; t < a.ntiles; t += kWaves) {
-        load_b(t + kWaves, bnext);                              // next tile in flight during this one
+    for (; t < a.ntiles; t += kEvalWaves) {
+        load_b(t + kEvalWaves, bnext);                              // next tile in flight during this one
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int32_t l = (int32_t)t * kEvalCols + 16 * h + c;   // this lane's plane
@@ -145,8 +146,8 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a) {
                 const int32_t ol = __shfl_xor(bl[rb][v], o);
                 better(bv[rb][v], bl[rb][v], ov, ol);
             }
-    __shared__ double sv[kWaves][kEvalRows];
-    __shared__ int32_t sl[kWaves][kEvalRows];
+    __shared__ double sv[kEvalWaves][kEvalRows];
+    __shared__ int32_t sl[kEvalWaves][kEvalRows];
     if (c == 0) {
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a) {
         const int r = threadIdx.x;
         double best = sv[0][r];
         int32_t bi = sl[0][r];
-        for (int w = 1; w < kWaves; ++w) better(best, bi, sv[w][r], sl[w][r]);
+        for (int w = 1; w < kEvalWaves; ++w) better(best, bi, sv[w][r], sl[w][r]);
         const int64_t m = m0 + r;
         if (m < a.M) {
             a.f[m] = best;
@@ -177,14 +178,14 @@ static int64_t eval_tiles(int64_t N) { return (N + kEvalCols - 1) / kEvalCols; }
 static hipError_t launch_eval(const EvalArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)((a.M + kEvalRows - 1) / kEvalRows));
     switch (eval_ks(a.n)) {
-        case 1: hipLaunchKernelGGL(k_eval<1>, grid, dim3(kBlock), 0, s, a); break;
-        case 2: hipLaunchKernelGGL(k_eval<2>, grid, dim3(kBlock), 0, s, a); break;
-        case 3: hipLaunchKernelGGL(k_eval<3>, grid, dim3(kBlock), 0, s, a); break;
-        case 4: hipLaunchKernelGGL(k_eval<4>, grid, dim3(kBlock), 0, s, a); break;
-        case 5: hipLaunchKernelGGL(k_eval<5>, grid, dim3(kBlock), 0, s, a); break;
-        case 6: hipLaunchKernelGGL(k_eval<6>, grid, dim3(kBlock), 0, s, a); break;
-        case 7: hipLaunchKernelGGL(k_eval<7>, grid, dim3(kBlock), 0, s, a); break;
-        case 8: hipLaunchKernelGGL(k_eval<8>, grid, dim3(kBlock), 0, s, a); break;
+        case 1: hipLaunchKernelGGL(k_eval<1>, grid, dim3(64 * kEvalWaves), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_eval<2>, grid, dim3(64 * kEvalWaves), 0, s, a); break;
+        case 3: hipLaunchKernelGGL(k_eval<3>, grid, dim3(64 * kEvalWaves), 0, s, a); break;
+        case 4: hipLaunchKernelGGL(k_eval<4>, grid, dim3(64 * kEvalWaves), 0, s, a); break;
+        case 5: hipLaunchKernelGGL(k_eval<5>, grid, dim3(64 * kEvalWaves), 0, s, a); break;
+        case 6: hipLaunchKernelGGL(k_eval<6>, grid, dim3(64 * kEvalWaves), 0, s, a); break;
+        case 7: hipLaunchKernelGGL(k_eval<7>, grid, dim3(64 * kEvalWaves), 0, s, a); break;
+        case 8: hipLaunchKernelGGL(k_eval<8>, grid, dim3(64 * kEvalWaves), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
