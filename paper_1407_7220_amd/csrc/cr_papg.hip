@@ -21,6 +21,8 @@
 //               theta2 * (C eta).  Tiles of 32 rows x 256 columns.
 //  k_papg_ball  ||theta||, the scale of the projection onto the ball of Q2.
 //  k_papg_scale the scale applied (only when the ball is active).
+//  k_papg_capply, k_papg_pnorm, k_papg_pstart
+//               optional power iteration for sigma_max(C)^2 (the step constant).
 //
 // The projection onto Q2 = {theta >= 0, ||theta|| <= B} is the clip at zero
 // followed by a radial scale: the ball is centred at the origin and the
