@@ -260,15 +260,18 @@ def resolve(params: Params, N: int, Bbar: float, gamma: float):
 
 def mapg(X, ybar, gamma, mu, theta, Ly, Lxi, y0, xi0, By, Bxi, alpha_y, alpha_xi,
          lmax, step_scale=0.5, adaptive=True, trace=None, shift=None):
-    """Modified accelerated projected gradient on P_k over Q_y x Q_xi.
+    """MAPG (Fig. 4): accelerated projected gradient on P_k over Q_y x Q_xi.
 
-    Iteration 0: y1_0 = y2_1 = y0, same for xi, t_1 = 1.  Iteration l:
-    block projected-gradient steps from the extrapolated point (y2_l, xi2_l)
-    with step step_scale/L per block, the momentum sequence
-    t_{l+1} = (1 + sqrt(1 + 4 t_l^2))/2, extrapolation with weight
-    (t_l - 1)/t_{l+1}, and return of (y1_l, xi1_l) when both block moves
-    ||y1_l - y2_l||, ||xi1_l - xi2_l|| are within alpha (adaptive) or l = lmax.
-    Returns (y, xi, iterations)."""
+    Each step takes a projected gradient step from the extrapolated point,
+    one block at a time (y with step_scale/Ly onto the ball around ybar, xi
+    with step_scale/Lxi onto the ball around 0), then extrapolates from the
+    new iterate along its change since the previous iterate with the weight
+    (t - 1)/t+ of the accelerated method, where t starts at 1 and
+    t+ = (1 + sqrt(1 + 4 t^2))/2.  The run begins at (y0, xi0) with no
+    momentum and returns the last projected iterate: after the first step
+    whose two block moves are both within alpha (adaptive) or after lmax
+    steps.  A list passed as `trace` receives (l, ||y1 - y2||, ||xi1 - xi2||,
+    t_l, weight_l) per step.  Returns (y, xi, steps)."""
     y1_prev, xi1_prev = y0.copy(), xi0.copy()
     y2, xi2 = y0.copy(), xi0.copy()
     t = 1.0
@@ -282,7 +285,7 @@ def mapg(X, ybar, gamma, mu, theta, Ly, Lxi, y0, xi0, By, Bxi, alpha_y, alpha_xi
         dy = float(np.sqrt(np.sum((y1 - y2) ** 2)))
         dxi = float(np.sqrt(np.sum((xi1 - xi2) ** 2)))
         if trace is not None:
-            trace.append((l, dy, dxi))
+            trace.append((l, dy, dxi, t, beta))
         y2 = y1 + beta * (y1 - y1_prev)
         xi2 = xi1 + beta * (xi1 - xi1_prev)
         y1_prev, xi1_prev = y1, xi1
@@ -320,6 +323,46 @@ def kkt_measures(X, ybar, gamma, y, xi, lam, shift=None):
                 objective=0.5 * float(np.sum((y - ybar) ** 2)))
 
 
+class _Schedule:
+    """The scalars ALCC carries from one outer iteration to the next (Fig. 3):
+    the penalty parameter mu_k, the subproblem tolerance tau_k and the two
+    MAPG stopping thresholds alpha^y_k, alpha^xi_k."""
+
+    def __init__(self, p: Params, N: int, Bbar: float, s2A1: float, s2A2: float, By: float, Bxi: float):
+        self.p, self.s2A1, self.s2A2, self.By, self.Bxi = p, s2A1, s2A2, By, Bxi
+        self.mu, self.ay, self.axi = resolve(p, N, Bbar, p.gamma)
+        self.tau = p.tau1
+
+    def constants(self):
+        """Block Lipschitz constants of grad P_k and the MAPG step budget l_max:
+        ceil(4 sqrt((L^y By^2 + L^xi Bxi^2)/tau_k)) clipped to [1, max_inner],
+        or the fixed count of a fixed schedule."""
+        p = self.p
+        Ly = p.Ly_override if p.Ly_override > 0 else 1.0 / self.mu + self.s2A1
+        Lxi = p.Lxi_override if p.Lxi_override > 0 else p.gamma / self.mu + self.s2A2
+        if p.inner_iters > 0:
+            return Ly, Lxi, p.inner_iters
+        lmax = int(math.ceil(4.0 * math.sqrt((Ly * self.By ** 2 + Lxi * self.Bxi ** 2) / self.tau)))
+        return Ly, Lxi, max(1, min(lmax, p.max_inner))
+
+    def advance(self, k: int):
+        """After outer iteration k: mu grows by c; tau and both alpha thresholds
+        shrink by (c k^{1+kappa})^2."""
+        p = self.p
+        decay = (p.c * k ** (1.0 + p.kappa)) ** 2
+        self.mu, self.tau = p.c * self.mu, self.tau / decay
+        self.ay, self.axi = self.ay / decay, self.axi / decay
+
+
+def multiplier_step(X, y, xi_c, theta, ratio):
+    """The ALCC multiplier update at the MAPG output: theta_{k+1} =
+    (mu_k/mu_{k+1}) (A1 y + A2 xi_c - theta_k)_- with ratio = mu_k/mu_{k+1};
+    xi_c are the slopes that enter the constraints.  Diagonal 0."""
+    Wk = neg_part(forward(X, y, xi_c) - theta)
+    np.fill_diagonal(Wk, 0.0)
+    return ratio * Wk
+
+
 @dataclasses.dataclass
 class Result:
     y: np.ndarray
@@ -334,19 +377,21 @@ class Result:
 
 def alcc(X, ybar, params: Optional[Params] = None, y0=None, xi0=None,
          record_kkt: bool = True, xi_shift=None) -> Result:
-    """ALCC (Fig. 3) on eq. "regularize", MAPG (Fig. 4) as the inner solver.
+    """ALCC (Fig. 3) on eq. "regularize", with MAPG (Fig. 4) as the inner solver.
 
-    Outer iteration k:
-      1. L^y_k = 1/mu_k + sigma_max(A1)^2,  L^xi_k = gamma/mu_k + sigma_max(A2)^2
-      2. l^max_k = ceil(4 sqrt((L^y Bbar_y^2 + L^xi Bbar_xi^2)/tau_k))   (fixed count
-         instead when params.inner_iters > 0; capped by params.max_inner)
-      3. (y_k, xi_k) = MAPG(P_k, ..., (y_{k-1}, xi_{k-1}), alpha_k, l^max_k)
-      4. theta_{k+1} = (mu_k/mu_{k+1}) (A1 y_k + A2 xi_k - theta_k)_-
-      5. mu_{k+1} = c mu_k,  tau_{k+1} = tau_k/(c k^{1+kappa})^2
-      6. alpha_{k+1} = alpha_k/(c k^{1+kappa})^2 (both blocks)
-    theta_1 = 0.  The multiplier estimate after step 4 is mu_{k+1} theta_{k+1};
-    the run stops after the first outer iteration whose KKT measure is within
-    params.kkt_tol (adaptive schedule only) or after params.max_outer.
+    The multipliers start at zero and the iterate at the affine fit.  Each
+    outer iteration minimises the penalty function P_k of eq. "subproblem"
+    approximately with MAPG, warm-started at the previous outer iterate, with
+    block Lipschitz constants 1/mu_k + sigma_max(A1)^2 and
+    gamma/mu_k + sigma_max(A2)^2 and a step budget that grows with the square
+    root of the constants over the tolerance tau_k (a fixed count instead when
+    params.inner_iters > 0; capped by params.max_inner).  The multipliers are
+    then moved to (mu_k/mu_{k+1}) (r - theta_k)_- at the MAPG output, the
+    penalty weight grows by c, and tau and both alpha thresholds shrink by
+    (c k^{1+kappa})^2.  The multiplier estimate of outer iteration k is
+    mu_{k+1} theta_{k+1}; the run stops after the first outer iteration whose
+    KKT measure is within params.kkt_tol (adaptive schedule only) or after
+    params.max_outer.
 
     xi_shift (N x n, optional) poses the problem in shifted slopes: with
     xi = xi' + shift the run solves
@@ -371,10 +416,7 @@ def alcc(X, ybar, params: Optional[Params] = None, y0=None, xi0=None,
         By = p.By_override
     if p.Bxi_override > 0:
         Bxi = p.Bxi_override
-    s2A1 = sigma2_A1(N)
-    s2A2 = sigma2_A2(X)
-    mu, ay, axi = resolve(p, N, Bbar, gamma)
-    tau = p.tau1
+    sched = _Schedule(p, N, Bbar, sigma2_A1(N), sigma2_A2(X), By, Bxi)
     y = yhat if y0 is None else _f64(y0).copy()
     xi = xihat if xi0 is None else _f64(xi0).reshape(N, n).copy()
     theta = np.zeros((N, N))
@@ -383,29 +425,19 @@ def alcc(X, ybar, params: Optional[Params] = None, y0=None, xi0=None,
     converged = False
     k = 0
     for k in range(1, p.max_outer + 1):
-        Ly = p.Ly_override if p.Ly_override > 0 else 1.0 / mu + s2A1
-        Lxi = p.Lxi_override if p.Lxi_override > 0 else gamma / mu + s2A2
-        if fixed:
-            lmax = p.inner_iters
-        else:
-            lmax = int(math.ceil(4.0 * math.sqrt((Ly * By ** 2 + Lxi * Bxi ** 2) / tau)))
-            lmax = max(1, min(lmax, p.max_inner))
-        y, xi, used = mapg(X, ybar, gamma, mu, theta, Ly, Lxi, y, xi, By, Bxi, ay, axi,
+        Ly, Lxi, lmax = sched.constants()
+        mu = sched.mu
+        y, xi, used = mapg(X, ybar, gamma, mu, theta, Ly, Lxi, y, xi, By, Bxi, sched.ay, sched.axi,
                            lmax, p.step_scale, adaptive=not fixed, shift=shift)
         inner_list.append(used)
         mu_next = p.c * mu
-        R = forward(X, y, _shifted(xi, shift))
-        Wk = neg_part(R - theta)
-        np.fill_diagonal(Wk, 0.0)
-        theta = (mu / mu_next) * Wk
+        theta = multiplier_step(X, y, _shifted(xi, shift), theta, mu / mu_next)
         if record_kkt:
             m = kkt_measures(X, ybar, gamma, y, xi, mu_next * theta, shift)
             m.update(k=k, inner=used, mu=mu)
             hist.append(m)
-            if not fixed and m["kkt"] <= p.kkt_tol:
-                converged = True
-        decay = (p.c * k ** (1.0 + p.kappa)) ** 2
-        mu, tau, ay, axi = mu_next, tau / decay, ay / decay, axi / decay
+            converged = not fixed and m["kkt"] <= p.kkt_tol
+        sched.advance(k)
         if converged:
             break
     return Result(y, xi, theta, k, int(sum(inner_list)), inner_list, hist, converged)

@@ -150,15 +150,17 @@ class PapgResult:
 def papg(X, ybar, K: int, gamma: float, iters: int, params: Optional[_o.Params] = None,
          L: float = 0.0, B_theta: float = math.inf, y_shift: Optional[float] = None,
          record: bool = False, accelerate: bool = True) -> PapgResult:
-    """P-APG (Fig. 2) for `iters` iterations.
+    """P-APG (Fig. 2) for `iters` iterations: accelerated projected gradient
+    ascent on the dual of eq. "omega_primal".
 
-    Iteration 0: theta^(1)_0 = theta^(2)_1 = 0, t_1 = 1.  Iteration l:
-      1. eta_l = argmin over Q1 of the Lagrangian at theta^(2)_l (step1)
-      2. theta^(1)_l = Pi_Q2(theta^(2)_l - C eta_l / L)
-      3. t_{l+1} = (1 + sqrt(1 + 4 t_l^2)) / 2
-      4. theta^(2)_{l+1} = theta^(1)_l + (t_l - 1)/t_{l+1} (theta^(1)_l - theta^(1)_{l-1})
-    `params` is the block ALCC's schedule (its gamma is replaced by `gamma`).
-    With accelerate=False steps 3-4 are dropped (theta^(2)_{l+1} = theta^(1)_l):
+    The multipliers start at zero with no momentum.  Each iteration solves the
+    K block problems at the extrapolated multipliers theta^(2) (step1, which
+    gives eta and hence the dual gradient -C eta), takes a projected step
+    theta^(1) = Pi_Q2(theta^(2) - C eta / L), and extrapolates the next
+    theta^(2) from theta^(1) along its change since the previous iteration
+    with the accelerated weight (t - 1)/t+, t+ = (1 + sqrt(1 + 4 t^2))/2,
+    t starting at 1.  `params` is the block ALCC's schedule (its gamma is
+    replaced by `gamma`).  With accelerate=False the weight is 0:
     projected gradient ascent on the same dual, the method P-APG is compared
     with in Sec. III.
 

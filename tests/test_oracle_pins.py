@@ -82,6 +82,11 @@ def test_single_entry_helpers_match_full():
         um, vm = oracle.adjoint_one(X, m, Z[m], Z[:, m])
         assert abs(um - u[m]) < 1e-12
         np.testing.assert_allclose(vm, v[m], atol=1e-12)
+        # the sampled-output checker of the full-size tests: row m and column m of R
+        row, col = oracle.residual_row_col(X, y, xi, m)
+        np.testing.assert_allclose(row, R[m], rtol=0, atol=1e-13)
+        np.testing.assert_allclose(col, R[:, m], rtol=0, atol=1e-13)
+        assert row[m] == 0.0 and col[m] == 0.0
 
 
 # --------------------------------------------------------------------------
@@ -154,26 +159,29 @@ def test_alcc_closed_form_cases(case):
     np.testing.assert_allclose(res.xi, case["xi"], atol=2e-5)
 
 
+@pytest.mark.parametrize("step_scale", [0.5, 1.0])
 @pytest.mark.parametrize("N,n,seed", [(4, 1, 0), (4, 2, 1)])
-def test_alcc_matches_active_set_brute_force(N, n, seed):
+def test_alcc_matches_active_set_brute_force(N, n, seed, step_scale):
+    """step_scale 1.0 is Fig. 4's step 1/L as printed, 0.5 the default reading."""
     rng = np.random.default_rng(seed)
     X = rng.uniform(-1, 1, size=(N, n))
     ybar = np.sum(X ** 2, axis=1) + 0.3 * rng.normal(size=N)
     gamma = 0.05
     y_ref, xi_ref = refqp.solve_qp_active_set(X, ybar, gamma)
-    res = oracle.alcc(X, ybar, _tight(gamma=gamma))
+    res = oracle.alcc(X, ybar, _tight(gamma=gamma, step_scale=step_scale))
     np.testing.assert_allclose(res.y, y_ref, atol=1e-5)
     np.testing.assert_allclose(res.xi, xi_ref, atol=1e-4)
 
 
-def test_alcc_matches_nnls_dual_qp():
+@pytest.mark.parametrize("step_scale", [0.5, 1.0])
+def test_alcc_matches_nnls_dual_qp(step_scale):
     p = synth.quadratic_uniform(30, 2, 0.1, seed=3)
     gamma = 1e-2
     y_ref, xi_ref, lam = refqp.solve_qp_nnls(p.X, p.ybar, gamma)
     # the reference itself satisfies the KKT conditions
     m = oracle.kkt_measures(p.X, p.ybar, gamma, y_ref, xi_ref, refqp.pairs_to_matrix(lam, 30))
     assert m["kkt"] < 1e-8
-    res = oracle.alcc(p.X, p.ybar, _tight(gamma=gamma, kkt_tol=1e-7))
+    res = oracle.alcc(p.X, p.ybar, _tight(gamma=gamma, kkt_tol=1e-7, step_scale=step_scale))
     assert res.converged
     assert np.linalg.norm(res.y - y_ref) <= 1e-4 * np.linalg.norm(y_ref)
     assert np.linalg.norm(res.xi - xi_ref) <= 1e-3 * np.linalg.norm(xi_ref)
@@ -330,3 +338,85 @@ def test_affine_fit_full_rank_and_degenerate():
     P = np.linalg.pinv(Xc) @ Xc
     np.testing.assert_allclose(P @ a, a, rtol=0, atol=1e-12)
     assert abs(Bbar - np.sqrt(1e-3 * 3 * a @ a)) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# MAPG steps (Fig. 4) on a hand-derived example, and the ball projection
+# --------------------------------------------------------------------------
+
+def _mapg_golden():
+    g = json.load(open(os.path.join(HERE, "golden", "mapg_momentum.json")))
+    pr = g["problem"]
+    args = dict(X=np.array(pr["X"]), ybar=np.array(pr["ybar"]), gamma=pr["gamma"], mu=pr["mu"],
+                theta=np.array(pr["theta"]), Ly=pr["Ly"], Lxi=pr["Lxi"], y0=np.array(pr["y0"]),
+                xi0=np.array(pr["xi0"]), By=pr["ball_radius"], Bxi=pr["ball_radius"])
+    return g, args, pr["step_scale"]
+
+
+def test_mapg_momentum_hand_example():
+    """t_l, the extrapolation weights and every iterate of the first five MAPG
+    steps against their hand derivation (the penalty stays idle, so the run is
+    the accelerated method on a known quadratic)."""
+    g, a, s = _mapg_golden()
+    for lmax in range(1, 6):
+        trace = []
+        y, xi, used = oracle.mapg(a["X"], a["ybar"], a["gamma"], a["mu"], a["theta"], a["Ly"], a["Lxi"],
+                                  a["y0"], a["xi0"], a["By"], a["Bxi"], 0.0, 0.0, lmax, step_scale=s,
+                                  adaptive=False, trace=trace)
+        assert used == lmax
+        np.testing.assert_array_equal(y, a["ybar"])
+        b = g["b1"][lmax - 1]
+        np.testing.assert_allclose(xi.ravel(), [-b, b], rtol=1e-14, atol=0)
+    assert [row[0] for row in trace] == [1, 2, 3, 4, 5]
+    np.testing.assert_allclose([row[3] for row in trace], g["t"], rtol=1e-15, atol=0)
+    np.testing.assert_allclose([row[4] for row in trace], g["beta"], rtol=1e-14, atol=1e-300)
+    np.testing.assert_allclose([row[2] for row in trace], g["xi_move"], rtol=1e-14, atol=0)
+    assert all(row[1] == 0.0 for row in trace)
+
+
+@pytest.mark.parametrize("alpha_xi,stop", [(0.36, 1), (0.2, 3), (0.11, 4), (0.1074868, 5), (0.01, 5)])
+def test_mapg_alpha_stop_returns_that_steps_iterate(alpha_xi, stop):
+    """The adaptive test stops after the first step whose two block moves are
+    within alpha and returns that step's projected iterate (not the
+    extrapolated one); otherwise the run ends at l_max = 5."""
+    g, a, s = _mapg_golden()
+    y, xi, used = oracle.mapg(a["X"], a["ybar"], a["gamma"], a["mu"], a["theta"], a["Ly"], a["Lxi"],
+                              a["y0"], a["xi0"], a["By"], a["Bxi"], 0.0, alpha_xi, 5, step_scale=s,
+                              adaptive=True)
+    assert used == stop
+    b = g["b1"][stop - 1]
+    np.testing.assert_allclose(xi.ravel(), [-b, b], rtol=1e-14, atol=0)
+    np.testing.assert_array_equal(y, a["ybar"])
+
+
+def test_project_ball_hand_values_and_variational_inequality():
+    """Euclidean projection onto a ball (Q_y, Q_xi of Sec. II-E): hand values
+    inside, outside and on the sphere, and the characterisation of the
+    projection onto a closed convex set: P(v) lies in the ball and
+    <v - P(v), z - P(v)> <= 0 for every z in it."""
+    o = np.zeros(2)
+    np.testing.assert_allclose(oracle.project_ball(np.array([3.0, 4.0]), o, 1.0), [0.6, 0.8], rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(oracle.project_ball(np.array([0.1, -0.2]), o, 1.0), [0.1, -0.2])
+    c = np.array([1.0, 1.0])
+    np.testing.assert_allclose(oracle.project_ball(np.array([1.0, 5.0]), c, 2.0), [1.0, 3.0], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(oracle.project_ball(np.array([-2.0, -3.0]), c, 2.5), [-0.5, -1.0], rtol=0,
+                               atol=1e-15)
+    np.testing.assert_array_equal(oracle.project_ball(np.array([1.0, 3.0]), c, 2.0), [1.0, 3.0])
+    rng = np.random.default_rng(8)
+    for trial in range(60):
+        shape = (7,) if trial % 2 else (4, 3)          # vectors and slope arrays alike
+        cen = rng.normal(size=shape)
+        v = cen + rng.normal(size=shape) * rng.choice([0.1, 1.0, 5.0])
+        r = float(rng.uniform(0.2, 3.0))
+        p = oracle.project_ball(v, cen, r)
+        assert p.shape == v.shape
+        assert np.linalg.norm(p - cen) <= r * (1 + 1e-13)
+        if np.linalg.norm(v - cen) <= r:
+            np.testing.assert_array_equal(p, v)
+        d = rng.normal(size=(200,) + shape)
+        norms = np.sqrt(np.sum(d.reshape(200, -1) ** 2, axis=1)).reshape((200,) + (1,) * len(shape))
+        u = rng.uniform(0, 1, size=(200,) + (1,) * len(shape)) ** (1.0 / v.size)
+        Z = cen + d / norms * r * u
+        Z[0] = cen + (p - cen)                          # a point on the sphere next to P(v)
+        vi = np.sum((Z - p) * (v - p), axis=tuple(range(1, 1 + len(shape))))
+        assert np.all(vi <= 1e-12 * (1 + np.linalg.norm(v - cen) * r))
