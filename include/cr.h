@@ -90,12 +90,19 @@ enum {
  *   tile_rows   rows of theta per pass workgroup (rounded up to 64);
  *               0 selects a heuristic; an autotuner picks it per
  *               (n, precision, N bucket) in the Python layer         [0]
+ *   deterministic 1: single-problem runs use the batched form's kernels
+ *               (pair pass, reduction, update) instead of completing each
+ *               MAPG step inside the next pass, so that a problem solved
+ *               alone gives the same bits as inside a cr_solve_batched
+ *               batch with the same tile_rows.  Every run is bitwise
+ *               reproducible either way (fixed-order sums, no atomics
+ *               in any sum)                                          [0]
  *   *_override  > 0 replaces the computed L^y, L^xi, Bbar_y, Bbar_xi [0]
  */
 typedef struct {
     double gamma, mu1, c, kappa, tau1, alpha_y1, alpha_xi1, step_scale, kkt_tol;
     int32_t max_outer, inner_iters, max_inner, precision;
-    int32_t tile_rows, reserved;
+    int32_t tile_rows, deterministic;
     double Ly_override, Lxi_override, By_override, Bxi_override;
 } cr_params;
 
@@ -437,6 +444,13 @@ cr_status cr_get_start(cr_ctx* ctx, void* y_dev, void* xi_dev);
 /* Host-synchronous: constants of the context and, after a CR_THETA_UPDATE
  * pass or a run, the KKT scalars of the last multiplier step. */
 cr_status cr_get_info(cr_ctx* ctx, cr_info* info);
+
+/* Per-ALCC-iteration record of the last cr_run (Fig. 3): the MAPG iterations
+ * of ALCC iteration k (the step at which Fig. 4's alpha test or l_max ended
+ * it) and the KKT measure after its multiplier step, k = 0 .. count - 1.
+ * Writes min(cap, count) entries to the host arrays and the total to *count.
+ * Errors: CR_ERR_ARG (NULL ctx or count, cap < 0, NULL arrays with cap > 0). */
+cr_status cr_get_outer_history(cr_ctx* ctx, int32_t cap, int64_t* inner_iters, double* kkt, int32_t* count);
 
 /* Host-synchronous: average device time in milliseconds of the gradient pair
  * pass that cr_run launches, run reps times back to back on the context's

@@ -376,7 +376,7 @@ class Result:
 
 
 def alcc(X, ybar, params: Optional[Params] = None, y0=None, xi0=None,
-         record_kkt: bool = True, xi_shift=None) -> Result:
+         record_kkt: bool = True, xi_shift=None, mapg_traces: Optional[list] = None) -> Result:
     """ALCC (Fig. 3) on eq. "regularize", with MAPG (Fig. 4) as the inner solver.
 
     The multipliers start at zero and the iterate at the affine fit.  Each
@@ -400,7 +400,10 @@ def alcc(X, ybar, params: Optional[Params] = None, y0=None, xi0=None,
     of each block subproblem of P-APG step 1 (Fig. 2, eq. "g_gamma").  The run
     returns xi'.  The affine fit stays the start; in shifted slopes it is
     (yhat, a - shift), feasible for the shifted constraints, and Bbar is the
-    objective there: Bbar^2 = ||yhat - ybar||^2 + gamma ||a - shift||^2."""
+    objective there: Bbar^2 = ||yhat - ybar||^2 + gamma ||a - shift||^2.
+
+    A list passed as `mapg_traces` receives, per outer iteration, the
+    thresholds (alpha_y, alpha_xi) and the MAPG trace (see `mapg`)."""
     p = params or Params()
     X, ybar = _f64(X), _f64(ybar)
     N, n = X.shape
@@ -427,8 +430,12 @@ def alcc(X, ybar, params: Optional[Params] = None, y0=None, xi0=None,
     for k in range(1, p.max_outer + 1):
         Ly, Lxi, lmax = sched.constants()
         mu = sched.mu
+        tr = None
+        if mapg_traces is not None:
+            tr = []
+            mapg_traces.append((sched.ay, sched.axi, tr))
         y, xi, used = mapg(X, ybar, gamma, mu, theta, Ly, Lxi, y, xi, By, Bxi, sched.ay, sched.axi,
-                           lmax, p.step_scale, adaptive=not fixed, shift=shift)
+                           lmax, p.step_scale, adaptive=not fixed, trace=tr, shift=shift)
         inner_list.append(used)
         mu_next = p.c * mu
         theta = multiplier_step(X, y, _shifted(xi, shift), theta, mu / mu_next)

@@ -40,7 +40,7 @@ class _CParams(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in
                 ("gamma", "mu1", "c", "kappa", "tau1", "alpha_y1", "alpha_xi1", "step_scale", "kkt_tol")] + \
                [(k, ctypes.c_int32) for k in ("max_outer", "inner_iters", "max_inner", "precision",
-                                              "tile_rows", "reserved")] + \
+                                              "tile_rows", "deterministic")] + \
                [(k, ctypes.c_double) for k in ("Ly_override", "Lxi_override", "By_override", "Bxi_override")]
 
 
@@ -98,6 +98,7 @@ def _load():
         "cr_get_start": (i32, [vp, vp, vp]),
         "cr_get_info": (i32, [vp, pi]),
         "cr_time_pass": (i32, [vp, i32, i32, ctypes.POINTER(dbl)]),
+        "cr_get_outer_history": (i32, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.POINTER(i32)]),
         "cr_batch_workspace_bytes": (i32, [ctypes.POINTER(_CProblem), i32, pp, ctypes.POINTER(ctypes.c_size_t)]),
         "cr_batch_init": (i32, [ctypes.POINTER(vp), ctypes.POINTER(_CProblem), i32, pp, vp, ctypes.c_size_t, vp]),
         "cr_batch_run": (i32, [vp, pi, ctypes.POINTER(dbl)]),
@@ -126,7 +127,7 @@ _lib = _load()
 
 EXPORTED = ("cr_params_default", "cr_status_string", "cr_last_error", "cr_workspace_bytes", "cr_init",
             "cr_destroy", "cr_pairwise_step", "cr_run", "cr_solve", "cr_get_theta", "cr_set_theta",
-            "cr_get_start", "cr_get_info", "cr_time_pass", "cr_batch_workspace_bytes", "cr_batch_init",
+            "cr_get_start", "cr_get_info", "cr_time_pass", "cr_get_outer_history", "cr_batch_workspace_bytes", "cr_batch_init",
             "cr_batch_run", "cr_batch_destroy", "cr_solve_batched", "cr_diff_workspace_bytes", "cr_diff_init",
             "cr_diff_forward", "cr_diff_backward", "cr_diff_destroy", "cr_diff_time_adjoint_pass",
             "cr_eval_workspace_bytes", "cr_eval", "cr_papg_workspace_bytes", "cr_papg")
@@ -161,6 +162,7 @@ class Params:
     max_inner: Optional[int] = None
     precision: Optional[int] = None
     tile_rows: Optional[int] = None
+    deterministic: Optional[int] = None
     Ly_override: Optional[float] = None
     Lxi_override: Optional[float] = None
     By_override: Optional[float] = None
@@ -303,6 +305,16 @@ class Context:
         ci = _CInfo()
         _check(_lib.cr_get_info(self._h, ctypes.byref(ci)), self._h)
         return Info.from_c(ci)
+
+    def outer_history(self):
+        """(MAPG iterations, KKT measure) of every ALCC iteration of the last run."""
+        cnt = ctypes.c_int32(0)
+        _check(_lib.cr_get_outer_history(self._h, 0, None, None, ctypes.byref(cnt)), self._h)
+        m = cnt.value
+        inner = (ctypes.c_int64 * max(m, 1))()
+        kkt = (ctypes.c_double * max(m, 1))()
+        _check(_lib.cr_get_outer_history(self._h, m, inner, kkt, ctypes.byref(cnt)), self._h)
+        return [int(inner[k]) for k in range(m)], [float(kkt[k]) for k in range(m)]
 
 
 def solve(X, ybar, params: Optional[Params] = None):

@@ -133,6 +133,7 @@ bool check_params(const cr_params* p, std::string& msg) {
     if (p->inner_iters == 0 && p->max_inner < 1) { msg = "max_inner must be >= 1"; return false; }
     if (!(p->kkt_tol >= 0)) { msg = "kkt_tol must be >= 0"; return false; }
     if (p->tile_rows < 0) { msg = "tile_rows must be >= 0"; return false; }
+    if (p->deterministic != 0 && p->deterministic != 1) { msg = "deterministic must be 0 or 1"; return false; }
     if (p->precision != CR_F64 && p->precision != CR_F32 && p->precision != CR_MIXED_BF16) {
         msg = "unknown precision";
         return false;
@@ -176,6 +177,8 @@ struct cr_ctx {
     double sigma2_A1 = 0, sigma2_A2 = 0, Bbar = 0, By = 0, Bxi = 0, ybar_inf = 0;
     std::string err;
     cr::DevState last{};
+    std::vector<int64_t> hist_inner;   // MAPG iterations of each ALCC iteration of the last run
+    std::vector<double> hist_kkt;      // and its KKT measure after the multiplier step
     bool have_kkt = false;
     bool verbose = false;
     bool lazy = false;   // MAPG iterations use lazy passes (single-problem runs whose chunk height allows them)
@@ -441,7 +444,7 @@ cr_status cr_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params, c
     c->n = n;
     c->f64 = params->precision == CR_F64;
     c->prec = params->precision;
-    c->lazy = L.lazy;
+    c->lazy = L.lazy && !params->deterministic;
     c->user_stream = (hipStream_t)stream;
     {
         const char* v = std::getenv("CR_VERBOSE");
@@ -625,6 +628,8 @@ cr_status cr_run(cr_ctx* c, void* y_dev, void* xi_dev, cr_info* info) {
     sch.start(c);
     cr_status result = CR_OK;
     cr::DevState h{};
+    c->hist_inner.clear();
+    c->hist_kkt.clear();
     for (int k = 1; k <= p.max_outer; ++k) {
         const cr::OuterArgs oa = sch.next(c);
         const double mu = sch.mu, mu_next = sch.mu_next(c);
@@ -655,6 +660,8 @@ cr_status cr_run(cr_ctx* c, void* y_dev, void* xi_dev, cr_info* info) {
         if (h.iterate_nonfinite) { result = CR_ERR_NONFINITE; break; }
         cr_info tmp{};
         fill_info(c, h, &tmp);
+        c->hist_inner.push_back(h.it);
+        c->hist_kkt.push_back(tmp.kkt);
         if (c->verbose)
             std::fprintf(stderr, "[cr] outer %d mu %.3e inner %lld (alpha stop %d) kkt %.3e stat_y %.2e stat_xi %.2e "
                          "infeas %.2e compl %.2e obj %.6e t %.3fs\n",
@@ -682,6 +689,18 @@ cr_status cr_run(cr_ctx* c, void* y_dev, void* xi_dev, cr_info* info) {
     }
     if (result == CR_ERR_NONFINITE) return fail(c, result, "non-finite iterate");
     return result;
+}
+
+cr_status cr_get_outer_history(cr_ctx* c, int32_t cap, int64_t* inner_iters, double* kkt, int32_t* count) {
+    if (!c || !count) return fail(c, CR_ERR_ARG, "ctx and count must be non-NULL");
+    if (cap < 0 || (cap > 0 && (!inner_iters || !kkt))) return fail(c, CR_ERR_ARG, "bad capacity or NULL arrays");
+    const int32_t m = (int32_t)c->hist_inner.size();
+    *count = m;
+    for (int32_t k = 0; k < std::min(cap, m); ++k) {
+        inner_iters[k] = c->hist_inner[k];
+        kkt[k] = c->hist_kkt[k];
+    }
+    return CR_OK;
 }
 
 cr_status cr_time_pass(cr_ctx* c, int32_t mode, int32_t reps, double* avg_ms) {

@@ -58,6 +58,9 @@ def test_workspace_bytes_validation_and_growth():
         cr.workspace_bytes(10, 2, cr.Params(step_scale=1.5))
     with pytest.raises(cr.CRError):
         cr.workspace_bytes(10, 2, cr.Params(precision=7))
+    with pytest.raises(cr.CRError):
+        cr.workspace_bytes(10, 2, cr.Params(deterministic=2))
+    assert cr.workspace_bytes(10, 2, cr.Params(deterministic=1)) == cr.workspace_bytes(10, 2)
 
 
 def test_init_rejects_before_touching_the_gpu():
@@ -79,6 +82,8 @@ def test_init_rejects_before_touching_the_gpu():
     # entry points that take a context reject NULL
     assert lib.cr_pairwise_step(None, 0, fake, fake, fake, fake, 1.0, 2.0) == cr.ERR_ARG
     assert lib.cr_run(None, fake, fake, None) == cr.ERR_ARG
+    cnt = ctypes.c_int32(0)
+    assert lib.cr_get_outer_history(None, 0, None, None, ctypes.byref(cnt)) == cr.ERR_ARG
     assert lib.cr_destroy(None) == cr.OK
     assert lib.cr_solve(fake, fake, 50, 3, ctypes.byref(p), None, fake, fake, need, None, None) == cr.ERR_ARG
 

@@ -88,7 +88,7 @@ def test_papg_matches_oracle(cr, case):
     ey, exi, eth = rel(y, ref.y), rel(xi, ref.xi), rel(th, ref.Th)
     say("  relative error vs FP64 oracle: y %.3e  xi %.3e  theta %.3e  (||theta|| %.3e)"
         % (ey, exi, eth, info["theta_norm"]))
-    assert ey < TOL and exi < TOL * 10 and eth < TOL * 10
+    assert ey < TOL and exi < TOL and eth < TOL
     np.testing.assert_allclose(thy, ref.th_y, rtol=0, atol=TOL * (1 + np.abs(ref.Th).max()))
     # structure: zero inside the diagonal blocks, nonnegative everywhere
     assert np.all(th[~opapg.cross_mask(p.N, K)] == 0.0) and np.all(th >= 0.0) and np.all(thy >= 0.0)
@@ -111,7 +111,7 @@ def test_papg_ball_active_and_given_constants(cr):
     assert np.count_nonzero(ref.th_y) > 0
     ey, eth = rel(y, ref.y), rel(th, ref.Th)
     say("  relative error vs FP64 oracle: y %.3e  theta %.3e  theta_y %.3e" % (ey, eth, rel(thy, ref.th_y)))
-    assert ey < TOL and eth < TOL * 10 and rel(thy, ref.th_y) < TOL * 10
+    assert ey < TOL and eth < TOL and rel(thy, ref.th_y) < TOL
 
 
 def test_papg_single_block_is_a_batched_solve(cr):
@@ -121,7 +121,7 @@ def test_papg_single_block_is_a_batched_solve(cr):
     say("papg K=1 N=80 n=4, 2 iterations of 3 x 32, against cr.solve")
     y, xi, info = cr.papg(dev(p.X), dev(p.ybar), cr.PapgParams(K=1, iters=2), cr.Params(precision=0, **sched))
     ys, xis, _ = cr.solve(dev(p.X), dev(p.ybar), cr.Params(precision=0, **sched))
-    assert rel(host(y), host(ys)) < TOL and rel(host(xi), host(xis)) < TOL * 10
+    assert rel(host(y), host(ys)) < TOL and rel(host(xi), host(xis)) < TOL
     assert info["theta_norm"] == 0.0
 
 
@@ -161,7 +161,7 @@ def test_gradient_ascent_matches_oracle(cr):
     ref, y, xi, info, th, thy = _run(cr, p, 4, 4, 32, 3, 0.1, accelerate=False)
     ey, eth = rel(y, ref.y), rel(th, ref.Th)
     say("  relative error vs FP64 oracle: y %.3e  theta %.3e" % (ey, eth))
-    assert ey < TOL and eth < TOL * 10
+    assert ey < TOL and eth < TOL
     _check_trace(info["trace"], ref)
 
 
@@ -174,7 +174,7 @@ def test_small_study_accelerated_against_gradient_ascent(cr):
     for acc in (True, False):
         ref, y, xi, info, th, thy = _run(cr, p, 2, 40, 40, 4, 0.05, accelerate=acc)
         _check_trace(info["trace"], ref)
-        assert rel(y, ref.y) < TOL and rel(th, ref.Th) < TOL * 10
+        assert rel(y, ref.y) < TOL and rel(th, ref.Th) < TOL
         out[acc] = info["trace"]
         say("  %s: infeasibility %.4e -> %.4e, ||theta|| %.4e"
             % ("P-APG" if acc else "ascent", info["trace"][0, 1], info["trace"][-1, 1], info["trace"][-1, 0]))

@@ -44,7 +44,10 @@ def rel(a, b):
 # Tolerances: FP64 pass vs FP64 oracle differs only by summation order (~1e-15
 # per term); the FP32 pass rounds theta, r and every in-tile sum to 24 bits.
 TOL_PASS = {0: 1e-12, 1: 3e-5, 2: 3e-4}
-TOL_SOLVE = {0: 1e-9, 1: 1e-5, 2: 1e-3}
+# After a fixed schedule: the spec bars for FP64 and FP32 (y and Xi
+# alike); the mixed form's bar is its measured error level (below 1e-5 on
+# every case here), stated rather than derived.
+TOL_SOLVE = {0: 1e-9, 1: 1e-5, 2: 3e-5}
 PREC_NAME = {0: "f64", 1: "f32", 2: "mixed_bf16"}
 
 
@@ -167,7 +170,70 @@ def test_fixed_schedule_small_quadratic(cr, prec):
     ey, exi = rel(host(y), ref.y), rel(host(xi), ref.xi)
     say("  relative error vs FP64 oracle: y %.3e  xi %.3e" % (ey, exi))
     assert ey < TOL_SOLVE[prec]
-    assert exi < TOL_SOLVE[prec] * 10
+    assert exi < TOL_SOLVE[prec]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+def test_fixed_schedule_step_as_printed(cr, prec):
+    """Fig. 4 with the step 1/L exactly as printed (step_scale = 1) on both
+    sides: the default reading takes half of it."""
+    say("fixed schedule small_quadratic N=200 n=2 10x50 step_scale=1 %s" % PREC_NAME[prec])
+    p = synth.workload("small_quadratic")
+    sched = dict(inner_iters=50, max_outer=10, step_scale=1.0)
+    ref = oracle.alcc(p.X, p.ybar, oracle.Params(**sched), record_kkt=False)
+    y, xi, info = cr.solve(dev(p.X), dev(p.ybar), cr.Params(precision=prec, **sched))
+    assert info.inner_iters == 500 and info.outer_iters == 10
+    ey, exi = rel(host(y), ref.y), rel(host(xi), ref.xi)
+    say("  relative error vs FP64 oracle: y %.3e  xi %.3e" % (ey, exi))
+    assert ey < TOL_SOLVE[prec]
+    assert exi < TOL_SOLVE[prec]
+
+
+def _alpha_margin(traces):
+    """Smallest relative distance of a MAPG step's block moves from the alpha
+    thresholds over a whole oracle run (the adaptive test's rounding margin)."""
+    worst = math.inf
+    for ay, axi, steps in traces:
+        for (_, dy, dxi, _, _) in steps:
+            worst = min(worst, abs(dy - ay) / ay, abs(dxi - axi) / axi)
+    return worst
+
+
+# Adaptive schedules (Fig. 3 l_max and tau/alpha decay, Fig. 4 alpha test) in
+# FP64: lazy passes with alpha stops and l_max caps, and tall chunks (the update
+# kernel) with capped runs.  Every step's block moves stay at least 1e-6
+# (relative) away from the thresholds, so both sides take the same branches.
+ADAPTIVE_CASES = [
+    # N, n, seed, max_inner, max_outer, tile_rows
+    (60, 2, 0, 20000, 30, 0),
+    (90, 5, 2, 3000, 6, 0),
+    (1600, 3, 4, 300, 4, 1600),
+]
+
+
+@pytest.mark.parametrize("N,n,seed,max_inner,max_outer,tile_rows", ADAPTIVE_CASES,
+                         ids=["N60-lazy", "N90-lazy-capped", "N1600-tall-chunks"])
+def test_adaptive_schedule_matches_oracle(cr, N, n, seed, max_inner, max_outer, tile_rows):
+    say("adaptive f64 N=%d n=%d seed=%d max_inner=%d max_outer=%d tile_rows=%d"
+        % (N, n, seed, max_inner, max_outer, tile_rows))
+    p = synth.quad_l1_gaussian(N, n, seed=seed)
+    sched = dict(kkt_tol=1e-4, max_inner=max_inner, max_outer=max_outer)
+    traces = []
+    ref = oracle.alcc(p.X, p.ybar, oracle.Params(**sched), mapg_traces=traces)
+    margin = _alpha_margin(traces)
+    say("  oracle: inner %s converged %s, alpha margin %.2e" % (ref.inner_per_outer, ref.converged, margin))
+    assert margin > 1e-6
+    ctx = cr.Context(dev(p.X), dev(p.ybar), cr.Params(precision=0, tile_rows=tile_rows, **sched))
+    y, xi, info = ctx.run()
+    inner, kkt = ctx.outer_history()
+    ey, exi = rel(host(y), ref.y), rel(host(xi), ref.xi)
+    say("  gpu: inner %s, y %.3e xi %.3e" % (inner, ey, exi))
+    assert inner == ref.inner_per_outer
+    assert info.outer_iters == ref.outer and info.inner_iters == ref.inner_total
+    assert (info.status == 0) == ref.converged
+    np.testing.assert_allclose(kkt, [h["kkt"] for h in ref.history], rtol=1e-6, atol=1e-12)
+    assert ey < TOL_SOLVE[0]
+    assert exi < TOL_SOLVE[0]
 
 
 # MAPG run lengths around the 32-iteration replay: a run that a reduce kernel
@@ -185,7 +251,7 @@ def test_fixed_schedule_run_lengths(cr, prec, inner):
     ey, exi = rel(host(y), ref.y), rel(host(xi), ref.xi)
     say("  y %.2e xi %.2e" % (ey, exi))
     assert ey < TOL_SOLVE[prec]
-    assert exi < TOL_SOLVE[prec] * 10
+    assert exi < TOL_SOLVE[prec]
 
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
@@ -205,7 +271,7 @@ def test_tall_chunks_match_short_chunks(cr, prec):
     for tr, (y, xi) in out.items():
         say("  tile_rows %d: y %.2e xi %.2e" % (tr, rel(y, ref.y), rel(xi, ref.xi)))
         assert rel(y, ref.y) < TOL_SOLVE[prec]
-        assert rel(xi, ref.xi) < TOL_SOLVE[prec] * 10
+        assert rel(xi, ref.xi) < TOL_SOLVE[prec]
     tol = 1e-12 if prec == 0 else 1e-5
     assert rel(out[256][0], out[4096][0]) < tol
 
@@ -233,7 +299,7 @@ def test_fixed_schedule_ragged(cr, N, n, seed):
     ref = oracle.alcc(p.X, p.ybar, oracle.Params(**sched), record_kkt=False)
     y, xi, info = cr.solve(dev(p.X), dev(p.ybar), cr.Params(precision=0, **sched))
     assert rel(host(y), ref.y) < 1e-9
-    assert rel(host(xi), ref.xi) < 1e-8
+    assert rel(host(xi), ref.xi) < 1e-9
 
 
 def test_nonfinite_inputs_rejected(cr):
@@ -262,7 +328,7 @@ def test_degenerate_and_widest_shapes(cr, N, n, prec):
     ey, exi = rel(host(y), ref.y), rel(host(xi), ref.xi)
     say("  y %.2e xi %.2e" % (ey, exi))
     assert ey < TOL_SOLVE[prec]
-    assert exi < TOL_SOLVE[prec] * 10
+    assert exi < TOL_SOLVE[prec]
 
 
 def test_constant_data_fixed_point(cr):
@@ -371,8 +437,8 @@ def test_full_size_fixed_schedule_benchmark_launch(cr, prec):
     ref = _full_size_reference()
     ey, exi = rel(host(y), ref.y), rel(host(xi), ref.xi)
     say("  relative error vs FP64 oracle: y %.3e  xi %.3e" % (ey, exi))
-    assert ey < {0: 1e-9, 1: 2e-5}[prec]
-    assert exi < {0: 1e-8, 1: 2e-4}[prec]
+    assert ey < TOL_SOLVE[prec]
+    assert exi < TOL_SOLVE[prec]
 
 
 # --------------------------------------------------------------------------
@@ -398,7 +464,7 @@ def test_batched_fixed_schedule_matches_oracle(cr, prec):
         ey, exi = rel(host(y), ref.y), rel(host(xi), ref.xi)
         say("  N=%d n=%d: y %.2e xi %.2e" % (p.N, p.n, ey, exi))
         assert ey < TOL_SOLVE[prec]
-        assert exi < TOL_SOLVE[prec] * 10
+        assert exi < TOL_SOLVE[prec]
 
 
 def test_batched_equals_single_problem_solves(cr):
@@ -410,6 +476,32 @@ def test_batched_equals_single_problem_solves(cr):
         ys, xis, _ = cr.solve(dev(p.X), dev(p.ybar), cr.Params(precision=0, **sched))
         assert rel(host(y), host(ys)) < 1e-12
         assert rel(host(xi), host(xis)) < 1e-11
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+def test_batched_equals_single_problem_bitwise_in_deterministic_mode(cr, prec):
+    """With deterministic = 1 a problem solved alone runs the batched form's
+    kernels; with the same tile heights its result has the same bits as inside
+    the batch (fixed and adaptive schedules)."""
+    shapes = [(37, 3), (150, 5), (300, 10), (513, 20)]
+    tiles = [64, 128, 192, 256]
+    say("batched vs single, bitwise, %s shapes %s tiles %s" % (PREC_NAME[prec], shapes, tiles))
+    probs = _batch_problems(shapes, seed0=400)
+    for sched in (dict(inner_iters=25, max_outer=3), dict(kkt_tol=1e-3, max_inner=400, max_outer=4)):
+        prm = cr.Params(precision=prec, deterministic=1, **sched)
+        b = cr.Batch([(dev(p.X), dev(p.ybar)) for p in probs], prm, tile_rows=tiles)
+        try:
+            outs, infos, _ = b.run()
+            outs = [(host(y), host(xi)) for y, xi in outs]
+        finally:
+            b.close()
+        for p, t, (y, xi), info in zip(probs, tiles, outs, infos):
+            ys, xis, infs = cr.solve(dev(p.X), dev(p.ybar), cr.Params(precision=prec, deterministic=1,
+                                                                     tile_rows=t, **sched))
+            say("  N=%d n=%d %s: inner %d / %d" % (p.N, p.n, sched, info.inner_iters, infs.inner_iters))
+            assert info.inner_iters == infs.inner_iters and info.outer_iters == infs.outer_iters
+            np.testing.assert_array_equal(y, host(ys))
+            np.testing.assert_array_equal(xi, host(xis))
 
 
 def test_batched_adaptive_converges_and_freezes(cr):
