@@ -431,6 +431,21 @@ cr_status cr_eval(const void* X_dev, const void* y_dev, const void* xi_dev, int6
                   const void* Q_dev, int64_t M, void* fhat_dev, int64_t* arg_dev, void* workspace_dev,
                   size_t ws_bytes, void* stream);
 
+/* cr_eval for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation and results as cr_eval, with the packed plane operands in
+ * a static device array of 32 MiB that the library holds on each GPU it runs
+ * on until the process ends, instead of a caller workspace.  Calls no
+ * allocating routine.  Every call on a GPU shares that GPU's array, so calls
+ * that overlap on one GPU (on different streams, or from several threads)
+ * race and must be ordered by the caller.  Inputs, outputs, ownership,
+ * asynchrony and errors as cr_eval, plus CR_ERR_NOMEM when the packed planes,
+ * 32 * ceil(N / 32) * 4 * ceil((n + 1) / 4) doubles, exceed 32 MiB (N up to
+ * 174752 at n = 20), and CR_ERR_HIP if the array's device address cannot be
+ * obtained (looked up once per device, on the first call there). */
+cr_status cr_eval_noalloc(const void* X_dev, const void* y_dev, const void* xi_dev, int64_t N, int32_t n,
+                          const void* Q_dev, int64_t M, void* fhat_dev, int64_t* arg_dev, void* stream);
+
 /* Inspection and test hooks --------------------------------------------- */
 
 /* Copy the context's theta to / from an N x N FP64 device array (diagonal

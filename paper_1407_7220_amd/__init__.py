@@ -112,6 +112,7 @@ def _load():
         "cr_diff_time_adjoint_pass": (i32, [vp, i32, ctypes.POINTER(dbl)]),
         "cr_eval_workspace_bytes": (i32, [i64, i32, ctypes.POINTER(ctypes.c_size_t)]),
         "cr_eval": (i32, [vp, vp, vp, i64, i32, vp, i64, vp, vp, vp, ctypes.c_size_t, vp]),
+        "cr_eval_noalloc": (i32, [vp, vp, vp, i64, i32, vp, i64, vp, vp, vp]),
         "cr_papg_workspace_bytes": (i32, [i64, i32, pp, ctypes.POINTER(_CPapgParams), ctypes.POINTER(ctypes.c_size_t)]),
         "cr_papg": (i32, [vp, vp, i64, i32, pp, ctypes.POINTER(_CPapgParams), vp, vp, vp, vp,
                           ctypes.POINTER(dbl), vp, ctypes.c_size_t, ctypes.POINTER(_CPapgInfo), vp]),
@@ -130,7 +131,7 @@ EXPORTED = ("cr_params_default", "cr_status_string", "cr_last_error", "cr_worksp
             "cr_get_start", "cr_get_info", "cr_time_pass", "cr_get_outer_history", "cr_batch_workspace_bytes", "cr_batch_init",
             "cr_batch_run", "cr_batch_destroy", "cr_solve_batched", "cr_diff_workspace_bytes", "cr_diff_init",
             "cr_diff_forward", "cr_diff_backward", "cr_diff_destroy", "cr_diff_time_adjoint_pass",
-            "cr_eval_workspace_bytes", "cr_eval", "cr_papg_workspace_bytes", "cr_papg")
+            "cr_eval_workspace_bytes", "cr_eval", "cr_eval_noalloc", "cr_papg_workspace_bytes", "cr_papg")
 
 
 class CRError(RuntimeError):
@@ -550,6 +551,19 @@ class Estimator:
 def evaluate(X, y, xi, Q, with_arg: bool = True):
     """One-shot ``Estimator(X, y, xi)(Q)``."""
     return Estimator(X, y, xi)(Q, with_arg)
+
+
+def evaluate_noalloc(X, y, xi, Q, fhat, arg=None):
+    """``cr_eval_noalloc``: the estimator at the rows of Q into the caller's
+    fhat (M,) float64 and arg (M,) int64 (or None) tensors, with no device
+    allocation by the library (a static 32 MiB scratch per GPU; calls that
+    overlap on one GPU race)."""
+    N, n = int(X.shape[0]), int(X.shape[1])
+    M = int(Q.shape[0])
+    _check(_lib.cr_eval_noalloc(_dev_f64(X, (N, n), "X"), _dev_f64(y, (N,), "y"), _dev_f64(xi, (N, n), "xi"),
+                                N, n, _dev_f64(Q, (M, n), "Q"), M, _dev_f64(fhat, (M,), "fhat"),
+                                ctypes.c_void_p(arg.data_ptr()) if arg is not None else None, _stream()))
+    return fhat, arg
 
 
 

@@ -20,6 +20,7 @@
 #include "../../include/cr.h"
 
 #include <cmath>
+#include <mutex>
 #include <string>
 
 namespace cr {
@@ -193,7 +194,19 @@ static hipError_t launch_eval(const EvalArgs& a, hipStream_t s) {
 
 }  // namespace cr
 
+// Static scratch of cr_eval_noalloc: the packed planes live in a file-scope
+// device array (one copy per GPU, held until the process ends) instead of a
+// workspace, for callers that cannot allocate.  32 MiB hold N * 4 ceil((n+1)/4)
+// doubles, e.g. 174752 planes at n = 20 or 1048576 at n = 3.
+constexpr size_t kEvalScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) double eval_scratch_mem[kEvalScratchBytes / sizeof(double)];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
 size_t eval_ws_bytes(int64_t N, int n) {
     return (size_t)(cr::eval_tiles(N) * cr::kEvalCols) * (size_t)(4 * cr::eval_ks(n)) * 8 + 256;
 }
@@ -202,6 +215,56 @@ cr_status eval_fail(cr_status s, const std::string& msg) {
     cr::set_last_error(msg);
     return s;
 }
+
+// Host-side argument checks shared by both entry points (before any HIP call).
+cr_status eval_check(const void* X_dev, const void* y_dev, const void* xi_dev, int64_t N, int32_t n,
+                     const void* Q_dev, int64_t M, const void* fhat_dev) {
+    if (N < 1 || n < 1 || M < 0) return eval_fail(CR_ERR_ARG, "N and n must be >= 1 and M >= 0");
+    if (N >= ((int64_t)1 << 31) - 64) return eval_fail(CR_ERR_UNSUPPORTED, "N must be below 2^31 - 64");
+    if (n > CR_MAX_DIM) return eval_fail(CR_ERR_UNSUPPORTED, "n above CR_MAX_DIM is not supported");
+    if (!X_dev || !y_dev || !xi_dev || (M > 0 && (!Q_dev || !fhat_dev)))
+        return eval_fail(CR_ERR_ARG, "X, y, xi, Q and fhat must be non-NULL");
+    return CR_OK;
+}
+
+// Packing kernel and evaluation kernel on the packed-plane buffer B (256-byte aligned).
+cr_status eval_launch(const void* X_dev, const void* y_dev, const void* xi_dev, int64_t N, int32_t n,
+                      const void* Q_dev, int64_t M, void* fhat_dev, int64_t* arg_dev, double* B, hipStream_t s) {
+    const int kp = 4 * cr::eval_ks(n);
+    const int64_t ntiles = cr::eval_tiles(N);
+    const int64_t Npad = ntiles * cr::kEvalCols;
+    const int64_t elems = Npad * kp;
+    hipLaunchKernelGGL(cr::k_eval_prep, dim3((unsigned)((elems + cr::kBlock - 1) / cr::kBlock)), dim3(cr::kBlock), 0, s,
+                       (const double*)X_dev, (const double*)y_dev, (const double*)xi_dev, N, (int)n, kp, Npad, B);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return eval_fail(CR_ERR_HIP, std::string("eval prep: ") + hipGetErrorString(e));
+    cr::EvalArgs a{};
+    a.N = N; a.M = M; a.n = n; a.kp = kp; a.ntiles = ntiles;
+    a.Q = (const double*)Q_dev; a.B = B; a.f = (double*)fhat_dev; a.arg = arg_dev;
+    e = cr::launch_eval(a, s);
+    if (e != hipSuccess) return eval_fail(CR_ERR_HIP, std::string("eval: ") + hipGetErrorString(e));
+    return CR_OK;
+}
+
+// Device address of this GPU's copy of eval_scratch_mem, looked up once per device
+// (with that device current) and kept; never the host-side name of the array.
+cr_status eval_scratch(double** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return eval_fail(CR_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return eval_fail(CR_ERR_UNSUPPORTED, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(eval_scratch_mem));
+        if (e != hipSuccess || !ptr)
+            return eval_fail(CR_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch[dev];
+    return CR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -217,29 +280,28 @@ cr_status cr_eval_workspace_bytes(int64_t N, int32_t n, size_t* bytes) {
 
 cr_status cr_eval(const void* X_dev, const void* y_dev, const void* xi_dev, int64_t N, int32_t n, const void* Q_dev,
                   int64_t M, void* fhat_dev, int64_t* arg_dev, void* workspace_dev, size_t ws_bytes, void* stream) {
-    if (N < 1 || n < 1 || M < 0) return eval_fail(CR_ERR_ARG, "N and n must be >= 1 and M >= 0");
-    if (N >= ((int64_t)1 << 31) - 64) return eval_fail(CR_ERR_UNSUPPORTED, "N must be below 2^31 - 64");
-    if (n > CR_MAX_DIM) return eval_fail(CR_ERR_UNSUPPORTED, "n above CR_MAX_DIM is not supported");
-    if (!X_dev || !y_dev || !xi_dev || !workspace_dev || (M > 0 && (!Q_dev || !fhat_dev)))
-        return eval_fail(CR_ERR_ARG, "X, y, xi, Q, fhat and the workspace must be non-NULL");
+    cr_status st = eval_check(X_dev, y_dev, xi_dev, N, n, Q_dev, M, fhat_dev);
+    if (st != CR_OK) return st;
+    if (!workspace_dev) return eval_fail(CR_ERR_ARG, "the workspace must be non-NULL");
     if (ws_bytes < eval_ws_bytes(N, n)) return eval_fail(CR_ERR_NOMEM, "workspace smaller than cr_eval_workspace_bytes()");
     if (M == 0) return CR_OK;
-    hipStream_t s = (hipStream_t)stream;
     double* B = reinterpret_cast<double*>(((uintptr_t)workspace_dev + 255) & ~(uintptr_t)255);
-    const int kp = 4 * cr::eval_ks(n);
-    const int64_t ntiles = cr::eval_tiles(N);
-    const int64_t Npad = ntiles * cr::kEvalCols;
-    const int64_t elems = Npad * kp;
-    hipLaunchKernelGGL(cr::k_eval_prep, dim3((unsigned)((elems + cr::kBlock - 1) / cr::kBlock)), dim3(cr::kBlock), 0, s,
-                       (const double*)X_dev, (const double*)y_dev, (const double*)xi_dev, N, (int)n, kp, Npad, B);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return eval_fail(CR_ERR_HIP, std::string("eval prep: ") + hipGetErrorString(e));
-    cr::EvalArgs a{};
-    a.N = N; a.M = M; a.n = n; a.kp = kp; a.ntiles = ntiles;
-    a.Q = (const double*)Q_dev; a.B = B; a.f = (double*)fhat_dev; a.arg = arg_dev;
-    e = cr::launch_eval(a, s);
-    if (e != hipSuccess) return eval_fail(CR_ERR_HIP, std::string("eval: ") + hipGetErrorString(e));
-    return CR_OK;
+    return eval_launch(X_dev, y_dev, xi_dev, N, n, Q_dev, M, fhat_dev, arg_dev, B, (hipStream_t)stream);
+}
+
+cr_status cr_eval_noalloc(const void* X_dev, const void* y_dev, const void* xi_dev, int64_t N, int32_t n,
+                          const void* Q_dev, int64_t M, void* fhat_dev, int64_t* arg_dev, void* stream) {
+    cr_status st = eval_check(X_dev, y_dev, xi_dev, N, n, Q_dev, M, fhat_dev);
+    if (st != CR_OK) return st;
+    if (eval_ws_bytes(N, n) - 256 > kEvalScratchBytes)
+        return eval_fail(CR_ERR_NOMEM, "the packed planes (" + std::to_string(eval_ws_bytes(N, n) - 256) +
+                                           " bytes) exceed the static scratch of cr_eval_noalloc (" +
+                                           std::to_string(kEvalScratchBytes) + " bytes)");
+    if (M == 0) return CR_OK;
+    double* B = nullptr;
+    st = eval_scratch(&B);
+    if (st != CR_OK) return st;
+    return eval_launch(X_dev, y_dev, xi_dev, N, n, Q_dev, M, fhat_dev, arg_dev, B, (hipStream_t)stream);
 }
 
 }  // extern "C"

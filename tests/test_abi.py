@@ -218,3 +218,20 @@ def test_papg_workspace_and_argument_checks():
     assert lib.cr_papg(fake, fake, 100, 5, ctypes.byref(cp), ctypes.byref(cpp), fake, fake, None, None, None, fake,
                        16, None, None) == 2
     assert b"workspace" in lib.cr_last_error(None)
+
+
+def test_eval_noalloc_rejects_on_host():
+    """Argument and size checks of the allocation-free estimator entry point
+    run before any HIP call: 174752 planes at n = 20 fit its 32 MiB scratch,
+    174753 do not."""
+    cr, lib = _lib()
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.cr_eval_noalloc(None, fake, fake, 10, 3, fake, 5, fake, None, None) == cr.ERR_ARG
+    assert lib.cr_eval_noalloc(fake, fake, fake, 0, 3, fake, 5, fake, None, None) == cr.ERR_ARG
+    assert lib.cr_eval_noalloc(fake, fake, fake, 10, 32, fake, 5, fake, None, None) == cr.ERR_UNSUPPORTED
+    assert lib.cr_eval_noalloc(fake, fake, fake, 174753, 20, fake, 5, fake, None, None) == cr.ERR_NOMEM
+    assert b"static scratch" in lib.cr_last_error(None)
+    assert lib.cr_eval_noalloc(fake, fake, fake, 1048577, 3, fake, 5, fake, None, None) == cr.ERR_NOMEM
+    # within the limit and M = 0: nothing to do, no HIP call
+    assert lib.cr_eval_noalloc(fake, fake, fake, 174752, 20, None, 0, None, None, None) == cr.OK
+    assert lib.cr_eval_noalloc(fake, fake, fake, 1048576, 3, None, 0, None, None, None) == cr.OK
