@@ -252,6 +252,13 @@ cr_status cr_batch_init(cr_batch** out, const cr_problem* probs, int32_t P, cons
                         void* workspace_dev, size_t ws_bytes, void* stream);
 cr_status cr_batch_run(cr_batch* batch, cr_info* infos, double* seconds);
 cr_status cr_batch_destroy(cr_batch* batch);
+/* Host-synchronous timing hook: average device milliseconds of one batched
+ * pair pass over every problem (one persistent pass kernel per operand class,
+ * back to back), run reps times on the batch's internal stream after one
+ * untimed pass, bracketed by HIP events.  Every problem is made active at its
+ * current operands first; theta is only read, and a later cr_batch_run starts
+ * afresh.  Errors: CR_ERR_ARG (NULL, reps < 1), CR_ERR_HIP. */
+cr_status cr_batch_time_pass(cr_batch* batch, int32_t reps, double* avg_ms);
 cr_status cr_solve_batched(const cr_problem* probs, int32_t P, const cr_params* params, void* workspace_dev,
                            size_t ws_bytes, cr_info* infos, void* stream);
 
@@ -466,6 +473,14 @@ cr_status cr_get_info(cr_ctx* ctx, cr_info* info);
  * Writes min(cap, count) entries to the host arrays and the total to *count.
  * Errors: CR_ERR_ARG (NULL ctx or count, cap < 0, NULL arrays with cap > 0). */
 cr_status cr_get_outer_history(cr_ctx* ctx, int32_t cap, int64_t* inner_iters, double* kkt, int32_t* count);
+
+/* Pure host arithmetic: the pair-pass launch layout cr_init would choose for
+ * (N, n, params): out[0] Nrow (rows of theta, N rounded up to 64), out[1] ld
+ * (its leading dimension), out[2] rows per workgroup chunk, out[3] chunks,
+ * out[4] column strips (16 TW columns each; TW = 2 in FP64, 4 otherwise),
+ * out[5] 1 if MAPG steps complete inside the next pass.  For tests of the
+ * pass's buffer-view offsets.  Errors as cr_workspace_bytes. */
+cr_status cr_pass_layout(int64_t N, int32_t n, const cr_params* params, int64_t* out);
 
 /* Host-synchronous: average device time in milliseconds of the gradient pair
  * pass that cr_run launches, run reps times back to back on the context's

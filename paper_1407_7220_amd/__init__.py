@@ -98,11 +98,13 @@ def _load():
         "cr_get_start": (i32, [vp, vp, vp]),
         "cr_get_info": (i32, [vp, pi]),
         "cr_time_pass": (i32, [vp, i32, i32, ctypes.POINTER(dbl)]),
+        "cr_pass_layout": (i32, [i64, i32, pp, ctypes.POINTER(i64)]),
         "cr_get_outer_history": (i32, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.POINTER(i32)]),
         "cr_batch_workspace_bytes": (i32, [ctypes.POINTER(_CProblem), i32, pp, ctypes.POINTER(ctypes.c_size_t)]),
         "cr_batch_init": (i32, [ctypes.POINTER(vp), ctypes.POINTER(_CProblem), i32, pp, vp, ctypes.c_size_t, vp]),
         "cr_batch_run": (i32, [vp, pi, ctypes.POINTER(dbl)]),
         "cr_batch_destroy": (i32, [vp]),
+        "cr_batch_time_pass": (i32, [vp, i32, ctypes.POINTER(dbl)]),
         "cr_solve_batched": (i32, [ctypes.POINTER(_CProblem), i32, pp, vp, ctypes.c_size_t, pi, vp]),
         "cr_diff_workspace_bytes": (i32, [i64, i32, pp, i32, ctypes.POINTER(ctypes.c_size_t)]),
         "cr_diff_init": (i32, [ctypes.POINTER(vp), i64, i32, pp, i32, vp, vp, vp, ctypes.c_size_t, vp]),
@@ -128,8 +130,8 @@ _lib = _load()
 
 EXPORTED = ("cr_params_default", "cr_status_string", "cr_last_error", "cr_workspace_bytes", "cr_init",
             "cr_destroy", "cr_pairwise_step", "cr_run", "cr_solve", "cr_get_theta", "cr_set_theta",
-            "cr_get_start", "cr_get_info", "cr_time_pass", "cr_get_outer_history", "cr_batch_workspace_bytes", "cr_batch_init",
-            "cr_batch_run", "cr_batch_destroy", "cr_solve_batched", "cr_diff_workspace_bytes", "cr_diff_init",
+            "cr_get_start", "cr_get_info", "cr_time_pass", "cr_get_outer_history", "cr_pass_layout", "cr_batch_workspace_bytes", "cr_batch_init",
+            "cr_batch_run", "cr_batch_destroy", "cr_batch_time_pass", "cr_solve_batched", "cr_diff_workspace_bytes", "cr_diff_init",
             "cr_diff_forward", "cr_diff_backward", "cr_diff_destroy", "cr_diff_time_adjoint_pass",
             "cr_eval_workspace_bytes", "cr_eval", "cr_eval_noalloc", "cr_papg_workspace_bytes", "cr_papg")
 
@@ -375,6 +377,12 @@ class Batch:
         _check(_lib.cr_batch_run(self._h, infos, ctypes.byref(secs)), None, allow=(OK, NOT_CONVERGED))
         return self.outputs, [Info.from_c(infos[p]) for p in range(self.P)], float(secs.value)
 
+    def time_pass(self, reps: int = 10) -> float:
+        """Average device milliseconds of one batched pair pass over every problem."""
+        out = ctypes.c_double(0.0)
+        _check(_lib.cr_batch_time_pass(self._h, int(reps), ctypes.byref(out)), None)
+        return float(out.value)
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.cr_batch_destroy(self._h)
@@ -513,6 +521,14 @@ def solve_unrolled(X, ybar, params: Params, y0=None, xi0=None, checkpoint_every:
     if xi0 is None:
         xi0 = torch.zeros(X.shape[0], X.shape[1], dtype=torch.float64, device=X.device)
     return _UNROLLED.apply(X, ybar, y0, xi0, params, int(checkpoint_every))
+
+
+def pass_layout(N: int, n: int, params: Optional[Params] = None) -> dict:
+    """The pair-pass launch layout cr_init would choose (host arithmetic only)."""
+    out = (ctypes.c_int64 * 6)()
+    cp = (params or Params()).to_c()
+    _check(_lib.cr_pass_layout(int(N), int(n), ctypes.byref(cp), out))
+    return dict(Nrow=out[0], ld=out[1], rows_per_chunk=out[2], chunks=out[3], strips=out[4], lazy=bool(out[5]))
 
 
 def eval_workspace_bytes(N: int, n: int) -> int:

@@ -424,6 +424,22 @@ cr_status cr_workspace_bytes(int64_t N, int32_t n, const cr_params* params, size
     return CR_OK;
 }
 
+cr_status cr_pass_layout(int64_t N, int32_t n, const cr_params* params, int64_t* out) {
+    std::string msg;
+    if (!out) return fail(nullptr, CR_ERR_ARG, "out is NULL");
+    cr_status s = check_dims(N, n, msg);
+    if (s != CR_OK) return fail(nullptr, s, msg);
+    if (!check_params(params, msg)) return fail(nullptr, CR_ERR_ARG, msg);
+    const Layout L = make_layout(N, n, params->precision, max_mapg_iters(*params), params->tile_rows);
+    out[0] = L.Nrow;
+    out[1] = L.ld;
+    out[2] = L.rpc;
+    out[3] = L.chunks;
+    out[4] = L.strips;
+    out[5] = L.lazy && !params->deterministic ? 1 : 0;
+    return CR_OK;
+}
+
 cr_status cr_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params, const void* X_dev,
                   const void* ybar_dev, void* workspace_dev, size_t ws_bytes, void* stream) {
     std::string msg;
@@ -1159,6 +1175,49 @@ cr_status cr_batch_run(cr_batch* b, cr_info* infos, double* seconds) {
     }
     if (result == CR_ERR_NONFINITE) return bfail(b, result, "non-finite iterate");
     return result;
+}
+
+cr_status cr_batch_time_pass(cr_batch* b, int32_t reps, double* avg_ms) {
+    if (!b || !avg_ms) return fail(nullptr, CR_ERR_ARG, "batch and avg_ms must be non-NULL");
+    if (reps < 1) return bfail(b, CR_ERR_ARG, "reps must be >= 1");
+    const BatchPlan& B = b->plan;
+    char* h = b->ws;
+    hipStream_t cs = b->cs;
+    BHIPCHK(b, hipEventRecord(b->ev[0], b->user_stream));
+    BHIPCHK(b, hipStreamWaitEvent(cs, b->ev[0], 0));
+    // every problem active, at its current operands (a later cr_batch_run starts afresh)
+    for (int q = 0; q < b->P; ++q) {
+        cr_ctx* c = b->sub[q];
+        Schedule sch;
+        sch.start(c);
+        BHIPCHK(b, cr::launch_begin_outer(sch.next(c), c->oa, c->st, cs));
+    }
+    auto step = [&]() {
+        hipError_t e = hipSuccess;
+        for (size_t ci = 0; ci < B.ks_classes.size() && e == hipSuccess; ++ci) {
+            const int grid = std::max(1, std::min(b->grid, B.class_cnt[ci]));
+            e = cr::launch_pass_batched(b->f64, B.ks_classes[ci], (const cr::PassArgs*)(h + B.off_pass),
+                                        (const int32_t*)(h + B.off_nstrips),
+                                        h + B.off_items + (size_t)B.class_off[ci] * sizeof(BatchItemH),
+                                        B.class_cnt[ci], grid, cs);
+        }
+        return e;
+    };
+    BHIPCHK(b, step());
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BHIPCHK(b, hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, cs);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = step();
+    if (e == hipSuccess) e = hipEventRecord(e1, cs);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (e != hipSuccess) return bfail(b, CR_ERR_HIP, std::string("batch time pass: ") + hipGetErrorString(e));
+    *avg_ms = (double)ms / reps;
+    return CR_OK;
 }
 
 cr_status cr_solve_batched(const cr_problem* probs, int32_t P, const cr_params* params, void* workspace_dev,

@@ -12,6 +12,11 @@ for scaling hardware byte counters.  Run it under rocprofv3, e.g.
                   forward and reverse run of 2 x 2 unrolled iterations;
 --kernel eval     estimator evaluations (k_eval) of the workload's tangent planes
                   (f0(x_l), grad f0(x_l)) at N query points q ~ U[-1,1]^n;
+--kernel batched  batched solves (k_pair_pass_batched, k_reduce_batched,
+                  k_update_batched) of the 64-problem FP32 workload
+                  (N_p ~ U{500..8000}, n_p in {5, 10, 20}) with the tuned
+                  tile heights, a fixed schedule of 1 x --reps MAPG steps per
+                  problem after one untimed run;
 --kernel papg     P-APG runs (cr_papg: k_papg_lin, k_papg_step2 and the batched
                   block solves) on the Sec. III study problem at N = 4096,
                   n = 5, K = 4, FP32 blocks of 4 x 40 MAPG steps, --reps
@@ -29,7 +34,7 @@ if ROOT not in sys.path:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--kernel", choices=("pass", "adjoint", "eval", "papg"), default="pass")
+    ap.add_argument("--kernel", choices=("pass", "adjoint", "eval", "papg", "batched"), default="pass")
     ap.add_argument("--workload", default=None)
     ap.add_argument("--precision", choices=("f32", "f64", "mixed_bf16"), default="f32")
     ap.add_argument("--reps", type=int, default=20)
@@ -50,6 +55,18 @@ def main():
         torch.cuda.synchronize()
         print("workload gaussian_quadratic N=4096 n=5 K=4: %d P-APG iterations, %.3f ms each"
               % (args.reps, (time.perf_counter() - t0) / args.reps * 1e3), flush=True)
+        return
+    if args.kernel == "batched":
+        probs = synth.batched_workload()
+        pairs = [(torch.from_numpy(q.X).cuda(), torch.from_numpy(q.ybar).cuda()) for q in probs]
+        tiles = [autotune.tile_rows_for(X, yb, cr.F32, form="batched", tune_if_missing=False) for X, yb in pairs]
+        b = cr.Batch(pairs, cr.Params(precision=cr.F32, inner_iters=args.reps, max_outer=1), tile_rows=tiles)
+        b.run()
+        _, infos, secs = b.run()
+        b.close()
+        pairs_per_it = sum(q.N * (q.N - 1) for q in probs)
+        print("workload batched (64 problems, %d pairs per MAPG iteration): %d MAPG iterations, %.3f ms each"
+              % (pairs_per_it, args.reps, secs / args.reps * 1e3), flush=True)
         return
     workload = args.workload or {"pass": "logsumexp_5000", "adjoint": "quadratic_10000",
                                  "eval": "maxaffine_20000"}[args.kernel]
