@@ -1,7 +1,10 @@
 """GPU parity of the HIP pair engine against the FP64 oracle (through the C ABI).
 
 Every case prints its name, sizes and seed before touching the GPU."""
+import hashlib
+import json
 import math
+import os
 import sys
 
 import numpy as np
@@ -439,6 +442,43 @@ def test_full_size_fixed_schedule_benchmark_launch(cr, prec):
     say("  relative error vs FP64 oracle: y %.3e  xi %.3e" % (ey, exi))
     assert ey < TOL_SOLVE[prec]
     assert exi < TOL_SOLVE[prec]
+
+
+_C3_FIXTURE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "maxaffine_20000_2x25.npz")
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "mixed"])
+def test_maxaffine_20000_fixed_schedule_against_oracle(cr, prec):
+    """The 20000-point, n = 20 workload (the mixed form's configuration) after 2
+    ALCC iterations of 25 MAPG steps, in the benchmark's launch configuration,
+    against the FP64 oracle's iterate stored by tests/golden/make_maxaffine_20000.py:
+    element by element (largest deviation relative to the largest entry) and in
+    norm.  FP64 and FP32 at the spec bars; the mixed BF16 form at its
+    measured level (the split drops only the lo*lo products, and W is split
+    hi/lo too): 1.9e-8 (y) and 1.1e-7 (Xi) in norm, 2.3e-7 at the largest entry."""
+    from paper_1407_7220_amd import autotune
+    d = np.load(_C3_FIXTURE)
+    meta = json.loads(str(d["meta"]))
+    p = synth.workload("maxaffine_20000")
+    assert hashlib.sha256(p.X.tobytes() + p.ybar.tobytes()).hexdigest() == meta["input_sha256"]
+    X, yb = dev(p.X), dev(p.ybar)
+    tile = autotune.tile_rows_for(X, yb, prec, tune_if_missing=False)
+    sched = meta["schedule"]
+    say("maxaffine_20000 %s tile_rows %d, %d x %d against the stored oracle iterate"
+        % (PREC_NAME[prec], tile, sched["max_outer"], sched["inner_iters"]))
+    y, xi, info = cr.solve(X, yb, cr.Params(precision=prec, tile_rows=tile, **sched))
+    assert info.inner_iters == sched["max_outer"] * sched["inner_iters"]
+    hy, hxi = host(y), host(xi)
+    del X, yb, y, xi
+    torch.cuda.empty_cache()
+    ey, exi = rel(hy, d["y"]), rel(hxi, d["xi"])
+    my = np.max(np.abs(hy - d["y"])) / np.max(np.abs(d["y"]))
+    mxi = np.max(np.abs(hxi - d["xi"])) / np.max(np.abs(d["xi"]))
+    say("  relative error vs FP64 oracle: y %.3e  xi %.3e (norm); y %.3e  xi %.3e (largest entry)"
+        % (ey, exi, my, mxi))
+    tol = {0: 1e-9, 1: 1e-5, 2: 1e-6}[prec]
+    assert ey < tol and exi < tol
+    assert my < tol and mxi < tol
 
 
 # --------------------------------------------------------------------------
