@@ -251,6 +251,19 @@ cr_status cr_batch_workspace_bytes(const cr_problem* probs, int32_t P, const cr_
 cr_status cr_batch_init(cr_batch** out, const cr_problem* probs, int32_t P, const cr_params* params,
                         void* workspace_dev, size_t ws_bytes, void* stream);
 cr_status cr_batch_run(cr_batch* batch, cr_info* infos, double* seconds);
+/* cr_batch_run in bounded pieces, for callers that interleave other work or
+ * report progress: cr_batch_start restarts every problem (asynchronous);
+ * cr_batch_advance launches at most max_replays graph replays (each one
+ * MAPG iteration block of every running problem plus the multiplier steps
+ * that became due; see cr_params inner_iters) and sets *running to 0 once
+ * every problem's schedule has finished (host-synchronous except for a fixed
+ * schedule, whose replay count is known and which only enqueues); and
+ * cr_batch_finish waits, writes the outputs and infos as cr_batch_run does
+ * and returns its status (seconds: since cr_batch_start).  CR_ERR_STATE when
+ * advance or finish is called without a start. */
+cr_status cr_batch_start(cr_batch* batch);
+cr_status cr_batch_advance(cr_batch* batch, int32_t max_replays, int32_t* running);
+cr_status cr_batch_finish(cr_batch* batch, cr_info* infos, double* seconds);
 cr_status cr_batch_destroy(cr_batch* batch);
 /* Host-synchronous timing hook: average device milliseconds of one batched
  * pair pass over every problem (one persistent pass kernel per operand class,

@@ -105,6 +105,9 @@ def _load():
         "cr_batch_run": (i32, [vp, pi, ctypes.POINTER(dbl)]),
         "cr_batch_destroy": (i32, [vp]),
         "cr_batch_time_pass": (i32, [vp, i32, ctypes.POINTER(dbl)]),
+        "cr_batch_start": (i32, [vp]),
+        "cr_batch_advance": (i32, [vp, i32, ctypes.POINTER(i32)]),
+        "cr_batch_finish": (i32, [vp, pi, ctypes.POINTER(dbl)]),
         "cr_solve_batched": (i32, [ctypes.POINTER(_CProblem), i32, pp, vp, ctypes.c_size_t, pi, vp]),
         "cr_diff_workspace_bytes": (i32, [i64, i32, pp, i32, ctypes.POINTER(ctypes.c_size_t)]),
         "cr_diff_init": (i32, [ctypes.POINTER(vp), i64, i32, pp, i32, vp, vp, vp, ctypes.c_size_t, vp]),
@@ -131,7 +134,7 @@ _lib = _load()
 EXPORTED = ("cr_params_default", "cr_status_string", "cr_last_error", "cr_workspace_bytes", "cr_init",
             "cr_destroy", "cr_pairwise_step", "cr_run", "cr_solve", "cr_get_theta", "cr_set_theta",
             "cr_get_start", "cr_get_info", "cr_time_pass", "cr_get_outer_history", "cr_pass_layout", "cr_batch_workspace_bytes", "cr_batch_init",
-            "cr_batch_run", "cr_batch_destroy", "cr_batch_time_pass", "cr_solve_batched", "cr_diff_workspace_bytes", "cr_diff_init",
+            "cr_batch_run", "cr_batch_destroy", "cr_batch_time_pass", "cr_batch_start", "cr_batch_advance", "cr_batch_finish", "cr_solve_batched", "cr_diff_workspace_bytes", "cr_diff_init",
             "cr_diff_forward", "cr_diff_backward", "cr_diff_destroy", "cr_diff_time_adjoint_pass",
             "cr_eval_workspace_bytes", "cr_eval", "cr_eval_noalloc", "cr_papg_workspace_bytes", "cr_papg")
 
@@ -375,6 +378,23 @@ class Batch:
         infos = (_CInfo * self.P)()
         secs = ctypes.c_double(0.0)
         _check(_lib.cr_batch_run(self._h, infos, ctypes.byref(secs)), None, allow=(OK, NOT_CONVERGED))
+        return self.outputs, [Info.from_c(infos[p]) for p in range(self.P)], float(secs.value)
+
+    def start(self):
+        """cr_batch_start: restart every problem (asynchronous)."""
+        _check(_lib.cr_batch_start(self._h), None)
+
+    def advance(self, max_replays: int) -> bool:
+        """cr_batch_advance: at most max_replays graph replays; True while a problem still runs."""
+        running = ctypes.c_int32(1)
+        _check(_lib.cr_batch_advance(self._h, int(max_replays), ctypes.byref(running)), None)
+        return bool(running.value)
+
+    def finish(self):
+        """cr_batch_finish: ([(y, xi), ...], [Info, ...], seconds since start)."""
+        infos = (_CInfo * self.P)()
+        secs = ctypes.c_double(0.0)
+        _check(_lib.cr_batch_finish(self._h, infos, ctypes.byref(secs)), None, allow=(OK, NOT_CONVERGED))
         return self.outputs, [Info.from_c(infos[p]) for p in range(self.P)], float(secs.value)
 
     def time_pass(self, reps: int = 10) -> float:

@@ -23,7 +23,6 @@
 namespace {
 
 constexpr int kGraphIters = 32;
-constexpr int kTailIters = 8;     // the batched form's short replay (fixed schedules)
 thread_local std::string g_last_error;
 
 struct Layout {
@@ -34,6 +33,7 @@ struct Layout {
     size_t off_y1p, off_y2, off_vy, off_y0, off_xi1p, off_xi2, off_vxi, off_xi0;
     size_t off_blockpart, off_supart, off_su, off_oa, off_st, off_beta, off_cvec;
     size_t off_y1p1, off_xi1p1, off_spart;   // second iterate buffers and stopping-test pieces (lazy passes)
+    size_t off_sched, off_hist;              // device ALCC schedule and its per-iteration history
     bool lazy = false;                       // MAPG runs use lazy passes (their LDS fits this chunk height)
     int prec = 0;
     int64_t nbeta = 0;
@@ -42,7 +42,11 @@ struct Layout {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-Layout make_layout(int64_t N, int n, int precision, int64_t max_iters, int tile_rows) {
+int64_t max_mapg_iters(const cr_params& p);
+
+Layout make_layout(int64_t N, int n, const cr_params& prm, int tile_rows) {
+    const int precision = prm.precision;
+    const int64_t max_iters = max_mapg_iters(prm);
     Layout L;
     L.N = N;
     L.n = n;
@@ -115,6 +119,8 @@ Layout make_layout(int64_t N, int n, int precision, int64_t max_iters, int tile_
     L.off_su = take((size_t)(3 * n + 2 + n * n + 8) * 8);
     L.off_oa = take(sizeof(cr::OuterArgs));
     L.off_st = take(sizeof(cr::DevState));
+    L.off_sched = take(sizeof(cr::AlccSched));
+    L.off_hist = take((size_t)std::max(prm.max_outer, 1) * 16);
     L.nbeta = max_iters + 2 * kGraphIters + 2;
     L.off_beta = take((size_t)L.nbeta * 8);
     L.total = o + 256;  // slack for re-aligning an unaligned base
@@ -143,6 +149,13 @@ bool check_params(const cr_params* p, std::string& msg) {
 
 // Longest MAPG run of any ALCC iteration: the length of the momentum table.
 int64_t max_mapg_iters(const cr_params& p) { return p.inner_iters > 0 ? p.inner_iters : p.max_inner; }
+
+// MAPG iterations per graph replay: a fixed schedule of at most 64 steps per
+// ALCC iteration replays exactly that many (no idle iterations), anything
+// else replays kGraphIters and lets the device stop the run inside a replay.
+int replay_iters(const cr_params& p) {
+    return p.inner_iters > 0 && p.inner_iters <= 2 * kGraphIters ? (int)p.inner_iters : kGraphIters;
+}
 
 cr_status check_dims(int64_t N, int32_t n, std::string& msg) {
     if (N < 2) { msg = "N must be >= 2"; return CR_ERR_ARG; }
@@ -174,6 +187,8 @@ struct cr_ctx {
     char* ws = nullptr;
     cr::DevState* st = nullptr;
     cr::OuterArgs* oa = nullptr;
+    cr::AlccSched* sched = nullptr;      // device ALCC schedule (constants written at init)
+    int replay = 32;                     // MAPG iterations per graph replay
     double sigma2_A1 = 0, sigma2_A2 = 0, Bbar = 0, By = 0, Bxi = 0, ybar_inf = 0;
     std::string err;
     cr::DevState last{};
@@ -288,13 +303,43 @@ static hipError_t enqueue_mapg_iteration(cr_ctx* c, int q, hipStream_t s) {
     return cr::launch_update(c->prec, ua, s);
 }
 
+// The multiplier step of the device schedule (Fig. 3 step 4 and the KKT
+// residuals), enqueued after every replay and gated on st->step_due: the
+// finish of the MAPG run, the point (y_k, xi_k), the multiplier pass, its KKT
+// reduction, then k_alcc_step (record, tests, next ALCC iteration).
+static hipError_t enqueue_device_step(cr_ctx* c, hipStream_t s) {
+    const Layout& L = c->L;
+    const int32_t* gate = &c->st->step_due;
+    hipError_t e = hipSuccess;
+    int nblk = cr::reduce_blocks(c->N, c->n);
+    if (c->lazy) {
+        if ((e = cr::launch_mapg_finish(lazy_pass_args(c, 0, 0).lz, L.N, s, gate)) != hipSuccess) return e;
+        nblk = 0;
+    }
+    if ((e = cr::launch_mapg_end(c->D(L.off_blockpart), nblk, -1, c->st, s, gate)) != hipSuccess) return e;
+    cr::PointArgs pt = point_args(c, c->D(L.off_y1p), c->D(L.off_xi1p), 1);
+    pt.gate = gate;
+    if ((e = cr::launch_set_point(c->prec, pt, s)) != hipSuccess) return e;
+    cr::PassArgs pa = pass_args(c, 1, 0.0, gate);
+    pa.theta_scale_p = &c->oa->theta_scale;
+    if ((e = cr::launch_pair_pass(c->prec, c->n, pa, pass_grid(L), s)) != hipSuccess) return e;
+    cr::ReduceArgs ra = reduce_args(c, 2, c->D(L.off_y1p), c->D(L.off_xi1p), nullptr, nullptr, 0.0);
+    ra.gate = gate;
+    ra.mu_dev = 1;
+    if ((e = cr::launch_reduce(c->f64, ra, s)) != hipSuccess) return e;
+    return cr::launch_alcc_step(c->sched, c->st, c->oa, s);
+}
+
+// One graph replay: c->replay MAPG iterations, the end-of-replay gate of the
+// device schedule, and the gated multiplier step.
 static cr_status build_graph(cr_ctx* c) {
     if (c->graph) return CR_OK;
     hipGraph_t g = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->cs, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int q = 0; q < kGraphIters && e == hipSuccess; ++q) e = enqueue_mapg_iteration(c, q, c->cs);
-    if (e == hipSuccess) e = cr::launch_replay_end(c->st, kGraphIters, c->cs);
+    for (int q = 0; q < c->replay && e == hipSuccess; ++q) e = enqueue_mapg_iteration(c, q, c->cs);
+    if (e == hipSuccess) e = cr::launch_alcc_gate(c->sched, c->st, c->oa, c->replay, c->cs);
+    if (e == hipSuccess) e = enqueue_device_step(c, c->cs);
     hipError_t e2 = hipStreamEndCapture(c->cs, &g);
     if (e != hipSuccess) return fail(c, CR_ERR_HIP, std::string("capture: ") + hipGetErrorString(e));
     if (e2 != hipSuccess) return fail(c, CR_ERR_HIP, std::string("end capture: ") + hipGetErrorString(e2));
@@ -420,7 +465,7 @@ cr_status cr_workspace_bytes(int64_t N, int32_t n, const cr_params* params, size
     cr_status s = check_dims(N, n, msg);
     if (s != CR_OK) return fail(nullptr, s, msg);
     if (!check_params(params, msg)) return fail(nullptr, CR_ERR_ARG, msg);
-    *bytes = make_layout(N, n, params->precision, max_mapg_iters(*params), params->tile_rows).total;
+    *bytes = make_layout(N, n, *params, params->tile_rows).total;
     return CR_OK;
 }
 
@@ -430,7 +475,7 @@ cr_status cr_pass_layout(int64_t N, int32_t n, const cr_params* params, int64_t*
     cr_status s = check_dims(N, n, msg);
     if (s != CR_OK) return fail(nullptr, s, msg);
     if (!check_params(params, msg)) return fail(nullptr, CR_ERR_ARG, msg);
-    const Layout L = make_layout(N, n, params->precision, max_mapg_iters(*params), params->tile_rows);
+    const Layout L = make_layout(N, n, *params, params->tile_rows);
     out[0] = L.Nrow;
     out[1] = L.ld;
     out[2] = L.rpc;
@@ -449,7 +494,7 @@ cr_status cr_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params, c
     if (s != CR_OK) return fail(nullptr, s, msg);
     if (!check_params(params, msg)) return fail(nullptr, CR_ERR_ARG, msg);
     if (!X_dev || !ybar_dev || !workspace_dev) return fail(nullptr, CR_ERR_ARG, "X, ybar and workspace must be non-NULL");
-    Layout L = make_layout(N, n, params->precision, max_mapg_iters(*params), params->tile_rows);
+    Layout L = make_layout(N, n, *params, params->tile_rows);
     if (ws_bytes < L.total) return fail(nullptr, CR_ERR_NOMEM, "workspace smaller than cr_workspace_bytes()");
 
     cr_ctx* c = new (std::nothrow) cr_ctx();
@@ -471,6 +516,8 @@ cr_status cr_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params, c
     c->ws = (char*)align256((size_t)workspace_dev);
     c->st = reinterpret_cast<cr::DevState*>(c->P(L.off_st));
     c->oa = reinterpret_cast<cr::OuterArgs*>(c->P(L.off_oa));
+    c->sched = reinterpret_cast<cr::AlccSched*>(c->P(L.off_sched));
+    c->replay = replay_iters(*params);
     auto bad = [&](cr_status st) { cr_destroy(c); return st; };
     hipError_t e = hipStreamCreateWithFlags(&c->cs, hipStreamNonBlocking);
     if (e != hipSuccess) { fail(nullptr, CR_ERR_HIP, std::string("stream: ") + hipGetErrorString(e)); return bad(CR_ERR_HIP); }
@@ -534,6 +581,23 @@ cr_status cr_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params, c
         fail(nullptr, CR_ERR_NONFINITE, "non-finite problem constants");
         return bad(CR_ERR_NONFINITE);
     }
+    {
+        // constants of the device ALCC schedule (the state is set by k_alcc_start)
+        cr::AlccSched sc{};
+        sc.mu1 = params->mu1 > 0 ? params->mu1 : 1.0 / (2.0 * (double)N);
+        sc.c = params->c; sc.kappa = params->kappa; sc.tau1 = params->tau1;
+        sc.ay1 = params->alpha_y1; sc.axi1 = params->alpha_xi1; sc.gamma = params->gamma;
+        sc.step_scale = params->step_scale; sc.kkt_tol = params->kkt_tol;
+        sc.Ly_ovr = params->Ly_override; sc.Lxi_ovr = params->Lxi_override;
+        sc.By_ovr = params->By_override; sc.Bxi_ovr = params->Bxi_override;
+        sc.sigma2_A1 = 2.0 * (double)N;
+        sc.inner_iters = params->inner_iters; sc.max_inner = params->max_inner; sc.max_outer = params->max_outer;
+        sc.hist_inner = reinterpret_cast<int64_t*>(c->P(L.off_hist));
+        sc.hist_kkt = reinterpret_cast<double*>(c->P(L.off_hist) + (size_t)std::max(params->max_outer, 1) * 8);
+        sc.phase = 2;
+        e = hipMemcpy(c->sched, &sc, sizeof(sc), hipMemcpyHostToDevice);
+        if (e != hipSuccess) { fail(nullptr, CR_ERR_HIP, std::string("schedule: ") + hipGetErrorString(e)); return bad(CR_ERR_HIP); }
+    }
     *out = c;
     return CR_OK;
 }
@@ -575,7 +639,7 @@ cr_status cr_pairwise_step(cr_ctx* c, int32_t mode, const void* y_dev, const voi
 
 static void fill_info(cr_ctx* c, const cr::DevState& h, cr_info* info) {
     info->objective = h.obj;
-    const double scale = 1.0 + c->ybar_inf;
+    const double scale = 1.0 + h.ybar_inf;
     info->stat_y = h.stat_y;
     info->stat_xi = h.stat_xi;
     info->infeas = h.infeas;
@@ -585,9 +649,9 @@ static void fill_info(cr_ctx* c, const cr::DevState& h, cr_info* info) {
     info->infeas_norm = std::sqrt(h.infeas_sq) / std::sqrt(np);
     info->gap_norm = h.gap / np;
     info->sigma2_A1 = c->sigma2_A1;
-    info->sigma2_A2 = c->sigma2_A2;
-    info->Bbar_y = c->By;
-    info->Bbar_xi = c->Bxi;
+    info->sigma2_A2 = h.sigma2_A2;
+    info->Bbar_y = c->p.By_override > 0 ? c->p.By_override : h.Bbar;
+    info->Bbar_xi = c->p.Bxi_override > 0 ? c->p.Bxi_override : h.Bbar / std::sqrt(c->p.gamma);
 }
 
 cr_status cr_get_info(cr_ctx* c, cr_info* info) {
@@ -621,6 +685,36 @@ cr_status cr_get_start(cr_ctx* c, void* y_dev, void* xi_dev) {
     return CR_OK;
 }
 
+// Host side of a device-scheduled run: enqueue graph replays until the
+// schedule is done.  A fixed schedule needs exactly max_outer x ceil(l / replay)
+// replays, all enqueued at once; otherwise the phase flag is polled one replay
+// behind (the replay in between finds nothing to do).  No read-back between
+// ALCC iterations either way.
+static cr_status replay_until_done(cr_ctx* c) {
+    const cr_params& p = c->p;
+    hipStream_t cs = c->cs;
+    if (p.inner_iters > 0) {
+        const int64_t per = (p.inner_iters + c->replay - 1) / c->replay;
+        for (int64_t r = 0; r < per * p.max_outer; ++r) HIPCHK(c, hipGraphLaunch(c->graph, cs));
+        return CR_OK;
+    }
+    // at most max_inner + one replay of MAPG iterations per ALCC iteration
+    const int64_t cap = (int64_t)p.max_outer * ((p.max_inner + c->replay - 1) / c->replay + 1) + 2;
+    int slot = 0, pending = -1;
+    for (int64_t r = 0; r < cap; ++r) {
+        HIPCHK(c, hipGraphLaunch(c->graph, cs));
+        HIPCHK(c, hipMemcpyAsync(c->pinned_flag + slot, &c->sched->phase, 4, hipMemcpyDeviceToHost, cs));
+        HIPCHK(c, hipEventRecord(c->ev[slot], cs));
+        if (pending >= 0) {
+            HIPCHK(c, hipEventSynchronize(c->ev[pending]));
+            if (c->pinned_flag[pending] == 2) return CR_OK;
+        }
+        pending = slot;
+        slot ^= 1;
+    }
+    return CR_OK;
+}
+
 cr_status cr_run(cr_ctx* c, void* y_dev, void* xi_dev, cr_info* info) {
     if (!c) return fail(nullptr, CR_ERR_ARG, "ctx is NULL");
     if (!y_dev || !xi_dev) return fail(c, CR_ERR_ARG, "y and xi must be non-NULL");
@@ -633,77 +727,50 @@ cr_status cr_run(cr_ctx* c, void* y_dev, void* xi_dev, cr_info* info) {
     if (bs != CR_OK) return bs;
 
     const auto t0 = std::chrono::steady_clock::now();
-    // theta_1 = 0 and (y_0, xi_0) = the affine fit
+    // theta_1 = 0 and (y_0, xi_0) = the affine fit; ALCC iteration 1 begins on the device
     HIPCHK(c, cr::launch_zero(c->P(L.off_theta), (size_t)L.Nrow * L.ld * L.esz, cs));
     cr::PointArgs start = point_args(c, c->D(L.off_y0), c->D(L.off_xi0), 1);
     HIPCHK(c, cr::launch_set_point(c->prec, start, cs));
+    HIPCHK(c, cr::launch_alcc_start(c->sched, c->oa, c->st, cs));
+    cr_status rs = replay_until_done(c);
+    if (rs != CR_OK) return rs;
 
     const int64_t N = c->N;
-    const bool fixed = p.inner_iters > 0;
-    Schedule sch;
-    sch.start(c);
-    cr_status result = CR_OK;
-    cr::DevState h{};
-    c->hist_inner.clear();
-    c->hist_kkt.clear();
-    for (int k = 1; k <= p.max_outer; ++k) {
-        const cr::OuterArgs oa = sch.next(c);
-        const double mu = sch.mu, mu_next = sch.mu_next(c);
-        const int64_t lmax = oa.lmax;
-        HIPCHK(c, cr::launch_begin_outer(oa, c->oa, c->st, cs));
-
-        // MAPG: replay the captured iterations until the device clears `active`.
-        int64_t launched = 0;
-        int slot = 0, pending = -1;
-        while (launched < lmax) {
-            HIPCHK(c, hipGraphLaunch(c->graph, cs));
-            launched += kGraphIters;
-            if (fixed) continue;
-            HIPCHK(c, hipMemcpyAsync(c->pinned_flag + slot, &c->st->active, 4, hipMemcpyDeviceToHost, cs));
-            HIPCHK(c, hipEventRecord(c->ev[slot], cs));
-            if (pending >= 0) {
-                HIPCHK(c, hipEventSynchronize(c->ev[pending]));
-                if (c->pinned_flag[pending] == 0) break;
-            }
-            pending = slot;
-            slot ^= 1;
-        }
-        HIPCHK(c, enqueue_multiplier_step(c, mu, mu_next, launched, cr::reduce_blocks(N, c->n), cs));
-        HIPCHK(c, hipStreamSynchronize(cs));
-        h = *c->pinned_state;
-        sch.total_inner += h.it;
-        c->have_kkt = true;
-        if (h.iterate_nonfinite) { result = CR_ERR_NONFINITE; break; }
-        cr_info tmp{};
-        fill_info(c, h, &tmp);
-        c->hist_inner.push_back(h.it);
-        c->hist_kkt.push_back(tmp.kkt);
-        if (c->verbose)
-            std::fprintf(stderr, "[cr] outer %d mu %.3e inner %lld (alpha stop %d) kkt %.3e stat_y %.2e stat_xi %.2e "
-                         "infeas %.2e compl %.2e obj %.6e t %.3fs\n",
-                         k, mu, (long long)h.it, h.stopped_by_alpha, tmp.kkt, h.stat_y, h.stat_xi, h.infeas, h.compl_,
-                         h.obj, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
-        if (!fixed && tmp.kkt <= p.kkt_tol) { sch.converged = true; break; }
-        sch.advance(c);
-    }
-    const int outer = sch.k;
-    const int64_t total_inner = sch.total_inner;
-    const bool converged = sch.converged;
     HIPCHK(c, hipMemcpyAsync(y_dev, c->D(L.off_y1p), (size_t)N * 8, hipMemcpyDeviceToDevice, cs));
     HIPCHK(c, hipMemcpyAsync(xi_dev, c->D(L.off_xi1p), (size_t)N * c->n * 8, hipMemcpyDeviceToDevice, cs));
+    cr::AlccSched sc{};
+    HIPCHK(c, hipMemcpyAsync(c->pinned_state, c->st, sizeof(cr::DevState), hipMemcpyDeviceToHost, cs));
     HIPCHK(c, hipStreamSynchronize(cs));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (result == CR_OK && !fixed && !converged) result = CR_NOT_CONVERGED;
+    HIPCHK(c, hipMemcpy(&sc, c->sched, sizeof(sc), hipMemcpyDeviceToHost));
+    const int outer = std::min(sc.k, p.max_outer);
+    c->hist_inner.assign((size_t)outer, 0);
+    c->hist_kkt.assign((size_t)outer, 0.0);
+    if (outer > 0) {
+        HIPCHK(c, hipMemcpy(c->hist_inner.data(), sc.hist_inner, (size_t)outer * 8, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(c->hist_kkt.data(), sc.hist_kkt, (size_t)outer * 8, hipMemcpyDeviceToHost));
+    }
+    const cr::DevState h = *c->pinned_state;
+    c->have_kkt = true;
+    if (c->verbose)
+        for (int k = 0; k < outer; ++k)
+            std::fprintf(stderr, "[cr] outer %d inner %lld kkt %.3e\n", k + 1, (long long)c->hist_inner[k],
+                         c->hist_kkt[k]);
+    cr_status result = CR_OK;
+    if (sc.nonfinite) result = CR_ERR_NONFINITE;
+    else if (sc.phase != 2) result = CR_ERR_STATE;
+    else if (p.inner_iters == 0 && !sc.converged) result = CR_NOT_CONVERGED;
     if (info) {
         std::memset(info, 0, sizeof(*info));
         fill_info(c, h, info);
         info->outer_iters = outer;
-        info->inner_iters = total_inner;
+        info->inner_iters = sc.total_inner;
         info->seconds = secs;
-        info->pair_updates = (double)N * (double)(N - 1) * (double)total_inner;
+        info->pair_updates = (double)N * (double)(N - 1) * (double)sc.total_inner;
         info->status = result;
     }
     if (result == CR_ERR_NONFINITE) return fail(c, result, "non-finite iterate");
+    if (result == CR_ERR_STATE) return fail(c, result, "the schedule did not finish within its replay cap");
     return result;
 }
 
@@ -803,6 +870,9 @@ struct BatchPlan {
     std::vector<BatchItemH> items;          // grouped by class
     std::vector<int> class_off, class_cnt;
     size_t off_pass, off_red, off_upd, off_nstrips, off_blocks, off_nblk, off_sts, off_any, off_items;
+    // device-schedule tables: schedules, outer arguments, update block records,
+    // and the multiplier step's pass / reduce / set-point arguments
+    size_t off_scheds, off_oas, off_bparts, off_pass1, off_red2, off_pt;
 };
 
 cr_status check_batch(const cr_problem* probs, int32_t P, const cr_params* params, std::string& msg) {
@@ -824,7 +894,7 @@ BatchPlan plan_batch(const cr_problem* probs, int32_t P, const cr_params* params
     B.G = nmax + 1 <= 16 ? 16 : 32;
     for (int p = 0; p < P; ++p) {
         const int tr = probs[p].tile_rows > 0 ? probs[p].tile_rows : params->tile_rows;
-        B.L.push_back(make_layout(probs[p].N, probs[p].n, params->precision, max_mapg_iters(*params), tr));
+        B.L.push_back(make_layout(probs[p].N, probs[p].n, *params, tr));
         const int nb = (int)((probs[p].N * B.G + cr::kBlock - 1) / cr::kBlock);
         B.nblk.push_back(nb);
         B.nblocks += nb;
@@ -852,6 +922,12 @@ BatchPlan plan_batch(const cr_problem* probs, int32_t P, const cr_params* params
     B.off_sts = take((size_t)P * sizeof(void*));
     B.off_any = take(64);
     B.off_items = take(B.items.size() * sizeof(BatchItemH));
+    B.off_scheds = take((size_t)P * sizeof(void*));
+    B.off_oas = take((size_t)P * sizeof(void*));
+    B.off_bparts = take((size_t)P * sizeof(void*));
+    B.off_pass1 = take((size_t)P * sizeof(cr::PassArgs));
+    B.off_red2 = take((size_t)P * sizeof(cr::ReduceArgs));
+    B.off_pt = take((size_t)P * sizeof(cr::PointArgs));
     B.hdr = o;
     for (int p = 0; p < P; ++p) B.off.push_back(take(B.L[p].total));
     B.total = o + 256;
@@ -867,8 +943,11 @@ struct cr_batch {
     std::vector<cr_problem> probs;
     std::vector<cr_ctx*> sub;
     hipStream_t user_stream = nullptr, cs = nullptr;
-    hipGraphExec_t graph = nullptr;        // kGraphIters MAPG iterations
-    hipGraphExec_t tail = nullptr;         // kTailIters, to finish a fixed schedule
+    hipGraphExec_t graph = nullptr;        // `replay` MAPG iterations of every problem + the multiplier steps
+    int replay = 32;
+    bool started = false;                  // between cr_batch_start and cr_batch_finish
+    int64_t launched = 0, total = 0;       // replays launched, and the cap (the exact count of a fixed schedule)
+    std::chrono::steady_clock::time_point t0;
     hipEvent_t ev[2] = {nullptr, nullptr};
     int32_t* pinned_flag = nullptr;
     char* ws = nullptr;
@@ -890,12 +969,14 @@ static cr_status bfail(cr_batch* b, cr_status s, const std::string& msg) {
             return bfail(b, CR_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));      \
     } while (0)
 
-// One graph of `iters` MAPG iterations of every problem (positions q = 0 ..
-// iters - 1 of the replay), closed by the replay-end kernel that advances each
-// problem's iteration base by `iters`.
-static cr_status capture_batch_graph(cr_batch* b, int iters, hipGraphExec_t* out) {
+// One graph replay: b->replay MAPG iterations of every problem (positions q =
+// 0 .. replay - 1), the end-of-replay gate of every problem's device schedule,
+// and the gated multiplier steps (MAPG end, set point, multiplier pass per
+// operand class, KKT reduction, schedule step) of the problems whose run is over.
+static cr_status capture_batch_graph(cr_batch* b, hipGraphExec_t* out) {
     const BatchPlan& B = b->plan;
     char* h = b->ws;
+    const int iters = b->replay;
     hipGraph_t g = nullptr;
     BHIPCHK(b, hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
@@ -914,9 +995,28 @@ static cr_status capture_batch_graph(cr_batch* b, int iters, hipGraphExec_t* out
             e = cr::launch_update_batched(b->f64, B.G, (const cr::UpdateArgs*)(h + B.off_upd), h + B.off_blocks,
                                           (const int32_t*)(h + B.off_nblk), B.nblocks, q, b->cs);
     }
+    auto scheds = (cr::AlccSched* const*)(h + B.off_scheds);
+    auto sts = (cr::DevState* const*)(h + B.off_sts);
+    auto oas = (cr::OuterArgs* const*)(h + B.off_oas);
     if (e == hipSuccess)
-        e = cr::launch_replay_end_batched((cr::DevState* const*)(h + B.off_sts), b->P, iters,
-                                          (int32_t*)(h + B.off_any), b->cs);
+        e = cr::launch_alcc_gate_batched(scheds, sts, oas, b->P, iters, (int32_t*)(h + B.off_any), b->cs);
+    if (e == hipSuccess)
+        e = cr::launch_mapg_end_batched((const double* const*)(h + B.off_bparts), (const int32_t*)(h + B.off_nblk),
+                                        sts, b->P, b->cs);
+    if (e == hipSuccess)
+        e = cr::launch_set_point_batched(b->f64, B.G, (const cr::PointArgs*)(h + B.off_pt), h + B.off_blocks,
+                                         (const int32_t*)(h + B.off_nblk), B.nblocks, b->cs);
+    for (size_t ci = 0; ci < B.ks_classes.size() && e == hipSuccess; ++ci) {
+        const int grid = std::max(1, std::min(b->grid, B.class_cnt[ci]));
+        e = cr::launch_theta_pass_batched(b->f64, B.ks_classes[ci], (const cr::PassArgs*)(h + B.off_pass1),
+                                          (const int32_t*)(h + B.off_nstrips),
+                                          h + B.off_items + (size_t)B.class_off[ci] * sizeof(BatchItemH),
+                                          B.class_cnt[ci], grid, b->cs);
+    }
+    if (e == hipSuccess)
+        e = cr::launch_reduce_batched(b->f64, B.G, (const cr::ReduceArgs*)(h + B.off_red2), h + B.off_blocks,
+                                      (const int32_t*)(h + B.off_nblk), B.nblocks, 0, b->cs);
+    if (e == hipSuccess) e = cr::launch_alcc_step_batched(scheds, sts, oas, b->P, b->cs);
     hipError_t e2 = hipStreamEndCapture(b->cs, &g);
     if (e != hipSuccess) return bfail(b, CR_ERR_HIP, std::string("batch capture: ") + hipGetErrorString(e));
     if (e2 != hipSuccess) return bfail(b, CR_ERR_HIP, std::string("batch end capture: ") + hipGetErrorString(e2));
@@ -927,12 +1027,7 @@ static cr_status capture_batch_graph(cr_batch* b, int iters, hipGraphExec_t* out
 }
 
 static cr_status build_batch_graph(cr_batch* b) {
-    if (!b->graph) {
-        cr_status s = capture_batch_graph(b, kGraphIters, &b->graph);
-        if (s != CR_OK) return s;
-    }
-    if (!b->tail && b->p.inner_iters > 0 && b->p.inner_iters % kGraphIters != 0)
-        return capture_batch_graph(b, kTailIters, &b->tail);
+    if (!b->graph) return capture_batch_graph(b, &b->graph);
     return CR_OK;
 }
 
@@ -951,7 +1046,6 @@ cr_status cr_batch_destroy(cr_batch* b) {
     if (!b) return CR_OK;
     if (b->cs) hipStreamSynchronize(b->cs);
     if (b->graph) hipGraphExecDestroy(b->graph);
-    if (b->tail) hipGraphExecDestroy(b->tail);
     for (cr_ctx* c : b->sub) cr_destroy(c);
     for (int q = 0; q < 2; ++q)
         if (b->ev[q]) hipEventDestroy(b->ev[q]);
@@ -986,6 +1080,7 @@ static cr_status batch_init_impl(cr_batch** out, const cr_problem* probs, int32_
     b->user_stream = (hipStream_t)stream;
     b->ws = (char*)align256((size_t)workspace_dev);
     b->f64 = params->precision == CR_F64;
+    b->replay = replay_iters(*params);
     auto bad = [&](cr_status st) { std::string m = g_last_error; cr_batch_destroy(b); g_last_error = m; return st; };
     hipError_t e = hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking);
     for (int q = 0; q < 2 && e == hipSuccess; ++q) e = hipEventCreateWithFlags(&b->ev[q], hipEventDisableTiming);
@@ -1014,7 +1109,10 @@ static cr_status batch_init_impl(cr_batch** out, const cr_problem* probs, int32_
     std::vector<cr::UpdateArgs> ua(P);
     std::vector<int32_t> nstrips(P);
     std::vector<int32_t> blocks;
-    std::vector<void*> sts(P);
+    std::vector<void*> sts(P), scheds(P), oas(P), bparts(P);
+    std::vector<cr::PassArgs> pa1(P);
+    std::vector<cr::ReduceArgs> ra2(P);
+    std::vector<cr::PointArgs> pt(P);
     for (int p = 0; p < P; ++p) {
         cr_ctx* c = b->sub[p];
         const Layout& L = c->L;
@@ -1023,6 +1121,17 @@ static cr_status batch_init_impl(cr_batch** out, const cr_problem* probs, int32_
         ua[p] = update_args(c);
         nstrips[p] = L.strips;
         sts[p] = c->st;
+        scheds[p] = c->sched;
+        oas[p] = c->oa;
+        bparts[p] = c->D(L.off_blockpart);
+        // the multiplier step of the device schedule, gated on the problem's step_due
+        pa1[p] = pass_args(c, 1, 0.0, &c->st->step_due);
+        pa1[p].theta_scale_p = &c->oa->theta_scale;
+        ra2[p] = reduce_args(c, 2, c->D(L.off_y1p), c->D(L.off_xi1p), nullptr, nullptr, 0.0);
+        ra2[p].gate = &c->st->step_due;
+        ra2[p].mu_dev = 1;
+        pt[p] = point_args(c, c->D(L.off_y1p), c->D(L.off_xi1p), 1);
+        pt[p].gate = &c->st->step_due;
         for (int q = 0; q < B.nblk[p]; ++q) { blocks.push_back(p); blocks.push_back(q); }
     }
     char* h = b->ws;
@@ -1035,6 +1144,12 @@ static cr_status batch_init_impl(cr_batch** out, const cr_problem* probs, int32_
     if (e == hipSuccess) e = hipMemcpy(h + B.off_sts, sts.data(), P * sizeof(void*), hipMemcpyHostToDevice);
     if (e == hipSuccess && !B.items.empty())
         e = hipMemcpy(h + B.off_items, B.items.data(), B.items.size() * sizeof(BatchItemH), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h + B.off_scheds, scheds.data(), P * sizeof(void*), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h + B.off_oas, oas.data(), P * sizeof(void*), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h + B.off_bparts, bparts.data(), P * sizeof(void*), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h + B.off_pass1, pa1.data(), P * sizeof(cr::PassArgs), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h + B.off_red2, ra2.data(), P * sizeof(cr::ReduceArgs), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h + B.off_pt, pt.data(), P * sizeof(cr::PointArgs), hipMemcpyHostToDevice);
     if (e != hipSuccess) { fail(nullptr, CR_ERR_HIP, std::string("batch tables: ") + hipGetErrorString(e)); return bad(CR_ERR_HIP); }
     *out = b;
     return CR_OK;
@@ -1047,134 +1162,142 @@ cr_status cr_batch_init(cr_batch** out, const cr_problem* probs, int32_t P, cons
     return batch_init_impl(out, probs, P, params, workspace_dev, ws_bytes, stream, nullptr);
 }
 
-cr_status cr_batch_run(cr_batch* b, cr_info* infos, double* seconds) {
+}  // extern "C"
+
+// Every problem's last ALCC iterate into its caller-owned y and xi (enqueued).
+static hipError_t batch_copy_outputs(cr_batch* b) {
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < b->P && e == hipSuccess; ++q) {
+        cr_ctx* c = b->sub[q];
+        const Layout& L = c->L;
+        e = hipMemcpyAsync(b->probs[q].y_dev, c->D(L.off_y1p), (size_t)c->N * 8, hipMemcpyDeviceToDevice, b->cs);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->probs[q].xi_dev, c->D(L.off_xi1p), (size_t)c->N * c->n * 8, hipMemcpyDeviceToDevice,
+                               b->cs);
+    }
+    return e;
+}
+
+extern "C" {
+
+cr_status cr_batch_start(cr_batch* b) {
     if (!b) return fail(nullptr, CR_ERR_ARG, "batch is NULL");
-    const int P = b->P;
-    const cr_params& p = b->p;
-    const bool fixed = p.inner_iters > 0;
     hipStream_t cs = b->cs;
     BHIPCHK(b, hipEventRecord(b->ev[0], b->user_stream));
     BHIPCHK(b, hipStreamWaitEvent(cs, b->ev[0], 0));
     cr_status bs = build_batch_graph(b);
     if (bs != CR_OK) return bs;
-    const auto t0 = std::chrono::steady_clock::now();
-    std::vector<Schedule> sch(P);
-    for (int q = 0; q < P; ++q) {
+    b->t0 = std::chrono::steady_clock::now();
+    for (int q = 0; q < b->P; ++q) {
         cr_ctx* c = b->sub[q];
         const Layout& L = c->L;
         BHIPCHK(b, cr::launch_zero(c->P(L.off_theta), (size_t)L.Nrow * L.ld * L.esz, cs));
         cr::PointArgs start = point_args(c, c->D(L.off_y0), c->D(L.off_xi0), 1);
         BHIPCHK(b, cr::launch_set_point(c->prec, start, cs));
-        sch[q].start(c);
     }
-    cr_status result = CR_OK;
-    std::vector<double> mus(P), mun(P);
-    for (int k = 1; k <= p.max_outer; ++k) {
-        int64_t lmax_all = 0;
-        for (int q = 0; q < P; ++q) {
-            cr_ctx* c = b->sub[q];
-            cr::OuterArgs oa{};
-            if (!sch[q].done) {
-                oa = sch[q].next(c);
-                mus[q] = sch[q].mu;
-                mun[q] = sch[q].mu_next(c);
-                lmax_all = std::max(lmax_all, oa.lmax);
-            } else {
-                oa.skip = 1;
-                oa.lmax = 0;
-            }
-            BHIPCHK(b, cr::launch_begin_outer(oa, c->oa, c->st, cs));
-        }
-        if (lmax_all == 0) break;
-        int64_t launched = 0;
-        int slot = 0, pending = -1;
-        int32_t* any = (int32_t*)(b->ws + b->plan.off_any);
-        while (launched < lmax_all) {
-            // a fixed schedule ends with short replays: at most kTailIters - 1
-            // iterations past l_max are launched (and skip their work)
-            if (fixed && b->tail && lmax_all - launched < kGraphIters) {
-                BHIPCHK(b, hipGraphLaunch(b->tail, cs));
-                launched += kTailIters;
-                continue;
-            }
-            BHIPCHK(b, hipGraphLaunch(b->graph, cs));
-            launched += kGraphIters;
-            if (fixed) continue;
-            BHIPCHK(b, hipMemcpyAsync(b->pinned_flag + slot, any, 4, hipMemcpyDeviceToHost, cs));
-            BHIPCHK(b, hipEventRecord(b->ev[slot], cs));
-            if (pending >= 0) {
-                BHIPCHK(b, hipEventSynchronize(b->ev[pending]));
-                if (b->pinned_flag[pending] == 0) break;
-            }
-            pending = slot;
-            slot ^= 1;
-        }
-        for (int q = 0; q < P; ++q)
-            if (!sch[q].done)
-                BHIPCHK(b, enqueue_multiplier_step(b->sub[q], mus[q], mun[q], launched, b->plan.nblk[q], cs));
-        if (fixed) {
-            // nothing of the schedule depends on the device: enqueue the next
-            // ALCC iteration at once; the state is read back after the last
-            // (a non-finite iterate stays non-finite until then)
-            for (int q = 0; q < P; ++q) {
-                sch[q].total_inner += lmax_all;
-                sch[q].advance(b->sub[q]);
-            }
-            continue;
-        }
-        BHIPCHK(b, hipStreamSynchronize(cs));
-        bool all_done = true;
-        for (int q = 0; q < P; ++q) {
-            if (sch[q].done) continue;
-            cr_ctx* c = b->sub[q];
-            const cr::DevState h = *c->pinned_state;
-            sch[q].total_inner += h.it;
-            sch[q].last = h;
-            if (h.iterate_nonfinite) { result = CR_ERR_NONFINITE; sch[q].done = true; continue; }
-            cr_info tmp{};
-            fill_info(c, h, &tmp);
-            if (!fixed && tmp.kkt <= p.kkt_tol) { sch[q].converged = true; sch[q].done = true; continue; }
-            sch[q].advance(c);
-            all_done = false;
-        }
-        if (all_done) break;
+    const char* h = b->ws;
+    BHIPCHK(b, cr::launch_alcc_start_batched((cr::AlccSched* const*)(h + b->plan.off_scheds),
+                                             (cr::OuterArgs* const*)(h + b->plan.off_oas),
+                                             (cr::DevState* const*)(h + b->plan.off_sts), b->P, cs));
+    const cr_params& p = b->p;
+    b->launched = 0;
+    if (p.inner_iters > 0) {
+        b->total = (int64_t)p.max_outer * ((p.inner_iters + b->replay - 1) / b->replay);
+    } else {
+        // a problem runs at most max_inner + one replay of MAPG iterations per ALCC iteration
+        b->total = (int64_t)p.max_outer * ((p.max_inner + b->replay - 1) / b->replay + 1) + 2;
     }
+    b->started = true;
+    return CR_OK;
+}
+
+cr_status cr_batch_advance(cr_batch* b, int32_t max_replays, int32_t* running) {
+    if (!b || !running) return fail(nullptr, CR_ERR_ARG, "batch and running must be non-NULL");
+    if (!b->started) return bfail(b, CR_ERR_STATE, "cr_batch_start first");
+    if (max_replays < 1) return bfail(b, CR_ERR_ARG, "max_replays must be >= 1");
+    hipStream_t cs = b->cs;
+    const bool fixed = b->p.inner_iters > 0;
+    int32_t* any = (int32_t*)(b->ws + b->plan.off_any);
+    *running = 1;
     if (fixed) {
-        BHIPCHK(b, hipStreamSynchronize(cs));
-        for (int q = 0; q < P; ++q) {
-            sch[q].last = *b->sub[q]->pinned_state;
-            if (sch[q].last.iterate_nonfinite) result = CR_ERR_NONFINITE;
-        }
+        // the replay count is known: enqueue, nothing to read back
+        const int64_t n = std::min<int64_t>(max_replays, b->total - b->launched);
+        for (int64_t r = 0; r < n; ++r) BHIPCHK(b, hipGraphLaunch(b->graph, cs));
+        b->launched += n;
+        if (b->launched >= b->total) *running = 0;
+        return CR_OK;
     }
+    int slot = 0, pending = -1;
+    for (int32_t r = 0; r < max_replays && b->launched < b->total; ++r) {
+        BHIPCHK(b, hipGraphLaunch(b->graph, cs));
+        b->launched += 1;
+        BHIPCHK(b, hipMemcpyAsync(b->pinned_flag + slot, any, 4, hipMemcpyDeviceToHost, cs));
+        BHIPCHK(b, hipEventRecord(b->ev[slot], cs));
+        if (pending >= 0) {
+            BHIPCHK(b, hipEventSynchronize(b->ev[pending]));
+            if (b->pinned_flag[pending] == 0) { *running = 0; break; }
+        }
+        pending = slot;
+        slot ^= 1;
+    }
+    if (*running) {
+        BHIPCHK(b, hipStreamSynchronize(cs));
+        if (pending >= 0 && b->pinned_flag[pending] == 0) *running = 0;
+        if (b->launched >= b->total) *running = 0;
+    }
+    return CR_OK;
+}
+
+cr_status cr_batch_finish(cr_batch* b, cr_info* infos, double* seconds) {
+    if (!b) return fail(nullptr, CR_ERR_ARG, "batch is NULL");
+    if (!b->started) return bfail(b, CR_ERR_STATE, "cr_batch_start first");
+    const int P = b->P;
+    const cr_params& p = b->p;
+    const bool fixed = p.inner_iters > 0;
+    hipStream_t cs = b->cs;
+    BHIPCHK(b, batch_copy_outputs(b));
+    BHIPCHK(b, hipStreamSynchronize(cs));
+    b->started = false;
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - b->t0).count();
+    if (seconds) *seconds = secs;
+    cr_status result = CR_OK;
     for (int q = 0; q < P; ++q) {
         cr_ctx* c = b->sub[q];
-        const Layout& L = c->L;
-        BHIPCHK(b, hipMemcpyAsync(b->probs[q].y_dev, c->D(L.off_y1p), (size_t)c->N * 8, hipMemcpyDeviceToDevice, cs));
-        BHIPCHK(b, hipMemcpyAsync(b->probs[q].xi_dev, c->D(L.off_xi1p), (size_t)c->N * c->n * 8,
-                                  hipMemcpyDeviceToDevice, cs));
-    }
-    BHIPCHK(b, hipStreamSynchronize(cs));
-    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (seconds) *seconds = secs;
-    bool all_conv = true;
-    for (int q = 0; q < P; ++q) all_conv = all_conv && (fixed || sch[q].converged);
-    if (result == CR_OK && !all_conv) result = CR_NOT_CONVERGED;
-    if (infos) {
-        for (int q = 0; q < P; ++q) {
-            cr_ctx* c = b->sub[q];
+        cr::AlccSched sc{};
+        cr::DevState h{};
+        BHIPCHK(b, hipMemcpy(&sc, c->sched, sizeof(sc), hipMemcpyDeviceToHost));
+        BHIPCHK(b, hipMemcpy(&h, c->st, sizeof(h), hipMemcpyDeviceToHost));
+        cr_status st = CR_OK;
+        if (sc.nonfinite) st = CR_ERR_NONFINITE;
+        else if (sc.phase != 2) st = CR_ERR_STATE;
+        else if (!fixed && !sc.converged) st = CR_NOT_CONVERGED;
+        if (st == CR_ERR_NONFINITE || st == CR_ERR_STATE) result = st;
+        else if (st == CR_NOT_CONVERGED && result == CR_OK) result = st;
+        if (infos) {
             cr_info& info = infos[q];
             std::memset(&info, 0, sizeof(info));
-            fill_info(c, sch[q].last, &info);
-            info.outer_iters = sch[q].k;
-            info.inner_iters = sch[q].total_inner;
+            fill_info(c, h, &info);
+            info.outer_iters = std::min(sc.k, p.max_outer);
+            info.inner_iters = sc.total_inner;
             info.seconds = secs;
-            info.pair_updates = (double)c->N * (double)(c->N - 1) * (double)sch[q].total_inner;
-            info.status = sch[q].last.iterate_nonfinite ? CR_ERR_NONFINITE
-                          : (fixed || sch[q].converged ? CR_OK : CR_NOT_CONVERGED);
+            info.pair_updates = (double)c->N * (double)(c->N - 1) * (double)sc.total_inner;
+            info.status = st;
         }
     }
     if (result == CR_ERR_NONFINITE) return bfail(b, result, "non-finite iterate");
+    if (result == CR_ERR_STATE) return bfail(b, result, "a schedule did not finish within its replay cap");
     return result;
+}
+
+cr_status cr_batch_run(cr_batch* b, cr_info* infos, double* seconds) {
+    cr_status s = cr_batch_start(b);
+    if (s != CR_OK) return s;
+    int32_t running = 1;
+    while (running) {
+        s = cr_batch_advance(b, 1 << 30, &running);
+        if (s != CR_OK) return s;
+    }
+    return cr_batch_finish(b, infos, seconds);
 }
 
 cr_status cr_batch_time_pass(cr_batch* b, int32_t reps, double* avg_ms) {
@@ -1402,7 +1525,7 @@ cr_status cr_diff_workspace_bytes(int64_t N, int32_t n, const cr_params* params,
     cr_status s = check_dims(N, n, msg);
     if (s != CR_OK) return fail(nullptr, s, msg);
     if (!check_diff(params, checkpoint_every, msg, s)) return fail(nullptr, s, msg);
-    Layout L = make_layout(N, n, params->precision, max_mapg_iters(*params), params->tile_rows);
+    Layout L = make_layout(N, n, *params, params->tile_rows);
     *bytes = L.total + make_diff_layout(L, *params, checkpoint_every).total;
     return CR_OK;
 }
@@ -1417,7 +1540,7 @@ cr_status cr_diff_init(cr_diff** out, int64_t N, int32_t n, const cr_params* par
     if (s != CR_OK) return fail(nullptr, s, msg);
     if (!check_diff(params, checkpoint_every, msg, s)) return fail(nullptr, s, msg);
     if (!X_dev || !ybar_dev || !workspace_dev) return fail(nullptr, CR_ERR_ARG, "X, ybar and workspace must be non-NULL");
-    Layout L = make_layout(N, n, params->precision, max_mapg_iters(*params), params->tile_rows);
+    Layout L = make_layout(N, n, *params, params->tile_rows);
     DiffLayout D = make_diff_layout(L, *params, checkpoint_every);
     if (ws_bytes < L.total + D.total) return fail(nullptr, CR_ERR_NOMEM, "workspace smaller than cr_diff_workspace_bytes()");
     cr_diff* d = new (std::nothrow) cr_diff();
@@ -1500,14 +1623,15 @@ cr_status cr_diff_forward(cr_diff* d, const void* y0_dev, const void* xi0_dev, v
             DHIPCHK(d, enqueue_mapg_iteration(c, l - 1, cs));
         }
         DHIPCHK(d, enqueue_multiplier_step(c, mu, mu_next, D.Lin, cr::reduce_blocks(c->N, c->n), cs));
-        DHIPCHK(d, hipStreamSynchronize(cs));
-        h = *c->pinned_state;
-        if (h.iterate_nonfinite) return dfail(d, CR_ERR_NONFINITE, "non-finite iterate");
         sch.total_inner += D.Lin;
         sch.advance(c);
     }
+    // the fixed schedule needs nothing from the device: one read-back at the end
+    // (a non-finite iterate stays non-finite through the later iterations)
     DHIPCHK(d, copy_pair(d, (double*)y_dev, (double*)xi_dev, c->D(L.off_y1p), c->D(L.off_xi1p), cs));
     DHIPCHK(d, hipStreamSynchronize(cs));
+    h = *c->pinned_state;
+    if (h.iterate_nonfinite) return dfail(d, CR_ERR_NONFINITE, "non-finite iterate");
     c->have_kkt = true;
     if (info) {
         std::memset(info, 0, sizeof(*info));
@@ -1755,20 +1879,9 @@ static hipError_t ctx_resetup(cr_ctx* c, hipStream_t cs) {
     if (e == hipSuccess && c->shift)
         e = cr::launch_setup_shift(c->D(L.off_y0), c->ybar, c->D(L.off_xi0), c->shift, c->N, c->n, c->p.gamma, c->st,
                                    cs);
-    if (e == hipSuccess) e = hipMemcpyAsync(c->pinned_state, c->st, sizeof(cr::DevState), hipMemcpyDeviceToHost, cs);
     return e;
 }
 
-static bool ctx_take_setup(cr_ctx* c) {
-    const cr::DevState& h = *c->pinned_state;
-    if (h.nonfinite || !std::isfinite(h.Bbar) || !std::isfinite(h.sigma2_A2)) return false;
-    c->sigma2_A2 = h.sigma2_A2;
-    c->Bbar = h.Bbar;
-    c->By = c->p.By_override > 0 ? c->p.By_override : h.Bbar;
-    c->Bxi = c->p.Bxi_override > 0 ? c->p.Bxi_override : h.Bbar / std::sqrt(c->p.gamma);
-    c->ybar_inf = h.ybar_inf;
-    return true;
-}
 
 extern "C" {
 
@@ -1880,17 +1993,33 @@ cr_status cr_papg(const void* X_dev, const void* ybar_dev, int64_t N, int32_t n,
 
     double t = 1.0;
     int64_t inner = 0;
-    std::vector<cr_info> infos(pp->K);
     cr_status result = CR_OK;
+    // Each iteration is enqueued behind the previous one: the block re-set-ups
+    // and the block solves' schedules run on the device, so with a fixed block
+    // schedule nothing is read back until the end (an adaptive one polls its
+    // replays' activity flag).
+    const bool fixed_blocks = alcc->inner_iters > 0;
     for (int l = 1; l <= pp->iters; ++l) {
         if (l > 1) PBCHK(cr::launch_papg_lin(a, cs));
         for (cr_ctx* c : b->sub) PBCHK(ctx_resetup(c, cs));
-        PBCHK(hipStreamSynchronize(cs));
-        for (cr_ctx* c : b->sub)
-            if (!ctx_take_setup(c)) return bfail(b, CR_ERR_NONFINITE, "non-finite block data");
-        s = cr_batch_run(b, infos.data(), nullptr);
-        if (s != CR_OK && s != CR_NOT_CONVERGED) return s;
-        for (const cr_info& f : infos) inner += f.inner_iters;
+        s = cr_batch_start(b);
+        if (s != CR_OK) return s;
+        int32_t running = 1;
+        while (running) {
+            s = cr_batch_advance(b, 1 << 30, &running);
+            if (s != CR_OK) return s;
+        }
+        PBCHK(batch_copy_outputs(b));
+        b->started = false;
+        if (fixed_blocks) {
+            inner += (int64_t)pp->K * alcc->max_outer * alcc->inner_iters;
+        } else {
+            for (cr_ctx* c : b->sub) {
+                int64_t ti = 0;
+                PBCHK(hipMemcpy(&ti, &c->sched->total_inner, 8, hipMemcpyDeviceToHost));
+                inner += ti;
+            }
+        }
         a.it = l - 1;
         PBCHK(cr::launch_papg_step2(a, cs));
         cur ^= 1;
@@ -1908,6 +2037,13 @@ cr_status cr_papg(const void* X_dev, const void* ybar_dev, int64_t N, int32_t n,
     PBCHK(hipMemcpyAsync(sc, a.scal, sizeof(sc), hipMemcpyDeviceToHost, cs));
     PBCHK(hipStreamSynchronize(cs));
     // the caller's stream waits for nothing more: the run is host-synchronous
+    for (cr_ctx* c : b->sub) {
+        cr::AlccSched bs{};
+        PBCHK(hipMemcpy(&bs, c->sched, sizeof(bs), hipMemcpyDeviceToHost));
+        if (bs.nonfinite) return bfail(b, CR_ERR_NONFINITE, "non-finite block solve");
+        if (bs.phase != 2) return bfail(b, CR_ERR_STATE, "a block schedule did not finish");
+        if (!fixed_blocks && !bs.converged) result = CR_NOT_CONVERGED;
+    }
     if (info) {
         std::memset(info, 0, sizeof(*info));
         info->L = L;

@@ -25,6 +25,28 @@ struct OuterArgs {
     int32_t skip;         // 1: problem already converged (batched form); MAPG does not run
 };
 
+// ALCC (Fig. 3) carried on the device.  The host writes the constants once
+// (cr_init); k_alcc_start, k_alcc_gate and k_alcc_step advance the state, so
+// a whole solve is enqueued with no read-back between ALCC iterations: the
+// schedule's scalars (mu_k, tau_k, alpha_k, l^max_k), the decision that a MAPG
+// run is over, the multiplier step that follows it and the KKT test all run
+// inside the captured graph.
+struct AlccSched {
+    // constants of the context
+    double mu1, c, kappa, tau1, ay1, axi1, gamma, step_scale, kkt_tol;
+    double Ly_ovr, Lxi_ovr, By_ovr, Bxi_ovr, sigma2_A1;
+    int64_t inner_iters, max_inner;
+    int32_t max_outer, pad0;
+    int64_t* hist_inner;      // max_outer entries: MAPG iterations of ALCC iteration k
+    double* hist_kkt;         // and the KKT measure after its multiplier step
+    // state of the current run
+    double mu, tau, ay, axi;
+    int64_t total_inner;
+    int32_t k;                // ALCC iterations begun
+    int32_t phase;            // 0 MAPG running, 1 multiplier step due, 2 done
+    int32_t converged, nonfinite;
+};
+
 // Device-side state.  Written by kernels only (the host reads it back).
 struct DevState {
     // problem constants (set up once)
@@ -37,7 +59,8 @@ struct DevState {
     double dy, dxi;                   // ||y1 - y2||, ||xi1 - xi2|| of the last step
     // KKT of the last multiplier step
     double stat_y, stat_xi, infeas, compl_, infeas_sq, gap, obj, xi_sq;
-    int32_t iterate_nonfinite, pad_k;
+    int32_t iterate_nonfinite;
+    int32_t step_due;                 // 1 from the end of a MAPG run until its multiplier step is done
     // arrival counters of the last-block reductions
     unsigned int cnt[4];
 };
@@ -102,6 +125,7 @@ struct PassArgs {
     void* cpart;              // chunks x ld x nc
     double* kktpart;          // (strips*chunks) x 4
     double theta_scale;       // mu_k / mu_{k+1} (multiplier pass)
+    const double* theta_scale_p;   // non-null: read mu_k / mu_{k+1} here instead (device schedule)
     const int32_t* active;
     const float* cvec;        // mixed precision: c_j = x_j^T xi_j - y_j in FP32 (ld)
     LazyStep lz;              // gradient passes of a captured MAPG run (lz.on = 1)
@@ -112,7 +136,8 @@ struct PassArgs {
 struct ReduceArgs {
     int64_t N, Nrow, ld;
     int32_t n, nc, strips, chunks, mode, npass;   // mode 0 MAPG step, 1 gradient out, 2 KKT
-    int32_t q, pad;           // mode 0: position of the iteration in the captured replay
+    int32_t q;                // mode 0: position of the iteration in the captured replay
+    int32_t mu_dev;           // mode 2: 1 = mu_k from oa->mu (device schedule), 0 = from `mu`
     const void* rowpart;
     const void* cpart;
     const double* X;
@@ -130,6 +155,7 @@ struct ReduceArgs {
     // (spart[0 .. chunks) for y, spart[chunks .. chunks + strips) for xi);
     // null: fields 2 and 3 of the update kernel's block records
     const double* spart;
+    const int32_t* gate;      // mode 2, non-null: run only while *gate != 0
 };
 
 // Completion of a MAPG step (Fig. 4): projections, momentum, stopping test.
@@ -179,6 +205,7 @@ struct PointArgs {
     void* ycol;
     float* cvec;     // mixed precision only
     const double* shift;   // slope shift c (null: none); operands from xi + c
+    const int32_t* gate;   // non-null: run only while *gate != 0
 };
 
 // Message for cr_last_error(NULL) (context-free calls outside cr_api.hip).
@@ -191,11 +218,38 @@ hipError_t launch_update(int prec, const UpdateArgs& a, hipStream_t s);
 hipError_t launch_set_point(int prec, const PointArgs& a, hipStream_t s);
 hipError_t launch_begin_outer(const OuterArgs& args, OuterArgs* dst, DevState* st, hipStream_t s,
                               int64_t base = 0);
-hipError_t launch_replay_end(DevState* st, int iters, hipStream_t s);
-hipError_t launch_mapg_end(const double* blockpart, int nblk, int64_t launched, DevState* st, hipStream_t s);
+// launched < 0: the iteration base st->base (device schedule); gate non-null:
+// only while *gate != 0.
+hipError_t launch_mapg_end(const double* blockpart, int nblk, int64_t launched, DevState* st, hipStream_t s,
+                           const int32_t* gate = nullptr);
 // After a run of lazy passes: y1_it (xi1_it) into y1p[0] (xi1p[0]); if the run
 // ended at l^max with no pass after the last step, that step's projection.
-hipError_t launch_mapg_finish(const LazyStep& lz, int64_t N, hipStream_t s);
+hipError_t launch_mapg_finish(const LazyStep& lz, int64_t N, hipStream_t s, const int32_t* gate = nullptr);
+// Device schedule (AlccSched): start of a run (first ALCC iteration begun),
+// end of a graph replay of `iters` MAPG iterations (the run is over once MAPG
+// stopped or l^max iterations ran: the multiplier step becomes due), and the
+// step after the multiplier step (history, KKT test, next ALCC iteration).
+hipError_t launch_alcc_start(AlccSched* s, OuterArgs* oa, DevState* st, hipStream_t strm);
+hipError_t launch_alcc_gate(AlccSched* s, DevState* st, const OuterArgs* oa, int iters, hipStream_t strm);
+hipError_t launch_alcc_step(AlccSched* s, DevState* st, OuterArgs* oa, hipStream_t strm);
+// The same over P problems (tables of per-problem pointers); the gate also
+// writes whether any problem is not done.
+hipError_t launch_alcc_start_batched(AlccSched* const* s, OuterArgs* const* oa, DevState* const* st, int P,
+                                     hipStream_t strm);
+hipError_t launch_alcc_gate_batched(AlccSched* const* s, DevState* const* st, OuterArgs* const* oa, int P,
+                                    int iters, int32_t* running, hipStream_t strm);
+hipError_t launch_alcc_step_batched(AlccSched* const* s, DevState* const* st, OuterArgs* const* oa, int P,
+                                    hipStream_t strm);
+// Batched multiplier-step pieces (device schedule), each gated per problem on
+// its step_due flag: the MAPG end, the set point, the multiplier pass of one
+// operand class (mode-1 PassArgs table) and the KKT reduction (mode-2
+// ReduceArgs table).
+hipError_t launch_mapg_end_batched(const double* const* blockparts, const int32_t* nblk, DevState* const* st, int P,
+                                   hipStream_t strm);
+hipError_t launch_set_point_batched(bool f64, int G, const PointArgs* args, const void* blocks, const int32_t* nblk,
+                                    int nblocks, hipStream_t strm);
+hipError_t launch_theta_pass_batched(bool f64, int ks, const PassArgs* args, const int32_t* nstrips,
+                                     const void* items, int nitems, int grid, hipStream_t strm);
 // Largest rows per chunk for which a lazy pass's LDS (row sums, y operands and
 // staged column operands) fits the pass workgroup's 32 KiB area.
 bool lazy_fits(int prec, int64_t rows_per_chunk);
@@ -257,7 +311,6 @@ hipError_t launch_reduce_batched(bool f64, int G, const ReduceArgs* args, const 
                                  int nblocks, int q, hipStream_t s);
 hipError_t launch_update_batched(bool f64, int G, const UpdateArgs* args, const void* blocks, const int32_t* nblk,
                                  int nblocks, int q, hipStream_t s);
-hipError_t launch_replay_end_batched(DevState* const* sts, int P, int iters, int32_t* any_active, hipStream_t s);
 hipError_t launch_prep_xp(int prec, const double* X, int64_t N, int n, int64_t Nrow, int ks, int qp, void* xp,
                           hipStream_t s);
 hipError_t launch_theta_import(bool f64, const double* src, int64_t N, int64_t Nrow, int64_t ld, void* theta,

@@ -230,6 +230,8 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
         for (int kb = 0; kb < NKB; ++kb) cacc[t][kb] = acc_t{0, 0, 0, 0};
 
     double k_rneg_max = 0.0, k_rneg_sq = 0.0, k_wr_max = 0.0, k_wr_sum = 0.0;
+    double theta_scale = 0.0;
+    if constexpr (theta_mode) theta_scale = a.theta_scale_p ? *a.theta_scale_p : a.theta_scale;
 
     constexpr int64_t step = 16 * kWaves;
     constexpr int NSET = Ops::NSET;   // staging sets (tiles in flight per wave)
@@ -331,7 +333,7 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
             for (int v = 0; v < 4; ++v) {
                 V16<T> o;
 #pragma unroll
-                for (int t = 0; t < TW; ++t) o.v[t] = (T)(a.theta_scale * (double)W[t][v]);
+                for (int t = 0; t < TW; ++t) o.v[t] = (T)(theta_scale * (double)W[t][v]);
                 st16(theta + (i0 + orow<Ops>(g, v)) * a.ld + jl, o);
             }
 #pragma unroll
@@ -485,7 +487,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void k_pair_pass(PassArgs a) {
 // stopped.  Each item is one workgroup tile of the single-problem pass.
 struct BatchItem { int32_t p, strip, chunk, pad; };
 
-template <typename T, int KS>
+template <typename T, int KS, int THETA_MODE = 0>
 __global__ __launch_bounds__(kBlock) void k_pair_pass_batched(const PassArgs* args, const int32_t* nstrips_of_p,
                                                               const BatchItem* items, int nitems) {
     __shared__ __align__(16) char lds[kPassLds];
@@ -493,7 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_pass_batched(const PassArgs* ar
         const BatchItem item = items[it];
         const PassArgs& a = args[item.p];
         if (*a.active == 0) continue;
-        pair_pass_item<PlainOps<T, KS>, 0>(a, item.strip, item.chunk, nstrips_of_p[item.p], lds);
+        pair_pass_item<PlainOps<T, KS>, THETA_MODE>(a, item.strip, item.chunk, nstrips_of_p[item.p], lds);
         __syncthreads();   // the next item reuses this workgroup's LDS
     }
 }
@@ -527,6 +529,7 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
         if (st->active == 0) return;
         l = st->base + a.q + 1;
     }
+    if (a.gate && *a.gate == 0) return;
     constexpr int PER = kBlock / G;
     const int k = threadIdx.x % G;
     const int64_t j = (int64_t)blk * PER + threadIdx.x / G;
@@ -538,7 +541,7 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
     if (a.mode == 0) {
         mu = a.oa->mu; gamma = a.oa->gamma; sy = a.oa->sy; sxi = a.oa->sxi;
     } else {
-        mu = a.mu; gamma = a.gamma;
+        mu = a.mu_dev ? a.oa->mu : a.mu; gamma = a.gamma;
     }
     // Every load of this point first, so that they are in flight together.
     // Lane k sums the strips k, k + G, ... and (k < n + 1) column k over the
@@ -682,7 +685,7 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
         a.blockpart[blk * 4 + 2] = b2;
         a.blockpart[blk * 4 + 3] = bb > 0.0 ? INFINITY : b3;
     }
-    if (last_block(&st->cnt[1])) {
+    if (last_block(&st->cnt[1], (unsigned int)nblk)) {
         const double m0 = block_gather(a.blockpart, nblk, 0, 1);
         const double m1 = block_gather(a.blockpart, nblk, 1, 1);
         const double s2 = block_gather(a.blockpart, nblk, 2, 0);
@@ -812,33 +815,13 @@ __global__ __launch_bounds__(kBlock) void k_update_batched(const UpdateArgs* arg
     update_block<T, G, 0>(a, bp.y, nblk_of_p[bp.x]);
 }
 
-// After each batched graph replay: advance every problem's iteration base and
-// record whether any problem's MAPG is still running.
-__global__ void k_replay_end_batched(DevState* const* sts, int P, int iters, int32_t* any_active) {
-    if (blockIdx.x != 0) return;
-    int any = 0;
-    for (int p = threadIdx.x; p < P; p += blockDim.x) {
-        sts[p]->base += iters;
-        any |= sts[p]->active;
-    }
-    __shared__ int s_any;
-    if (threadIdx.x == 0) s_any = 0;
-    __syncthreads();
-    if (any) atomicOr(&s_any, 1);
-    __syncthreads();
-    if (threadIdx.x == 0) *any_active = s_any;
-}
-
-// After each graph replay: advance the iteration base by the replay length.
-__global__ void k_replay_end(DevState* st, int iters) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) st->base += iters;
-}
-
 // After the last replay of an ALCC iteration: if no reduce kernel has stopped
 // MAPG yet, the run ended at exactly `launched` = l_max iterations.
 __global__ __launch_bounds__(kBlock) void k_mapg_end(const double* blockpart, int nblk, int64_t launched,
-                                                     DevState* st) {
+                                                     DevState* st, const int32_t* gate) {
+    if (gate && *gate == 0) return;
     if (st->active == 0) return;
+    if (launched < 0) launched = st->base;
     double dy2, dx2;
     gather_sum2(blockpart, nblk, 2, 3, dy2, dx2);
     const double dy = sqrt(dy2), dxi = sqrt(dx2);
@@ -858,7 +841,8 @@ __global__ __launch_bounds__(kBlock) void k_mapg_end(const double* blockpart, in
 // goes to y1p[0] / xi1p[0].  `active` is read here and cleared afterwards by
 // k_mapg_end.
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_mapg_finish(LazyStep z, int64_t N) {
+__global__ __launch_bounds__(kBlock) void k_mapg_finish(LazyStep z, int64_t N, const int32_t* gate) {
+    if (gate && *gate == 0) return;
     constexpr int PER = kBlock / G;
     const int k = threadIdx.x % G;
     const int64_t j = (int64_t)blockIdx.x * PER + threadIdx.x / G;
@@ -889,10 +873,11 @@ __global__ __launch_bounds__(kBlock) void k_mapg_finish(LazyStep z, int64_t N) {
 // y^(1)_0 = y^(2)_1 = y and likewise xi.
 
 template <typename T, int G, int MIX>
-__global__ __launch_bounds__(kBlock) void k_set_point(PointArgs a) {
+__device__ void set_point_block(const PointArgs& a, const int blk) {
+    if (a.gate && *a.gate == 0) return;
     constexpr int PER = kBlock / G;
     const int k = threadIdx.x % G;
-    const int64_t j = (int64_t)blockIdx.x * PER + threadIdx.x / G;
+    const int64_t j = (int64_t)blk * PER + threadIdx.x / G;
     const int n = a.n;
     double prod = 0.0, x = 0.0;
     const bool valid = j < a.N;
@@ -932,6 +917,18 @@ __global__ __launch_bounds__(kBlock) void k_set_point(PointArgs a) {
     }
 }
 
+template <typename T, int G, int MIX>
+__global__ __launch_bounds__(kBlock) void k_set_point(PointArgs a) {
+    set_point_block<T, G, MIX>(a, blockIdx.x);
+}
+
+// Batched set point: block b is local block blocks[b].y of problem blocks[b].x.
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_set_point_batched(const PointArgs* args, const int2* blocks) {
+    const int2 bp = blocks[blockIdx.x];
+    set_point_block<T, G, 0>(args[bp.x], bp.y);
+}
+
 __global__ void k_begin_outer(OuterArgs args, OuterArgs* dst, DevState* st, int64_t base) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         *dst = args;
@@ -941,6 +938,143 @@ __global__ void k_begin_outer(OuterArgs args, OuterArgs* dst, DevState* st, int6
         st->stopped_by_alpha = 0;
         st->one = 1;
         for (int q = 0; q < 4; ++q) st->cnt[q] = 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// ALCC schedule on the device (Fig. 3; AlccSched).  One thread per problem.
+// ---------------------------------------------------------------------------
+
+// Begin ALCC iteration k + 1: L^y_k = 1/mu_k + sigma_max(A1)^2, L^xi_k =
+// gamma/mu_k + sigma_max(A2)^2, the radii of Q_y and Q_xi, l^max_k =
+// ceil(4 sqrt((L^y By^2 + L^xi Bxi^2)/tau_k)) (capped; a fixed count for a
+// fixed schedule), the steps and thresholds; MAPG restarts (t = 1) at the
+// current iterate, whose operands the previous multiplier step left in place.
+__device__ void alcc_begin(AlccSched* s, OuterArgs* oa, DevState* st) {
+    s->k += 1;
+    const double Ly = s->Ly_ovr > 0 ? s->Ly_ovr : 1.0 / s->mu + s->sigma2_A1;
+    const double Lxi = s->Lxi_ovr > 0 ? s->Lxi_ovr : s->gamma / s->mu + st->sigma2_A2;
+    const double By = s->By_ovr > 0 ? s->By_ovr : st->Bbar;
+    const double Bxi = s->Bxi_ovr > 0 ? s->Bxi_ovr : st->Bbar / sqrt(s->gamma);
+    int64_t lmax;
+    if (s->inner_iters > 0) {
+        lmax = s->inner_iters;
+    } else {
+        const double f = ceil(4.0 * sqrt((Ly * By * By + Lxi * Bxi * Bxi) / s->tau));
+        lmax = (int64_t)fmax(1.0, fmin(f, (double)s->max_inner));
+    }
+    OuterArgs a;
+    a.mu = s->mu; a.gamma = s->gamma; a.sy = s->step_scale / Ly; a.sxi = s->step_scale / Lxi;
+    a.alpha_y = s->ay; a.alpha_xi = s->axi; a.By = By; a.Bxi = Bxi;
+    a.theta_scale = 1.0 / s->c; a.lmax = lmax; a.adaptive = s->inner_iters > 0 ? 0 : 1; a.skip = 0;
+    *oa = a;
+    st->base = 0;
+    st->it = 0;
+    st->active = 1;
+    st->stopped_by_alpha = 0;
+    st->step_due = 0;
+    st->one = 1;
+    for (int q = 0; q < 4; ++q) st->cnt[q] = 0u;
+    s->phase = 0;
+}
+
+// Start of a run: mu_1, tau_1 and the alpha thresholds (1e-2 Bbar unless
+// given), then ALCC iteration 1.
+__device__ void alcc_start(AlccSched* s, OuterArgs* oa, DevState* st) {
+    s->mu = s->mu1;
+    s->tau = s->tau1;
+    s->ay = s->ay1 > 0 ? s->ay1 : 1e-2 * st->Bbar;
+    s->axi = s->axi1 > 0 ? s->axi1 : 1e-2 * st->Bbar;
+    s->k = 0;
+    s->total_inner = 0;
+    s->converged = 0;
+    s->nonfinite = 0;
+    alcc_begin(s, oa, st);
+}
+
+// End of a replay of `iters` MAPG iterations: the run is over once MAPG has
+// stopped (alpha test or l^max, decided by a reduce kernel) or l^max
+// iterations have run (the stop of the last one is then not yet decided;
+// k_mapg_end takes it).  Then the multiplier step is due.
+__device__ void alcc_gate(AlccSched* s, DevState* st, const OuterArgs* oa, int iters) {
+    st->base += iters;
+    if (s->phase == 0 && (st->active == 0 || st->base >= oa->lmax)) {
+        s->phase = 1;
+        st->step_due = 1;
+    }
+}
+
+// After the multiplier step (Fig. 3 step 4) and its KKT reduction: record the
+// ALCC iteration, stop on the KKT test (adaptive schedules), on max_outer or
+// on a non-finite iterate; otherwise mu_{k+1} = c mu_k, tau and both alpha
+// thresholds divided by (c k^{1+kappa})^2, and the next ALCC iteration begins.
+__device__ void alcc_step(AlccSched* s, DevState* st, OuterArgs* oa) {
+    if (s->phase != 1) return;
+    const double kkt = fmax(fmax(st->stat_y, st->stat_xi), fmax(st->infeas, st->compl_)) / (1.0 + st->ybar_inf);
+    const int idx = s->k - 1;
+    if (idx >= 0 && idx < s->max_outer) {
+        s->hist_inner[idx] = st->it;
+        s->hist_kkt[idx] = kkt;
+    }
+    s->total_inner += st->it;
+    st->step_due = 0;
+    if (st->iterate_nonfinite) { s->nonfinite = 1; s->phase = 2; return; }
+    if (s->inner_iters == 0 && kkt <= s->kkt_tol) { s->converged = 1; s->phase = 2; return; }
+    if (s->k >= s->max_outer) { s->phase = 2; return; }
+    const double decay = pow(s->c * pow((double)s->k, 1.0 + s->kappa), 2.0);
+    s->mu = s->c * s->mu;
+    s->tau /= decay;
+    s->ay /= decay;
+    s->axi /= decay;
+    alcc_begin(s, oa, st);
+}
+
+__global__ void k_alcc_start(AlccSched* s, OuterArgs* oa, DevState* st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) alcc_start(s, oa, st);
+}
+__global__ void k_alcc_gate(AlccSched* s, DevState* st, const OuterArgs* oa, int iters) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) alcc_gate(s, st, oa, iters);
+}
+__global__ void k_alcc_step(AlccSched* s, DevState* st, OuterArgs* oa) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) alcc_step(s, st, oa);
+}
+__global__ void k_alcc_start_batched(AlccSched* const* s, OuterArgs* const* oa, DevState* const* st, int P) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < P) alcc_start(s[p], oa[p], st[p]);
+}
+__global__ void k_alcc_gate_batched(AlccSched* const* s, DevState* const* st, OuterArgs* const* oa, int P, int iters,
+                                    int32_t* running) {
+    int any = 0;
+    for (int p = threadIdx.x; p < P; p += blockDim.x) {
+        alcc_gate(s[p], st[p], oa[p], iters);
+        any |= s[p]->phase != 2;
+    }
+    __shared__ int s_any;
+    if (threadIdx.x == 0) s_any = 0;
+    __syncthreads();
+    if (any) atomicOr(&s_any, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) *running = s_any;
+}
+__global__ void k_alcc_step_batched(AlccSched* const* s, DevState* const* st, OuterArgs* const* oa, int P) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < P) alcc_step(s[p], st[p], oa[p]);
+}
+
+// k_mapg_end of every problem whose multiplier step is due (block p: problem p).
+__global__ __launch_bounds__(kBlock) void k_mapg_end_batched(const double* const* blockparts, const int32_t* nblk,
+                                                             DevState* const* sts) {
+    DevState* st = sts[blockIdx.x];
+    if (st->step_due == 0 || st->active == 0) return;
+    double dy2, dx2;
+    gather_sum2(blockparts[blockIdx.x], nblk[blockIdx.x], 2, 3, dy2, dx2);
+    const double dy = sqrt(dy2), dxi = sqrt(dx2);
+    if (threadIdx.x == 0) {
+        st->active = 0;
+        st->it = st->base;
+        st->stopped_by_alpha = 0;
+        st->dy = dy;
+        st->dxi = dxi;
     }
 }
 
@@ -1371,30 +1505,30 @@ hipError_t launch_update(int prec, const UpdateArgs& a, hipStream_t s) {
 
 int reduce_blocks(int64_t N, int n) { return (int)points_grid(N, group_of(n)).x; }
 
-hipError_t launch_mapg_finish(const LazyStep& z, int64_t N, hipStream_t s) {
-    if (group_of(z.n) == 16) hipLaunchKernelGGL((k_mapg_finish<16>), points_grid(N, 16), dim3(kBlock), 0, s, z, N);
-    else hipLaunchKernelGGL((k_mapg_finish<32>), points_grid(N, 32), dim3(kBlock), 0, s, z, N);
+hipError_t launch_mapg_finish(const LazyStep& z, int64_t N, hipStream_t s, const int32_t* gate) {
+    if (group_of(z.n) == 16) hipLaunchKernelGGL((k_mapg_finish<16>), points_grid(N, 16), dim3(kBlock), 0, s, z, N, gate);
+    else hipLaunchKernelGGL((k_mapg_finish<32>), points_grid(N, 32), dim3(kBlock), 0, s, z, N, gate);
     return hipGetLastError();
 }
 int reduce_blocks_g(int64_t N, int G) { return (int)points_grid(N, G).x; }
 
-template <typename T, int KS>
+template <typename T, int KS, int MODE>
 static void pass_batched_ks(const PassArgs* args, const int32_t* nstrips, const BatchItem* it, int nitems, int grid,
                             hipStream_t s) {
-    hipLaunchKernelGGL((k_pair_pass_batched<T, KS>), dim3(grid), dim3(kBlock), 0, s, args, nstrips, it, nitems);
+    hipLaunchKernelGGL((k_pair_pass_batched<T, KS, MODE>), dim3(grid), dim3(kBlock), 0, s, args, nstrips, it, nitems);
 }
-template <typename T>
+template <typename T, int MODE>
 static hipError_t pass_batched_t(int ks, const PassArgs* args, const int32_t* nstrips, const BatchItem* it,
                                  int nitems, int grid, hipStream_t s) {
     switch (ks) {
-        case 1: pass_batched_ks<T, 1>(args, nstrips, it, nitems, grid, s); break;
-        case 2: pass_batched_ks<T, 2>(args, nstrips, it, nitems, grid, s); break;
-        case 3: pass_batched_ks<T, 3>(args, nstrips, it, nitems, grid, s); break;
-        case 4: pass_batched_ks<T, 4>(args, nstrips, it, nitems, grid, s); break;
-        case 5: pass_batched_ks<T, 5>(args, nstrips, it, nitems, grid, s); break;
-        case 6: pass_batched_ks<T, 6>(args, nstrips, it, nitems, grid, s); break;
-        case 7: pass_batched_ks<T, 7>(args, nstrips, it, nitems, grid, s); break;
-        case 8: pass_batched_ks<T, 8>(args, nstrips, it, nitems, grid, s); break;
+        case 1: pass_batched_ks<T, 1, MODE>(args, nstrips, it, nitems, grid, s); break;
+        case 2: pass_batched_ks<T, 2, MODE>(args, nstrips, it, nitems, grid, s); break;
+        case 3: pass_batched_ks<T, 3, MODE>(args, nstrips, it, nitems, grid, s); break;
+        case 4: pass_batched_ks<T, 4, MODE>(args, nstrips, it, nitems, grid, s); break;
+        case 5: pass_batched_ks<T, 5, MODE>(args, nstrips, it, nitems, grid, s); break;
+        case 6: pass_batched_ks<T, 6, MODE>(args, nstrips, it, nitems, grid, s); break;
+        case 7: pass_batched_ks<T, 7, MODE>(args, nstrips, it, nitems, grid, s); break;
+        case 8: pass_batched_ks<T, 8, MODE>(args, nstrips, it, nitems, grid, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1403,8 +1537,15 @@ static hipError_t pass_batched_t(int ks, const PassArgs* args, const int32_t* ns
 hipError_t launch_pass_batched(bool f64, int ks, const PassArgs* args, const int32_t* nstrips, const void* items,
                                int nitems, int grid, hipStream_t s) {
     const BatchItem* it = (const BatchItem*)items;
-    return f64 ? pass_batched_t<double>(ks, args, nstrips, it, nitems, grid, s)
-               : pass_batched_t<float>(ks, args, nstrips, it, nitems, grid, s);
+    return f64 ? pass_batched_t<double, 0>(ks, args, nstrips, it, nitems, grid, s)
+               : pass_batched_t<float, 0>(ks, args, nstrips, it, nitems, grid, s);
+}
+
+hipError_t launch_theta_pass_batched(bool f64, int ks, const PassArgs* args, const int32_t* nstrips, const void* items,
+                                     int nitems, int grid, hipStream_t s) {
+    const BatchItem* it = (const BatchItem*)items;
+    return f64 ? pass_batched_t<double, 1>(ks, args, nstrips, it, nitems, grid, s)
+               : pass_batched_t<float, 1>(ks, args, nstrips, it, nitems, grid, s);
 }
 
 hipError_t launch_reduce_batched(bool f64, int G, const ReduceArgs* args, const void* blocks, const int32_t* nblk,
@@ -1433,18 +1574,54 @@ hipError_t launch_update_batched(bool f64, int G, const UpdateArgs* args, const 
     return hipGetLastError();
 }
 
-hipError_t launch_replay_end_batched(DevState* const* sts, int P, int iters, int32_t* any_active, hipStream_t s) {
-    hipLaunchKernelGGL(k_replay_end_batched, dim3(1), dim3(kBlock), 0, s, sts, P, iters, any_active);
+hipError_t launch_mapg_end(const double* blockpart, int nblk, int64_t launched, DevState* st, hipStream_t s,
+                           const int32_t* gate) {
+    hipLaunchKernelGGL(k_mapg_end, dim3(1), dim3(kBlock), 0, s, blockpart, nblk, launched, st, gate);
     return hipGetLastError();
 }
 
-hipError_t launch_replay_end(DevState* st, int iters, hipStream_t s) {
-    hipLaunchKernelGGL(k_replay_end, dim3(1), dim3(64), 0, s, st, iters);
+hipError_t launch_alcc_start(AlccSched* sc, OuterArgs* oa, DevState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_alcc_start, dim3(1), dim3(64), 0, s, sc, oa, st);
     return hipGetLastError();
 }
-
-hipError_t launch_mapg_end(const double* blockpart, int nblk, int64_t launched, DevState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_mapg_end, dim3(1), dim3(kBlock), 0, s, blockpart, nblk, launched, st);
+hipError_t launch_alcc_gate(AlccSched* sc, DevState* st, const OuterArgs* oa, int iters, hipStream_t s) {
+    hipLaunchKernelGGL(k_alcc_gate, dim3(1), dim3(64), 0, s, sc, st, oa, iters);
+    return hipGetLastError();
+}
+hipError_t launch_alcc_step(AlccSched* sc, DevState* st, OuterArgs* oa, hipStream_t s) {
+    hipLaunchKernelGGL(k_alcc_step, dim3(1), dim3(64), 0, s, sc, st, oa);
+    return hipGetLastError();
+}
+hipError_t launch_alcc_start_batched(AlccSched* const* sc, OuterArgs* const* oa, DevState* const* st, int P,
+                                     hipStream_t s) {
+    hipLaunchKernelGGL(k_alcc_start_batched, dim3((P + 63) / 64), dim3(64), 0, s, sc, oa, st, P);
+    return hipGetLastError();
+}
+hipError_t launch_alcc_gate_batched(AlccSched* const* sc, DevState* const* st, OuterArgs* const* oa, int P, int iters,
+                                    int32_t* running, hipStream_t s) {
+    hipLaunchKernelGGL(k_alcc_gate_batched, dim3(1), dim3(kBlock), 0, s, sc, st, oa, P, iters, running);
+    return hipGetLastError();
+}
+hipError_t launch_alcc_step_batched(AlccSched* const* sc, DevState* const* st, OuterArgs* const* oa, int P,
+                                    hipStream_t s) {
+    hipLaunchKernelGGL(k_alcc_step_batched, dim3((P + 63) / 64), dim3(64), 0, s, sc, st, oa, P);
+    return hipGetLastError();
+}
+hipError_t launch_mapg_end_batched(const double* const* blockparts, const int32_t* nblk, DevState* const* st, int P,
+                                   hipStream_t s) {
+    hipLaunchKernelGGL(k_mapg_end_batched, dim3(P), dim3(kBlock), 0, s, blockparts, nblk, st);
+    return hipGetLastError();
+}
+hipError_t launch_set_point_batched(bool f64, int G, const PointArgs* args, const void* blocks, const int32_t*,
+                                    int nblocks, hipStream_t s) {
+    const int2* b = (const int2*)blocks;
+    if (f64) {
+        if (G == 16) hipLaunchKernelGGL((k_set_point_batched<double, 16>), dim3(nblocks), dim3(kBlock), 0, s, args, b);
+        else hipLaunchKernelGGL((k_set_point_batched<double, 32>), dim3(nblocks), dim3(kBlock), 0, s, args, b);
+    } else {
+        if (G == 16) hipLaunchKernelGGL((k_set_point_batched<float, 16>), dim3(nblocks), dim3(kBlock), 0, s, args, b);
+        else hipLaunchKernelGGL((k_set_point_batched<float, 32>), dim3(nblocks), dim3(kBlock), 0, s, args, b);
+    }
     return hipGetLastError();
 }
 

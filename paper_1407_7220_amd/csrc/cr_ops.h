@@ -151,16 +151,16 @@ static __device__ void gather_sum2(const double* part, int count, int q0, int q1
     block_sum2(s0, s1);
 }
 
-// Each block calls this once after writing its partial results; it returns
-// true in every thread of the one block that arrives last (that block then
-// sees every other block's partials) and re-arms the counter.
-static __device__ bool last_block(unsigned int* counter) {
+// Each of `total` blocks calls this once after writing its partial results; it
+// returns true in every thread of the one block that arrives last (that block
+// then sees every other block's partials) and re-arms the counter.
+static __device__ bool last_block(unsigned int* counter, unsigned int total) {
     __shared__ int is_last;
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned int prev = atomicAdd(counter, 1u);
-        is_last = (prev == gridDim.x * gridDim.y - 1) ? 1 : 0;
+        is_last = (prev == total - 1) ? 1 : 0;
         if (is_last) atomicExch(counter, 0u);
     }
     __syncthreads();

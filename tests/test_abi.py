@@ -117,6 +117,10 @@ def test_batch_arguments_rejected_on_host():
     arr[0].y_dev = None
     assert lib.cr_batch_init(ctypes.byref(h), arr, 1, ctypes.byref(p), ctypes.c_void_p(0x1000), one, None) == cr.ERR_ARG
     assert lib.cr_batch_run(None, None, None) == cr.ERR_ARG
+    running = ctypes.c_int32(0)
+    assert lib.cr_batch_start(None) == cr.ERR_ARG
+    assert lib.cr_batch_advance(None, 1, ctypes.byref(running)) == cr.ERR_ARG
+    assert lib.cr_batch_finish(None, None, None) == cr.ERR_ARG
     assert lib.cr_batch_destroy(None) == cr.OK
 
 

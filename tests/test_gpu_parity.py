@@ -544,6 +544,32 @@ def test_batched_equals_single_problem_bitwise_in_deterministic_mode(cr, prec):
             np.testing.assert_array_equal(xi, host(xis))
 
 
+def test_batched_in_bounded_pieces_equals_one_run(cr):
+    """cr_batch_start / cr_batch_advance (a few replays at a time) / cr_batch_finish
+    give the bits of one cr_batch_run, for an adaptive and a fixed schedule."""
+    say("batched run in pieces vs one run, f64")
+    probs = _batch_problems([(40, 2), (90, 5), (130, 3)], seed0=500)
+    pairs = [(dev(p.X), dev(p.ybar)) for p in probs]
+    for sched in (dict(kkt_tol=1e-4, max_inner=300, max_outer=6), dict(inner_iters=40, max_outer=3)):
+        b = cr.Batch(pairs, cr.Params(precision=0, **sched))
+        try:
+            outs, infos, _ = b.run()
+            ref = [(host(y).copy(), host(xi).copy()) for y, xi in outs]
+            ref_inner = [i.inner_iters for i in infos]
+            b.start()
+            steps = 0
+            while b.advance(3):
+                steps += 1
+            outs, infos, _ = b.finish()
+        finally:
+            b.close()
+        say("  %s: %d advance calls, inner %s" % (sched, steps + 1, ref_inner))
+        assert [i.inner_iters for i in infos] == ref_inner
+        for (y, xi), (ry, rxi) in zip(outs, ref):
+            np.testing.assert_array_equal(host(y), ry)
+            np.testing.assert_array_equal(host(xi), rxi)
+
+
 def test_batched_adaptive_converges_and_freezes(cr):
     say("batched adaptive f32")
     probs = _batch_problems([(40, 2), (60, 3), (80, 5)], seed0=300)
