@@ -952,7 +952,7 @@ struct cr_batch {
     int32_t* pinned_flag = nullptr;
     char* ws = nullptr;
     bool f64 = false;
-    int grid = 512;
+    int cus = 256;                         // compute units (sizes the persistent pass grids)
     std::string err;
 };
 
@@ -982,11 +982,10 @@ static cr_status capture_batch_graph(cr_batch* b, hipGraphExec_t* out) {
     hipError_t e = hipSuccess;
     for (int q = 0; q < iters && e == hipSuccess; ++q) {
         for (size_t ci = 0; ci < B.ks_classes.size() && e == hipSuccess; ++ci) {
-            const int grid = std::max(1, std::min(b->grid, B.class_cnt[ci]));
             e = cr::launch_pass_batched(b->f64, B.ks_classes[ci], (const cr::PassArgs*)(h + B.off_pass),
                                         (const int32_t*)(h + B.off_nstrips),
                                         h + B.off_items + (size_t)B.class_off[ci] * sizeof(BatchItemH),
-                                        B.class_cnt[ci], grid, b->cs);
+                                        B.class_cnt[ci], b->cus, b->cs);
         }
         if (e == hipSuccess)
             e = cr::launch_reduce_batched(b->f64, B.G, (const cr::ReduceArgs*)(h + B.off_red), h + B.off_blocks,
@@ -1007,11 +1006,10 @@ static cr_status capture_batch_graph(cr_batch* b, hipGraphExec_t* out) {
         e = cr::launch_set_point_batched(b->f64, B.G, (const cr::PointArgs*)(h + B.off_pt), h + B.off_blocks,
                                          (const int32_t*)(h + B.off_nblk), B.nblocks, b->cs);
     for (size_t ci = 0; ci < B.ks_classes.size() && e == hipSuccess; ++ci) {
-        const int grid = std::max(1, std::min(b->grid, B.class_cnt[ci]));
         e = cr::launch_theta_pass_batched(b->f64, B.ks_classes[ci], (const cr::PassArgs*)(h + B.off_pass1),
                                           (const int32_t*)(h + B.off_nstrips),
                                           h + B.off_items + (size_t)B.class_off[ci] * sizeof(BatchItemH),
-                                          B.class_cnt[ci], grid, b->cs);
+                                          B.class_cnt[ci], b->cus, b->cs);
     }
     if (e == hipSuccess)
         e = cr::launch_reduce_batched(b->f64, B.G, (const cr::ReduceArgs*)(h + B.off_red2), h + B.off_blocks,
@@ -1089,7 +1087,7 @@ static cr_status batch_init_impl(cr_batch** out, const cr_problem* probs, int32_
     {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-            b->grid = 2 * cus;
+            b->cus = cus;
     }
     // per-problem contexts (set-up of each problem on its own slice)
     for (int p = 0; p < P; ++p) {
@@ -1318,11 +1316,10 @@ cr_status cr_batch_time_pass(cr_batch* b, int32_t reps, double* avg_ms) {
     auto step = [&]() {
         hipError_t e = hipSuccess;
         for (size_t ci = 0; ci < B.ks_classes.size() && e == hipSuccess; ++ci) {
-            const int grid = std::max(1, std::min(b->grid, B.class_cnt[ci]));
             e = cr::launch_pass_batched(b->f64, B.ks_classes[ci], (const cr::PassArgs*)(h + B.off_pass),
                                         (const int32_t*)(h + B.off_nstrips),
                                         h + B.off_items + (size_t)B.class_off[ci] * sizeof(BatchItemH),
-                                        B.class_cnt[ci], grid, cs);
+                                        B.class_cnt[ci], b->cus, cs);
         }
         return e;
     };

@@ -249,7 +249,7 @@ hipError_t launch_mapg_end_batched(const double* const* blockparts, const int32_
 hipError_t launch_set_point_batched(bool f64, int G, const PointArgs* args, const void* blocks, const int32_t* nblk,
                                     int nblocks, hipStream_t strm);
 hipError_t launch_theta_pass_batched(bool f64, int ks, const PassArgs* args, const int32_t* nstrips,
-                                     const void* items, int nitems, int grid, hipStream_t strm);
+                                     const void* items, int nitems, int cus, hipStream_t strm);
 // Largest rows per chunk for which a lazy pass's LDS (row sums, y operands and
 // staged column operands) fits the pass workgroup's 32 KiB area.
 bool lazy_fits(int prec, int64_t rows_per_chunk);
@@ -304,9 +304,10 @@ hipError_t launch_papg_power(const PapgArgs& a, double* vy, double* vxi, const d
 int reduce_blocks(int64_t N, int n);
 int reduce_blocks_g(int64_t N, int G);
 // Batched form (plain precisions): see cr_batch.hip.
-// One persistent pass per operand class ks = ceil((n + 1) / 4) over that class's items.
+// One persistent pass per operand class ks = ceil((n + 1) / 4) over that class's
+// items; the grid is sized from the compute-unit count `cus`.
 hipError_t launch_pass_batched(bool f64, int ks, const PassArgs* args, const int32_t* nstrips, const void* items,
-                               int nitems, int grid, hipStream_t s);
+                               int nitems, int cus, hipStream_t s);
 hipError_t launch_reduce_batched(bool f64, int G, const ReduceArgs* args, const void* blocks, const int32_t* nblk,
                                  int nblocks, int q, hipStream_t s);
 hipError_t launch_update_batched(bool f64, int G, const UpdateArgs* args, const void* blocks, const int32_t* nblk,

@@ -487,8 +487,8 @@ __global__ __launch_bounds__(kBlock, WAVES) void k_pair_pass(PassArgs a) {
 // stopped.  Each item is one workgroup tile of the single-problem pass.
 struct BatchItem { int32_t p, strip, chunk, pad; };
 
-template <typename T, int KS, int THETA_MODE = 0>
-__global__ __launch_bounds__(kBlock) void k_pair_pass_batched(const PassArgs* args, const int32_t* nstrips_of_p,
+template <typename T, int KS, int THETA_MODE, int WAVES>
+__global__ __launch_bounds__(kBlock, WAVES) void k_pair_pass_batched(const PassArgs* args, const int32_t* nstrips_of_p,
                                                               const BatchItem* items, int nitems) {
     __shared__ __align__(16) char lds[kPassLds];
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -1512,40 +1512,45 @@ hipError_t launch_mapg_finish(const LazyStep& z, int64_t N, hipStream_t s, const
 }
 int reduce_blocks_g(int64_t N, int G) { return (int)points_grid(N, G).x; }
 
+// The persistent grid holds as many workgroups as the class's register budget
+// lets each CU keep resident (WAVES per SIMD, the single-problem pass's
+// figure), so every item a workgroup takes starts at once.
 template <typename T, int KS, int MODE>
-static void pass_batched_ks(const PassArgs* args, const int32_t* nstrips, const BatchItem* it, int nitems, int grid,
+static void pass_batched_ks(const PassArgs* args, const int32_t* nstrips, const BatchItem* it, int nitems, int cus,
                             hipStream_t s) {
-    hipLaunchKernelGGL((k_pair_pass_batched<T, KS, MODE>), dim3(grid), dim3(kBlock), 0, s, args, nstrips, it, nitems);
+    constexpr int W = MODE == 1 ? 2 : (sizeof(T) == 4 && KS <= 2 ? 4 : (KS <= 4 ? 3 : 2));
+    const int grid = std::max(1, std::min(nitems, W * cus));
+    hipLaunchKernelGGL((k_pair_pass_batched<T, KS, MODE, W>), dim3(grid), dim3(kBlock), 0, s, args, nstrips, it, nitems);
 }
 template <typename T, int MODE>
 static hipError_t pass_batched_t(int ks, const PassArgs* args, const int32_t* nstrips, const BatchItem* it,
-                                 int nitems, int grid, hipStream_t s) {
+                                 int nitems, int cus, hipStream_t s) {
     switch (ks) {
-        case 1: pass_batched_ks<T, 1, MODE>(args, nstrips, it, nitems, grid, s); break;
-        case 2: pass_batched_ks<T, 2, MODE>(args, nstrips, it, nitems, grid, s); break;
-        case 3: pass_batched_ks<T, 3, MODE>(args, nstrips, it, nitems, grid, s); break;
-        case 4: pass_batched_ks<T, 4, MODE>(args, nstrips, it, nitems, grid, s); break;
-        case 5: pass_batched_ks<T, 5, MODE>(args, nstrips, it, nitems, grid, s); break;
-        case 6: pass_batched_ks<T, 6, MODE>(args, nstrips, it, nitems, grid, s); break;
-        case 7: pass_batched_ks<T, 7, MODE>(args, nstrips, it, nitems, grid, s); break;
-        case 8: pass_batched_ks<T, 8, MODE>(args, nstrips, it, nitems, grid, s); break;
+        case 1: pass_batched_ks<T, 1, MODE>(args, nstrips, it, nitems, cus, s); break;
+        case 2: pass_batched_ks<T, 2, MODE>(args, nstrips, it, nitems, cus, s); break;
+        case 3: pass_batched_ks<T, 3, MODE>(args, nstrips, it, nitems, cus, s); break;
+        case 4: pass_batched_ks<T, 4, MODE>(args, nstrips, it, nitems, cus, s); break;
+        case 5: pass_batched_ks<T, 5, MODE>(args, nstrips, it, nitems, cus, s); break;
+        case 6: pass_batched_ks<T, 6, MODE>(args, nstrips, it, nitems, cus, s); break;
+        case 7: pass_batched_ks<T, 7, MODE>(args, nstrips, it, nitems, cus, s); break;
+        case 8: pass_batched_ks<T, 8, MODE>(args, nstrips, it, nitems, cus, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_pass_batched(bool f64, int ks, const PassArgs* args, const int32_t* nstrips, const void* items,
-                               int nitems, int grid, hipStream_t s) {
+                               int nitems, int cus, hipStream_t s) {
     const BatchItem* it = (const BatchItem*)items;
-    return f64 ? pass_batched_t<double, 0>(ks, args, nstrips, it, nitems, grid, s)
-               : pass_batched_t<float, 0>(ks, args, nstrips, it, nitems, grid, s);
+    return f64 ? pass_batched_t<double, 0>(ks, args, nstrips, it, nitems, cus, s)
+               : pass_batched_t<float, 0>(ks, args, nstrips, it, nitems, cus, s);
 }
 
 hipError_t launch_theta_pass_batched(bool f64, int ks, const PassArgs* args, const int32_t* nstrips, const void* items,
-                                     int nitems, int grid, hipStream_t s) {
+                                     int nitems, int cus, hipStream_t s) {
     const BatchItem* it = (const BatchItem*)items;
-    return f64 ? pass_batched_t<double, 1>(ks, args, nstrips, it, nitems, grid, s)
-               : pass_batched_t<float, 1>(ks, args, nstrips, it, nitems, grid, s);
+    return f64 ? pass_batched_t<double, 1>(ks, args, nstrips, it, nitems, cus, s)
+               : pass_batched_t<float, 1>(ks, args, nstrips, it, nitems, cus, s);
 }
 
 hipError_t launch_reduce_batched(bool f64, int G, const ReduceArgs* args, const void* blocks, const int32_t* nblk,
