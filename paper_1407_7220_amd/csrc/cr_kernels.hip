@@ -104,7 +104,7 @@ __device__ void lazy_operands(const PassArgs& a, const int strip, const int chun
     }
     double jv = 0.0, jb = 0.0, jp = 0.0;
     if (vj) { jv = vy[j]; jb = ybar[j]; jp = y1in[j]; }
-    constexpr int RB = 2;
+    constexpr int RB = 3;      // rows per thread loaded with the first batch (768-row chunks in one round trip)
     double rv[RB], rb[RB], rp[RB], ro[RB];
 #pragma unroll
     for (int e = 0; e < RB; ++e) {
@@ -355,29 +355,23 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
 
         Ops::colsums(cacc, W, xop);
 
-        // row sums over this workgroup's columns (16-lane DPP reduction)
-        T rs[4];
+        // row sums over this workgroup's columns: the TW j-tiles in the lane,
+        // then the 16 lanes of the row group by exchange (lane c ends with row
+        // orow(g, c >> 2))
+        T rs4[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             T s = W[0][v];
 #pragma unroll
             for (int t = 1; t < TW; ++t) s += W[t][v];
-            rs[v] = row16_sum(s);
+            rs4[v] = s;
         }
-        if (c == 0) {
+        const T rsum = row16_sum4(rs4, c);
+        if ((c & 3) == 0) {
             // staged in LDS (no global store inside the tile loop, so that the
             // prefetched loads stay in flight across iterations); written once
             // per workgroup after the loop
-            T* dst = srow + (i0 - I0);
-            if (Ops::RM4 && sizeof(T) == 4) {
-                V16<T> o;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) o.v[e] = rs[e];
-                st16(dst + 4 * g, o);
-            } else {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) dst[orow<Ops>(g, v)] = rs[v];
-            }
+            srow[(i0 - I0) + orow<Ops>(g, c >> 2)] = rsum;
         }
     };
 

@@ -60,6 +60,27 @@ __device__ __forceinline__ T row16_sum(T v) {
     return v;
 }
 
+// Sums over each 16-lane row of the wave of four values at once, by exchange:
+// at each step a lane keeps half of its values and adds its partner's
+// copies of them (partners 15 - c, then the mirror within 8 lanes, then the
+// quad pairs), so after four steps lane c of the row holds the total of value
+// s[c >> 2] (lanes 0, 4, 8, 12 hold values 0, 1, 2, 3).  27 instructions in
+// FP64 and 11 in FP32 instead of 48 and 16 for four separate sums.
+template <typename T>
+__device__ __forceinline__ T row16_sum4(const T s[4], int c) {
+    const bool hi8 = c >= 8, hi4 = (c & 4) != 0;
+    T k0 = hi8 ? s[2] : s[0], k1 = hi8 ? s[3] : s[1];
+    const T p0 = hi8 ? s[0] : s[2], p1 = hi8 ? s[1] : s[3];
+    k0 += dpp_f<0x140>(p0);
+    k1 += dpp_f<0x140>(p1);
+    T k = hi4 ? k1 : k0;
+    const T p = hi4 ? k0 : k1;
+    k += dpp_f<0x141>(p);
+    k += dpp_f<0xB1>(k);
+    k += dpp_f<0x4E>(k);
+    return k;
+}
+
 template <typename T>
 __device__ __forceinline__ V16<T> ld16(const T* p) { return *reinterpret_cast<const V16<T>*>(p); }
 template <typename T>
