@@ -29,7 +29,7 @@ if __package__ in (None, ""):
 else:
     from . import Context, Params, F64, F32, MIXED_BF16
 
-CANDIDATES = (128, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096)
+CANDIDATES = (128, 256, 384, 512, 640, 768, 896, 1024, 1536, 2048, 2560, 3072, 4096)
 _PREC = {F64: "f64", F32: "f32", MIXED_BF16: "mixed_bf16"}
 
 

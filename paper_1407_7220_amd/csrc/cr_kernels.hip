@@ -539,10 +539,11 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
     }
     // Every load of this point first, so that they are in flight together.
     // Lane k sums the strips k, k + G, ... and (k < n + 1) column k over the
-    // chunks, each in index order.  Buffer views of 8 strips x G (16 chunks)
+    // chunks, each in index order.  Buffer views of 12 strips x G (16 chunks)
     // per batch, based at the wave's first point: entries past the last strip
-    // (chunk) read as zeros, so there is no per-entry branch.
-    constexpr int URS = 8, UCK = 16;
+    // (chunk) read as zeros, so there is no per-entry branch.  One batch covers
+    // 192 strips at G = 16 (N up to 6144 in FP64, 12288 otherwise).
+    constexpr int URS = 12, UCK = 16;
     const int p = (threadIdx.x & 63) / G;
     const int64_t j0 = __builtin_amdgcn_readfirstlane((int)(j - p));   // the same in every lane of the wave
     const uint32_t rvo = ((uint32_t)k * (uint32_t)a.Nrow + (uint32_t)p) * (uint32_t)sizeof(T);

@@ -97,6 +97,47 @@ def _check_layout(N, n, prec, tile_rows):
             assert (y_off[vm] + ext <= y_view).all() and (y_off[~vm] >= y_view).all()
 
 
+def _check_reduce_views(N, n, prec, tile_rows):
+    """The reduce kernel's views of the row partials (strip-major, strips x Nrow)
+    and column partials (chunks x ld x (n + 1)): batches of 12 strips x G and
+    16 chunks, based at the wave's first point; every offset of a batch fits 32
+    bits and entries of existing strips (chunks) lie inside the view."""
+    cr = _cr()
+    L = cr.pass_layout(N, n, cr.Params(precision=prec, tile_rows=tile_rows))
+    esz = 8 if prec == 0 else 4
+    G = 16 if n + 1 <= 16 else 32
+    URS, UCK = 12, 16
+    Nrow, ld, strips, chunks, nc = L["Nrow"], L["ld"], L["strips"], L["chunks"], n + 1
+    k = np.arange(G)
+    for p in (0, 64 // G - 1):
+        rvo = (k * Nrow + p) * esz
+        rso = G * Nrow * esz
+        cvo = (p * nc + k) * esz
+        cso = ld * nc * esz
+        e_r = np.arange(URS)[:, None]
+        e_c = np.arange(UCK)[:, None]
+        assert (rvo[None, :] + e_r * rso + esz < U32).all()
+        assert (cvo[None, :] + e_c * cso + esz < U32).all()
+        for s0 in range(0, strips, G * URS):
+            view = min((strips - s0) * Nrow * esz, U32 - 1)
+            strip = s0 + k[None, :] + G * e_r
+            off = rvo[None, :] + e_r * rso
+            assert (off[strip < strips] + esz <= view).all()
+        for h0 in range(0, chunks, UCK):
+            view = min((chunks - h0) * ld * nc * esz, U32 - 1)
+            chunk = h0 + e_c + 0 * k[None, :]
+            off = cvo[None, :] + e_c * cso
+            assert (off[(chunk < chunks) & (k[None, :] < nc)] + esz <= view).all()
+
+
+def test_reduce_views():
+    for prec in (0, 1):
+        for n in (1, 10, 20, 31):
+            for N in (37, 5000, 20000, 65536, 1 << 20):
+                for tr in (0, 64, 4096):
+                    _check_reduce_views(N, n, prec, tr)
+
+
 CASES = [(N, n, prec, tr)
          for prec in (0, 1, 2)
          for n in (1, 3, 10, 20, 31)
