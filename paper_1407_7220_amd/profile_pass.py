@@ -17,6 +17,9 @@ for scaling hardware byte counters.  Run it under rocprofv3, e.g.
                   (N_p ~ U{500..8000}, n_p in {5, 10, 20}) with the tuned
                   tile heights, a fixed schedule of 1 x --reps MAPG steps per
                   problem after one untimed run;
+--kernel solve    one fixed-schedule solve (2 ALCC iterations of --reps MAPG
+                  steps) in the benchmark's launch configuration: the MAPG
+                  iteration's kernels (lazy pass, reduce) and the multiplier step's;
 --kernel papg     P-APG runs (cr_papg: k_papg_lin, k_papg_step2 and the batched
                   block solves) on the Sec. III study problem at N = 4096,
                   n = 5, K = 4, FP32 blocks of 4 x 40 MAPG steps, --reps
@@ -34,7 +37,7 @@ if ROOT not in sys.path:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--kernel", choices=("pass", "adjoint", "eval", "papg", "batched"), default="pass")
+    ap.add_argument("--kernel", choices=("pass", "adjoint", "eval", "papg", "batched", "solve"), default="pass")
     ap.add_argument("--workload", default=None)
     ap.add_argument("--precision", choices=("f32", "f64", "mixed_bf16"), default="f32")
     ap.add_argument("--reps", type=int, default=20)
@@ -69,7 +72,7 @@ def main():
               % (pairs_per_it, args.reps, secs / args.reps * 1e3), flush=True)
         return
     workload = args.workload or {"pass": "logsumexp_5000", "adjoint": "quadratic_10000",
-                                 "eval": "maxaffine_20000"}[args.kernel]
+                                 "eval": "maxaffine_20000", "solve": "logsumexp_5000"}[args.kernel]
     p = synth.workload(workload)
     if args.kernel == "eval":
         Q = torch.from_numpy(synth.query_points(p.N, p.n)).cuda()
@@ -90,6 +93,13 @@ def main():
     yb = torch.from_numpy(p.ybar).cuda()
     tile = autotune.tile_rows_for(X, yb, prec, tune_if_missing=False)
     esz = 8 if prec == cr.F64 else 4
+    if args.kernel == "solve":
+        ctx = cr.Context(X, yb, cr.Params(precision=prec, tile_rows=tile, inner_iters=args.reps, max_outer=2))
+        ctx.run()
+        _, _, info = ctx.run()
+        print("workload %s N=%d n=%d precision %s tile_rows %d: 2 x %d MAPG iterations, %.3f us each"
+              % (workload, p.N, p.n, args.precision, tile, args.reps, info.seconds / info.inner_iters * 1e6), flush=True)
+        return
     if args.kernel == "pass":
         ctx = cr.Context(X, yb, cr.Params(precision=prec, tile_rows=tile))
         ms = ctx.time_pass(args.reps)
