@@ -353,6 +353,25 @@ def test_adaptive_reaches_kkt(cr, prec):
     assert rel(host(y), ref.y) < 1e-3
 
 
+def test_mixed_adaptive_against_fp64_at_the_same_kkt(cr):
+    """The mixed BF16 form solved to KKT <= 1e-4 at n = 20 (the mixed form's
+    dimension), against the FP64 form solved to the same tolerance and to
+    1e-7: both land within the KKT-level distance of the optimum."""
+    p = synth.max_affine_uniform(1500, 20, 50, 0.1, seed=3)
+    say("adaptive mixed vs f64 N=1500 n=20 maxaffine seed 3")
+    X, yb = dev(p.X), dev(p.ybar)
+    ym, xim, im = cr.solve(X, yb, cr.Params(precision=2, kkt_tol=1e-4))
+    yd, xid, idd = cr.solve(X, yb, cr.Params(precision=0, kkt_tol=1e-4))
+    yt, xit, it = cr.solve(X, yb, cr.Params(precision=0, kkt_tol=1e-7, max_outer=40))
+    say("  KKT mixed %.2e (%d MAPG), f64 %.2e (%d MAPG), tight f64 %.2e" % (im.kkt, im.inner_iters, idd.kkt,
+                                                                          idd.inner_iters, it.kkt))
+    assert im.status == 0 and im.kkt <= 1e-4 and idd.status == 0
+    em, ed = rel(host(ym), host(yt)), rel(host(yd), host(yt))
+    exm, exd = rel(host(xim), host(xit)), rel(host(xid), host(xit))
+    say("  distance to the tight solution: mixed y %.2e xi %.2e, f64 y %.2e xi %.2e" % (em, exm, ed, exd))
+    assert em < 1e-3 and ed < 1e-3 and exm < 1e-2 and exd < 1e-2
+
+
 @pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "mixed"])
 def test_full_size_pass_sampled(cr, prec):
     """One gradient pass at the 5000-point, n=10 workload, in the launch
