@@ -109,6 +109,7 @@ struct LazyStep {
     double* spart;            // chunks + strips stopping-test pieces
     const OuterArgs* oa;
     DevState* st;
+    const double* shift;      // slope shift c (N x n, null: none): column operands from xi2 + c
 };
 
 struct PassArgs {
@@ -225,6 +226,9 @@ hipError_t launch_mapg_end(const double* blockpart, int nblk, int64_t launched, 
 // After a run of lazy passes: y1_it (xi1_it) into y1p[0] (xi1p[0]); if the run
 // ended at l^max with no pass after the last step, that step's projection.
 hipError_t launch_mapg_finish(const LazyStep& lz, int64_t N, hipStream_t s, const int32_t* gate = nullptr);
+// The same over the problems of a batch whose multiplier step is due (lazy
+// gradient-pass table `args`, block table of G lanes per point).
+hipError_t launch_mapg_finish_batched(int G, const PassArgs* args, const void* blocks, int nblocks, hipStream_t s);
 // Device schedule (AlccSched): start of a run (first ALCC iteration begun),
 // end of a graph replay of `iters` MAPG iterations (the run is over once MAPG
 // stopped or l^max iterations ran: the multiplier step becomes due), and the
@@ -249,7 +253,7 @@ hipError_t launch_mapg_end_batched(const double* const* blockparts, const int32_
 hipError_t launch_set_point_batched(bool f64, int G, const PointArgs* args, const void* blocks, const int32_t* nblk,
                                     int nblocks, hipStream_t strm);
 hipError_t launch_theta_pass_batched(bool f64, int ks, const PassArgs* args, const int32_t* nstrips,
-                                     const void* items, int nitems, int cus, hipStream_t strm);
+                                     const void* items, int nitems, hipStream_t strm);
 // Largest rows per chunk for which a lazy pass's LDS (row sums, y operands and
 // staged column operands) fits the pass workgroup's 32 KiB area.
 bool lazy_fits(int prec, int64_t rows_per_chunk);
@@ -304,10 +308,11 @@ hipError_t launch_papg_power(const PapgArgs& a, double* vy, double* vxi, const d
 int reduce_blocks(int64_t N, int n);
 int reduce_blocks_g(int64_t N, int G);
 // Batched form (plain precisions): see cr_batch.hip.
-// One persistent pass per operand class ks = ceil((n + 1) / 4) over that class's
-// items; the grid is sized from the compute-unit count `cus`.
+// One pass per operand class ks = ceil((n + 1) / 4), one workgroup per item of
+// that class.  lazy: the passes complete the previous MAPG step (LazyStep of
+// each table entry) at replay position q.
 hipError_t launch_pass_batched(bool f64, int ks, const PassArgs* args, const int32_t* nstrips, const void* items,
-                               int nitems, int cus, hipStream_t s);
+                               int nitems, hipStream_t s, bool lazy = false, int q = 0);
 hipError_t launch_reduce_batched(bool f64, int G, const ReduceArgs* args, const void* blocks, const int32_t* nblk,
                                  int nblocks, int q, hipStream_t s);
 hipError_t launch_update_batched(bool f64, int G, const UpdateArgs* args, const void* blocks, const int32_t* nblk,

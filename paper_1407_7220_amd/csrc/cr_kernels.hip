@@ -57,11 +57,11 @@ template <typename Ops> struct LazyShape {
 template <typename Ops>
 __device__ void lazy_operands(const PassArgs& a, const int strip, const int chunk, const int64_t I0, const int64_t I1,
                               const int64_t J0, char* __restrict__ lds, typename Ops::elem* __restrict__ ylds,
-                              typename Ops::Breg& breg, const int g, const int c, double* stop) {
+                              typename Ops::Breg& breg, const int g, const int c, double* stop, const int lq) {
     typedef typename Ops::elem T;
     typedef LazyShape<Ops> S;
     const LazyStep& z = a.lz;
-    const int64_t l = z.lfix > 0 ? (int64_t)z.lfix : z.st->base + z.q + 1;
+    const int64_t l = z.lfix > 0 ? (int64_t)z.lfix : z.st->base + lq + 1;
     const int rows = (int)(I1 - I0);
     if (l <= 1) {
         // first iteration of the run: the operands k_set_point wrote
@@ -128,6 +128,7 @@ __device__ void lazy_operands(const PassArgs& a, const int strip, const int chun
     double dy = 0.0, dx = 0.0;
 
     // columns: -xi2_jk, and c_j = x_j^T xi2_j - y2_j from the PT threads' products
+    // (with a slope shift, both from the constraint slope xi2 + c)
     T* Bs = reinterpret_cast<T*>(lds + 2 * lazy_rbytes(rows, (int)sizeof(T)));
     T* brow = Bs + jj * kBsStride;
     double prod = 0.0;
@@ -137,8 +138,9 @@ __device__ void lazy_operands(const PassArgs& a, const int strip, const int chun
         if (k < n) {
             const double x1 = px ? sx * cv[e] : cv[e];          // projection onto Q_xi
             const double x2n = x1 + beta * (x1 - cp[e]);        // extrapolation
-            prod += cx[e] * x2n;
-            brow[k] = vj ? (T)(-x2n) : (T)0;
+            const double xo = z.shift && vj ? x2n + z.shift[j * n + k] : x2n;
+            prod += cx[e] * xo;
+            brow[k] = vj ? (T)(-xo) : (T)0;
             if (wcols && vj) {
                 const int64_t q = j * n + k;
                 dx += (x1 - co[e]) * (x1 - co[e]);
@@ -195,9 +197,10 @@ __device__ void lazy_operands(const PassArgs& a, const int strip, const int chun
     Ops::load_breg_lds(breg, Bs, Ops::TW * c, g, n);
 }
 
+// lq: replay position of a lazy gradient pass (LazyStep).
 template <typename Ops, int THETA_MODE, int LAZY = 0>
 __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chunk, const int nstrips,
-                               char* __restrict__ lds) {
+                               char* __restrict__ lds, const int lq) {
     typedef typename Ops::elem T;
     typedef typename Ops::acc_t acc_t;
     constexpr int TW = Ops::TW;
@@ -386,7 +389,7 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
         // one tile in flight during the operand set-up (more would spill)
         load_tile(0, xs[0], ys[0], ts[0]);
         __builtin_amdgcn_sched_barrier(0);
-        lazy_operands<Ops>(a, strip, chunk, I0, I1, J0, lds, ylds, breg, g, c, stop);
+        lazy_operands<Ops>(a, strip, chunk, I0, I1, J0, lds, ylds, breg, g, c, stop, lq);
 #pragma unroll
         for (int b = 1; b < NSET; ++b) {
             load_tile(b, xs[b], ys[b], ts[b]);
@@ -413,7 +416,7 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
     // rowpart[strip][i] of this chunk's rows, from the LDS staging area
     __syncthreads();
     if constexpr (LAZY) {
-        const int64_t l = a.lz.lfix > 0 ? (int64_t)a.lz.lfix : a.lz.st->base + a.lz.q + 1;
+        const int64_t l = a.lz.lfix > 0 ? (int64_t)a.lz.lfix : a.lz.st->base + lq + 1;
         if (threadIdx.x == 0 && l > 1 && (strip == 0 || chunk == 0)) {
             double sy2 = stop[0], sx2 = stop[kWaves];
             for (int w = 1; w < kWaves; ++w) { sy2 += stop[w]; sx2 += stop[kWaves + w]; }
@@ -473,25 +476,25 @@ template <typename Ops, int THETA_MODE, int WAVES, int LAZY = 0>
 __global__ __launch_bounds__(kBlock, WAVES) void k_pair_pass(PassArgs a) {
     if (*a.active == 0) return;
     __shared__ __align__(16) char lds[kPassLds];
-    pair_pass_item<Ops, THETA_MODE, LAZY>(a, blockIdx.x, blockIdx.y, gridDim.x, lds);
+    pair_pass_item<Ops, THETA_MODE, LAZY>(a, blockIdx.x, blockIdx.y, gridDim.x, lds, a.lz.q);
 }
 
-// Batched pass: a persistent grid walks the (problem, strip, chunk) items of
-// every problem in a fixed round-robin order, skipping problems whose MAPG has
-// stopped.  Each item is one workgroup tile of the single-problem pass.
+// Batched pass: workgroup b takes item b of the (problem, strip, chunk) list
+// and returns at once when that problem's MAPG has stopped.  Each item is one
+// workgroup tile of the single-problem pass; LAZY gradient passes complete
+// each problem's previous MAPG step (LazyStep of its table entry, replay
+// position q).  (A persistent grid walking the items held some 20-40 more
+// VGPRs per lane across its item loop, which cost a wave per SIMD.)
 struct BatchItem { int32_t p, strip, chunk, pad; };
 
-template <typename T, int KS, int THETA_MODE, int WAVES>
+template <typename T, int KS, int THETA_MODE, int WAVES, int LAZY = 0>
 __global__ __launch_bounds__(kBlock, WAVES) void k_pair_pass_batched(const PassArgs* args, const int32_t* nstrips_of_p,
-                                                              const BatchItem* items, int nitems) {
+                                                              const BatchItem* items, int q) {
     __shared__ __align__(16) char lds[kPassLds];
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const BatchItem item = items[it];
-        const PassArgs& a = args[item.p];
-        if (*a.active == 0) continue;
-        pair_pass_item<PlainOps<T, KS>, THETA_MODE>(a, item.strip, item.chunk, nstrips_of_p[item.p], lds);
-        __syncthreads();   // the next item reuses this workgroup's LDS
-    }
+    const BatchItem item = items[blockIdx.x];
+    const PassArgs& a = args[item.p];
+    if (*a.active == 0) return;
+    pair_pass_item<PlainOps<T, KS>, THETA_MODE, LAZY>(a, item.strip, item.chunk, nstrips_of_p[item.p], lds, q);
 }
 
 // A group of G lanes (G >= n + 1, a power of two dividing 64) owns one point j:
@@ -836,11 +839,10 @@ __global__ __launch_bounds__(kBlock) void k_mapg_end(const double* blockpart, in
 // goes to y1p[0] / xi1p[0].  `active` is read here and cleared afterwards by
 // k_mapg_end.
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_mapg_finish(LazyStep z, int64_t N, const int32_t* gate) {
-    if (gate && *gate == 0) return;
+__device__ void mapg_finish_block(const LazyStep& z, const int64_t N, const int blk) {
     constexpr int PER = kBlock / G;
     const int k = threadIdx.x % G;
-    const int64_t j = (int64_t)blockIdx.x * PER + threadIdx.x / G;
+    const int64_t j = (int64_t)blk * PER + threadIdx.x / G;
     const int n = z.n;
     const bool valid = j < N;
     const DevState* st = z.st;
@@ -861,6 +863,22 @@ __global__ __launch_bounds__(kBlock) void k_mapg_finish(LazyStep z, int64_t N, c
         if (valid && k == n) z.y1p[0][j] = z.y1p[1][j];
         else if (valid && k < n) z.xi1p[0][j * n + k] = z.xi1p[1][j * n + k];
     }
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_mapg_finish(LazyStep z, int64_t N, const int32_t* gate) {
+    if (gate && *gate == 0) return;
+    mapg_finish_block<G>(z, N, blockIdx.x);
+}
+
+// Batched: block b is local block blocks[b].y of problem blocks[b].x, run only
+// when that problem's multiplier step is due.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_mapg_finish_batched(const PassArgs* args, const int2* blocks) {
+    const int2 bp = blocks[blockIdx.x];
+    const LazyStep& z = args[bp.x].lz;
+    if (z.st->step_due == 0) return;
+    mapg_finish_block<G>(z, args[bp.x].N, bp.y);
 }
 
 // Set the point of the next pass (and optionally restart MAPG there):
@@ -1507,45 +1525,58 @@ hipError_t launch_mapg_finish(const LazyStep& z, int64_t N, hipStream_t s, const
 }
 int reduce_blocks_g(int64_t N, int G) { return (int)points_grid(N, G).x; }
 
-// The persistent grid holds as many workgroups as the class's register budget
-// lets each CU keep resident (WAVES per SIMD, the single-problem pass's
-// figure), so every item a workgroup takes starts at once.
-template <typename T, int KS, int MODE>
-static void pass_batched_ks(const PassArgs* args, const int32_t* nstrips, const BatchItem* it, int nitems, int cus,
-                            hipStream_t s) {
-    constexpr int W = MODE == 1 ? 2 : (sizeof(T) == 4 && KS <= 2 ? 4 : (KS <= 4 ? 3 : 2));
-    const int grid = std::max(1, std::min(nitems, W * cus));
-    hipLaunchKernelGGL((k_pair_pass_batched<T, KS, MODE, W>), dim3(grid), dim3(kBlock), 0, s, args, nstrips, it, nitems);
+hipError_t launch_mapg_finish_batched(int G, const PassArgs* args, const void* blocks, int nblocks, hipStream_t s) {
+    const int2* b = (const int2*)blocks;
+    if (G == 16) hipLaunchKernelGGL((k_mapg_finish_batched<16>), dim3(nblocks), dim3(kBlock), 0, s, args, b);
+    else hipLaunchKernelGGL((k_mapg_finish_batched<32>), dim3(nblocks), dim3(kBlock), 0, s, args, b);
+    return hipGetLastError();
 }
-template <typename T, int MODE>
+
+// One workgroup per item.  WAVES: the waves per SIMD the class's register
+// budget allows without spills (the single-problem pass's figures; the lazy
+// FP32 KS = 3 class takes one less).
+template <typename T, int KS, int MODE, int LAZY>
+static void pass_batched_ks(const PassArgs* args, const int32_t* nstrips, const BatchItem* it, int nitems, int q,
+                            hipStream_t s) {
+    constexpr int W = MODE == 1 ? 2
+                    : sizeof(T) == 4 ? (KS <= 2 ? 4 : KS == 3 ? (LAZY ? 3 : 4) : KS == 4 ? 3 : 2)
+                                     : (KS <= 4 ? 3 : 2);
+    if (nitems < 1) return;
+    hipLaunchKernelGGL((k_pair_pass_batched<T, KS, MODE, W, LAZY>), dim3(nitems), dim3(kBlock), 0, s, args, nstrips, it,
+                       q);
+}
+template <typename T, int MODE, int LAZY>
 static hipError_t pass_batched_t(int ks, const PassArgs* args, const int32_t* nstrips, const BatchItem* it,
-                                 int nitems, int cus, hipStream_t s) {
+                                 int nitems, int q, hipStream_t s) {
     switch (ks) {
-        case 1: pass_batched_ks<T, 1, MODE>(args, nstrips, it, nitems, cus, s); break;
-        case 2: pass_batched_ks<T, 2, MODE>(args, nstrips, it, nitems, cus, s); break;
-        case 3: pass_batched_ks<T, 3, MODE>(args, nstrips, it, nitems, cus, s); break;
-        case 4: pass_batched_ks<T, 4, MODE>(args, nstrips, it, nitems, cus, s); break;
-        case 5: pass_batched_ks<T, 5, MODE>(args, nstrips, it, nitems, cus, s); break;
-        case 6: pass_batched_ks<T, 6, MODE>(args, nstrips, it, nitems, cus, s); break;
-        case 7: pass_batched_ks<T, 7, MODE>(args, nstrips, it, nitems, cus, s); break;
-        case 8: pass_batched_ks<T, 8, MODE>(args, nstrips, it, nitems, cus, s); break;
+        case 1: pass_batched_ks<T, 1, MODE, LAZY>(args, nstrips, it, nitems, q, s); break;
+        case 2: pass_batched_ks<T, 2, MODE, LAZY>(args, nstrips, it, nitems, q, s); break;
+        case 3: pass_batched_ks<T, 3, MODE, LAZY>(args, nstrips, it, nitems, q, s); break;
+        case 4: pass_batched_ks<T, 4, MODE, LAZY>(args, nstrips, it, nitems, q, s); break;
+        case 5: pass_batched_ks<T, 5, MODE, LAZY>(args, nstrips, it, nitems, q, s); break;
+        case 6: pass_batched_ks<T, 6, MODE, LAZY>(args, nstrips, it, nitems, q, s); break;
+        case 7: pass_batched_ks<T, 7, MODE, LAZY>(args, nstrips, it, nitems, q, s); break;
+        case 8: pass_batched_ks<T, 8, MODE, LAZY>(args, nstrips, it, nitems, q, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_pass_batched(bool f64, int ks, const PassArgs* args, const int32_t* nstrips, const void* items,
-                               int nitems, int cus, hipStream_t s) {
+                               int nitems, hipStream_t s, bool lazy, int q) {
     const BatchItem* it = (const BatchItem*)items;
-    return f64 ? pass_batched_t<double, 0>(ks, args, nstrips, it, nitems, cus, s)
-               : pass_batched_t<float, 0>(ks, args, nstrips, it, nitems, cus, s);
+    if (lazy)
+        return f64 ? pass_batched_t<double, 0, 1>(ks, args, nstrips, it, nitems, q, s)
+                   : pass_batched_t<float, 0, 1>(ks, args, nstrips, it, nitems, q, s);
+    return f64 ? pass_batched_t<double, 0, 0>(ks, args, nstrips, it, nitems, q, s)
+               : pass_batched_t<float, 0, 0>(ks, args, nstrips, it, nitems, q, s);
 }
 
 hipError_t launch_theta_pass_batched(bool f64, int ks, const PassArgs* args, const int32_t* nstrips, const void* items,
-                                     int nitems, int cus, hipStream_t s) {
+                                     int nitems, hipStream_t s) {
     const BatchItem* it = (const BatchItem*)items;
-    return f64 ? pass_batched_t<double, 1>(ks, args, nstrips, it, nitems, cus, s)
-               : pass_batched_t<float, 1>(ks, args, nstrips, it, nitems, cus, s);
+    return f64 ? pass_batched_t<double, 1, 0>(ks, args, nstrips, it, nitems, 0, s)
+               : pass_batched_t<float, 1, 0>(ks, args, nstrips, it, nitems, 0, s);
 }
 
 hipError_t launch_reduce_batched(bool f64, int G, const ReduceArgs* args, const void* blocks, const int32_t* nblk,
