@@ -62,9 +62,9 @@ Layout make_layout(int64_t N, int n, const cr_params& prm, int tile_rows) {
     size_t xp_bytes = (size_t)(L.Nrow / 16) * 64 * L.qp * L.esz;
     size_t xiaug_bytes = (size_t)L.ld * L.kp * L.esz;
     if (precision == CR_MIXED_BF16) {
-        // BF16 operand slots: kp per column, (KB + 2 NKB) 16-byte vectors per lane and tile
+        // BF16 operand slots: kp per column, (KB + NKB) 16-byte vectors per lane and tile
         L.kp = 32 * cr::mixed_kb(n);
-        L.qp = cr::mixed_kb(n) + 2 * ((n + 1 + 15) / 16);
+        L.qp = cr::mixed_kb(n) + (n + 1 + 15) / 16;
         xp_bytes = (size_t)(L.Nrow / 16) * 64 * L.qp * 16;
         xiaug_bytes = (size_t)L.ld * L.kp * 2;
     }

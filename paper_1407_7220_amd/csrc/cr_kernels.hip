@@ -1133,7 +1133,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_xp_mixed(const double* X, int64
     if (gid >= (Nrow / 16) * 64) return;
     const int64_t i0 = (gid / 64) * 16;
     const int lane = (int)(gid % 64), g = lane >> 4, c = lane & 15;
-    bf16x8* out = xp + gid * (kb_r + 2 * nkb);
+    bf16x8* out = xp + gid * (kb_r + nkb);
     for (int kb = 0; kb < kb_r; ++kb) {
         bf16x8 v;
         for (int e = 0; e < 8; ++e) {
@@ -1144,16 +1144,16 @@ __global__ __launch_bounds__(kBlock) void k_prep_xp_mixed(const double* X, int64
         }
         out[kb] = v;
     }
+    // column blocks: [x_hi, x_lo] of the lane's rows 4g .. 4g + 3 at feature 16 kb + c
     for (int kb = 0; kb < nkb; ++kb) {
-        bf16x8 v1, v2;
+        bf16x8 v;
         for (int e = 0; e < 4; ++e) {
             __bf16 hi, lo;
             bf16_split((float)xaug_at(X, N, n, i0 + 4 * g + e, 16 * kb + c), hi, lo);
-            v1[e] = hi; v1[e + 4] = hi;
-            v2[e] = lo; v2[e + 4] = (__bf16)0.0f;
+            v[e] = hi;
+            v[e + 4] = lo;
         }
-        out[kb_r + 2 * kb] = v1;
-        out[kb_r + 2 * kb + 1] = v2;
+        out[kb_r + kb] = v;
     }
 }
 

@@ -282,8 +282,11 @@ template <typename T, int KS, int NSET_ = 0> struct PlainOps {
 // Mixed: BF16 16x16x32 MFMA on hi/lo splits with FP32 accumulation; theta,
 // W and the accumulators are FP32.  R: K-slots [x_hi | x_lo | x_hi] against
 // [-xi_hi | -xi_hi | -xi_lo] (K = 3n, KB blocks of 32), accumulator started
-// at y_i + c_j in FP32.  C: [W_hi(4 rows), W_lo(4 rows)] . [X_hi, X_hi] plus
-// [W_hi, 0] . [X_lo, 0].
+// at y_i + c_j in FP32.  C: [W_hi, W_hi] . [X_hi, X_lo] plus
+// [W_lo, W_lo] . [X_hi, X_lo] over the lane's 4 rows (all four products of
+// the splits), so one 16-byte X operand per column block serves both.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
 template <int KB, int NKB_> struct MixedOps {
     typedef float elem;
     typedef f32x4 acc_t;
@@ -292,7 +295,7 @@ template <int KB, int NKB_> struct MixedOps {
     static constexpr int NSET = KB + NKB <= 2 ? 3 : 2;
     static constexpr int RM4 = 1;
     struct Breg { bf16x8 b[KB][TW]; float cc[TW]; };
-    struct Xop { bf16x8 r[KB]; bf16x8 c1[NKB]; bf16x8 c2[NKB]; };
+    struct Xop { bf16x8 r[KB]; bf16x8 cx[NKB]; };
     static __device__ void load_breg(Breg& B, const PassArgs& a, int64_t jl, int g) {
         const __bf16* xb = (const __bf16*)a.xiaug;
 #pragma unroll
@@ -330,21 +333,19 @@ template <int KB, int NKB_> struct MixedOps {
         }
     }
     static __device__ void load_xop(Xop& X, const PassArgs& a, int64_t i0, int lane) {
-        const bf16x8* xp = (const bf16x8*)a.xp + ((i0 >> 4) * 64 + lane) * (KB + 2 * NKB);
+        const bf16x8* xp = (const bf16x8*)a.xp + ((i0 >> 4) * 64 + lane) * (KB + NKB);
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) X.r[kb] = xp[kb];
 #pragma unroll
-        for (int kb = 0; kb < NKB; ++kb) { X.c1[kb] = xp[KB + 2 * kb]; X.c2[kb] = xp[KB + 2 * kb + 1]; }
+        for (int kb = 0; kb < NKB; ++kb) X.cx[kb] = xp[KB + kb];
     }
-    static constexpr int XPB = (KB + 2 * NKB) * 16;
+    static constexpr int XPB = (KB + NKB) * 16;
     static __device__ void load_xop_b(Xop& X, rsrc_t r, uint32_t voff, uint32_t soff) {
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) X.r[kb] = __builtin_bit_cast(bf16x8, bld16<float>(r, voff + 16 * kb, soff));
 #pragma unroll
-        for (int kb = 0; kb < NKB; ++kb) {
-            X.c1[kb] = __builtin_bit_cast(bf16x8, bld16<float>(r, voff + 16 * (KB + 2 * kb), soff));
-            X.c2[kb] = __builtin_bit_cast(bf16x8, bld16<float>(r, voff + 16 * (KB + 2 * kb + 1), soff));
-        }
+        for (int kb = 0; kb < NKB; ++kb)
+            X.cx[kb] = __builtin_bit_cast(bf16x8, bld16<float>(r, voff + 16 * (KB + kb), soff));
     }
     static __device__ void residual(acc_t R[TW], const Xop& X, const Breg& B, const float yv[4]) {
 #pragma unroll
@@ -354,22 +355,30 @@ template <int KB, int NKB_> struct MixedOps {
             for (int kb = 0; kb < KB; ++kb) R[t] = mfma_bf16(X.r[kb], B.b[kb][t], R[t]);
         }
     }
+    // Split of four FP32 values into packed BF16 pairs: hi = RNE(w), lo =
+    // RNE(w - hi) (w - hi is exact in FP32; hi read back from its bits).
+    static __device__ __forceinline__ void split4(const float w[4], unsigned int h[2], unsigned int l[2]) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const bf16x2 hb = {(__bf16)w[2 * p], (__bf16)w[2 * p + 1]};
+            const unsigned int u = __builtin_bit_cast(unsigned int, hb);
+            const float h0 = __builtin_bit_cast(float, u << 16), h1 = __builtin_bit_cast(float, u & 0xffff0000u);
+            const bf16x2 lb = {(__bf16)(w[2 * p] - h0), (__bf16)(w[2 * p + 1] - h1)};
+            h[p] = u;
+            l[p] = __builtin_bit_cast(unsigned int, lb);
+        }
+    }
     static __device__ void colsums(acc_t C[TW][NKB], const float W[TW][4], const Xop& X) {
 #pragma unroll
         for (int t = 0; t < TW; ++t) {
-            bf16x8 w1, w2;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const __bf16 hi = (__bf16)W[t][v];
-                w1[v] = hi;
-                w1[v + 4] = (__bf16)(W[t][v] - (float)hi);
-                w2[v] = hi;
-                w2[v + 4] = (__bf16)0.0f;
-            }
+            unsigned int h[2], l[2];
+            split4(W[t], h, l);
+            const bf16x8 wh = __builtin_bit_cast(bf16x8, u32x4{h[0], h[1], h[0], h[1]});
+            const bf16x8 wl = __builtin_bit_cast(bf16x8, u32x4{l[0], l[1], l[0], l[1]});
 #pragma unroll
             for (int kb = 0; kb < NKB; ++kb) {
-                C[t][kb] = mfma_bf16(w1, X.c1[kb], C[t][kb]);
-                C[t][kb] = mfma_bf16(w2, X.c2[kb], C[t][kb]);
+                C[t][kb] = mfma_bf16(wh, X.cx[kb], C[t][kb]);
+                C[t][kb] = mfma_bf16(wl, X.cx[kb], C[t][kb]);
             }
         }
     }

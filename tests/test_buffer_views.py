@@ -36,7 +36,7 @@ def _ops(prec, n):
     if prec == 2:
         kb = (3 * n + 31) // 32
         nkb = (n + 1 + 15) // 16
-        return 4, 4, (3 if kb + nkb <= 2 else 2), (kb + 2 * nkb) * 16, "rm4"
+        return 4, 4, (3 if kb + nkb <= 2 else 2), (kb + nkb) * 16, "rm4"
     esz = 8 if prec == 0 else 4
     ks = (n + 1 + 3) // 4
     nkb = 1 if ks <= 4 else 2
