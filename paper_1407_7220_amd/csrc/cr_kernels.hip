@@ -150,8 +150,7 @@ __device__ void lazy_operands(const PassArgs& a, const int strip, const int chun
         }
     }
     for (int k = n + 1 + r0; k < kBsStride; k += S::PT) brow[k] = (T)0;
-#pragma unroll
-    for (int o = S::PT / 2; o > 0; o >>= 1) prod += __shfl_xor(prod, o);
+    prod = lane_group_sum<S::PT>(prod);
     {
         const double y1 = py ? jb + sy * (jv - jb) : jv;
         const double y2j = y1 + beta * (y1 - jp);
@@ -500,13 +499,6 @@ __global__ __launch_bounds__(kBlock, WAVES) void k_pair_pass_batched(const PassA
 // A group of G lanes (G >= n + 1, a power of two dividing 64) owns one point j:
 // lane k < n handles xi_jk, lane n handles y_j; the partial sums of point j are
 // contiguous, so every group reads them with unit stride.
-template <int G>
-__device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
 // Sum (op 0) or max (op 1) of field q of the first `count` 4-double records,
 // by all threads of the block in a fixed order.
 __device__ double block_gather(const double* part, int count, int q, int op) {

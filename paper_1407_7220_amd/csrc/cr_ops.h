@@ -60,6 +60,50 @@ __device__ __forceinline__ T row16_sum(T v) {
     return v;
 }
 
+// Sum over each aligned group of P consecutive lanes (P = 1, 2, 4, 8 or 16),
+// by the first log2(P) steps of row16_sum.
+template <int P, typename T>
+__device__ __forceinline__ T lane_group_sum(T v) {
+    if constexpr (P >= 2) v += dpp_f<0xB1>(v);
+    if constexpr (P >= 4) v += dpp_f<0x4E>(v);
+    if constexpr (P >= 8) v += dpp_f<0x141>(v);
+    if constexpr (P >= 16) v += dpp_f<0x140>(v);
+    return v;
+}
+
+// Rows of a wave pairwise (gfx950 lane swaps, no LDS): with the same value in
+// both operands, v_permlane16_swap returns in every lane the value of the even
+// row and of the odd row of its row pair (SW = 16), v_permlane32_swap those of
+// the lower and upper half (SW = 32); ev and od are the same in both lanes of a
+// pair, so an operation on them gives bit-identical results there.
+template <int SW>
+__device__ __forceinline__ void row_pair(double v, double& ev, double& od) {
+    const long long u = __builtin_bit_cast(long long, v);
+    const int lo = (int)(u & 0xffffffffLL), hi = (int)(u >> 32);
+    if constexpr (SW == 16) {
+        const auto L = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto H = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        ev = __builtin_bit_cast(double, ((long long)H[0] << 32) | (unsigned int)L[0]);
+        od = __builtin_bit_cast(double, ((long long)H[1] << 32) | (unsigned int)L[1]);
+    } else {
+        const auto L = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto H = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        ev = __builtin_bit_cast(double, ((long long)H[0] << 32) | (unsigned int)L[0]);
+        od = __builtin_bit_cast(double, ((long long)H[1] << 32) | (unsigned int)L[1]);
+    }
+}
+
+// Sum over each aligned group of G = 16, 32 or 64 lanes (every lane of the
+// group receives it): DPP within a row, lane swaps across rows.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+    v = row16_sum(v);
+    double e, o;
+    if constexpr (G >= 32) { row_pair<16>(v, e, o); v = e + o; }
+    if constexpr (G >= 64) { row_pair<32>(v, e, o); v = e + o; }
+    return v;
+}
+
 // Sums over each 16-lane row of the wave of four values at once, by exchange:
 // at each step a lane keeps half of its values and adds its partner's
 // copies of them (partners 15 - c, then the mirror within 8 lanes, then the
@@ -113,13 +157,17 @@ template <> __device__ __forceinline__ double bld_t<double>(rsrc_t r, uint32_t v
 // ---------------------------------------------------------------------------
 // Block reductions (256 threads) and the last-arriving-block handshake.
 // ---------------------------------------------------------------------------
-static __device__ __forceinline__ double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
+static __device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); }
 static __device__ __forceinline__ double wave_max(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    return v;
+    v = fmax(v, dpp_f<0xB1>(v));
+    v = fmax(v, dpp_f<0x4E>(v));
+    v = fmax(v, dpp_f<0x141>(v));
+    v = fmax(v, dpp_f<0x140>(v));
+    double e, o;
+    row_pair<16>(v, e, o);
+    v = fmax(e, o);
+    row_pair<32>(v, e, o);
+    return fmax(e, o);
 }
 
 // Sum (op 0) or max (op 1) of one double per thread; result valid in every thread.
