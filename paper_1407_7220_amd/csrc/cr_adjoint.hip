@@ -209,6 +209,74 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_pass(AdjPassArgs a) {
             for (int t = 0; t < TW; ++t) cw[t] += (W[t][0] + W[t][1]) + (W[t][2] + W[t][3]);
         }
 
+        if constexpr (sizeof(T) == 4) {
+            // Row-direction terms and the row sums of z as one MFMA contraction
+            // over the tile's 64 columns: D[i][k] = sum_j W_ij (-b_jk) + Z_ij xi_jk
+            // for k < n, and D[i][n] = sum_j Z_ij.  The W and Z tiles go through this
+            // wave's LDS rows ([16][NW], row-major) from the accumulator layout
+            // (lane (g, c): rows 4g + v, columns TW c .. TW c + 3) to the A layout
+            // (lane (g, c): row c, columns 16 g .. 16 g + 15, MFMA step s <-> column
+            // 16 g + s); the staged -b (sb) and -xi (sx) give B (feature 16 kb + c).
+            static_assert(kWaves * 2 * 16 * NW * 4 <= AdjTile<T>::kCsum, "W/Z staging");
+            float* wl = reinterpret_cast<float*>(lds) + wave * (2 * 16 * NW);
+            float* zl = wl + 16 * NW;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                V16<T> zo;
+#pragma unroll
+                for (int t = 0; t < TW; ++t) zo.v[t] = Z[t][v];
+                st16(zl + (4 * g + v) * NW + TW * c, zo);
+                if (MODE == 0) {
+                    V16<T> wo;
+#pragma unroll
+                    for (int t = 0; t < TW; ++t) wo.v[t] = W[t][v];
+                    st16(wl + (4 * g + v) * NW + TW * c, wo);
+                }
+            }
+            V16<T> aw[4], az[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                az[q] = ld16(zl + c * NW + 16 * g + 4 * q);
+                if (MODE == 0) aw[q] = ld16(wl + c * NW + 16 * g + 4 * q);
+            }
+#pragma unroll
+            for (int kb = 0; kb < NKB; ++kb) {
+                const int f = 16 * kb + c;            // feature of this lane's B column
+                V16<T> bb[4], bx[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) { bb[q].v[e] = (T)0; bx[q].v[e] = (T)0; }
+                    if (f < KX) {
+                        bx[q] = ld16(sx + f * NW + 16 * g + 4 * q);
+                        if (MODE == 0) bb[q] = ld16(sb + f * NW + 16 * g + 4 * q);
+                    }
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) bx[q].v[e] = f == n ? (T)1 : -bx[q].v[e];
+                }
+                acc_t dz = acc_t{0, 0, 0, 0}, dw = acc_t{0, 0, 0, 0};
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        dz = mfma4(az[q].v[e], bx[q].v[e], dz);
+                        if (MODE == 0) dw = mfma4(aw[q].v[e], bb[q].v[e], dw);
+                    }
+                // lane (g, c) holds D[4g + v][f]
+                if (f < n) {
+                    T* rv = (T*)a.rowvpart;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        rv[((int64_t)strip * a.Nrow + i0 + 4 * g + v) * n + f] = MODE == 0 ? dw[v] + dz[v] : dz[v];
+                } else if (f == n) {
+                    T* dst = (T*)a.rowpart + (int64_t)strip * a.Nrow + i0;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) dst[4 * g + v] = dz[v];
+                }
+            }
+            return;
+        }
+
         // row sums of z
         T rs[4];
 #pragma unroll
@@ -281,6 +349,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_pass(AdjPassArgs a) {
     }
 
     // combine the 4 waves' column sums (fixed order) and write this chunk's partials
+    // (the FP32 path staged its W and Z tiles in this area: every wave done first)
+    if constexpr (sizeof(T) == 4) __syncthreads();
     typedef T cl_t[TW][NKB][4][64];
     cl_t* cl = reinterpret_cast<cl_t*>(lds);
 #pragma unroll
