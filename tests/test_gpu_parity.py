@@ -526,6 +526,48 @@ def test_batched_fixed_schedule_matches_oracle(cr, prec):
         assert exi < TOL_SOLVE[prec]
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+def test_batched_update_form_with_a_large_problem_matches_oracle(cr, prec):
+    """A batch holding a problem past the lazy form's 2048-point limit runs the
+    update-kernel form for every problem; both sizes against the oracle."""
+    shapes = [(2300, 5), (700, 10)]
+    say("batched update form %s shapes %s" % (PREC_NAME[prec], shapes))
+    probs = _batch_problems(shapes, seed0=600)
+    sched = dict(inner_iters=10, max_outer=2)
+    outs, infos = cr.solve_batched([(dev(p.X), dev(p.ybar)) for p in probs], cr.Params(precision=prec, **sched))
+    for p, (y, xi), info in zip(probs, outs, infos):
+        ref = oracle.alcc(p.X, p.ybar, oracle.Params(**sched), record_kkt=False)
+        assert info.inner_iters == 20 and info.outer_iters == 2
+        ey, exi = rel(host(y), ref.y), rel(host(xi), ref.xi)
+        say("  N=%d n=%d: y %.2e xi %.2e" % (p.N, p.n, ey, exi))
+        assert ey < TOL_SOLVE[prec]
+        assert exi < TOL_SOLVE[prec]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+def test_batched_lazy_form_over_several_tiles_matches_oracle(cr, prec):
+    """A batch of problems up to 2048 points runs lazy passes; with tile heights
+    that give several chunks and strips per problem (and a ragged last chunk)."""
+    shapes = [(1800, 10), (1100, 3), (333, 20)]
+    tiles = [256, 384, 128]
+    say("batched lazy form %s shapes %s tiles %s" % (PREC_NAME[prec], shapes, tiles))
+    probs = _batch_problems(shapes, seed0=700)
+    sched = dict(inner_iters=12, max_outer=2)
+    b = cr.Batch([(dev(p.X), dev(p.ybar)) for p in probs], cr.Params(precision=prec, **sched), tile_rows=tiles)
+    try:
+        outs, infos, _ = b.run()
+        outs = [(host(y), host(xi)) for y, xi in outs]
+    finally:
+        b.close()
+    for p, (y, xi), info in zip(probs, outs, infos):
+        ref = oracle.alcc(p.X, p.ybar, oracle.Params(**sched), record_kkt=False)
+        assert info.inner_iters == 24 and info.outer_iters == 2
+        ey, exi = rel(y, ref.y), rel(xi, ref.xi)
+        say("  N=%d n=%d: y %.2e xi %.2e" % (p.N, p.n, ey, exi))
+        assert ey < TOL_SOLVE[prec]
+        assert exi < TOL_SOLVE[prec]
+
+
 def test_batched_equals_single_problem_solves(cr):
     say("batched vs single-problem solves, f64")
     probs = _batch_problems(BATCH_SHAPES[:4], seed0=200)
