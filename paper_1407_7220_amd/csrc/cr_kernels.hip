@@ -1181,14 +1181,21 @@ __global__ void k_su_sums(const double* X, const double* ybar, int64_t N, int n,
     // phase 0: e < n: sum x_ik; e = n: sum ybar; e = n+1: max |ybar|; e = n+2: # non-finite
     // phase 1: e < n*n: sum u_ik u_il; n*n <= e < n*n+n: sum u_ik (ybar_i - ybar_mean)
     // phase 2: e < n: sum u_ik (ybar_i - ybar_mean) (the entries n*n + e of phase 1)
-    // Each thread owns output entries e and walks the workgroup's rows with
-    // four interleaved accumulators (rows i, i+1, i+2, i+3 of every step), so
-    // that four loads are in flight; the four are combined in a fixed order.
+    // Thread (e, p) owns entry e and the rows r0 + p, r0 + p + P, ... of the
+    // workgroup's rows (P = 256 / #entries row lanes, so that the loads of a
+    // workgroup are in flight together); the P pieces of an entry are then
+    // combined in LDS in index order.  With more entries than threads each
+    // thread walks all the rows of its entries (P = 1).
     const int64_t r0 = (int64_t)blockIdx.x * rows, r1 = min(r0 + rows, N);
     const int ne = phase == 0 ? n + 3 : (phase == 1 ? n * n + n : n);
     const int eq = phase == 2 ? n * n : 0;        // phase 2 computes phase 1's entries n*n + e
     const double ym = phase != 0 ? su[n] : 0.0;
-    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    const int P = ne < (int)blockDim.x ? (int)blockDim.x / ne : 1;
+    __shared__ double piece[kBlock];
+    for (int e0 = 0; e0 < ne; e0 += (int)blockDim.x / P) {
+        const int e = e0 + (int)threadIdx.x % (ne < (int)blockDim.x ? ne : (int)blockDim.x);
+        const int p = P > 1 ? (int)threadIdx.x / ne : 0;
+        const bool active = e < ne && p < P;
         const bool is_max = phase == 0 && e == n + 1;
         auto term = [&](int64_t i) -> double {
             if (phase == 0) {
@@ -1207,22 +1214,30 @@ __global__ void k_su_sums(const double* X, const double* ybar, int64_t N, int n,
             const int k = ee - n * n;
             return (X[i * n + k] - su[k]) * (ybar[i] - ym);
         };
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int64_t i = r0;
-        if (is_max) {
-            for (; i + 4 <= r1; i += 4) {
-                a0 = fmax(a0, term(i)); a1 = fmax(a1, term(i + 1));
-                a2 = fmax(a2, term(i + 2)); a3 = fmax(a3, term(i + 3));
+        double a0 = 0.0, a1 = 0.0;
+        if (active) {
+            int64_t i = r0 + p;
+            for (; i + P < r1; i += 2 * P) {
+                const double t0 = term(i), t1 = term(i + P);
+                a0 = is_max ? fmax(a0, t0) : a0 + t0;
+                a1 = is_max ? fmax(a1, t1) : a1 + t1;
             }
-            for (; i < r1; ++i) a0 = fmax(a0, term(i));
-            part[(int64_t)blockIdx.x * ne + e] = fmax(fmax(a0, a1), fmax(a2, a3));
-        } else {
-            for (; i + 4 <= r1; i += 4) {
-                a0 += term(i); a1 += term(i + 1);
-                a2 += term(i + 2); a3 += term(i + 3);
-            }
-            for (; i < r1; ++i) a0 += term(i);
-            part[(int64_t)blockIdx.x * ne + e] = (a0 + a1) + (a2 + a3);
+            if (i < r1) { const double t0 = term(i); a0 = is_max ? fmax(a0, t0) : a0 + t0; }
+        }
+        const double v = is_max ? fmax(a0, a1) : a0 + a1;
+        if (P == 1) {
+            if (active) part[(int64_t)blockIdx.x * ne + e] = v;
+            continue;
+        }
+        __syncthreads();
+        if (active) piece[p * ne + e] = v;
+        __syncthreads();
+        if (threadIdx.x < ne) {
+            const int ee = threadIdx.x;
+            const bool mx = phase == 0 && ee == n + 1;
+            double acc = piece[ee];
+            for (int q = 1; q < P; ++q) acc = mx ? fmax(acc, piece[q * ne + ee]) : acc + piece[q * ne + ee];
+            part[(int64_t)blockIdx.x * ne + ee] = acc;
         }
     }
 }
