@@ -865,7 +865,11 @@ struct BatchPlan {
     std::vector<Layout> L;
     std::vector<size_t> off;     // sub-workspace offsets
     size_t hdr = 0, total = 0;
-    int G = 16, nblocks = 0;
+    // O(N n) kernels of the batch run G = 16 or 32 lanes per point by each
+    // problem's own n (as a problem solved alone does): its blocks sit in the
+    // block table's segment for that G (16 first), nblk blocks per problem.
+    int nblocks = 0;
+    int gseg_start[2] = {0, 0}, gseg_count[2] = {0, 0};
     std::vector<int32_t> nblk;
     std::vector<int> ks_classes;
     std::vector<BatchItemH> items;          // grouped by class
@@ -896,17 +900,19 @@ cr_status check_batch(const cr_problem* probs, int32_t P, const cr_params* param
 // Largest problem of a batch that runs lazy passes (see plan_batch).
 constexpr int64_t kBatchLazyMaxN = 2048;
 
+// Lanes per point of a problem's O(N n) kernels (lane k < n: xi_k, lane n: y).
+int batch_group(int n) { return n + 1 <= 16 ? 16 : 32; }
+
 BatchPlan plan_batch(const cr_problem* probs, int32_t P, const cr_params* params) {
     BatchPlan B;
-    int nmax = 0;
-    for (int p = 0; p < P; ++p) nmax = std::max(nmax, (int)probs[p].n);
-    B.G = nmax + 1 <= 16 ? 16 : 32;
     for (int p = 0; p < P; ++p) {
         const int tr = probs[p].tile_rows > 0 ? probs[p].tile_rows : params->tile_rows;
         B.L.push_back(make_layout(probs[p].N, probs[p].n, *params, tr));
-        const int nb = (int)((probs[p].N * B.G + cr::kBlock - 1) / cr::kBlock);
+        const int G = batch_group(probs[p].n);
+        const int nb = (int)((probs[p].N * G + cr::kBlock - 1) / cr::kBlock);
         B.nblk.push_back(nb);
         B.nblocks += nb;
+        B.gseg_count[G == 16 ? 0 : 1] += nb;
         const int ks = cr::ks_of(probs[p].n);
         if (std::find(B.ks_classes.begin(), B.ks_classes.end(), ks) == B.ks_classes.end()) B.ks_classes.push_back(ks);
     }
@@ -914,6 +920,7 @@ BatchPlan plan_batch(const cr_problem* probs, int32_t P, const cr_params* params
     // grows with the problem; measured on the MI355X: 3.83 against 4.07 ms per
     // P-APG iteration with 1024-point blocks, 2.20 against 2.05 ms per MAPG
     // iteration of 64 problems of 500 to 8000 points.
+    B.gseg_start[1] = B.gseg_count[0];
     B.lazy = !params->deterministic;
     for (int p = 0; p < P; ++p) B.lazy = B.lazy && B.L[p].lazy && probs[p].N <= kBatchLazyMaxN;
     std::sort(B.ks_classes.begin(), B.ks_classes.end());
@@ -994,6 +1001,8 @@ static cr_status capture_batch_graph(cr_batch* b, hipGraphExec_t* out) {
     const BatchPlan& B = b->plan;
     char* h = b->ws;
     const int iters = b->replay;
+    // block-table segment of the problems with G = 16 << gs lanes per point
+    auto seg = [&](int gs) { return (const void*)(h + B.off_blocks + (size_t)B.gseg_start[gs] * 8); };
     hipGraph_t g = nullptr;
     BHIPCHK(b, hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
@@ -1004,12 +1013,14 @@ static cr_status capture_batch_graph(cr_batch* b, hipGraphExec_t* out) {
                                         h + B.off_items + (size_t)B.class_off[ci] * sizeof(BatchItemH),
                                         B.class_cnt[ci], b->cs, B.lazy, q);
         }
-        if (e == hipSuccess)
-            e = cr::launch_reduce_batched(b->f64, B.G, (const cr::ReduceArgs*)(h + B.off_red), h + B.off_blocks,
-                                          (const int32_t*)(h + B.off_nblk), B.nblocks, q, b->cs);
-        if (e == hipSuccess && !B.lazy)
-            e = cr::launch_update_batched(b->f64, B.G, (const cr::UpdateArgs*)(h + B.off_upd), h + B.off_blocks,
-                                          (const int32_t*)(h + B.off_nblk), B.nblocks, q, b->cs);
+        for (int gs = 0; gs < 2 && e == hipSuccess; ++gs)
+            if (B.gseg_count[gs])
+                e = cr::launch_reduce_batched(b->f64, 16 << gs, (const cr::ReduceArgs*)(h + B.off_red), seg(gs),
+                                              (const int32_t*)(h + B.off_nblk), B.gseg_count[gs], q, b->cs);
+        for (int gs = 0; gs < 2 && e == hipSuccess && !B.lazy; ++gs)
+            if (B.gseg_count[gs])
+                e = cr::launch_update_batched(b->f64, 16 << gs, (const cr::UpdateArgs*)(h + B.off_upd), seg(gs),
+                                              (const int32_t*)(h + B.off_nblk), B.gseg_count[gs], q, b->cs);
     }
     auto scheds = (cr::AlccSched* const*)(h + B.off_scheds);
     auto sts = (cr::DevState* const*)(h + B.off_sts);
@@ -1018,24 +1029,27 @@ static cr_status capture_batch_graph(cr_batch* b, hipGraphExec_t* out) {
         e = cr::launch_alcc_gate_batched(scheds, sts, oas, b->P, iters, (int32_t*)(h + B.off_any), b->cs);
     // lazy runs: the last iterate into y1p[0] / xi1p[0] first; the stopping
     // pieces then come from the reduce, not from update-kernel records
-    if (e == hipSuccess && B.lazy)
-        e = cr::launch_mapg_finish_batched(B.G, (const cr::PassArgs*)(h + B.off_pass), h + B.off_blocks, B.nblocks,
-                                           b->cs);
+    for (int gs = 0; gs < 2 && e == hipSuccess && B.lazy; ++gs)
+        if (B.gseg_count[gs])
+            e = cr::launch_mapg_finish_batched(16 << gs, (const cr::PassArgs*)(h + B.off_pass), seg(gs),
+                                               B.gseg_count[gs], b->cs);
     if (e == hipSuccess)
         e = cr::launch_mapg_end_batched((const double* const*)(h + B.off_bparts),
                                         (const int32_t*)(h + (B.lazy ? B.off_nblk0 : B.off_nblk)), sts, b->P, b->cs);
-    if (e == hipSuccess)
-        e = cr::launch_set_point_batched(b->f64, B.G, (const cr::PointArgs*)(h + B.off_pt), h + B.off_blocks,
-                                         (const int32_t*)(h + B.off_nblk), B.nblocks, b->cs);
+    for (int gs = 0; gs < 2 && e == hipSuccess; ++gs)
+        if (B.gseg_count[gs])
+            e = cr::launch_set_point_batched(b->f64, 16 << gs, (const cr::PointArgs*)(h + B.off_pt), seg(gs),
+                                             (const int32_t*)(h + B.off_nblk), B.gseg_count[gs], b->cs);
     for (size_t ci = 0; ci < B.ks_classes.size() && e == hipSuccess; ++ci) {
         e = cr::launch_theta_pass_batched(b->f64, B.ks_classes[ci], (const cr::PassArgs*)(h + B.off_pass1),
                                           (const int32_t*)(h + B.off_nstrips),
                                           h + B.off_items + (size_t)B.class_off[ci] * sizeof(BatchItemH),
                                           B.class_cnt[ci], b->cs);
     }
-    if (e == hipSuccess)
-        e = cr::launch_reduce_batched(b->f64, B.G, (const cr::ReduceArgs*)(h + B.off_red2), h + B.off_blocks,
-                                      (const int32_t*)(h + B.off_nblk), B.nblocks, 0, b->cs);
+    for (int gs = 0; gs < 2 && e == hipSuccess; ++gs)
+        if (B.gseg_count[gs])
+            e = cr::launch_reduce_batched(b->f64, 16 << gs, (const cr::ReduceArgs*)(h + B.off_red2), seg(gs),
+                                          (const int32_t*)(h + B.off_nblk), B.gseg_count[gs], 0, b->cs);
     if (e == hipSuccess) e = cr::launch_alcc_step_batched(scheds, sts, oas, b->P, b->cs);
     hipError_t e2 = hipStreamEndCapture(b->cs, &g);
     if (e != hipSuccess) return bfail(b, CR_ERR_HIP, std::string("batch capture: ") + hipGetErrorString(e));
@@ -1134,7 +1148,7 @@ static cr_status batch_init_impl(cr_batch** out, const cr_problem* probs, int32_
         cr_ctx* c = b->sub[p];
         const Layout& L = c->L;
         if (B.lazy) {
-            // the reduce blocks of the batch (B.G lanes per point) leave the norm pieces
+            // the reduce blocks of the problem (batch_group(n) lanes per point) leave the norm pieces
             pa[p] = lazy_pass_args(c, 0, 0);
             pa[p].lz.nblk = B.nblk[p];
             pat[p] = lazy_pass_args(c, 0, 2);
@@ -1159,8 +1173,11 @@ static cr_status batch_init_impl(cr_batch** out, const cr_problem* probs, int32_
         ra2[p].mu_dev = 1;
         pt[p] = point_args(c, c->D(L.off_y1p), c->D(L.off_xi1p), 1);
         pt[p].gate = &c->st->step_due;
-        for (int q = 0; q < B.nblk[p]; ++q) { blocks.push_back(p); blocks.push_back(q); }
     }
+    for (int gs = 0; gs < 2; ++gs)
+        for (int p = 0; p < P; ++p)
+            if ((batch_group(probs[p].n) == 16) == (gs == 0))
+                for (int q = 0; q < B.nblk[p]; ++q) { blocks.push_back(p); blocks.push_back(q); }
     char* h = b->ws;
     e = hipMemcpy(h + B.off_pass, pa.data(), P * sizeof(cr::PassArgs), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(h + B.off_red, ra.data(), P * sizeof(cr::ReduceArgs), hipMemcpyHostToDevice);
