@@ -57,11 +57,10 @@ template <typename Ops> struct LazyShape {
 template <typename Ops>
 __device__ void lazy_operands(const PassArgs& a, const int strip, const int chunk, const int64_t I0, const int64_t I1,
                               const int64_t J0, char* __restrict__ lds, typename Ops::elem* __restrict__ ylds,
-                              typename Ops::Breg& breg, const int g, const int c, double* stop, const int lq) {
+                              typename Ops::Breg& breg, const int g, const int c, double* stop, const int64_t l) {
     typedef typename Ops::elem T;
     typedef LazyShape<Ops> S;
     const LazyStep& z = a.lz;
-    const int64_t l = z.lfix > 0 ? (int64_t)z.lfix : z.st->base + lq + 1;
     const int rows = (int)(I1 - I0);
     if (l <= 1) {
         // first iteration of the run: the operands k_set_point wrote
@@ -196,7 +195,10 @@ __device__ void lazy_operands(const PassArgs& a, const int strip, const int chun
     Ops::load_breg_lds(breg, Bs, Ops::TW * c, g, n);
 }
 
-// lq: replay position of a lazy gradient pass (LazyStep).
+// lq: replay position of a lazy gradient pass (LazyStep).  The workgroup
+// returns after issuing its first tile loads when the activity flag is 0 (the
+// flag and the replay base are read together with those loads, so that the
+// pass's start waits on one round trip instead of three).
 template <typename Ops, int THETA_MODE, int LAZY = 0>
 __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chunk, const int nstrips,
                                char* __restrict__ lds, const int lq) {
@@ -384,11 +386,18 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
     // program order, so the prologue leaves the same pending-load sequence as
     // the loop's back edge; otherwise the wait-count merge at the loop head
     // drains nearly every prefetched load once per NSET tiles.
+    const int act_v = vld_i32(a.active);
+    u32x2 base_v = {0u, 0u};
+    if constexpr (LAZY) base_v = vld_i64(&a.lz.st->base);
+    __builtin_amdgcn_sched_barrier(0);
+    int64_t l = 0;
     if constexpr (LAZY) {
         // one tile in flight during the operand set-up (more would spill)
         load_tile(0, xs[0], ys[0], ts[0]);
         __builtin_amdgcn_sched_barrier(0);
-        lazy_operands<Ops>(a, strip, chunk, I0, I1, J0, lds, ylds, breg, g, c, stop, lq);
+        if (uniform(act_v) == 0) return;
+        l = a.lz.lfix > 0 ? (int64_t)a.lz.lfix : uniform(base_v) + lq + 1;
+        lazy_operands<Ops>(a, strip, chunk, I0, I1, J0, lds, ylds, breg, g, c, stop, l);
 #pragma unroll
         for (int b = 1; b < NSET; ++b) {
             load_tile(b, xs[b], ys[b], ts[b]);
@@ -400,6 +409,7 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
             load_tile(b, xs[b], ys[b], ts[b]);
             __builtin_amdgcn_sched_barrier(0);
         }
+        if (uniform(act_v) == 0) return;
     }
 #pragma nounroll
     for (int m = 0; m < ntile; m += NSET) {
@@ -415,7 +425,6 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
     // rowpart[strip][i] of this chunk's rows, from the LDS staging area
     __syncthreads();
     if constexpr (LAZY) {
-        const int64_t l = a.lz.lfix > 0 ? (int64_t)a.lz.lfix : a.lz.st->base + lq + 1;
         if (threadIdx.x == 0 && l > 1 && (strip == 0 || chunk == 0)) {
             double sy2 = stop[0], sx2 = stop[kWaves];
             for (int w = 1; w < kWaves; ++w) { sy2 += stop[w]; sx2 += stop[kWaves + w]; }
@@ -473,13 +482,12 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
 // 4 for FP32 with KS <= 3, 3 for FP32 KS = 4 and FP64 KS <= 4, 2 otherwise).
 template <typename Ops, int THETA_MODE, int WAVES, int LAZY = 0>
 __global__ __launch_bounds__(kBlock, WAVES) void k_pair_pass(PassArgs a) {
-    if (*a.active == 0) return;
     __shared__ __align__(16) char lds[kPassLds];
     pair_pass_item<Ops, THETA_MODE, LAZY>(a, blockIdx.x, blockIdx.y, gridDim.x, lds, a.lz.q);
 }
 
 // Batched pass: workgroup b takes item b of the (problem, strip, chunk) list
-// and returns at once when that problem's MAPG has stopped.  Each item is one
+// and returns after its first loads when that problem's MAPG has stopped.  Each item is one
 // workgroup tile of the single-problem pass; LAZY gradient passes complete
 // each problem's previous MAPG step (LazyStep of its table entry, replay
 // position q).  (A persistent grid walking the items held some 20-40 more
@@ -492,7 +500,6 @@ __global__ __launch_bounds__(kBlock, WAVES) void k_pair_pass_batched(const PassA
     __shared__ __align__(16) char lds[kPassLds];
     const BatchItem item = items[blockIdx.x];
     const PassArgs& a = args[item.p];
-    if (*a.active == 0) return;
     pair_pass_item<PlainOps<T, KS>, THETA_MODE, LAZY>(a, item.strip, item.chunk, nstrips_of_p[item.p], lds, q);
 }
 
@@ -512,13 +519,21 @@ __device__ double block_gather(const double* part, int count, int q, int op) {
 
 template <typename T, int G>
 __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk) {
+    // The activity flag, the gate and the replay base are read together with
+    // the partial sums (every load below stays inside its array), and the
+    // block returns once they arrive if there is nothing to do: the kernel's
+    // start then waits on one round trip of loads instead of two.
     DevState* st = a.st;
-    int64_t l = 0;
-    if (a.mode == 0) {
-        if (st->active == 0) return;
-        l = st->base + a.q + 1;
-    }
-    if (a.gate && *a.gate == 0) return;
+    const bool m0 = a.mode == 0;
+    const int act_v = vld_i32(&st->active, m0);
+    const u32x2 base_v = vld_i64(&st->base, m0);
+    const int gate_v = vld_i32(a.gate, a.gate != nullptr);
+    // mu, gamma and the block steps (the first four fields of OuterArgs) where
+    // they come from the device schedule
+    const bool use_oa = m0 || a.mu_dev;
+    const rsrc_t oar = make_rsrc(a.oa, use_oa ? 32u : 0u);
+    const V16<double> o01 = bld16<double>(oar, 0, 0), o23 = bld16<double>(oar, 16, 0);
+    __builtin_amdgcn_sched_barrier(0);
     constexpr int PER = kBlock / G;
     const int k = threadIdx.x % G;
     const int64_t j = (int64_t)blk * PER + threadIdx.x / G;
@@ -526,12 +541,6 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
     const T* rowpart = (const T*)a.rowpart;
     const T* cpart = (const T*)a.cpart;
     const int n = a.n, nc = a.nc;
-    double mu, gamma, sy = 0.0, sxi = 0.0;
-    if (a.mode == 0) {
-        mu = a.oa->mu; gamma = a.oa->gamma; sy = a.oa->sy; sxi = a.oa->sxi;
-    } else {
-        mu = a.mu_dev ? a.oa->mu : a.mu; gamma = a.gamma;
-    }
     // Every load of this point first, so that they are in flight together.
     // Lane k sums the strips k, k + G, ... and (k < n + 1) column k over the
     // chunks, each in index order.  Buffer views of 12 strips x G (16 chunks)
@@ -555,14 +564,14 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
     };
     // Block 0 takes the stopping decision of iteration l - 1 (below); the
     // first record of each of its two sums is loaded here with the rest.
-    const bool decide = a.mode == 0 && l > 1 && blk == 0;
+    const bool may_decide = a.mode == 0 && blk == 0;
     const int tid = threadIdx.x;
     const int d0 = a.spart ? a.chunks : nblk, d1 = a.spart ? a.strips : nblk;
-    double x0 = 0.0, x1 = 0.0;
-    if (decide) {
-        x0 = a.spart ? a.spart[min(tid, d0 - 1)] : a.blockpart[(int64_t)min(tid, d0 - 1) * 4 + 2];
-        x1 = a.spart ? a.spart[d0 + min(tid, d1 - 1)] : a.blockpart[(int64_t)min(tid, d1 - 1) * 4 + 3];
-    }
+    const rsrc_t dr = make_rsrc(a.spart ? (const double*)a.spart : a.blockpart,
+                                may_decide ? (uint32_t)(a.spart ? (d0 + d1) * 8 : nblk * 32) : 0u);
+    const uint32_t t0 = (uint32_t)min(tid, d0 - 1), t1 = (uint32_t)min(tid, d1 - 1);
+    const double x0 = bld8(dr, a.spart ? 8 * t0 : 8 * (4 * t0 + 2), 0);
+    const double x1 = bld8(dr, a.spart ? 8 * (d0 + t1) : 8 * (4 * t1 + 3), 0);
     // first batches and the point's own values, all issued before any sum
     T ur[URS], uc[UCK];
     {
@@ -575,6 +584,12 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
     const int64_t jc = valid ? j : a.N - 1;
     const int kk = min(k, n - 1);
     const double y_l = a.y[jc], yb_l = a.ybar[jc], x_l = a.X[jc * n + kk], xi_l = a.xi[jc * n + kk];
+    __builtin_amdgcn_sched_barrier(0);   // keeps the loads above ahead of the test
+    if ((m0 && uniform(act_v) == 0) || (a.gate && uniform(gate_v) == 0)) return;
+    const int64_t l = a.mode == 0 ? uniform(base_v) + a.q + 1 : 0;
+    const bool decide = may_decide && l > 1;
+    const double mu = use_oa ? o01.v[0] : a.mu, gamma = m0 ? o01.v[1] : a.gamma;
+    const double sy = m0 ? o23.v[0] : 0.0, sxi = m0 ? o23.v[1] : 0.0;
     double rs = 0.0, ck = 0.0;
 #pragma unroll
     for (int e = 0; e < URS; ++e) rs += (double)ur[e];

@@ -146,6 +146,26 @@ __device__ __forceinline__ V16<T> bld16(rsrc_t r, uint32_t voff, uint32_t soff) 
 __device__ __forceinline__ double bld8(rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
+// A value that is the same for every lane, read with a vector load (vld_*)
+// and made uniform at its first use (uniform()): vector loads complete in issue
+// order, so waiting for this one does not drain the loads issued after it (a
+// scalar load's wait would take every outstanding scalar load with it, the
+// kernel arguments of those later loads among them).
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+// With ok false the view is empty: the load reads 0 and touches no memory (p
+// may then be anything), so the load needs no branch around it.
+__device__ __forceinline__ int vld_i32(const int32_t* p, bool ok = true) {
+    return (int)__builtin_amdgcn_raw_buffer_load_b32(make_rsrc(p, ok ? 4u : 0u), 0, 0, 0);
+}
+__device__ __forceinline__ u32x2 vld_i64(const int64_t* p, bool ok = true) {
+    return __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(make_rsrc(p, ok ? 8u : 0u), 0, 0, 0));
+}
+__device__ __forceinline__ int32_t uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform(u32x2 v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)v.x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)v.y);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 template <typename T> __device__ __forceinline__ T bld_t(rsrc_t r, uint32_t voff, uint32_t soff);
 template <> __device__ __forceinline__ float bld_t<float>(rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
