@@ -54,76 +54,103 @@ template <typename Ops> struct LazyShape {
 // [I0, I1) into ylds, the column operands of [J0, J0 + 16 TW) into breg, and
 // the state and stopping-test pieces that this workgroup owns.  The pieces
 // (per-wave sums) go to `stop` (2 x kWaves doubles) for the epilogue.
+// The loads that do not depend on the iteration number l go out before the
+// activity flag and the replay base (act_v, base_v, vector loads issued by the
+// caller) are waited for; returns false, with nothing written, when the flag
+// is 0, else sets l.
 template <typename Ops>
-__device__ void lazy_operands(const PassArgs& a, const int strip, const int chunk, const int64_t I0, const int64_t I1,
+__device__ bool lazy_operands(const PassArgs& a, const int strip, const int chunk, const int64_t I0, const int64_t I1,
                               const int64_t J0, char* __restrict__ lds, typename Ops::elem* __restrict__ ylds,
-                              typename Ops::Breg& breg, const int g, const int c, double* stop, const int64_t l) {
+                              typename Ops::Breg& breg, const int g, const int c, double* stop, const int act_v,
+                              const u32x2 base_v, const int lq, int64_t& l) {
     typedef typename Ops::elem T;
     typedef LazyShape<Ops> S;
     const LazyStep& z = a.lz;
     const int rows = (int)(I1 - I0);
-    if (l <= 1) {
-        // first iteration of the run: the operands k_set_point wrote
-        const T* yc = (const T*)a.ycol + I0;
-        for (int r = threadIdx.x; r < rows; r += kBlock) ylds[r] = yc[r];
-        Ops::load_breg(breg, a, J0 + Ops::TW * c, g);
-        __syncthreads();
-        return;
-    }
     const int64_t N = a.N;
     const int n = z.n;
     const bool wrows = strip == 0, wcols = chunk == 0;
-    const int par = (int)(l & 1);                        // y1_{l-2} in y1p[l & 1]
-    const double* __restrict__ vy = z.vy;
-    const double* __restrict__ vxi = z.vxi;
-    const double* __restrict__ X = z.X;
-    const double* __restrict__ ybar = z.ybar;
-    const double* __restrict__ y1in = z.y1p[par];
-    const double* __restrict__ xi1in = z.xi1p[par];
-    double* __restrict__ y1out = z.y1p[par ^ 1];
-    double* __restrict__ xi1out = z.xi1p[par ^ 1];
-    double* __restrict__ y2 = z.y2;
-    double* __restrict__ xi2 = z.xi2;
+    const gp<const double> __restrict__ vy = glob(z.vy);
+    const gp<const double> __restrict__ vxi = glob(z.vxi);
+    const gp<const double> __restrict__ X = glob(z.X);
+    const gp<const double> __restrict__ ybar = glob(z.ybar);
+    const gp<double> __restrict__ y2 = glob(z.y2);
+    const gp<double> __restrict__ xi2 = glob(z.xi2);
 
-    // Every load first (column j = J0 + jj, k = r0 + PT e; then the first rows),
-    // so that they are in flight together with the norm gather.
+    // Loads independent of l (column j = J0 + jj, k = r0 + PT e; the first
+    // rows; the first records of the norm pieces; the ball radii), all in
+    // flight together with the flag and the base.
     const int jj = threadIdx.x / S::PT, r0 = threadIdx.x % S::PT;
     const int64_t j = J0 + jj;
     const bool vj = j < N;
-    double cv[S::KMAX], cp[S::KMAX], cx[S::KMAX], co[S::KMAX];
+    double cv[S::KMAX], cx[S::KMAX], co[S::KMAX];
 #pragma unroll
     for (int e = 0; e < S::KMAX; ++e) {
         const int k = r0 + S::PT * e;
-        cv[e] = cp[e] = cx[e] = co[e] = 0.0;
+        cv[e] = cx[e] = co[e] = 0.0;
         if (vj && k < n) {
             const int64_t q = j * n + k;
-            cv[e] = vxi[q]; cp[e] = xi1in[q]; cx[e] = X[q];
+            cv[e] = vxi[q]; cx[e] = X[q];
             if (wcols) co[e] = xi2[q];
         }
     }
-    double jv = 0.0, jb = 0.0, jp = 0.0;
-    if (vj) { jv = vy[j]; jb = ybar[j]; jp = y1in[j]; }
+    double jv = 0.0, jb = 0.0;
+    if (vj) { jv = vy[j]; jb = ybar[j]; }
     constexpr int RB = 3;      // rows per thread loaded with the first batch (768-row chunks in one round trip)
-    double rv[RB], rb[RB], rp[RB], ro[RB];
+    double rv[RB], rb[RB], ro[RB];
 #pragma unroll
     for (int e = 0; e < RB; ++e) {
         const int r = threadIdx.x + kBlock * e;
         const int64_t i = I0 + r;
-        rv[e] = rb[e] = rp[e] = ro[e] = 0.0;
+        rv[e] = rb[e] = ro[e] = 0.0;
         if (r < rows && i < N) {
-            rv[e] = vy[i]; rb[e] = ybar[i]; rp[e] = y1in[i];
+            rv[e] = vy[i]; rb[e] = ybar[i];
             if (wrows) ro[e] = y2[i];
         }
     }
+    double u0[4], u1[4];
+    gather_issue(z.npart, z.nblk, 0, 1, u0, u1);
+    const gp<const OuterArgs> oa = glob(z.oa);
+    const double By = oa->By, Bxi = oa->Bxi;
+    __builtin_amdgcn_sched_barrier(0);
+
+    if (uniform(act_v) == 0) return false;
+    l = z.lfix > 0 ? (int64_t)z.lfix : uniform(base_v) + lq + 1;
+    if (l <= 1) {
+        // first iteration of the run: the operands k_set_point wrote
+        const gp<const T> yc = glob((const T*)a.ycol + I0);
+        for (int r = threadIdx.x; r < rows; r += kBlock) ylds[r] = yc[r];
+        Ops::load_breg(breg, a, J0 + Ops::TW * c, g);
+        __syncthreads();
+        return true;
+    }
+    const int par = (int)(l & 1);                        // y1_{l-2} in y1p[l & 1]
+    const gp<const double> __restrict__ y1in = glob((const double*)z.y1p[par]);
+    const gp<const double> __restrict__ xi1in = glob((const double*)z.xi1p[par]);
+    const gp<double> __restrict__ y1out = glob(z.y1p[par ^ 1]);
+    const gp<double> __restrict__ xi1out = glob(z.xi1p[par ^ 1]);
+    double cp[S::KMAX];
+#pragma unroll
+    for (int e = 0; e < S::KMAX; ++e) {
+        const int k = r0 + S::PT * e;
+        cp[e] = vj && k < n ? xi1in[j * n + k] : 0.0;
+    }
+    const double jp = vj ? y1in[j] : 0.0;
+    double rp[RB];
+#pragma unroll
+    for (int e = 0; e < RB; ++e) {
+        const int r = threadIdx.x + kBlock * e;
+        const int64_t i = I0 + r;
+        rp[e] = r < rows && i < N ? y1in[i] : 0.0;
+    }
+    const double beta = glob(z.beta)[l - 1];         // (t_{l-1} - 1) / t_l
 
     // Fig. 4 steps 1-2 of iteration l - 1: the ball projections' scales
     double ny2, nx2;
-    gather_sum2(z.npart, z.nblk, 0, 1, ny2, nx2);
+    gather_finish(z.npart, z.nblk, 0, 1, u0, u1, ny2, nx2);
     const double ny = sqrt(ny2), nx = sqrt(nx2);
-    const OuterArgs* oa = z.oa;
-    const bool py = ny > oa->By, px = nx > oa->Bxi;
-    const double sy = py ? oa->By / ny : 1.0, sx = px ? oa->Bxi / nx : 1.0;
-    const double beta = z.beta[l - 1];               // (t_{l-1} - 1) / t_l
+    const bool py = ny > By, px = nx > Bxi;
+    const double sy = py ? By / ny : 1.0, sx = px ? Bxi / nx : 1.0;
     double dy = 0.0, dx = 0.0;
 
     // columns: -xi2_jk, and c_j = x_j^T xi2_j - y2_j from the PT threads' products
@@ -137,7 +164,7 @@ __device__ void lazy_operands(const PassArgs& a, const int strip, const int chun
         if (k < n) {
             const double x1 = px ? sx * cv[e] : cv[e];          // projection onto Q_xi
             const double x2n = x1 + beta * (x1 - cp[e]);        // extrapolation
-            const double xo = z.shift && vj ? x2n + z.shift[j * n + k] : x2n;
+            const double xo = z.shift && vj ? x2n + glob(z.shift)[j * n + k] : x2n;
             prod += cx[e] * xo;
             brow[k] = vj ? (T)(-xo) : (T)0;
             if (wcols && vj) {
@@ -193,6 +220,7 @@ __device__ void lazy_operands(const PassArgs& a, const int strip, const int chun
     }
     __syncthreads();
     Ops::load_breg_lds(breg, Bs, Ops::TW * c, g, n);
+    return true;
 }
 
 // lq: replay position of a lazy gradient pass (LazyStep).  The workgroup
@@ -235,7 +263,7 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
 
     double k_rneg_max = 0.0, k_rneg_sq = 0.0, k_wr_max = 0.0, k_wr_sum = 0.0;
     double theta_scale = 0.0;
-    if constexpr (theta_mode) theta_scale = a.theta_scale_p ? *a.theta_scale_p : a.theta_scale;
+    if constexpr (theta_mode) theta_scale = a.theta_scale_p ? *glob(a.theta_scale_p) : a.theta_scale;
 
     constexpr int64_t step = 16 * kWaves;
     constexpr int NSET = Ops::NSET;   // staging sets (tiles in flight per wave)
@@ -395,9 +423,7 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
         // one tile in flight during the operand set-up (more would spill)
         load_tile(0, xs[0], ys[0], ts[0]);
         __builtin_amdgcn_sched_barrier(0);
-        if (uniform(act_v) == 0) return;
-        l = a.lz.lfix > 0 ? (int64_t)a.lz.lfix : uniform(base_v) + lq + 1;
-        lazy_operands<Ops>(a, strip, chunk, I0, I1, J0, lds, ylds, breg, g, c, stop, l);
+        if (!lazy_operands<Ops>(a, strip, chunk, I0, I1, J0, lds, ylds, breg, g, c, stop, act_v, base_v, lq, l)) return;
 #pragma unroll
         for (int b = 1; b < NSET; ++b) {
             load_tile(b, xs[b], ys[b], ts[b]);
@@ -428,12 +454,12 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
         if (threadIdx.x == 0 && l > 1 && (strip == 0 || chunk == 0)) {
             double sy2 = stop[0], sx2 = stop[kWaves];
             for (int w = 1; w < kWaves; ++w) { sy2 += stop[w]; sx2 += stop[kWaves + w]; }
-            if (strip == 0) a.lz.spart[chunk] = sy2;
-            if (chunk == 0) a.lz.spart[a.lz.chunks + strip] = sx2;
+            if (strip == 0) glob(a.lz.spart)[chunk] = sy2;
+            if (chunk == 0) glob(a.lz.spart)[a.lz.chunks + strip] = sx2;
         }
     }
     {
-        T* dst = (T*)a.rowpart + (int64_t)strip * a.Nrow + I0;
+        const gp<T> dst = glob((T*)a.rowpart + (int64_t)strip * a.Nrow + I0);
         for (int r = threadIdx.x; r < (int)(I1 - I0); r += kBlock) dst[r] = srow[r];
     }
     __syncthreads();
@@ -449,7 +475,7 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
 #pragma unroll
             for (int v = 0; v < 4; ++v) cl[wave][t][kb][v][lane] = cacc[t][kb][v];
     __syncthreads();
-    T* cpart = (T*)a.cpart;
+    const gp<T> cpart = glob((T*)a.cpart);
     for (int e = threadIdx.x; e < TW * NKB * 4 * 64; e += kBlock) {
         const int ln = e & 63, v = (e >> 6) & 3, rest = e >> 8;
         const int kb = rest % NKB, t = rest / NKB;
@@ -467,7 +493,7 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
         if (lane == 0) { kr[0][wave] = q0; kr[1][wave] = q1; kr[2][wave] = q2; kr[3][wave] = q3; }
         __syncthreads();
         if (threadIdx.x == 0) {
-            double* o = a.kktpart + ((int64_t)chunk * nstrips + strip) * 4;
+            const gp<double> o = glob(a.kktpart + ((int64_t)chunk * nstrips + strip) * 4);
             double m0 = kr[0][0], s1 = kr[1][0], m2 = kr[2][0], s3 = kr[3][0];
             for (int w = 1; w < kWaves; ++w) {
                 m0 = fmax(m0, kr[0][w]); s1 += kr[1][w]; m2 = fmax(m2, kr[2][w]); s3 += kr[3][w];
@@ -495,8 +521,9 @@ __global__ __launch_bounds__(kBlock, WAVES) void k_pair_pass(PassArgs a) {
 struct BatchItem { int32_t p, strip, chunk, pad; };
 
 template <typename T, int KS, int THETA_MODE, int WAVES, int LAZY = 0>
-__global__ __launch_bounds__(kBlock, WAVES) void k_pair_pass_batched(const PassArgs* args, const int32_t* nstrips_of_p,
-                                                              const BatchItem* items, int q) {
+__global__ __launch_bounds__(kBlock, WAVES) void k_pair_pass_batched(const PassArgs* __restrict__ args,
+                                                              const int32_t* __restrict__ nstrips_of_p,
+                                                              const BatchItem* __restrict__ items, int q) {
     __shared__ __align__(16) char lds[kPassLds];
     const BatchItem item = items[blockIdx.x];
     const PassArgs& a = args[item.p];
@@ -583,7 +610,8 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
     }
     const int64_t jc = valid ? j : a.N - 1;
     const int kk = min(k, n - 1);
-    const double y_l = a.y[jc], yb_l = a.ybar[jc], x_l = a.X[jc * n + kk], xi_l = a.xi[jc * n + kk];
+    const double y_l = glob(a.y)[jc], yb_l = glob(a.ybar)[jc], x_l = glob(a.X)[jc * n + kk];
+    const double xi_l = glob(a.xi)[jc * n + kk];
     __builtin_amdgcn_sched_barrier(0);   // keeps the loads above ahead of the test
     if ((m0 && uniform(act_v) == 0) || (a.gate && uniform(gate_v) == 0)) return;
     const int64_t l = a.mode == 0 ? uniform(base_v) + a.q + 1 : 0;
@@ -621,19 +649,21 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
         // step's output once MAPG has stopped.
         double g0 = tid < d0 ? x0 : 0.0, g1 = tid < d1 ? x1 : 0.0;
         for (int b = tid + kBlock; b < max(d0, d1); b += kBlock) {
-            if (b < d0) g0 += a.spart ? a.spart[b] : a.blockpart[(int64_t)b * 4 + 2];
-            if (b < d1) g1 += a.spart ? a.spart[d0 + b] : a.blockpart[(int64_t)b * 4 + 3];
+            if (b < d0) g0 += a.spart ? glob(a.spart)[b] : glob(a.blockpart)[(int64_t)b * 4 + 2];
+            if (b < d1) g1 += a.spart ? glob(a.spart)[d0 + b] : glob(a.blockpart)[(int64_t)b * 4 + 3];
         }
         double dy2 = g0, dx2 = g1;
         block_sum2(dy2, dx2);
         const double dy = sqrt(dy2), dxi = sqrt(dx2);
-        const bool alpha_stop = a.oa->adaptive && dy <= a.oa->alpha_y && dxi <= a.oa->alpha_xi;
-        if ((alpha_stop || l - 1 >= a.oa->lmax) && threadIdx.x == 0) {
-            st->active = 0;
-            st->it = l - 1;
-            st->stopped_by_alpha = alpha_stop ? 1 : 0;
-            st->dy = dy;
-            st->dxi = dxi;
+        const gp<const OuterArgs> oa = glob(a.oa);
+        const bool alpha_stop = oa->adaptive && dy <= oa->alpha_y && dxi <= oa->alpha_xi;
+        if ((alpha_stop || l - 1 >= oa->lmax) && threadIdx.x == 0) {
+            const gp<DevState> sg = glob(st);
+            sg->active = 0;
+            sg->it = l - 1;
+            sg->stopped_by_alpha = alpha_stop ? 1 : 0;
+            sg->dy = dy;
+            sg->dxi = dxi;
         }
     }
     rs = group_sum<G>(rs);
@@ -645,13 +675,13 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
         if (a.mode == 0) {
             const double gy = (yj - ybj) / mu - rs + cs;
             const double vy = yj - sy * gy;
-            a.out_y[j] = vy;
+            glob(a.out_y)[j] = vy;
             acc0 = (vy - ybj) * (vy - ybj);
         } else if (a.mode == 1) {
-            a.out_y[j] = (yj - ybj) / mu - rs + cs;
+            glob(a.out_y)[j] = (yj - ybj) / mu - rs + cs;
         } else {
             const double sty = yj - ybj - mu * (rs - cs);
-            if (a.out_y) a.out_y[j] = sty;
+            if (a.out_y) glob(a.out_y)[j] = sty;
             acc0 = fabs(sty);
             acc2 = (yj - ybj) * (yj - ybj);
             bad = !isfinite(yj);
@@ -661,13 +691,13 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
         if (a.mode == 0) {
             const double gx = (gamma / mu) * xik + aw;
             const double vx = xik - sxi * gx;
-            a.out_xi[j * n + k] = vx;
+            glob(a.out_xi)[j * n + k] = vx;
             acc1 = vx * vx;
         } else if (a.mode == 1) {
-            a.out_xi[j * n + k] = (gamma / mu) * xik + aw;
+            glob(a.out_xi)[j * n + k] = (gamma / mu) * xik + aw;
         } else {
             const double stx = gamma * xik + mu * aw;
-            if (a.out_xi) a.out_xi[j * n + k] = stx;
+            if (a.out_xi) glob(a.out_xi)[j * n + k] = stx;
             acc1 = fabs(stx);
             acc3 = xik * xik;
             bad = !isfinite(xik);
@@ -677,7 +707,7 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
     if (a.mode == 0) {
         // per-block pieces of ||v_y - ybar||^2 and ||v_xi||^2; k_update combines them
         block_sum2(acc0, acc1);
-        if (threadIdx.x == 0) { a.blockpart[blk * 4 + 0] = acc0; a.blockpart[blk * 4 + 1] = acc1; }
+        if (threadIdx.x == 0) { glob(a.blockpart)[blk * 4 + 0] = acc0; glob(a.blockpart)[blk * 4 + 1] = acc1; }
         return;
     }
     // mode 2: KKT residuals of the multiplier step
@@ -685,10 +715,10 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
     const double b2 = block_reduce(acc2, 0), b3 = block_reduce(acc3, 0);
     const double bb = block_reduce(bad ? 1.0 : 0.0, 1);
     if (threadIdx.x == 0) {
-        a.blockpart[blk * 4 + 0] = b0;
-        a.blockpart[blk * 4 + 1] = b1;
-        a.blockpart[blk * 4 + 2] = b2;
-        a.blockpart[blk * 4 + 3] = bb > 0.0 ? INFINITY : b3;
+        glob(a.blockpart)[blk * 4 + 0] = b0;
+        glob(a.blockpart)[blk * 4 + 1] = b1;
+        glob(a.blockpart)[blk * 4 + 2] = b2;
+        glob(a.blockpart)[blk * 4 + 3] = bb > 0.0 ? INFINITY : b3;
     }
     if (last_block(&st->cnt[1], (unsigned int)nblk)) {
         const double m0 = block_gather(a.blockpart, nblk, 0, 1);

@@ -125,6 +125,13 @@ __device__ __forceinline__ T row16_sum4(const T s[4], int c) {
     return k;
 }
 
+// Global-memory view of a pointer.  Pointers read from device memory (the
+// batched kernels' argument tables) are otherwise generic, accessed with flat
+// instructions whose completion the compiler cannot order against other
+// loads (so every wait on one drains all of them).
+template <typename T> using gp = T __attribute__((address_space(1)))*;
+template <typename T> __device__ __forceinline__ gp<T> glob(T* p) { return (gp<T>)p; }
+
 template <typename T>
 __device__ __forceinline__ V16<T> ld16(const T* p) { return *reinterpret_cast<const V16<T>*>(p); }
 template <typename T>
@@ -240,6 +247,43 @@ static __device__ void gather_sum2(const double* part, int count, int q0, int q1
     block_sum2(s0, s1);
 }
 
+// gather_sum2 in two steps, with the same sums in the same order: the loads of
+// the first 4 kBlock records (issue), then the rest and the block sum (finish).
+static __device__ __forceinline__ void gather_issue(const double* part_, int count, int q0, int q1, double u0[4],
+                                                    double u1[4]) {
+    const gp<const double> part = glob(part_);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int r = threadIdx.x + e * kBlock;
+        const int64_t rc = max(min(r, count - 1), 0);
+        const double x0 = part[rc * 4 + q0], x1 = part[rc * 4 + q1];
+        u0[e] = r < count ? x0 : 0.0;
+        u1[e] = r < count ? x1 : 0.0;
+    }
+}
+static __device__ void gather_finish(const double* part_, int count, int q0, int q1, const double u0[4],
+                                     const double u1[4], double& s0, double& s1) {
+    const gp<const double> part = glob(part_);
+    s0 = 0.0;
+    s1 = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) { s0 += u0[e]; s1 += u1[e]; }
+    for (int b = threadIdx.x + 4 * kBlock; b < count; b += 4 * kBlock) {
+        double w0[4], w1[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = b + e * kBlock;
+            const int64_t rc = min(r, count - 1);
+            const double x0 = part[rc * 4 + q0], x1 = part[rc * 4 + q1];
+            w0[e] = r < count ? x0 : 0.0;
+            w1[e] = r < count ? x1 : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) { s0 += w0[e]; s1 += w1[e]; }
+    }
+    block_sum2(s0, s1);
+}
+
 // Each of `total` blocks calls this once after writing its partial results; it
 // returns true in every thread of the one block that arrives last (that block
 // then sees every other block's partials) and re-arms the counter.
@@ -292,10 +336,10 @@ template <typename T, int KS, int NSET_ = 0> struct PlainOps {
     struct Xop { T q[QP]; };
     // B operand of R for every j-tile: [-xi_j, c_j, 0...] (k = 4 s + g)
     static __device__ void load_breg(Breg& B, const PassArgs& a, int64_t jl, int g) {
-        const T* xiaug = (const T*)a.xiaug;
+        const gp<const T> xiaug = glob((const T*)a.xiaug);
 #pragma unroll
         for (int t = 0; t < TW; ++t) {
-            const T* row = xiaug + (jl + t) * (4 * KS);
+            const gp<const T> row = xiaug + (jl + t) * (4 * KS);
 #pragma unroll
             for (int s = 0; s < KS; ++s) B.b[s][t] = row[4 * s + g];
         }
@@ -370,8 +414,8 @@ template <int KB, int NKB_> struct MixedOps {
         for (int t = 0; t < TW; ++t) {
 #pragma unroll
             for (int kb = 0; kb < KB; ++kb)
-                B.b[kb][t] = *reinterpret_cast<const bf16x8*>(xb + ((jl + t) * KB + kb) * 32 + 8 * g);
-            B.cc[t] = a.cvec[jl + t];
+                B.b[kb][t] = *glob(reinterpret_cast<const bf16x8*>(xb + ((jl + t) * KB + kb) * 32 + 8 * g));
+            B.cc[t] = glob(a.cvec)[jl + t];
         }
     }
     // -xi_j entries of one column (3n <= 32 KB)
