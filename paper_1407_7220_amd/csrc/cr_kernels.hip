@@ -569,21 +569,26 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
     const T* cpart = (const T*)a.cpart;
     const int n = a.n, nc = a.nc;
     // Every load of this point first, so that they are in flight together.
-    // Lane k sums the strips k, k + G, ... and (k < n + 1) column k over the
-    // chunks, each in index order.  Buffer views of 12 strips x G (16 chunks)
-    // per batch, based at the wave's first point: entries past the last strip
-    // (chunk) read as zeros, so there is no per-entry branch.  One batch covers
-    // 192 strips at G = 16 (N up to 6144 in FP64, 12288 otherwise).
+    // Lane k of a point sums the strips k, k + G, ... and (k < n + 1) column k
+    // over the chunks, each in index order.  Buffer views of 12 strips x G (16
+    // chunks) per batch: entries past the last strip (chunk) read as zeros, so
+    // there is no per-entry branch.  One batch covers 192 strips at G = 16 (N up
+    // to 6144 in FP64, 12288 otherwise).  The strip sums are loaded by thread
+    // (point t % PER, strip group t / PER), so that the threads of a wave read
+    // whole runs of consecutive points of a few strips, and handed to lane k of
+    // their point through LDS.
     constexpr int URS = 12, UCK = 16;
     const int p = (threadIdx.x & 63) / G;
     const int64_t j0 = __builtin_amdgcn_readfirstlane((int)(j - p));   // the same in every lane of the wave
-    const uint32_t rvo = ((uint32_t)k * (uint32_t)a.Nrow + (uint32_t)p) * (uint32_t)sizeof(T);
+    const int64_t jb = (int64_t)blk * PER;                             // the block's first point
+    const int pr = threadIdx.x % PER, kr = threadIdx.x / PER;
+    const uint32_t rvo = ((uint32_t)kr * (uint32_t)a.Nrow + (uint32_t)pr) * (uint32_t)sizeof(T);
     const uint32_t rso = (uint32_t)G * (uint32_t)a.Nrow * (uint32_t)sizeof(T);
     const uint32_t cvo = ((uint32_t)p * (uint32_t)nc + (uint32_t)k) * (uint32_t)sizeof(T);
     const uint32_t cso = (uint32_t)(a.ld * nc) * (uint32_t)sizeof(T);
     auto rs_view = [&](int s0) {
         const uint64_t rem = (uint64_t)(a.strips - s0) * (uint64_t)a.Nrow * sizeof(T);
-        return make_rsrc(rowpart + (int64_t)s0 * a.Nrow + j0, (uint32_t)min(rem, (uint64_t)0xffffffffu));
+        return make_rsrc(rowpart + (int64_t)s0 * a.Nrow + jb, (uint32_t)min(rem, (uint64_t)0xffffffffu));
     };
     auto ck_view = [&](int h0) {
         const uint64_t rem = (uint64_t)(a.chunks - h0) * (uint64_t)(a.ld * nc) * sizeof(T);
@@ -627,6 +632,13 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
         for (int e = 0; e < URS; ++e) ur[e] = bld_t<T>(r, rvo, (uint32_t)e * rso);
 #pragma unroll
         for (int e = 0; e < URS; ++e) rs += (double)ur[e];
+    }
+    {
+        // (point pr, strips kr + G m) -> lane kr of point pr
+        __shared__ double rsl[kBlock];
+        rsl[kr * PER + pr] = rs;
+        __syncthreads();
+        rs = rsl[k * PER + threadIdx.x / G];
     }
 #pragma unroll
     for (int e = 0; e < UCK; ++e) ck += (double)uc[e];
@@ -822,7 +834,7 @@ __device__ void update_block(const UpdateArgs& a, const int blk, const int nblk)
 
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) {
-    reduce_block<T, G>(a, blockIdx.x, gridDim.x);
+    reduce_block<T, G>(a, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
 template <typename T, int G, int MIX>
@@ -835,7 +847,7 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_reduce_batched(const ReduceArgs* args, const int2* blocks,
                                                            const int32_t* nblk_of_p, int q) {
-    const int2 bp = blocks[blockIdx.x];
+    const int2 bp = blocks[xcd_remap(blockIdx.x, gridDim.x)];
     ReduceArgs a = args[bp.x];
     a.q = q;
     reduce_block<T, G>(a, bp.y, nblk_of_p[bp.x]);

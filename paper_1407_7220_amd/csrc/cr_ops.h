@@ -247,6 +247,18 @@ static __device__ void gather_sum2(const double* part, int count, int q0, int q1
     block_sum2(s0, s1);
 }
 
+// Workgroup b of a launch runs on XCD b mod 8 (round-robin dispatch, each
+// XCD with its own L2).  xcd_remap maps b to a logical index such that every
+// XCD takes one contiguous range of logical indices, so workgroups that share
+// cache lines (neighbouring points of the partial-sum arrays) share an L2.
+// A bijection on [0, n).
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+    constexpr int X = 8;
+    const int q = (n + X - 1) / X, tall = n % X == 0 ? X : n % X;
+    const int x = b % X, i = b / X;
+    return x < tall ? x * q + i : tall * q + (x - tall) * (q - 1) + i;
+}
+
 // gather_sum2 in two steps, with the same sums in the same order: the loads of
 // the first 4 kBlock records (issue), then the rest and the block sum (finish).
 static __device__ __forceinline__ void gather_issue(const double* part_, int count, int q0, int q1, double u0[4],
