@@ -109,7 +109,7 @@ __device__ bool lazy_operands(const PassArgs& a, const int strip, const int chun
         }
     }
     double u0[4], u1[4];
-    gather_issue(z.npart, z.nblk, 0, 1, u0, u1);
+    gather_issue<1>(z.npart, z.nblk, 0, 1, u0, u1);
     const gp<const OuterArgs> oa = glob(z.oa);
     const double By = oa->By, Bxi = oa->Bxi;
     __builtin_amdgcn_sched_barrier(0);
@@ -147,7 +147,7 @@ __device__ bool lazy_operands(const PassArgs& a, const int strip, const int chun
 
     // Fig. 4 steps 1-2 of iteration l - 1: the ball projections' scales
     double ny2, nx2;
-    gather_finish(z.npart, z.nblk, 0, 1, u0, u1, ny2, nx2);
+    gather_finish<1>(z.npart, z.nblk, 0, 1, u0, u1, ny2, nx2);
     const double ny = sqrt(ny2), nx = sqrt(nx2);
     const bool py = ny > By, px = nx > Bxi;
     const double sy = py ? By / ny : 1.0, sx = px ? Bxi / nx : 1.0;
@@ -770,48 +770,60 @@ __device__ __forceinline__ void bf16_split(float v, __bf16& hi, __bf16& lo) {
 
 template <typename T, int G, int MIX>
 __device__ void update_block(const UpdateArgs& a, const int blk, const int nblk) {
+    // Everything that does not depend on the iteration number is loaded with
+    // the activity flag and the replay base (the point's state, the norm pieces
+    // of up to 4096 reduce blocks, the ball radii), before the first wait.
     DevState* st = a.st;
-    if (st->active == 0) return;
+    const int act_v = vld_i32(&st->active);
+    const u32x2 base_v = vld_i64(&st->base);
+    __builtin_amdgcn_sched_barrier(0);
     constexpr int PER = kBlock / G;
     const int k = threadIdx.x % G;
     const int64_t j = (int64_t)blk * PER + threadIdx.x / G;
     const bool valid = j < a.N;
     const int n = a.n;
-    const double beta = a.beta[st->base + a.q + 1];   // (t_l - 1) / t_{l+1}
-    // this point's state first, so that the loads overlap the norm gather
-    double v = 0.0, c2 = 0.0, c1p = 0.0, cb = 0.0, xe = 0.0;
+    // branch-free: every lane loads its point's y entries (one address per
+    // point) and its xi entries at a clamped index, then keeps what it owns
     const int64_t e = j * n + k;
-    if (valid && k == n) {
-        v = a.vy[j]; c2 = a.y2[j]; c1p = a.y1p[j]; cb = a.ybar[j];
-    } else if (valid && k < n) {
-        v = a.vxi[e]; c2 = a.xi2[e]; c1p = a.xi1p[e]; xe = a.X[e];
-    }
+    const bool isy = valid && k == n, isx = valid && k < n;
+    const int64_t jc = valid ? j : 0, ec = isx ? e : 0;
+    const double yv = glob(a.vy)[jc], y2v = glob(a.y2)[jc], y1v = glob(a.y1p)[jc], ybv = glob(a.ybar)[jc];
+    const double xv = glob(a.vxi)[ec], x2v = glob(a.xi2)[ec], x1v = glob(a.xi1p)[ec], Xv = glob(a.X)[ec];
+    const double v = isy ? yv : isx ? xv : 0.0, c2 = isy ? y2v : isx ? x2v : 0.0;
+    const double c1p = isy ? y1v : isx ? x1v : 0.0, cb = isy ? ybv : 0.0, xe = isx ? Xv : 0.0;
+    double u0[16], u1[16];
+    gather_issue<4>(a.blockpart, nblk, 0, 1, u0, u1);
+    const gp<const OuterArgs> oa = glob(a.oa);
+    const double By = oa->By, Bxi = oa->Bxi;
+    __builtin_amdgcn_sched_barrier(0);
+    if (uniform(act_v) == 0) return;
+    const double beta = glob(a.beta)[uniform(base_v) + a.q + 1];   // (t_l - 1) / t_{l+1}
     // ball projections (Fig. 4 steps 1-2): every block forms the same norms
     double ny2, nx2;
-    gather_sum2(a.blockpart, nblk, 0, 1, ny2, nx2);
+    gather_finish<4>(a.blockpart, nblk, 0, 1, u0, u1, ny2, nx2);
     const double ny = sqrt(ny2), nx = sqrt(nx2);
-    const double sc_y = ny > a.oa->By ? a.oa->By / ny : 1.0;
-    const double sc_xi = nx > a.oa->Bxi ? a.oa->Bxi / nx : 1.0;
+    const double sc_y = ny > By ? By / ny : 1.0;
+    const double sc_xi = nx > Bxi ? Bxi / nx : 1.0;
     double dy2 = 0.0, dx2 = 0.0, prod = 0.0, y2n = 0.0;
-    T* xa = (T*)a.xiaug + j * a.kp;
-    if (a.sv_nrm && blk == 0 && threadIdx.x == 0) { a.sv_nrm[0] = ny; a.sv_nrm[1] = nx; }
+    const gp<T> xa = glob((T*)a.xiaug + j * a.kp);
+    if (a.sv_nrm && blk == 0 && threadIdx.x == 0) { glob(a.sv_nrm)[0] = ny; glob(a.sv_nrm)[1] = nx; }
     if (valid && k == n) {
-        const double y1 = ny > a.oa->By ? cb + sc_y * (v - cb) : v;   // projection onto Q_y
-        if (a.sv_y2) { a.sv_y2[j] = c2; a.sv_vy[j] = v; }
+        const double y1 = ny > By ? cb + sc_y * (v - cb) : v;   // projection onto Q_y
+        if (a.sv_y2) { glob(a.sv_y2)[j] = c2; glob(a.sv_vy)[j] = v; }
         dy2 = (y1 - c2) * (y1 - c2);
         y2n = y1 + beta * (y1 - c1p);                       // extrapolation
-        a.y1p[j] = y1;
-        a.y2[j] = y2n;
+        glob(a.y1p)[j] = y1;
+        glob(a.y2)[j] = y2n;
     } else if (valid && k < n) {
         const double x1 = sc_xi * v;                        // projection onto Q_xi
-        if (a.sv_y2) { a.sv_xi2[e] = c2; a.sv_vxi[e] = v; }
+        if (a.sv_y2) { glob(a.sv_xi2)[e] = c2; glob(a.sv_vxi)[e] = v; }
         dx2 = (x1 - c2) * (x1 - c2);
         const double x2n = x1 + beta * (x1 - c1p);
-        a.xi1p[e] = x1;
-        a.xi2[e] = x2n;
-        const double xo = a.shift ? x2n + a.shift[e] : x2n;   // slope of the next pass's operands
+        glob(a.xi1p)[e] = x1;
+        glob(a.xi2)[e] = x2n;
+        const double xo = a.shift ? x2n + glob(a.shift)[e] : x2n;   // slope of the next pass's operands
         if (MIX) {
-            __bf16* xb = (__bf16*)a.xiaug + j * a.kp;
+            const gp<__bf16> xb = glob((__bf16*)a.xiaug + j * a.kp);
             __bf16 hi, lo;
             bf16_split((float)(-xo), hi, lo);
             xb[k] = hi;
@@ -824,12 +836,12 @@ __device__ void update_block(const UpdateArgs& a, const int blk, const int nblk)
     }
     const double d = group_sum<G>(prod);                    // x_j^T xi_j
     if (valid && k == n) {
-        if (MIX) a.cvec[j] = (float)(d - y2n);
+        if (MIX) glob(a.cvec)[j] = (float)(d - y2n);
         else xa[n] = (T)(d - y2n);
-        ((T*)a.ycol)[j] = (T)y2n;
+        glob((T*)a.ycol)[j] = (T)y2n;
     }
     block_sum2(dy2, dx2);
-    if (threadIdx.x == 0) { a.blockpart[blk * 4 + 2] = dy2; a.blockpart[blk * 4 + 3] = dx2; }
+    if (threadIdx.x == 0) { glob(a.blockpart)[blk * 4 + 2] = dy2; glob(a.blockpart)[blk * 4 + 3] = dx2; }
 }
 
 template <typename T, int G>

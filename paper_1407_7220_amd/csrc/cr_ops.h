@@ -260,12 +260,14 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
 }
 
 // gather_sum2 in two steps, with the same sums in the same order: the loads of
-// the first 4 kBlock records (issue), then the rest and the block sum (finish).
-static __device__ __forceinline__ void gather_issue(const double* part_, int count, int q0, int q1, double u0[4],
-                                                    double u1[4]) {
+// the first NB x 4 kBlock records (issue), then the rest and the block sum
+// (finish).  Records past `count` read as 0.0, which leaves the sums unchanged.
+template <int NB>
+static __device__ __forceinline__ void gather_issue(const double* part_, int count, int q0, int q1,
+                                                    double u0[4 * NB], double u1[4 * NB]) {
     const gp<const double> part = glob(part_);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < 4 * NB; ++e) {
         const int r = threadIdx.x + e * kBlock;
         const int64_t rc = max(min(r, count - 1), 0);
         const double x0 = part[rc * 4 + q0], x1 = part[rc * 4 + q1];
@@ -273,14 +275,15 @@ static __device__ __forceinline__ void gather_issue(const double* part_, int cou
         u1[e] = r < count ? x1 : 0.0;
     }
 }
-static __device__ void gather_finish(const double* part_, int count, int q0, int q1, const double u0[4],
-                                     const double u1[4], double& s0, double& s1) {
+template <int NB>
+static __device__ void gather_finish(const double* part_, int count, int q0, int q1, const double u0[4 * NB],
+                                     const double u1[4 * NB], double& s0, double& s1) {
     const gp<const double> part = glob(part_);
     s0 = 0.0;
     s1 = 0.0;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) { s0 += u0[e]; s1 += u1[e]; }
-    for (int b = threadIdx.x + 4 * kBlock; b < count; b += 4 * kBlock) {
+    for (int e = 0; e < 4 * NB; ++e) { s0 += u0[e]; s1 += u1[e]; }
+    for (int b = threadIdx.x + 4 * NB * kBlock; b < count; b += 4 * kBlock) {
         double w0[4], w1[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
