@@ -204,14 +204,24 @@ __device__ bool lazy_operands(const PassArgs& a, const int strip, const int chun
         const int r = threadIdx.x + kBlock * e;
         if (r < rows) row(r, rv[e], rb[e], rp[e], ro[e]);
     }
-    for (int r = threadIdx.x + kBlock * RB; r < rows; r += kBlock) {
-        const int64_t i = I0 + r;
-        double v = 0.0, b = 0.0, p = 0.0, o = 0.0;
-        if (i < N) {
-            v = vy[i]; b = ybar[i]; p = y1in[i];
-            if (wrows) o = y2[i];
+    // taller chunks: the further rows RB at a time, each batch's loads together
+    for (int q0 = threadIdx.x + kBlock * RB; q0 < rows; q0 += kBlock * RB) {
+        double v[RB], b[RB], p[RB], o[RB];
+#pragma unroll
+        for (int e = 0; e < RB; ++e) {
+            const int r = q0 + kBlock * e;
+            const int64_t i = I0 + r;
+            v[e] = b[e] = p[e] = o[e] = 0.0;
+            if (r < rows && i < N) {
+                v[e] = vy[i]; b[e] = ybar[i]; p[e] = y1in[i];
+                if (wrows) o[e] = y2[i];
+            }
         }
-        row(r, v, b, p, o);
+#pragma unroll
+        for (int e = 0; e < RB; ++e) {
+            const int r = q0 + kBlock * e;
+            if (r < rows) row(r, v[e], b[e], p[e], o[e]);
+        }
     }
     if (wrows || wcols) {
         dy = wave_sum(dy);
