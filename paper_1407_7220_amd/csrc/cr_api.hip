@@ -1930,6 +1930,24 @@ static hipError_t ctx_resetup(cr_ctx* c, hipStream_t cs) {
     return e;
 }
 
+// The re-fit of every block problem, one launch per step for all of them
+// (the per-problem sequence of ctx_resetup when there are more than
+// kMaxRefit blocks).
+static bool refit_table(const std::vector<cr_ctx*>& sub, cr::RefitTable& t) {
+    if (sub.size() > (size_t)cr::kMaxRefit) return false;
+    t = cr::RefitTable{};
+    t.K = (int32_t)sub.size();
+    for (size_t p = 0; p < sub.size(); ++p) {
+        const cr_ctx* c = sub[p];
+        const Layout& L = c->L;
+        cr::RefitArgs& a = t.p[p];
+        a.X = c->X; a.ybar = c->ybar; a.N = c->N; a.n = c->n; a.gamma = c->p.gamma;
+        a.su = c->D(L.off_su); a.part = c->D(L.off_supart); a.y0 = c->D(L.off_y0); a.xi0 = c->D(L.off_xi0);
+        a.st = c->st; a.shift = c->shift;
+    }
+    return true;
+}
+
 
 extern "C" {
 
@@ -2047,9 +2065,13 @@ cr_status cr_papg(const void* X_dev, const void* ybar_dev, int64_t N, int32_t n,
     // schedule nothing is read back until the end (an adaptive one polls its
     // replays' activity flag).
     const bool fixed_blocks = alcc->inner_iters > 0;
+    cr::RefitTable rt;
+    const bool batched_refit = refit_table(b->sub, rt);
     for (int l = 1; l <= pp->iters; ++l) {
         if (l > 1) PBCHK(cr::launch_papg_lin(a, cs));
-        for (cr_ctx* c : b->sub) PBCHK(ctx_resetup(c, cs));
+        if (batched_refit) PBCHK(cr::launch_refit_batched(rt, cs));
+        else
+            for (cr_ctx* c : b->sub) PBCHK(ctx_resetup(c, cs));
         s = cr_batch_start(b);
         if (s != CR_OK) return s;
         int32_t running = 1;

@@ -267,6 +267,25 @@ constexpr int64_t kSuRows = 64;
 // The set-up again for new data ybar on the same points: means, the affine fit
 // from the eigen-decomposition the full set-up left in su, the start point and
 // Bbar; sigma_max(A2)^2 (a function of X alone) is kept.
+// Re-fit of up to kMaxRefit problems in one launch per step (launch_refit's
+// kernels, then the slope shift where a problem has one); the table travels in
+// the kernel arguments.
+constexpr int kMaxRefit = 16;
+struct RefitArgs {
+    const double* X;
+    const double* ybar;
+    int64_t N;
+    int32_t n, pad;
+    double gamma;
+    double* su;
+    double* part;
+    double* y0;
+    double* xi0;
+    DevState* st;
+    const double* shift;      // null: no slope shift
+};
+struct RefitTable { RefitArgs p[kMaxRefit]; int32_t K; };
+hipError_t launch_refit_batched(const RefitTable& t, hipStream_t s);
 hipError_t launch_refit(const double* X, const double* ybar, int64_t N, int n, double gamma, double* su,
                         double* part, double* y0, double* xi0, DevState* st, hipStream_t s);
 

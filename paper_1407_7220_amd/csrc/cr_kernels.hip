@@ -1255,8 +1255,8 @@ __global__ void k_zero16(uint4* p, int64_t n16) {
 // Scratch `su` layout: [0,n) xbar | [n] ybar mean | [n+1,2n+1) a | [2n+1] b |
 //   [2n+2, 3n+2) eigenvalues | [3n+2, 3n+2+n^2) eigenvectors (column k = vector k)
 // ---------------------------------------------------------------------------
-__global__ void k_su_sums(const double* X, const double* ybar, int64_t N, int n, int64_t rows,
-                          const double* su, int phase, double* part) {
+__device__ void su_sums_body(const double* X, const double* ybar, int64_t N, int n, int64_t rows,
+                             const double* su, int phase, double* part, const int blk) {
     // phase 0: e < n: sum x_ik; e = n: sum ybar; e = n+1: max |ybar|; e = n+2: # non-finite
     // phase 1: e < n*n: sum u_ik u_il; n*n <= e < n*n+n: sum u_ik (ybar_i - ybar_mean)
     // phase 2: e < n: sum u_ik (ybar_i - ybar_mean) (the entries n*n + e of phase 1)
@@ -1265,7 +1265,7 @@ __global__ void k_su_sums(const double* X, const double* ybar, int64_t N, int n,
     // workgroup are in flight together); the P pieces of an entry are then
     // combined in LDS in index order.  With more entries than threads each
     // thread walks all the rows of its entries (P = 1).
-    const int64_t r0 = (int64_t)blockIdx.x * rows, r1 = min(r0 + rows, N);
+    const int64_t r0 = (int64_t)blk * rows, r1 = min(r0 + rows, N);
     const int ne = phase == 0 ? n + 3 : (phase == 1 ? n * n + n : n);
     const int eq = phase == 2 ? n * n : 0;        // phase 2 computes phase 1's entries n*n + e
     const double ym = phase != 0 ? su[n] : 0.0;
@@ -1305,7 +1305,7 @@ __global__ void k_su_sums(const double* X, const double* ybar, int64_t N, int n,
         }
         const double v = is_max ? fmax(a0, a1) : a0 + a1;
         if (P == 1) {
-            if (active) part[(int64_t)blockIdx.x * ne + e] = v;
+            if (active) part[(int64_t)blk * ne + e] = v;
             continue;
         }
         __syncthreads();
@@ -1316,12 +1316,17 @@ __global__ void k_su_sums(const double* X, const double* ybar, int64_t N, int n,
             const bool mx = phase == 0 && ee == n + 1;
             double acc = piece[ee];
             for (int q = 1; q < P; ++q) acc = mx ? fmax(acc, piece[q * ne + ee]) : acc + piece[q * ne + ee];
-            part[(int64_t)blockIdx.x * ne + ee] = acc;
+            part[(int64_t)blk * ne + ee] = acc;
         }
     }
 }
 
-__global__ void k_su_means_final(const double* part, int nblk, int64_t N, int n, double* su, DevState* st) {
+__global__ void k_su_sums(const double* X, const double* ybar, int64_t N, int n, int64_t rows,
+                          const double* su, int phase, double* part) {
+    su_sums_body(X, ybar, N, n, rows, su, phase, part, blockIdx.x);
+}
+
+__device__ void su_means_final_body(const double* part, int nblk, int64_t N, int n, double* su, DevState* st) {
     // one thread per entry, blocks summed in index order
     const int ne = n + 3;
     const int e = threadIdx.x;
@@ -1334,23 +1339,29 @@ __global__ void k_su_means_final(const double* part, int nblk, int64_t N, int n,
     else if (e == n + 1) st->ybar_inf = acc;
     else st->nonfinite = acc > 0.0 ? 1 : 0;
 }
+__global__ void k_su_means_final(const double* part, int nblk, int64_t N, int n, double* su, DevState* st) {
+    su_means_final_body(part, nblk, N, n, su, st);
+}
 
 // The affine fit for new data on the same points: q = X_c^T ybar_c from the
 // phase-2 partials, then a and b from the eigen-decomposition already in su
-// (the same formula and order as k_su_eig_final).
-__global__ void k_su_fit_final(const double* part, int nblk, int n, double* su) {
-    if (threadIdx.x != 0) return;
-    double q[kMaxDim];
-    for (int e = 0; e < n; ++e) {
+// (the same formula and order as k_su_eig_final).  The sums of q, the
+// eigen-pairs and the means are staged in LDS by the whole workgroup first,
+// so that thread 0's arithmetic reads no global memory between its stores.
+__device__ void su_fit_final_body(const double* part, int nblk, int n, double* su) {
+    __shared__ double q[kMaxDim], lam[kMaxDim], V[kMaxDim * kMaxDim], xm[kMaxDim + 1], acoef[kMaxDim];
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
         double acc = 0.0;
         for (int b = 0; b < nblk; ++b) acc += part[b * n + e];
         q[e] = acc;
     }
-    const double* lam = su + 2 * n + 2;
-    const double* V = su + 3 * n + 2;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) lam[e] = su[2 * n + 2 + e];
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) V[e] = su[3 * n + 2 + e];
+    for (int e = threadIdx.x; e <= n; e += blockDim.x) xm[e] = su[e];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     double lmax = 0.0;
     for (int k = 0; k < n; ++k) lmax = fmax(lmax, lam[k]);
-    double* acoef = su + n + 1;
     for (int l = 0; l < n; ++l) acoef[l] = 0.0;
     for (int k = 0; k < n; ++k) {
         if (!(lam[k] > 1e-12 * lmax)) continue;
@@ -1359,9 +1370,13 @@ __global__ void k_su_fit_final(const double* part, int nblk, int n, double* su) 
         proj /= lam[k];
         for (int l = 0; l < n; ++l) acoef[l] += proj * V[l * n + k];
     }
-    double b = su[n];
-    for (int l = 0; l < n; ++l) b -= su[l] * acoef[l];
+    double b = xm[n];
+    for (int l = 0; l < n; ++l) b -= xm[l] * acoef[l];
+    for (int l = 0; l < n; ++l) su[n + 1 + l] = acoef[l];
     su[2 * n + 1] = b;
+}
+__global__ void k_su_fit_final(const double* part, int nblk, int n, double* su) {
+    su_fit_final_body(part, nblk, n, su);
 }
 
 // Cyclic Jacobi eigen-decomposition of the centred scatter matrix M0 and the
@@ -1472,9 +1487,9 @@ __global__ void k_su_sigma2_final(const double* part, int nblk, DevState* st) {
 }
 
 // Start point (Sec. II-E): yhat = X a + b, xihat_l = a; Bbar^2 = |yhat - ybar|^2 + gamma |xihat|^2.
-__global__ __launch_bounds__(kBlock) void k_su_start(const double* X, const double* ybar, int64_t N, int n,
-                                                     const double* su, double* y0, double* xi0, double* part) {
-    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__device__ void su_start_body(const double* X, const double* ybar, int64_t N, int n, const double* su, double* y0,
+                              double* xi0, double* part, const int blk) {
+    const int64_t j = (int64_t)blk * kBlock + threadIdx.x;
     const double* acoef = su + n + 1;
     double r2 = 0.0;
     if (j < N) {
@@ -1487,11 +1502,15 @@ __global__ __launch_bounds__(kBlock) void k_su_start(const double* X, const doub
         r2 = (v - ybar[j]) * (v - ybar[j]);
     }
     const double b = block_reduce(r2, 0);
-    if (threadIdx.x == 0) part[blockIdx.x] = b;
+    if (threadIdx.x == 0) part[blk] = b;
+}
+__global__ __launch_bounds__(kBlock) void k_su_start(const double* X, const double* ybar, int64_t N, int n,
+                                                     const double* su, double* y0, double* xi0, double* part) {
+    su_start_body(X, ybar, N, n, su, y0, xi0, part, blockIdx.x);
 }
 
-__global__ void k_su_start_final(const double* part, int nblk, int64_t N, int n, double gamma, const double* su,
-                                 DevState* st) {
+__device__ void su_start_final_body(const double* part, int nblk, int64_t N, int n, double gamma, const double* su,
+                                    DevState* st) {
     if (threadIdx.x != 0) return;
     double s = 0.0;
     for (int b = 0; b < nblk; ++b) s += part[b];
@@ -1500,13 +1519,16 @@ __global__ void k_su_start_final(const double* part, int nblk, int64_t N, int n,
     st->aff_b = su[2 * n + 1];
     st->Bbar = sqrt(s + gamma * (double)N * aa);
 }
+__global__ void k_su_start_final(const double* part, int nblk, int64_t N, int n, double gamma, const double* su,
+                                 DevState* st) {
+    su_start_final_body(part, nblk, N, n, gamma, su, st);
+}
 
 // Start of a problem in shifted slopes xi = xi' + c: the affine fit (yhat, a)
 // is (yhat, a - c) there, still feasible; Bbar is the objective at it.  One
 // workgroup; fixed summation order.
-__global__ __launch_bounds__(kBlock) void k_su_shift(const double* y0, const double* ybar, double* xi0,
-                                                     const double* shift, int64_t N, int n, double gamma,
-                                                     DevState* st) {
+__device__ void su_shift_body(const double* y0, const double* ybar, double* xi0, const double* shift, int64_t N, int n,
+                              double gamma, DevState* st) {
     double r2 = 0.0, x2 = 0.0;
     for (int64_t j = threadIdx.x; j < N; j += kBlock) {
         const double d = y0[j] - ybar[j];
@@ -1519,6 +1541,41 @@ __global__ __launch_bounds__(kBlock) void k_su_shift(const double* y0, const dou
     }
     const double R2 = block_reduce(r2, 0), X2 = block_reduce(x2, 0);
     if (threadIdx.x == 0) st->Bbar = sqrt(R2 + gamma * X2);
+}
+__global__ __launch_bounds__(kBlock) void k_su_shift(const double* y0, const double* ybar, double* xi0,
+                                                     const double* shift, int64_t N, int n, double gamma,
+                                                     DevState* st) {
+    su_shift_body(y0, ybar, xi0, shift, N, n, gamma, st);
+}
+
+// The re-fit of several problems (P-APG's blocks) in one launch per step:
+// problem blockIdx.y of the table, its blocks past its own count return.
+__global__ __launch_bounds__(kBlock) void k_refit_sums_b(RefitTable t, int phase) {
+    const RefitArgs& a = t.p[blockIdx.y];
+    if ((int64_t)blockIdx.x * kSuRows >= a.N) return;
+    su_sums_body(a.X, a.ybar, a.N, a.n, kSuRows, a.su, phase, a.part, blockIdx.x);
+}
+__global__ void k_refit_means_b(RefitTable t) {
+    const RefitArgs& a = t.p[blockIdx.y];
+    su_means_final_body(a.part, (int)((a.N + kSuRows - 1) / kSuRows), a.N, a.n, a.su, a.st);
+}
+__global__ void k_refit_fit_b(RefitTable t) {
+    const RefitArgs& a = t.p[blockIdx.y];
+    su_fit_final_body(a.part, (int)((a.N + kSuRows - 1) / kSuRows), a.n, a.su);
+}
+__global__ __launch_bounds__(kBlock) void k_refit_start_b(RefitTable t) {
+    const RefitArgs& a = t.p[blockIdx.y];
+    if ((int64_t)blockIdx.x * kBlock >= a.N) return;
+    su_start_body(a.X, a.ybar, a.N, a.n, a.su, a.y0, a.xi0, a.part, blockIdx.x);
+}
+__global__ void k_refit_start_final_b(RefitTable t) {
+    const RefitArgs& a = t.p[blockIdx.y];
+    su_start_final_body(a.part, (int)((a.N + kBlock - 1) / kBlock), a.N, a.n, a.gamma, a.su, a.st);
+}
+__global__ __launch_bounds__(kBlock) void k_refit_shift_b(RefitTable t) {
+    const RefitArgs& a = t.p[blockIdx.y];
+    if (!a.shift) return;
+    su_shift_body(a.y0, a.ybar, a.xi0, a.shift, a.N, a.n, a.gamma, a.st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1807,6 +1864,22 @@ hipError_t launch_refit(const double* X, const double* ybar, int64_t N, int n, d
     hipLaunchKernelGGL(k_su_start, dim3(nb), dim3(kBlock), 0, s, X, ybar, N, n, (const double*)su, y0, xi0, part);
     hipLaunchKernelGGL(k_su_start_final, dim3(1), dim3(64), 0, s, (const double*)part, nb, N, n, gamma,
                        (const double*)su, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_refit_batched(const RefitTable& t, hipStream_t s) {
+    if (t.K < 1 || t.K > kMaxRefit) return hipErrorInvalidValue;
+    int64_t nmax = 0;
+    for (int p = 0; p < t.K; ++p) nmax = std::max(nmax, t.p[p].N);
+    const unsigned nblk = (unsigned)((nmax + kSuRows - 1) / kSuRows), nb = (unsigned)((nmax + kBlock - 1) / kBlock);
+    const unsigned K = (unsigned)t.K;
+    hipLaunchKernelGGL(k_refit_sums_b, dim3(nblk, K), dim3(kBlock), 0, s, t, 0);
+    hipLaunchKernelGGL(k_refit_means_b, dim3(1, K), dim3(64), 0, s, t);
+    hipLaunchKernelGGL(k_refit_sums_b, dim3(nblk, K), dim3(kBlock), 0, s, t, 2);
+    hipLaunchKernelGGL(k_refit_fit_b, dim3(1, K), dim3(64), 0, s, t);
+    hipLaunchKernelGGL(k_refit_start_b, dim3(nb, K), dim3(kBlock), 0, s, t);
+    hipLaunchKernelGGL(k_refit_start_final_b, dim3(1, K), dim3(64), 0, s, t);
+    hipLaunchKernelGGL(k_refit_shift_b, dim3(1, K), dim3(kBlock), 0, s, t);
     return hipGetLastError();
 }
 
