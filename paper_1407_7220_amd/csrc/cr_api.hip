@@ -323,10 +323,12 @@ static hipError_t enqueue_device_step(cr_ctx* c, hipStream_t s) {
     if ((e = cr::launch_set_point(c->prec, pt, s)) != hipSuccess) return e;
     cr::PassArgs pa = pass_args(c, 1, 0.0, gate);
     pa.theta_scale_p = &c->oa->theta_scale;
+    pa.check_first = 1;                          // the gate is closed in most replays
     if ((e = cr::launch_pair_pass(c->prec, c->n, pa, pass_grid(L), s)) != hipSuccess) return e;
     cr::ReduceArgs ra = reduce_args(c, 2, c->D(L.off_y1p), c->D(L.off_xi1p), nullptr, nullptr, 0.0);
     ra.gate = gate;
     ra.mu_dev = 1;
+    ra.check_first = 1;
     if ((e = cr::launch_reduce(c->f64, ra, s)) != hipSuccess) return e;
     return cr::launch_alcc_step(c->sched, c->st, c->oa, s);
 }
@@ -1159,6 +1161,10 @@ static cr_status batch_init_impl(cr_batch** out, const cr_problem* probs, int32_
         }
         ra[p] = reduce_args(c, 0, c->D(L.off_y2), c->D(L.off_xi2), c->D(L.off_vy), c->D(L.off_vxi), 0.0);
         if (B.lazy) ra[p].spart = c->D(L.off_spart);
+        // adaptive schedules freeze problems at different times: their passes
+        // and reduces test the activity flag before loading anything
+        const int cf = params->inner_iters > 0 ? 0 : 1;
+        pa[p].check_first = pat[p].check_first = ra[p].check_first = cf;
         ua[p] = update_args(c);
         nstrips[p] = L.strips;
         sts[p] = c->st;
@@ -1168,9 +1174,11 @@ static cr_status batch_init_impl(cr_batch** out, const cr_problem* probs, int32_
         // the multiplier step of the device schedule, gated on the problem's step_due
         pa1[p] = pass_args(c, 1, 0.0, &c->st->step_due);
         pa1[p].theta_scale_p = &c->oa->theta_scale;
+        pa1[p].check_first = 1;                  // the gate is closed in most replays
         ra2[p] = reduce_args(c, 2, c->D(L.off_y1p), c->D(L.off_xi1p), nullptr, nullptr, 0.0);
         ra2[p].gate = &c->st->step_due;
         ra2[p].mu_dev = 1;
+        ra2[p].check_first = 1;
         pt[p] = point_args(c, c->D(L.off_y1p), c->D(L.off_xi1p), 1);
         pt[p].gate = &c->st->step_due;
     }

@@ -117,7 +117,7 @@ struct PassArgs {
     int32_t nc;               // n + 1
     int32_t rows_per_chunk;   // multiple of 64
     int32_t mode;             // 0 gradient pass, 1 multiplier (theta) pass
-    int32_t pad;
+    int32_t check_first;      // 1: test the activity flag before any tile load (batched adaptive runs)
     void* theta;              // Nrow x ld, pass precision
     const void* xp;           // packed X operands, (Nrow/16) x 64 x QP
     const void* xiaug;        // ld x KP: [-xi_j, d_j - y_j, 0..]
@@ -139,6 +139,7 @@ struct ReduceArgs {
     int32_t n, nc, strips, chunks, mode, npass;   // mode 0 MAPG step, 1 gradient out, 2 KKT
     int32_t q;                // mode 0: position of the iteration in the captured replay
     int32_t mu_dev;           // mode 2: 1 = mu_k from oa->mu (device schedule), 0 = from `mu`
+    int32_t check_first, pad; // check_first as in PassArgs
     const void* rowpart;
     const void* cpart;
     const double* X;

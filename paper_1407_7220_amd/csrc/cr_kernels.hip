@@ -236,7 +236,10 @@ __device__ bool lazy_operands(const PassArgs& a, const int strip, const int chun
 // lq: replay position of a lazy gradient pass (LazyStep).  The workgroup
 // returns after issuing its first tile loads when the activity flag is 0 (the
 // flag and the replay base are read together with those loads, so that the
-// pass's start waits on one round trip instead of three).
+// pass's start waits on one round trip instead of three).  With
+// a.check_first (batched adaptive runs, where many problems sit frozen for
+// most of a solve) it returns before any tile load instead, so that a frozen
+// problem's workgroups cost no memory traffic.
 template <typename Ops, int THETA_MODE, int LAZY = 0>
 __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chunk, const int nstrips,
                                char* __restrict__ lds, const int lq) {
@@ -428,6 +431,7 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
     u32x2 base_v = {0u, 0u};
     if constexpr (LAZY) base_v = vld_i64(&a.lz.st->base);
     __builtin_amdgcn_sched_barrier(0);
+    if (a.check_first && uniform(act_v) == 0) return;
     int64_t l = 0;
     if constexpr (LAZY) {
         // one tile in flight during the operand set-up (more would spill)
@@ -554,6 +558,8 @@ __device__ double block_gather(const double* part, int count, int q, int op) {
     return block_reduce(v, op);
 }
 
+// a.check_first: return before loading partial sums when the problem is
+// frozen (see pair_pass_item).
 template <typename T, int G>
 __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk) {
     // The activity flag, the gate and the replay base are read together with
@@ -571,6 +577,7 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
     const rsrc_t oar = make_rsrc(a.oa, use_oa ? 32u : 0u);
     const V16<double> o01 = bld16<double>(oar, 0, 0), o23 = bld16<double>(oar, 16, 0);
     __builtin_amdgcn_sched_barrier(0);
+    if (a.check_first && ((m0 && uniform(act_v) == 0) || (a.gate && uniform(gate_v) == 0))) return;
     constexpr int PER = kBlock / G;
     const int k = threadIdx.x % G;
     const int64_t j = (int64_t)blk * PER + threadIdx.x / G;
@@ -778,7 +785,7 @@ __device__ __forceinline__ void bf16_split(float v, __bf16& hi, __bf16& lo) {
     lo = (__bf16)(v - (float)hi);
 }
 
-template <typename T, int G, int MIX>
+template <typename T, int G, int MIX, bool CHECK_FIRST = false>
 __device__ void update_block(const UpdateArgs& a, const int blk, const int nblk) {
     // Everything that does not depend on the iteration number is loaded with
     // the activity flag and the replay base (the point's state, the norm pieces
@@ -787,6 +794,7 @@ __device__ void update_block(const UpdateArgs& a, const int blk, const int nblk)
     const int act_v = vld_i32(&st->active);
     const u32x2 base_v = vld_i64(&st->base);
     __builtin_amdgcn_sched_barrier(0);
+    if (CHECK_FIRST && uniform(act_v) == 0) return;
     constexpr int PER = kBlock / G;
     const int k = threadIdx.x % G;
     const int64_t j = (int64_t)blk * PER + threadIdx.x / G;
@@ -881,7 +889,7 @@ __global__ __launch_bounds__(kBlock) void k_update_batched(const UpdateArgs* arg
     const int2 bp = blocks[blockIdx.x];
     UpdateArgs a = args[bp.x];
     a.q = q;
-    update_block<T, G, 0>(a, bp.y, nblk_of_p[bp.x]);
+    update_block<T, G, 0, true>(a, bp.y, nblk_of_p[bp.x]);
 }
 
 // After the last replay of an ALCC iteration: if no reduce kernel has stopped
