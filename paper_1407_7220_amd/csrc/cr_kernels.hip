@@ -248,6 +248,9 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
     constexpr int TW = Ops::TW;
     constexpr int NKB = Ops::NKB;
     constexpr int EV = 16 / (int)sizeof(T);
+    // check_first: a plain (scalar) read of the flag before anything else, the
+    // cheapest exit for the many workgroups of frozen problems
+    if (a.check_first && *a.active == 0) return;
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, c = lane & 15;
@@ -431,7 +434,6 @@ __device__ void pair_pass_item(const PassArgs& a, const int strip, const int chu
     u32x2 base_v = {0u, 0u};
     if constexpr (LAZY) base_v = vld_i64(&a.lz.st->base);
     __builtin_amdgcn_sched_barrier(0);
-    if (a.check_first && uniform(act_v) == 0) return;
     int64_t l = 0;
     if constexpr (LAZY) {
         // one tile in flight during the operand set-up (more would spill)
@@ -568,6 +570,7 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
     // start then waits on one round trip of loads instead of two.
     DevState* st = a.st;
     const bool m0 = a.mode == 0;
+    if (a.check_first && ((m0 && st->active == 0) || (a.gate && *a.gate == 0))) return;
     const int act_v = vld_i32(&st->active, m0);
     const u32x2 base_v = vld_i64(&st->base, m0);
     const int gate_v = vld_i32(a.gate, a.gate != nullptr);
@@ -577,7 +580,6 @@ __device__ void reduce_block(const ReduceArgs& a, const int blk, const int nblk)
     const rsrc_t oar = make_rsrc(a.oa, use_oa ? 32u : 0u);
     const V16<double> o01 = bld16<double>(oar, 0, 0), o23 = bld16<double>(oar, 16, 0);
     __builtin_amdgcn_sched_barrier(0);
-    if (a.check_first && ((m0 && uniform(act_v) == 0) || (a.gate && uniform(gate_v) == 0))) return;
     constexpr int PER = kBlock / G;
     const int k = threadIdx.x % G;
     const int64_t j = (int64_t)blk * PER + threadIdx.x / G;
@@ -791,10 +793,10 @@ __device__ void update_block(const UpdateArgs& a, const int blk, const int nblk)
     // the activity flag and the replay base (the point's state, the norm pieces
     // of up to 4096 reduce blocks, the ball radii), before the first wait.
     DevState* st = a.st;
+    if (CHECK_FIRST && st->active == 0) return;
     const int act_v = vld_i32(&st->active);
     const u32x2 base_v = vld_i64(&st->base);
     __builtin_amdgcn_sched_barrier(0);
-    if (CHECK_FIRST && uniform(act_v) == 0) return;
     constexpr int PER = kBlock / G;
     const int k = threadIdx.x % G;
     const int64_t j = (int64_t)blk * PER + threadIdx.x / G;
@@ -877,7 +879,9 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_reduce_batched(const ReduceArgs* args, const int2* blocks,
                                                            const int32_t* nblk_of_p, int q) {
-    const int2 bp = blocks[xcd_remap(blockIdx.x, gridDim.x)];
+    // no XCD remap here: a problem's blocks stay spread over all XCDs, so the
+    // last problems still running in an adaptive batch use the whole chip
+    const int2 bp = blocks[blockIdx.x];
     ReduceArgs a = args[bp.x];
     a.q = q;
     reduce_block<T, G>(a, bp.y, nblk_of_p[bp.x]);
