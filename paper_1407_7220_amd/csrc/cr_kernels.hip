@@ -1392,9 +1392,14 @@ __global__ void k_su_fit_final(const double* part, int nblk, int n, double* su) 
 }
 
 // Cyclic Jacobi eigen-decomposition of the centred scatter matrix M0 and the
-// affine fit a = M0^+ X_c^T ybar_c, b = mean(ybar) - xbar^T a.
+// affine fit a = M0^+ X_c^T ybar_c, b = mean(ybar) - xbar^T a.  Each rotation's
+// column, row and eigenvector updates run with one thread per index k (the
+// elements a thread updates are its own, so every value is computed exactly
+// as a single thread walking k would); the sweep's stopping test and the
+// rotation angle are formed from the same LDS values in the same order.
 __global__ void k_su_eig_final(const double* part, int nblk, int n, double* su) {
     __shared__ double A[kMaxDim * kMaxDim], V[kMaxDim * kMaxDim], q[kMaxDim];
+    __shared__ int done;
     const int ne = n * n + n;
     for (int e = threadIdx.x; e < ne; e += blockDim.x) {
         double acc = 0.0;
@@ -1402,41 +1407,47 @@ __global__ void k_su_eig_final(const double* part, int nblk, int n, double* su) 
         if (e < n * n) A[e] = acc;
         else q[e - n * n] = acc;
     }
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) V[e] = e / n == e % n ? 1.0 : 0.0;
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    for (int k = 0; k < n; ++k)
-        for (int l = 0; l < n; ++l) V[k * n + l] = k == l ? 1.0 : 0.0;
+    const int k = threadIdx.x;
     for (int sweep = 0; sweep < 100; ++sweep) {
-        double off = 0.0, diag = 0.0;
-        for (int p = 0; p < n; ++p) {
-            diag += A[p * n + p] * A[p * n + p];
-            for (int r = p + 1; r < n; ++r) off += A[p * n + r] * A[p * n + r];
+        if (threadIdx.x == 0) {
+            double off = 0.0, diag = 0.0;
+            for (int p = 0; p < n; ++p) {
+                diag += A[p * n + p] * A[p * n + p];
+                for (int r = p + 1; r < n; ++r) off += A[p * n + r] * A[p * n + r];
+            }
+            done = off <= 1e-32 * diag || off == 0.0;
         }
-        if (off <= 1e-32 * diag || off == 0.0) break;
+        __syncthreads();
+        if (done) break;
         for (int p = 0; p < n; ++p)
             for (int r = p + 1; r < n; ++r) {
                 const double apr = A[p * n + r];
-                if (apr == 0.0) continue;
-                const double tau = (A[r * n + r] - A[p * n + p]) / (2.0 * apr);
+                const double app = A[p * n + p], arr = A[r * n + r];
+                __syncthreads();                     // every thread has read the pivot entries
+                if (apr == 0.0) continue;            // the same value in every thread
+                const double tau = (arr - app) / (2.0 * apr);
                 const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                 const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = tt * cs;
-                for (int k = 0; k < n; ++k) {       // columns p, r
+                if (k < n) {                         // columns p, r
                     const double akp = A[k * n + p], akr = A[k * n + r];
                     A[k * n + p] = cs * akp - sn * akr;
                     A[k * n + r] = sn * akp + cs * akr;
                 }
-                for (int k = 0; k < n; ++k) {       // rows p, r
+                __syncthreads();
+                if (k < n) {                         // rows p, r; eigenvectors
                     const double apk = A[p * n + k], ark = A[r * n + k];
                     A[p * n + k] = cs * apk - sn * ark;
                     A[r * n + k] = sn * apk + cs * ark;
-                }
-                for (int k = 0; k < n; ++k) {
                     const double vkp = V[k * n + p], vkr = V[k * n + r];
                     V[k * n + p] = cs * vkp - sn * vkr;
                     V[k * n + r] = sn * vkp + cs * vkr;
                 }
+                __syncthreads();
             }
     }
+    if (threadIdx.x != 0) return;
     double lmax = 0.0;
     for (int k = 0; k < n; ++k) lmax = fmax(lmax, A[k * n + k]);
     double* lam = su + 2 * n + 2;
