@@ -178,6 +178,7 @@ struct cr_ctx {
     int prec;
     hipStream_t user_stream = nullptr;
     hipStream_t cs = nullptr;            // internal stream (graph capture needs a non-null stream)
+    bool owns_cs = true;                 // false: the stream of the batch this context belongs to
     hipGraphExec_t graph = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     int32_t* pinned_flag = nullptr;      // 2 slots
@@ -488,8 +489,11 @@ cr_status cr_pass_layout(int64_t N, int32_t n, const cr_params* params, int64_t*
     return CR_OK;
 }
 
-cr_status cr_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params, const void* X_dev,
-                  const void* ybar_dev, void* workspace_dev, size_t ws_bytes, void* stream) {
+// shared_cs non-null: the context runs on that stream (a batch's problems) and
+// neither creates nor destroys one.
+static cr_status ctx_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params, const void* X_dev,
+                          const void* ybar_dev, void* workspace_dev, size_t ws_bytes, void* stream,
+                          hipStream_t shared_cs) {
     std::string msg;
     if (!out) return fail(nullptr, CR_ERR_ARG, "out is NULL");
     *out = nullptr;
@@ -522,15 +526,22 @@ cr_status cr_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params, c
     c->sched = reinterpret_cast<cr::AlccSched*>(c->P(L.off_sched));
     c->replay = replay_iters(*params);
     auto bad = [&](cr_status st) { cr_destroy(c); return st; };
-    hipError_t e = hipStreamCreateWithFlags(&c->cs, hipStreamNonBlocking);
+    hipError_t e = hipSuccess;
+    if (shared_cs) {
+        c->cs = shared_cs;
+        c->owns_cs = false;
+    } else {
+        e = hipStreamCreateWithFlags(&c->cs, hipStreamNonBlocking);
+    }
     if (e != hipSuccess) { fail(nullptr, CR_ERR_HIP, std::string("stream: ") + hipGetErrorString(e)); return bad(CR_ERR_HIP); }
     for (int q = 0; q < 2; ++q) {
         e = hipEventCreateWithFlags(&c->ev[q], hipEventDisableTiming);
         if (e != hipSuccess) { fail(nullptr, CR_ERR_HIP, "event create"); return bad(CR_ERR_HIP); }
     }
-    e = hipHostMalloc((void**)&c->pinned_flag, 64, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&c->pinned_state, sizeof(cr::DevState), hipHostMallocDefault);
+    // one pinned block: the two flag slots, then the state read-back
+    e = hipHostMalloc((void**)&c->pinned_flag, 64 + sizeof(cr::DevState), hipHostMallocDefault);
     if (e != hipSuccess) { fail(nullptr, CR_ERR_HIP, "pinned host allocation"); return bad(CR_ERR_HIP); }
+    c->pinned_state = reinterpret_cast<cr::DevState*>(reinterpret_cast<char*>(c->pinned_flag) + 64);
 
     // order after the caller's prior work on its stream
     hipEvent_t ue = c->ev[0];
@@ -549,21 +560,34 @@ cr_status cr_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params, c
     if (e == hipSuccess) e = cr::launch_prep_xp(c->prec, c->X, N, n, L.Nrow, L.ks, L.qp, c->P(L.off_xp), cs);
     if (e == hipSuccess) {
         // momentum weights of Fig. 4: t_1 = 1, t_{l+1} = (1 + sqrt(1 + 4 t_l^2)) / 2,
-        // beta_l = (t_l - 1) / t_{l+1}; entry 0 is unused
-        double* hb = nullptr;
-        e = hipHostMalloc((void**)&hb, (size_t)L.nbeta * 8, hipHostMallocDefault);
-        if (e == hipSuccess) {
-            double t = 1.0;
-            hb[0] = 0.0;
-            for (int64_t l = 1; l < L.nbeta; ++l) {
-                const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
-                hb[l] = (t - 1.0) / tn;
-                t = tn;
-            }
-            e = hipMemcpyAsync(c->P(L.off_beta), hb, (size_t)L.nbeta * 8, hipMemcpyHostToDevice, cs);
-            if (e == hipSuccess) e = hipStreamSynchronize(cs);
-            hipHostFree(hb);
+        // beta_l = (t_l - 1) / t_{l+1}; entry 0 is unused.  The copy is from
+        // pageable memory: the runtime stages it before the call returns.
+        std::vector<double> hb((size_t)L.nbeta);
+        double t = 1.0;
+        hb[0] = 0.0;
+        for (int64_t l = 1; l < L.nbeta; ++l) {
+            const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+            hb[l] = (t - 1.0) / tn;
+            t = tn;
         }
+        e = hipMemcpyAsync(c->P(L.off_beta), hb.data(), (size_t)L.nbeta * 8, hipMemcpyHostToDevice, cs);
+    }
+    {
+        // constants of the device ALCC schedule (the state is set by k_alcc_start)
+        cr::AlccSched sc{};
+        sc.mu1 = params->mu1 > 0 ? params->mu1 : 1.0 / (2.0 * (double)N);
+        sc.c = params->c; sc.kappa = params->kappa; sc.tau1 = params->tau1;
+        sc.ay1 = params->alpha_y1; sc.axi1 = params->alpha_xi1; sc.gamma = params->gamma;
+        sc.step_scale = params->step_scale; sc.kkt_tol = params->kkt_tol;
+        sc.Ly_ovr = params->Ly_override; sc.Lxi_ovr = params->Lxi_override;
+        sc.By_ovr = params->By_override; sc.Bxi_ovr = params->Bxi_override;
+        sc.sigma2_A1 = 2.0 * (double)N;
+        sc.inner_iters = params->inner_iters; sc.max_inner = params->max_inner; sc.max_outer = params->max_outer;
+        sc.hist_inner = reinterpret_cast<int64_t*>(c->P(L.off_hist));
+        sc.hist_kkt = reinterpret_cast<double*>(c->P(L.off_hist) + (size_t)std::max(params->max_outer, 1) * 8);
+        sc.phase = 2;
+        // staged from pageable memory; complete at the stream synchronisation below
+        if (e == hipSuccess) e = hipMemcpyAsync(c->sched, &sc, sizeof(sc), hipMemcpyHostToDevice, cs);
     }
     if (e == hipSuccess) {
         cr::PointArgs pa = point_args(c, c->D(L.off_y0), c->D(L.off_xi0), 1);
@@ -584,25 +608,13 @@ cr_status cr_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params, c
         fail(nullptr, CR_ERR_NONFINITE, "non-finite problem constants");
         return bad(CR_ERR_NONFINITE);
     }
-    {
-        // constants of the device ALCC schedule (the state is set by k_alcc_start)
-        cr::AlccSched sc{};
-        sc.mu1 = params->mu1 > 0 ? params->mu1 : 1.0 / (2.0 * (double)N);
-        sc.c = params->c; sc.kappa = params->kappa; sc.tau1 = params->tau1;
-        sc.ay1 = params->alpha_y1; sc.axi1 = params->alpha_xi1; sc.gamma = params->gamma;
-        sc.step_scale = params->step_scale; sc.kkt_tol = params->kkt_tol;
-        sc.Ly_ovr = params->Ly_override; sc.Lxi_ovr = params->Lxi_override;
-        sc.By_ovr = params->By_override; sc.Bxi_ovr = params->Bxi_override;
-        sc.sigma2_A1 = 2.0 * (double)N;
-        sc.inner_iters = params->inner_iters; sc.max_inner = params->max_inner; sc.max_outer = params->max_outer;
-        sc.hist_inner = reinterpret_cast<int64_t*>(c->P(L.off_hist));
-        sc.hist_kkt = reinterpret_cast<double*>(c->P(L.off_hist) + (size_t)std::max(params->max_outer, 1) * 8);
-        sc.phase = 2;
-        e = hipMemcpy(c->sched, &sc, sizeof(sc), hipMemcpyHostToDevice);
-        if (e != hipSuccess) { fail(nullptr, CR_ERR_HIP, std::string("schedule: ") + hipGetErrorString(e)); return bad(CR_ERR_HIP); }
-    }
     *out = c;
     return CR_OK;
+}
+
+cr_status cr_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* params, const void* X_dev,
+                  const void* ybar_dev, void* workspace_dev, size_t ws_bytes, void* stream) {
+    return ctx_init(out, N, n, params, X_dev, ybar_dev, workspace_dev, ws_bytes, stream, nullptr);
 }
 
 cr_status cr_destroy(cr_ctx* c) {
@@ -611,9 +623,8 @@ cr_status cr_destroy(cr_ctx* c) {
     if (c->graph) hipGraphExecDestroy(c->graph);
     for (int q = 0; q < 2; ++q)
         if (c->ev[q]) hipEventDestroy(c->ev[q]);
-    if (c->pinned_flag) hipHostFree(c->pinned_flag);
-    if (c->pinned_state) hipHostFree(c->pinned_state);
-    if (c->cs) hipStreamDestroy(c->cs);
+    if (c->pinned_flag) hipHostFree(c->pinned_flag);     // the state read-back shares its block
+    if (c->cs && c->owns_cs) hipStreamDestroy(c->cs);
     delete c;
     return CR_OK;
 }
@@ -1127,8 +1138,8 @@ static cr_status batch_init_impl(cr_batch** out, const cr_problem* probs, int32_
         cr_ctx* c = nullptr;
         cr_params pp = *params;
         if (probs[p].tile_rows > 0) pp.tile_rows = probs[p].tile_rows;
-        cr_status st = cr_init(&c, probs[p].N, probs[p].n, &pp, probs[p].X_dev, probs[p].ybar_dev,
-                               b->ws + B.off[p], B.L[p].total, stream);
+        cr_status st = ctx_init(&c, probs[p].N, probs[p].n, &pp, probs[p].X_dev, probs[p].ybar_dev,
+                                b->ws + B.off[p], B.L[p].total, stream, b->cs);
         if (st != CR_OK) { g_last_error = "problem " + std::to_string(p) + ": " + g_last_error; return bad(st); }
         // lazy batches: the next pass completes each MAPG step (no update kernel)
         c->lazy = B.lazy;
