@@ -1198,24 +1198,26 @@ static cr_status batch_init_impl(cr_batch** out, const cr_problem* probs, int32_
             if ((batch_group(probs[p].n) == 16) == (gs == 0))
                 for (int q = 0; q < B.nblk[p]; ++q) { blocks.push_back(p); blocks.push_back(q); }
     char* h = b->ws;
-    e = hipMemcpy(h + B.off_pass, pa.data(), P * sizeof(cr::PassArgs), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(h + B.off_red, ra.data(), P * sizeof(cr::ReduceArgs), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(h + B.off_upd, ua.data(), P * sizeof(cr::UpdateArgs), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(h + B.off_nstrips, nstrips.data(), P * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(h + B.off_blocks, blocks.data(), blocks.size() * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(h + B.off_nblk, B.nblk.data(), P * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(h + B.off_sts, sts.data(), P * sizeof(void*), hipMemcpyHostToDevice);
+    // tables copied on the batch's stream, ahead of every kernel that reads them
+    // (staged from pageable memory before each call returns)
+    e = hipMemcpyAsync(h + B.off_pass, pa.data(), P * sizeof(cr::PassArgs), hipMemcpyHostToDevice, b->cs);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + B.off_red, ra.data(), P * sizeof(cr::ReduceArgs), hipMemcpyHostToDevice, b->cs);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + B.off_upd, ua.data(), P * sizeof(cr::UpdateArgs), hipMemcpyHostToDevice, b->cs);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + B.off_nstrips, nstrips.data(), P * 4, hipMemcpyHostToDevice, b->cs);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + B.off_blocks, blocks.data(), blocks.size() * 4, hipMemcpyHostToDevice, b->cs);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + B.off_nblk, B.nblk.data(), P * 4, hipMemcpyHostToDevice, b->cs);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + B.off_sts, sts.data(), P * sizeof(void*), hipMemcpyHostToDevice, b->cs);
     if (e == hipSuccess && !B.items.empty())
-        e = hipMemcpy(h + B.off_items, B.items.data(), B.items.size() * sizeof(BatchItemH), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(h + B.off_scheds, scheds.data(), P * sizeof(void*), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(h + B.off_oas, oas.data(), P * sizeof(void*), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(h + B.off_bparts, bparts.data(), P * sizeof(void*), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(h + B.off_pass1, pa1.data(), P * sizeof(cr::PassArgs), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(h + B.off_red2, ra2.data(), P * sizeof(cr::ReduceArgs), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(h + B.off_pt, pt.data(), P * sizeof(cr::PointArgs), hipMemcpyHostToDevice);
+        e = hipMemcpyAsync(h + B.off_items, B.items.data(), B.items.size() * sizeof(BatchItemH), hipMemcpyHostToDevice, b->cs);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + B.off_scheds, scheds.data(), P * sizeof(void*), hipMemcpyHostToDevice, b->cs);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + B.off_oas, oas.data(), P * sizeof(void*), hipMemcpyHostToDevice, b->cs);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + B.off_bparts, bparts.data(), P * sizeof(void*), hipMemcpyHostToDevice, b->cs);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + B.off_pass1, pa1.data(), P * sizeof(cr::PassArgs), hipMemcpyHostToDevice, b->cs);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + B.off_red2, ra2.data(), P * sizeof(cr::ReduceArgs), hipMemcpyHostToDevice, b->cs);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + B.off_pt, pt.data(), P * sizeof(cr::PointArgs), hipMemcpyHostToDevice, b->cs);
     if (e == hipSuccess)
-        e = hipMemcpy(h + B.off_pass_time, pat.data(), P * sizeof(cr::PassArgs), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(h + B.off_nblk0, zeros.data(), P * 4, hipMemcpyHostToDevice);
+        e = hipMemcpyAsync(h + B.off_pass_time, pat.data(), P * sizeof(cr::PassArgs), hipMemcpyHostToDevice, b->cs);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + B.off_nblk0, zeros.data(), P * 4, hipMemcpyHostToDevice, b->cs);
     if (e != hipSuccess) { fail(nullptr, CR_ERR_HIP, std::string("batch tables: ") + hipGetErrorString(e)); return bad(CR_ERR_HIP); }
     *out = b;
     return CR_OK;
