@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -179,6 +180,7 @@ struct cr_ctx {
     hipStream_t user_stream = nullptr;
     hipStream_t cs = nullptr;            // internal stream (graph capture needs a non-null stream)
     bool owns_cs = true;                 // false: the stream of the batch this context belongs to
+    int dev = 0;                         // device current at creation (its pools take the stream and block back)
     hipGraphExec_t graph = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     int32_t* pinned_flag = nullptr;      // 2 slots
@@ -215,6 +217,66 @@ static cr_status fail(cr_ctx* ctx, cr_status s, const std::string& msg) {
         if (e_ != hipSuccess)                                                                    \
             return fail(ctx, CR_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));     \
     } while (0)
+
+// Pinned host blocks (a context's flag slots and state read-back, a batch's
+// flag) and internal streams are pooled per device for the life of the
+// process: each allocation or creation costs tens of microseconds, and a P-APG
+// call builds a batch of contexts every time.  Streams go back idle (their
+// owners synchronise them first).
+constexpr size_t kPinnedBytes = (64 + sizeof(cr::DevState) + 255) / 256 * 256;
+struct HostPools {
+    std::mutex mu;
+    std::vector<std::vector<void*>> pinned;           // per device
+    std::vector<std::vector<hipStream_t>> streams;    // per device
+};
+static HostPools& pools() {
+    static HostPools p;
+    return p;
+}
+static int current_device() {
+    int d = 0;
+    return hipGetDevice(&d) == hipSuccess && d >= 0 ? d : 0;
+}
+static hipError_t pinned_get(void** out) {
+    const int d = current_device();
+    {
+        HostPools& P = pools();
+        std::lock_guard<std::mutex> g(P.mu);
+        if ((int)P.pinned.size() > d && !P.pinned[d].empty()) {
+            *out = P.pinned[d].back();
+            P.pinned[d].pop_back();
+            return hipSuccess;
+        }
+    }
+    return hipHostMalloc(out, kPinnedBytes, hipHostMallocDefault);
+}
+static void pinned_put(void* p, int d) {
+    if (!p) return;
+    HostPools& P = pools();
+    std::lock_guard<std::mutex> g(P.mu);
+    if ((int)P.pinned.size() <= d) P.pinned.resize(d + 1);
+    P.pinned[d].push_back(p);
+}
+static hipError_t stream_get(hipStream_t* out) {
+    const int d = current_device();
+    {
+        HostPools& P = pools();
+        std::lock_guard<std::mutex> g(P.mu);
+        if ((int)P.streams.size() > d && !P.streams[d].empty()) {
+            *out = P.streams[d].back();
+            P.streams[d].pop_back();
+            return hipSuccess;
+        }
+    }
+    return hipStreamCreateWithFlags(out, hipStreamNonBlocking);
+}
+static void stream_put(hipStream_t s, int d) {
+    if (!s) return;
+    HostPools& P = pools();
+    std::lock_guard<std::mutex> g(P.mu);
+    if ((int)P.streams.size() <= d) P.streams.resize(d + 1);
+    P.streams[d].push_back(s);
+}
 
 static cr::PassArgs pass_args(cr_ctx* c, int mode, double theta_scale, const int32_t* active) {
     const Layout& L = c->L;
@@ -526,12 +588,13 @@ static cr_status ctx_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* p
     c->sched = reinterpret_cast<cr::AlccSched*>(c->P(L.off_sched));
     c->replay = replay_iters(*params);
     auto bad = [&](cr_status st) { cr_destroy(c); return st; };
+    c->dev = current_device();
     hipError_t e = hipSuccess;
     if (shared_cs) {
         c->cs = shared_cs;
         c->owns_cs = false;
     } else {
-        e = hipStreamCreateWithFlags(&c->cs, hipStreamNonBlocking);
+        e = stream_get(&c->cs);
     }
     if (e != hipSuccess) { fail(nullptr, CR_ERR_HIP, std::string("stream: ") + hipGetErrorString(e)); return bad(CR_ERR_HIP); }
     for (int q = 0; q < 2; ++q) {
@@ -539,7 +602,7 @@ static cr_status ctx_init(cr_ctx** out, int64_t N, int32_t n, const cr_params* p
         if (e != hipSuccess) { fail(nullptr, CR_ERR_HIP, "event create"); return bad(CR_ERR_HIP); }
     }
     // one pinned block: the two flag slots, then the state read-back
-    e = hipHostMalloc((void**)&c->pinned_flag, 64 + sizeof(cr::DevState), hipHostMallocDefault);
+    e = pinned_get((void**)&c->pinned_flag);
     if (e != hipSuccess) { fail(nullptr, CR_ERR_HIP, "pinned host allocation"); return bad(CR_ERR_HIP); }
     c->pinned_state = reinterpret_cast<cr::DevState*>(reinterpret_cast<char*>(c->pinned_flag) + 64);
 
@@ -623,8 +686,8 @@ cr_status cr_destroy(cr_ctx* c) {
     if (c->graph) hipGraphExecDestroy(c->graph);
     for (int q = 0; q < 2; ++q)
         if (c->ev[q]) hipEventDestroy(c->ev[q]);
-    if (c->pinned_flag) hipHostFree(c->pinned_flag);     // the state read-back shares its block
-    if (c->cs && c->owns_cs) hipStreamDestroy(c->cs);
+    pinned_put(c->pinned_flag, c->dev);                // the state read-back shares its block
+    if (c->owns_cs) stream_put(c->cs, c->dev);
     delete c;
     return CR_OK;
 }
@@ -987,6 +1050,7 @@ struct cr_batch {
     std::chrono::steady_clock::time_point t0;
     hipEvent_t ev[2] = {nullptr, nullptr};
     int32_t* pinned_flag = nullptr;
+    int dev = 0;                 // device current at creation
     char* ws = nullptr;
     bool f64 = false;
     std::string err;
@@ -1096,8 +1160,8 @@ cr_status cr_batch_destroy(cr_batch* b) {
     for (cr_ctx* c : b->sub) cr_destroy(c);
     for (int q = 0; q < 2; ++q)
         if (b->ev[q]) hipEventDestroy(b->ev[q]);
-    if (b->pinned_flag) hipHostFree(b->pinned_flag);
-    if (b->cs) hipStreamDestroy(b->cs);
+    pinned_put(b->pinned_flag, b->dev);
+    stream_put(b->cs, b->dev);
     delete b;
     return CR_OK;
 }
@@ -1129,9 +1193,10 @@ static cr_status batch_init_impl(cr_batch** out, const cr_problem* probs, int32_
     b->f64 = params->precision == CR_F64;
     b->replay = replay_iters(*params);
     auto bad = [&](cr_status st) { std::string m = g_last_error; cr_batch_destroy(b); g_last_error = m; return st; };
-    hipError_t e = hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking);
+    b->dev = current_device();
+    hipError_t e = stream_get(&b->cs);
     for (int q = 0; q < 2 && e == hipSuccess; ++q) e = hipEventCreateWithFlags(&b->ev[q], hipEventDisableTiming);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&b->pinned_flag, 64, hipHostMallocDefault);
+    if (e == hipSuccess) e = pinned_get((void**)&b->pinned_flag);
     if (e != hipSuccess) { fail(nullptr, CR_ERR_HIP, std::string("batch resources: ") + hipGetErrorString(e)); return bad(CR_ERR_HIP); }
     // per-problem contexts (set-up of each problem on its own slice)
     for (int p = 0; p < P; ++p) {
